@@ -1,0 +1,28 @@
+"""Seeded synthetic problem data for the FFT-VIE matvec and solver.
+
+This package holds the *problem* only -- voxel grids, material maps of the
+synthetic phantoms, incident fields, right-hand sides, the Galerkin Green's
+tensor of the volume operator and seeded random vectors.  It holds none of
+the compressed-matvec method (compression, circulant embedding, FFTs,
+Hadamard products, Krylov solves): the oracle and the GPU library implement
+those independently and both consume the arrays built here.
+
+Array conventions (numpy, C order): a vector field is (3, n3, n2, n1)
+complex with x fastest; a scalar map is (n3, n2, n1); the Green's tensor is
+(6, n3, n2, n1) complex128, components xx, yy, zz, xy, xz, yz, entry
+[c, k, j, i] = Nt_c(offset (i, j, k)).
+"""
+from .constants import C0, EPS0, MU0, COMPONENTS, omega, wavenumber
+from .grid import voxel_centres
+from .materials import complex_permittivity, TISSUES_298MHZ
+from .phantoms import sphere_phantom, head_phantom, head_semi_axes
+from .fields import plane_wave, dipole_field, dipole_ring, dipole_cylinder, rhs_from_field
+from .green import green_tensor
+from .random import random_field, random_complex
+
+__all__ = [
+    "C0", "EPS0", "MU0", "COMPONENTS", "omega", "wavenumber", "voxel_centres",
+    "complex_permittivity", "TISSUES_298MHZ", "sphere_phantom", "head_phantom",
+    "head_semi_axes", "plane_wave", "dipole_field", "dipole_ring", "dipole_cylinder",
+    "rhs_from_field", "green_tensor", "random_field", "random_complex",
+]

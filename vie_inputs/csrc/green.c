@@ -1,0 +1,341 @@
+/*
+ * Galerkin Green's tensor of the electric volume operator N for piecewise-
+ * constant (pulse) current basis functions on a uniform cubic voxel grid.
+ *
+ * Problem data, not part of the compressed-matvec method: the paper defines
+ * the entries as L2 inner products of a test pulse in voxel 0 with N applied
+ * to a basis pulse in voxel Delta (Sec. II-B, eq. 8a-8b, with the operator N
+ * of eq. 5 and the kernel of eq. 6) but leaves their evaluation to external
+ * singular-integral routines.  This file evaluates them directly.
+ *
+ * Reading used (dimensionless coordinates x = r/h, kappa = k0*h):
+ *   N u = u + (k0^2 + grad div) int g u      (curl curl = grad div - laplacian,
+ *                                            and (lap + k0^2) g = -delta)
+ *   The 6-D Galerkin integral of two unit pulses collapses to a 3-D integral
+ *   against the pulse autocorrelation tau_D(x) = prod_i lam(x_i - D_i),
+ *   lam(t) = max(1 - |t|, 0).  Rows are divided by the voxel volume, so the
+ *   mass matrix is the identity and
+ *     Nt_pq(D) = d_pq d_D0 + kappa^2 d_pq J0(D) + Jpq(D)
+ *     J0(D)    = int g^(x) tau_D(x) dx
+ *     Jpq(D)   = int g^(x) d_p d_q tau_D(x) dx        (distributional)
+ *   with g^(x) = exp(-i kappa |x|) / (4 pi |x|).
+ *   For max_i D_i >= 2 the kernel is smooth on the support and the classical
+ *   form Nt_pq(D) = int Gd_pq(x) tau_D(x) dx is used, with the dyadic
+ *   Gd_pq = (kappa^2 d_pq + d_p d_q) g^.
+ *   For max_i D_i <= 1 the support touches the singularity: J0 and Jpq
+ *   (p != q, where d_p d_q tau = lam' lam' lam) are volume integrals over the
+ *   8 cells cut by the kinks of tau, with a Duffy transform on cells that have
+ *   the origin at a corner; Jpp uses lam'' = delta(t+1) - 2 delta(t) +
+ *   delta(t-1), i.e. three plane integrals per component, with a 2-D Duffy
+ *   transform on the plane through the origin.
+ *
+ * Output layout: out[((c*n3 + k)*n2 + j)*n1 + i] (complex128 interleaved),
+ * components c = xx, yy, zz, xy, xz, yz, entry = Nt_c(D = (i, j, k)).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+#define QMAX 40
+static double gl_x[QMAX + 1][QMAX];
+static double gl_w[QMAX + 1][QMAX];
+static int gl_ready = 0;
+
+/* Gauss-Legendre nodes and weights on [0, 1] by Newton iteration on the
+ * Legendre polynomial P_q (three-term recurrence). */
+static void legendre(int q, double z, double *p, double *dp)
+{
+    double p0 = 1.0, p1 = 0.0;
+    for (int j = 1; j <= q; ++j) {
+        double p2 = p1;
+        p1 = p0;
+        p0 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p2) / j;
+    }
+    *p = p0;
+    *dp = q * (z * p0 - p1) / (z * z - 1.0);
+}
+
+static void gl_init(void)
+{
+    if (gl_ready) return;
+    for (int q = 1; q <= QMAX; ++q) {
+        for (int i = 0; i < q; ++i) {
+            double z = cos(M_PI * (i + 0.75) / (q + 0.5)), p, dp;
+            for (int it = 0; it < 100; ++it) {
+                legendre(q, z, &p, &dp);
+                double dz = p / dp;
+                z -= dz;
+                if (fabs(dz) < 1e-15) break;
+            }
+            legendre(q, z, &p, &dp);
+            gl_x[q][i] = 0.5 * (1.0 - z);
+            gl_w[q][i] = 1.0 / ((1.0 - z * z) * dp * dp);
+        }
+    }
+    gl_ready = 1;
+}
+
+static const int comp_p[6] = {0, 1, 2, 0, 0, 1};
+static const int comp_q[6] = {0, 1, 2, 1, 2, 2};
+
+/* scalar kernel g^(x) = exp(-i kappa r) / (4 pi r) */
+static inline cplx ghat(double r, double kappa)
+{
+    return cexp(-I * kappa * r) / (4.0 * M_PI * r);
+}
+
+/* lam(t) and its derivative on the open cell containing t */
+static inline double lam(double t) { double a = 1.0 - fabs(t); return a > 0 ? a : 0.0; }
+
+/* ---------------- far field: smooth dyadic against tau_D ---------------- */
+static void far_entry(const int D[3], double kappa, int q, cplx out[6])
+{
+    cplx acc[6] = {0, 0, 0, 0, 0, 0};
+    const double *gx = gl_x[q], *gw = gl_w[q];
+    /* 8 cells: per axis t in [-1,0] or [0,1] around D, tent weight 1-|t| */
+    for (int cell = 0; cell < 8; ++cell) {
+        double lo[3];
+        for (int a = 0; a < 3; ++a) lo[a] = ((cell >> a) & 1) ? 0.0 : -1.0;
+        for (int ia = 0; ia < q; ++ia) {
+            double t0 = lo[0] + gx[ia];
+            double w0 = gw[ia] * (1.0 - fabs(t0));
+            double x0 = D[0] + t0;
+            for (int ib = 0; ib < q; ++ib) {
+                double t1 = lo[1] + gx[ib];
+                double w1 = w0 * gw[ib] * (1.0 - fabs(t1));
+                double x1 = D[1] + t1;
+                for (int ic = 0; ic < q; ++ic) {
+                    double t2 = lo[2] + gx[ic];
+                    double w = w1 * gw[ic] * (1.0 - fabs(t2));
+                    double x2 = D[2] + t2;
+                    double r2 = x0 * x0 + x1 * x1 + x2 * x2;
+                    double r = sqrt(r2);
+                    cplx g = ghat(r, kappa);
+                    cplx ikr = I * kappa * r;
+                    cplx diag = g * (kappa * kappa - (1.0 + ikr) / r2);
+                    cplx radial = g * (3.0 + 3.0 * ikr - kappa * kappa * r2) / (r2 * r2);
+                    double xs[3] = {x0, x1, x2};
+                    for (int c = 0; c < 6; ++c) {
+                        int p = comp_p[c], qq = comp_q[c];
+                        cplx v = radial * xs[p] * xs[qq];
+                        if (p == qq) v += diag;
+                        acc[c] += w * v;
+                    }
+                }
+            }
+        }
+    }
+    for (int c = 0; c < 6; ++c) out[c] = acc[c];
+}
+
+/* ---------------- near field helpers ---------------- */
+
+/* integrand weight for the volume integrals J0 and Jpq (p != q) at x:
+ * returns tau_D(x) in w[0] and lam' lam' lam for the 3 off-diagonal pairs
+ * (xy, xz, yz) in w[1..3].  x must lie strictly inside a cell. */
+static inline void vol_weights(const double x[3], const int D[3], double w[4])
+{
+    double l[3], d[3];
+    for (int a = 0; a < 3; ++a) {
+        double t = x[a] - D[a];
+        l[a] = lam(t);
+        d[a] = (fabs(t) < 1.0) ? (t > 0 ? -1.0 : 1.0) : 0.0;
+    }
+    w[0] = l[0] * l[1] * l[2];
+    w[1] = d[0] * d[1] * l[2];
+    w[2] = d[0] * d[2] * l[1];
+    w[3] = d[1] * d[2] * l[0];
+}
+
+/* volume integral of g^ * {tau, lam'lam'lam (3 pairs)} over a unit cell
+ * [lo, lo+1]^3 that does not contain the origin in its closure */
+static void vol_cell_regular(const double lo[3], const int D[3], double kappa, int q, cplx acc[4])
+{
+    const double *gx = gl_x[q], *gw = gl_w[q];
+    for (int ia = 0; ia < q; ++ia)
+        for (int ib = 0; ib < q; ++ib)
+            for (int ic = 0; ic < q; ++ic) {
+                double x[3] = {lo[0] + gx[ia], lo[1] + gx[ib], lo[2] + gx[ic]};
+                double w = gw[ia] * gw[ib] * gw[ic];
+                double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+                cplx g = ghat(r, kappa) * w;
+                double wt[4];
+                vol_weights(x, D, wt);
+                for (int m = 0; m < 4; ++m) acc[m] += g * wt[m];
+            }
+}
+
+/* same over a unit cell with the origin at one corner: the cell is
+ * {sigma_a * y_a, y in [0,1]^3}; Duffy split into three pyramids with apex
+ * at the origin, each mapped to [0,1]^3 with Jacobian s^2, which cancels
+ * the 1/r singularity of g^. */
+static void vol_cell_corner(const double sigma[3], const int D[3], double kappa, int q, cplx acc[4])
+{
+    const double *gx = gl_x[q], *gw = gl_w[q];
+    for (int face = 0; face < 3; ++face) {
+        int a1 = (face + 1) % 3, a2 = (face + 2) % 3;
+        for (int is = 0; is < q; ++is) {
+            double s = gx[is];
+            for (int ib = 0; ib < q; ++ib)
+                for (int ic = 0; ic < q; ++ic) {
+                    double y[3];
+                    y[face] = s;
+                    y[a1] = s * gx[ib];
+                    y[a2] = s * gx[ic];
+                    double x[3] = {sigma[0] * y[0], sigma[1] * y[1], sigma[2] * y[2]};
+                    double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+                    double w = gw[is] * gw[ib] * gw[ic] * s * s;
+                    cplx g = ghat(r, kappa) * w;
+                    double wt[4];
+                    vol_weights(x, D, wt);
+                    for (int m = 0; m < 4; ++m) acc[m] += g * wt[m];
+                }
+        }
+    }
+}
+
+/* plane integral over the unit square [lo_a, lo_a+1] x [lo_b, lo_b+1] in the
+ * plane x_p = c of g^ * lam(x_a - D_a) * lam(x_b - D_b) */
+static cplx plane_cell(int p, double c, const double lo2[2], const double sig2[2], int corner,
+                       const int D[3], double kappa, int q)
+{
+    const double *gx = gl_x[q], *gw = gl_w[q];
+    int a = (p + 1) % 3, b = (p + 2) % 3;
+    cplx acc = 0;
+    if (!corner) {
+        for (int i = 0; i < q; ++i)
+            for (int j = 0; j < q; ++j) {
+                double xa = lo2[0] + gx[i], xb = lo2[1] + gx[j];
+                double r = sqrt(c * c + xa * xa + xb * xb);
+                acc += gw[i] * gw[j] * lam(xa - D[a]) * lam(xb - D[b]) * ghat(r, kappa);
+            }
+    } else {
+        /* origin at a corner of the square and c == 0: two triangles */
+        for (int tri = 0; tri < 2; ++tri)
+            for (int i = 0; i < q; ++i) {
+                double s = gx[i];
+                for (int j = 0; j < q; ++j) {
+                    double ya = tri == 0 ? s : s * gx[j];
+                    double yb = tri == 0 ? s * gx[j] : s;
+                    double xa = sig2[0] * ya, xb = sig2[1] * yb;
+                    double r = sqrt(ya * ya + yb * yb);
+                    acc += gw[i] * gw[j] * s * lam(xa - D[a]) * lam(xb - D[b]) * ghat(r, kappa);
+                }
+            }
+    }
+    return acc;
+}
+
+static void near_entry(const int D[3], double kappa, int q, cplx out[6])
+{
+    /* volume part: J0 and the three off-diagonal Jpq */
+    cplx vol[4] = {0, 0, 0, 0};
+    for (int cell = 0; cell < 8; ++cell) {
+        double lo[3];
+        int corner = 1;
+        double sigma[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = D[a] + (((cell >> a) & 1) ? 0.0 : -1.0);
+            if (lo[a] == 0.0) sigma[a] = 1.0;
+            else if (lo[a] == -1.0) sigma[a] = -1.0;
+            else corner = 0;
+        }
+        if (corner) vol_cell_corner(sigma, D, kappa, q, vol);
+        else vol_cell_regular(lo, D, kappa, q, vol);
+    }
+    /* plane part: Jpp = sum_s c_s * plane integral at x_p = D_p + s */
+    cplx jpp[3];
+    for (int p = 0; p < 3; ++p) {
+        int a = (p + 1) % 3, b = (p + 2) % 3;
+        cplx acc = 0;
+        for (int sft = -1; sft <= 1; ++sft) {
+            double c = D[p] + sft;
+            double coef = (sft == 0) ? -2.0 : 1.0;
+            for (int cell = 0; cell < 4; ++cell) {
+                double lo2[2] = {D[a] + ((cell & 1) ? 0.0 : -1.0), D[b] + ((cell & 2) ? 0.0 : -1.0)};
+                int corner = (c == 0.0);
+                double sig2[2];
+                for (int m = 0; m < 2; ++m) {
+                    if (lo2[m] == 0.0) sig2[m] = 1.0;
+                    else if (lo2[m] == -1.0) sig2[m] = -1.0;
+                    else corner = 0;
+                }
+                acc += coef * plane_cell(p, c, lo2, sig2, corner, D, kappa, q);
+            }
+        }
+        jpp[p] = acc;
+    }
+    int self = (D[0] == 0 && D[1] == 0 && D[2] == 0);
+    for (int p = 0; p < 3; ++p) out[p] = (self ? 1.0 : 0.0) + kappa * kappa * vol[0] + jpp[p];
+    out[3] = vol[1];
+    out[4] = vol[2];
+    out[5] = vol[3];
+}
+
+static int far_order(int d, int boost)
+{
+    int q;
+    if (d <= 2) q = 10;
+    else if (d == 3) q = 8;
+    else if (d <= 5) q = 6;
+    else if (d <= 11) q = 4;
+    else if (d <= 31) q = 3;
+    else q = 2;
+    q += boost;
+    return q > QMAX ? QMAX : q;
+}
+
+/* Fill the dense defining tensor.  near_q: Gauss order of the singular
+ * (Duffy) integrals; boost: extra order on every far-field shell.  Only
+ * entries with offset index in [lo_lin, hi_lin) of the linear (i fastest)
+ * offset order are computed, so callers can split work. */
+int vie_green_fill(int n1, int n2, int n3, double kappa, int near_q, int boost,
+                   double *out, long lo_lin, long hi_lin)
+{
+    gl_init();
+    if (near_q < 2 || near_q > QMAX) return -1;
+    long V = (long)n1 * n2 * n3;
+    if (hi_lin > V) hi_lin = V;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long lin = lo_lin; lin < hi_lin; ++lin) {
+        int D[3] = {(int)(lin % n1), (int)((lin / n1) % n2), (int)(lin / ((long)n1 * n2))};
+        int d = D[0];
+        if (D[1] > d) d = D[1];
+        if (D[2] > d) d = D[2];
+        cplx e[6];
+        if (d <= 1) near_entry(D, kappa, near_q, e);
+        else far_entry(D, kappa, far_order(d, boost), e);
+        for (int c = 0; c < 6; ++c) {
+            out[2 * (c * V + lin)] = creal(e[c]);
+            out[2 * (c * V + lin) + 1] = cimag(e[c]);
+        }
+    }
+    return 0;
+}
+
+/* Dimensionless dyadic Gd_pq(x) = (kappa^2 d_pq + d_p d_q) g^(x) at points
+ * x (npts x 3), all six components: used for point-sampled incident fields
+ * of Hertzian dipoles.  out: npts x 6 complex interleaved. */
+void vie_dyadic_points(long npts, const double *x, double kappa, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (long m = 0; m < npts; ++m) {
+        double x0 = x[3 * m], x1 = x[3 * m + 1], x2 = x[3 * m + 2];
+        double r2 = x0 * x0 + x1 * x1 + x2 * x2;
+        double r = sqrt(r2);
+        cplx g = ghat(r, kappa);
+        cplx ikr = I * kappa * r;
+        cplx diag = g * (kappa * kappa - (1.0 + ikr) / r2);
+        cplx radial = g * (3.0 + 3.0 * ikr - kappa * kappa * r2) / (r2 * r2);
+        double xs[3] = {x0, x1, x2};
+        for (int c = 0; c < 6; ++c) {
+            cplx v = radial * xs[comp_p[c]] * xs[comp_q[c]];
+            if (comp_p[c] == comp_q[c]) v += diag;
+            out[2 * (6 * m + c)] = creal(v);
+            out[2 * (6 * m + c) + 1] = cimag(v);
+        }
+    }
+}

@@ -1,0 +1,72 @@
+"""Incident fields and right-hand sides.
+
+Incident fields are sampled at voxel centres.  The right-hand side of the
+electric current equation is b = c_e chi e_inc with c_e = i omega eps0 and
+chi = eps_c - 1 (eq. 1-2 of the paper, electric block).
+"""
+import math
+
+import numpy as np
+
+from . import _native
+from .constants import EPS0, omega, wavenumber
+from .grid import voxel_centres
+
+
+def plane_wave(n, h, freq_hz, pol=0, amplitude=1.0):
+    """Unit plane wave pol-hat * exp(-i k0 z) travelling along +z
+    (exp(+i omega t) convention).  Shape (3, n3, n2, n1) complex128."""
+    _, _, z = voxel_centres(n, h)
+    e = np.zeros((3,) + z.shape, dtype=np.complex128)
+    e[pol] = amplitude * np.exp(-1j * wavenumber(freq_hz) * z)
+    return e
+
+
+def _dyadic(points, k0):
+    """(k0^2 I + grad grad) exp(-i k0 R)/(4 pi R) at the given points
+    (N x 3, metres), six components per point."""
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    out = np.empty((pts.shape[0], 6, 2), dtype=np.float64)
+    _native.lib().vie_dyadic_points(pts.shape[0], pts.ctypes.data, float(k0), out.ctypes.data)
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def dipole_field(n, h, freq_hz, r_d, mask, moment=1.0):
+    """Field of a z-directed Hertzian dipole of moment I*l = ``moment`` A m at
+    ``r_d`` (metres): E = (I l / (i omega eps0)) [(k0^2 I + grad grad) g] z-hat,
+    evaluated at the centres of voxels where ``mask`` is true and set to zero
+    elsewhere (the dipole may sit inside the grid's bounding box)."""
+    x, y, z = voxel_centres(n, h)
+    sel = np.nonzero(mask.ravel())[0]
+    pts = np.stack([x.ravel()[sel] - r_d[0], y.ravel()[sel] - r_d[1], z.ravel()[sel] - r_d[2]], axis=1)
+    G = _dyadic(pts, wavenumber(freq_hz))
+    pref = moment / (1j * omega(freq_hz) * EPS0)
+    e = np.zeros((3, x.size), dtype=np.complex128)
+    # components (x,z), (y,z), (z,z) are indices 4, 5, 2 of xx,yy,zz,xy,xz,yz
+    e[0, sel] = pref * G[:, 4]
+    e[1, sel] = pref * G[:, 5]
+    e[2, sel] = pref * G[:, 2]
+    return e.reshape((3,) + x.shape)
+
+
+def dipole_ring(count=8, radius=0.15, z=0.0):
+    """Dipole positions (count x 3) on a ring in the z = ``z`` plane,
+    angles 2 pi k / count."""
+    phi = 2.0 * math.pi * np.arange(count) / count
+    return np.stack([radius * np.cos(phi), radius * np.sin(phi), np.full(count, z)], axis=1)
+
+
+def dipole_cylinder(count, radius, half_height, seed):
+    """Seeded dipole positions on a cylinder: phi ~ U(0, 2 pi) then
+    z ~ U(-half_height, half_height), both from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    phi = rng.uniform(0.0, 2.0 * math.pi, count)
+    zz = rng.uniform(-half_height, half_height, count)
+    return np.stack([radius * np.cos(phi), radius * np.sin(phi), zz], axis=1)
+
+
+def rhs_from_field(eps_c, e_inc, freq_hz):
+    """b = c_e chi e_inc with c_e = i omega eps0, chi = eps_c - 1."""
+    ce = 1j * omega(freq_hz) * EPS0
+    chi = np.asarray(eps_c) - 1.0
+    return ce * chi[None] * e_inc
