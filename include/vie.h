@@ -1,0 +1,259 @@
+/*
+ * vie.h -- C ABI of the MI355X (gfx950) Tucker-compressed FFT-VIE library.
+ *
+ * Operation (Giannakopoulos, Litsarev, Polimeridis, "Memory footprint
+ * reduction for the FFT-based volume integral equation method via tensor
+ * decompositions"): the electric block of the current-based VIE system
+ * (eq. 1-4) on a uniform n1 x n2 x n3 voxel grid with piecewise-constant
+ * current coefficients,
+ *
+ *     (A u)_p(m) = eps_c(m) u_p(m) - chi(m) sum_q sum_m' Nt_pq(m - m') u_q(m'),
+ *     chi = eps_c - 1,
+ *
+ * where the Toeplitz (BTTB, Sec. II-B) defining tensors Nt_c of the six unique
+ * components c = xx, yy, zz, xy, xz, yz are held only in Tucker form (HOSVD,
+ * Sec. IV-A, Alg. 1), with circulant embedding and FFT applied to the factor
+ * columns (Sec. V-A), and are reconstructed on the fly inside the matvec
+ * (the "component decompression" of Sec. V-B, done per pencil, never into a
+ * dense buffer).
+ *
+ * Conventions shared by every call:
+ *  - Complex numbers are interleaved (re, im); complex64 = 2 x float,
+ *    complex128 = 2 x double.
+ *  - Vector layout [nrhs][3][n3][n2][n1], x fastest (component q = x, y, z).
+ *    Scalar maps [n3][n2][n1].
+ *  - DEVICE pointers are HIP device allocations owned by the caller; HOST
+ *    pointers are ordinary host memory owned by the caller.  The library owns
+ *    only the memory of a vie_op.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *    enqueued asynchronously on it; vie_solve synchronises it internally.
+ *  - Return value: VIE_OK (0), a positive warning (result valid), or a
+ *    negative error.  On an argument error nothing is enqueued and outputs are
+ *    untouched; on VIE_E_HIP outputs are undefined.  vie_last_error() gives a
+ *    thread-local message for the last negative status.
+ */
+#ifndef VIE_H
+#define VIE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int vie_status;
+enum {
+    VIE_OK = 0,
+    VIE_NOT_CONVERGED = 1,   /* solve ended at its iteration limit; x holds the last iterate */
+    VIE_E_ARG = -1,          /* invalid argument (null pointer, bad size, aliasing, small workspace) */
+    VIE_E_NOMEM = -2,        /* device or host allocation failed */
+    VIE_E_HIP = -3,          /* a HIP runtime call failed */
+    VIE_E_NONFINITE = -4,    /* NaN or Inf met in an input norm or a Krylov quantity */
+    VIE_E_UNSUPPORTED = -5   /* size, rank or option outside what the kernels implement */
+};
+
+/* vector / FFT precision */
+enum { VIE_C64 = 0, VIE_C128 = 1 };
+/* arithmetic of the on-the-fly Tucker reconstruction */
+enum { VIE_RECON_AUTO = 0,   /* FP32 for VIE_C64, FP64 for VIE_C128 */
+       VIE_RECON_FP32 = 1,
+       VIE_RECON_BF16 = 2,   /* BF16 factors and core on MFMA, FP32 accumulate (VIE_C64 only) */
+       VIE_RECON_FP64 = 3 };
+/* which operator a matvec applies */
+enum { VIE_OP_A = 0,         /* eps_c u - chi (N u)             (eq. 4, electric block) */
+       VIE_OP_N = 1 };       /* N u (bare Green's operator)                              */
+/* source of the Fourier-domain Green's tensor inside the matvec */
+enum { VIE_NHAT_TUCKER = 0,  /* reconstructed per pencil from core + factors (default) */
+       VIE_NHAT_DENSE = 1 }; /* read from a dense half-spectrum store (the uncompressed
+                                method, for comparison; see vie_op_densify) */
+
+typedef struct vie_op vie_op;   /* opaque; immutable after vie_compress except
+                                   vie_op_densify / vie_op_set_nhat; shareable
+                                   across streams */
+
+typedef struct {
+    double tol;          /* HOSVD tolerance eps (eq. 12); relative Frobenius error bound */
+    int trunc_rule;      /* 0: discarded Frobenius tail of each unfolding <= tol/sqrt(3) ||A||_F
+                            (default); 1: keep sigma_k >= tol/sqrt(3) sigma_max (Alg. 1 as printed) */
+    int max_rank;        /* 0 = no cap; else cap every r_i (VIE_E_UNSUPPORTED if the tail bound
+                            then exceeds tol) */
+} vie_compress_opts;
+
+typedef struct {
+    int ranks[6][3];         /* Tucker ranks (r1, r2, r3) per component */
+    double tail_bound[6];    /* sqrt(sum of discarded sigma^2 over the 3 unfoldings) / ||A||_F */
+    double fro_norm[6];      /* ||A_c||_F of each defining tensor */
+    size_t tucker_bytes_c64; /* device bytes of cores + Fourier factors at complex64 */
+    size_t dense_bytes_c64;  /* bytes of the 6 dense circulant spectra (8 n1 n2 n3 points each)
+                                at complex64: what the uncompressed method stores */
+    double seconds;          /* host time of the compression */
+} vie_compress_info;
+
+/*
+ * vie_compress -- HOSVD (Alg. 1) of each defining tensor on the host in FP64,
+ * then circulant embedding + DFT of the factor columns (Sec. V-A), upload of
+ * cores and Fourier factors to the current device in FP64, FP32 and BF16.
+ *   n      HOST int[3]: grid (n1, n2, n3), 1 <= n_i <= 256.
+ *   green  HOST complex128 [6][n3][n2][n1]: Nt_c(offset (i, j, k)), component order
+ *          xx, yy, zz, xy, xz, yz, normalised so that the identity part of N has
+ *          unit diagonal (Galerkin rows divided by the voxel volume).  xy, xz, yz
+ *          must be odd along their two axes (zero at offset 0 along them); the
+ *          negative offsets are implied by that parity.
+ *   opts   HOST, may be NULL (tol 1e-6, rule 0, no cap).
+ *   out    receives the new operator (library-owned device memory).
+ *   info   HOST, may be NULL.
+ * Synchronous.  Errors: VIE_E_ARG, VIE_E_NOMEM, VIE_E_HIP, VIE_E_UNSUPPORTED.
+ */
+vie_status vie_compress(const int n[3], const double* green, const vie_compress_opts* opts,
+                        vie_op** out, vie_compress_info* info);
+
+/* Release the operator's device memory.  NULL is accepted. */
+vie_status vie_op_destroy(vie_op* op);
+
+/* Grid and ranks of an operator (HOST outputs, any may be NULL). */
+vie_status vie_op_query(const vie_op* op, int n[3], int ranks[6][3]);
+
+/*
+ * vie_op_densify -- materialise the Fourier-domain tensor of every component
+ * densely from the Tucker form on the device (half spectrum
+ * (n1+1)(n2+1)(n3+1) points per component, the rest follows from parity), at
+ * complex64 and, if with_c128, complex128.  Enables VIE_NHAT_DENSE for
+ * comparison runs; memory is released by vie_op_destroy.
+ */
+vie_status vie_op_densify(vie_op* op, int with_c128);
+/* Select VIE_NHAT_TUCKER or VIE_NHAT_DENSE for subsequent matvecs. */
+vie_status vie_op_set_nhat(vie_op* op, int source);
+
+/* Device workspace (bytes) that vie_matvec / vie_matvec_adjoint need for
+ * `nrhs` right-hand sides at precision `dtype` (18 n1 n2 n3 complex per rhs). */
+size_t vie_workspace_bytes(const vie_op* op, int dtype, int nrhs);
+
+/*
+ * vie_matvec -- y = A x (kind VIE_OP_A) or y = N x (kind VIE_OP_N) for nrhs
+ * right-hand sides sharing one operator and one eps_c.
+ *   dtype   VIE_C64 or VIE_C128: element type of eps_c, x, y and of the FFTs.
+ *   recon   VIE_RECON_*: arithmetic of the Tucker reconstruction.
+ *   eps_c   DEVICE [n3][n2][n1] complex relative permittivity
+ *           eps_r - i sigma/(omega eps0); ignored (may be NULL) for VIE_OP_N.
+ *   x       DEVICE [nrhs][3][n3][n2][n1] input.
+ *   y       DEVICE, same shape; must not overlap x.
+ *   ws      DEVICE workspace of at least vie_workspace_bytes(op, dtype, nrhs).
+ * Asynchronous on `stream`.  Errors: VIE_E_ARG, VIE_E_UNSUPPORTED, VIE_E_HIP.
+ */
+vie_status vie_matvec(const vie_op* op, int kind, int dtype, int recon, const void* eps_c,
+                      const void* x, void* y, int nrhs, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * vie_matvec_adjoint -- y = A^H x (VIE_OP_A): conj(eps_c) x - N^H(conj(chi) x),
+ * or y = N^H x (VIE_OP_N).  N is complex symmetric (Nt_pq = Nt_qp and every
+ * embedded component is even in the full offset), so N^H applies conj(N^).
+ * Same arguments and errors as vie_matvec.
+ */
+vie_status vie_matvec_adjoint(const vie_op* op, int kind, int dtype, int recon, const void* eps_c,
+                              const void* x, void* y, int nrhs, void* ws, size_t ws_bytes,
+                              void* stream);
+
+typedef struct {
+    double tol;        /* target relative residual ||b - A x|| / ||b|| (true residual) */
+    int restart;       /* GMRES restart length m (inner iterations per cycle), 1..200 */
+    int max_outer;     /* maximum restart cycles (plain) or refinement steps (refine = 1) */
+    int adjoint;       /* 0: solve A x = b;  1: solve A^H x = b */
+    int refine;        /* 0: plain GMRES in `dtype`; 1: iterative refinement: FP64 true
+                          residual with the FP64 operator, inner GMRES(m) cycles with FP64
+                          Arnoldi on the `inner_recon` operator computed in FP32 (dtype must
+                          be VIE_C128) */
+    int inner_recon;   /* refine = 1: VIE_RECON_FP32 or VIE_RECON_BF16 */
+    double inner_tol;  /* refine = 1: relative reduction asked of each inner cycle */
+} vie_solve_opts;
+
+typedef struct {
+    int matvecs;          /* operator applications in the working precision */
+    int matvecs_fp64;     /* FP64 residual matvecs (refine = 1) */
+    int restarts;         /* completed GMRES cycles */
+    int refine_steps;     /* refinement steps (refine = 1) */
+    int converged;        /* 1 if the true relative residual reached tol */
+    double rel_residual;  /* final true relative residual (in the solve's dtype) */
+    double* history;      /* HOST, optional: true relative residual per cycle/step */
+    int hist_cap;         /* capacity of history */
+    int hist_len;         /* entries written */
+} vie_solve_info;
+
+/* Device workspace (bytes) for vie_solve with these options. */
+size_t vie_solve_workspace_bytes(const vie_op* op, int dtype, int nrhs, const vie_solve_opts* opts);
+
+/*
+ * vie_solve -- restarted GMRES (the paper's solver, Sec. VI-C) on
+ * A x = b (or A^H x = b) for nrhs independent right-hand sides.
+ *   eps_c   DEVICE [n3][n2][n1] complex (dtype).
+ *   b       DEVICE [nrhs][3][n3][n2][n1] complex (dtype).
+ *   x       DEVICE, same shape: in = initial guess (zeros for a cold start),
+ *           out = solution.  Must not overlap b.
+ *   opts    HOST (NULL = tol 1e-6, restart 50, max_outer 200, plain).
+ *   info    HOST array of nrhs entries, may be NULL.
+ * Arnoldi (classical Gram-Schmidt with one re-orthogonalisation) runs in the
+ * precision of dtype; the small Hessenberg least-squares problem is solved on
+ * the host.  Systems that converge are dropped from further matvecs.
+ * Returns VIE_OK if every system converged, VIE_NOT_CONVERGED if one did not
+ * (x is still the last iterate), VIE_E_NONFINITE on a NaN/Inf residual.
+ * Synchronises `stream`.
+ */
+vie_status vie_solve(const vie_op* op, int dtype, const void* eps_c, const void* b, void* x,
+                     int nrhs, const vie_solve_opts* opts, vie_solve_info* info, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/*
+ * vie_field_gradient -- g_n = sum_q conj(z_q(n)) E_q(n) for every voxel n
+ * (the voxel-wise factor of the adjoint gradient: dL/d eps_r = Re g,
+ * dL/d sigma = Im g / (omega eps0)).
+ *   z, E   DEVICE [3][n3][n2][n1] complex (dtype);  g DEVICE [n3][n2][n1] complex.
+ * Asynchronous.
+ */
+vie_status vie_field_gradient(const vie_op* op, int dtype, const void* z, const void* E, void* g,
+                              void* stream);
+
+/*
+ * Debug / test entry points (bit-exact checks of indexing).
+ * vie_debug_nhat: Fourier-domain tensor values N^_c(k1, k2, k3) at `count`
+ *   HOST points idx[4*m .. 4*m+3] = (c, k1, k2, k3), 0 <= k_i < 2 n_i, from the
+ *   device-resident Tucker form (precision dtype/recon), written to HOST
+ *   out[2*m], out[2*m+1] as double.  Includes the 1/(8 n1 n2 n3) inverse-FFT
+ *   normalisation that the device core carries.
+ */
+vie_status vie_debug_nhat(const vie_op* op, int dtype, int recon, const int* idx, int count,
+                          double* out);
+
+/*
+ * vie_debug_hosvd: the host part of vie_compress for ONE defining tensor,
+ * with no device work (for CPU tests of the compression logic).
+ *   n       HOST int[3]; tensor HOST complex128 [n3][n2][n1].
+ *   ranks   HOST int[3] out: truncation ranks (tol, rule as in vie_compress_opts).
+ *   svals   HOST double[n1 + n2 + n3] out (may be NULL): singular values of the
+ *           mode-1, mode-2, mode-3 unfoldings, each block descending.
+ *   recon   HOST complex128 [n3][n2][n1] out (may be NULL): the Tucker
+ *           reconstruction G x1 U1 x2 U2 x3 U3 (eq. 14) of the result.
+ *   tail    HOST double out (may be NULL): the discarded-tail bound / ||A||_F.
+ */
+vie_status vie_debug_hosvd(const int n[3], const double* tensor, double tol, int rule, int ranks[3],
+                           double* svals, double* recon, double* tail);
+
+/*
+ * Per-pass timing of the matvec pipeline (for benchmarks).  While enabled,
+ * every matvec records a HIP event pair on its stream around each of its five
+ * passes (0 = pad + x FFT, 1 = y FFT, 2 = fused z pass with the Tucker
+ * reconstruction and component product, 3 = inverse y FFT + crop, 4 =
+ * inverse x FFT + crop + contrast).  vie_profile_collect waits for the
+ * recorded events, returns the summed milliseconds and launch counts per
+ * pass (HOST double[5], int[5]) and clears the record.  Process-wide, not
+ * thread-safe; the recording costs two event records per pass.
+ */
+vie_status vie_profile_enable(int on);
+vie_status vie_profile_collect(double ms[5], int counts[5]);
+
+const char* vie_last_error(void);
+/* library version string */
+const char* vie_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VIE_H */

@@ -1,0 +1,9 @@
+"""MI355X (gfx950) Tucker-compressed FFT-VIE matvec and GMRES solver.
+
+The product path is ``libvie.so`` (HIP kernels + C ABI, ``include/vie.h``);
+``vie`` is its thin ctypes binding and ``autograd`` the adjoint-gradient
+``torch.autograd.Function`` built on it.
+"""
+from . import vie  # noqa: F401
+from .vie import (Operator, VieError, compress, debug_nhat, densify, field_gradient, matvec, set_nhat,  # noqa: F401
+                  solve)

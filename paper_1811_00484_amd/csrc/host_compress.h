@@ -1,0 +1,36 @@
+// Host-side HOSVD compression (FP64) of the Green's defining tensors.
+#pragma once
+#include <complex>
+#include <vector>
+
+namespace vie {
+
+struct TuckerComponent {
+    int r[3] = {0, 0, 0};
+    std::vector<std::complex<double>> U[3];   // U[a]: n_a x r_a row-major (left singular vectors)
+    std::vector<std::complex<double>> G;      // core [r1][r2][r3], r3 fastest
+    std::vector<double> sv[3];                // all singular values of each unfolding
+    double fro = 0;                           // ||A||_F
+    double tail_rel = 0;                      // sqrt(sum of discarded sigma^2) / ||A||_F
+};
+
+int host_threads();
+
+// Left singular vectors (U, m x m row-major, columns by descending singular
+// value) and singular values of a row-major m x N matrix, m <= N.
+void svd_left(const std::complex<double>* Y, int m, long N, std::vector<std::complex<double>>& U,
+              std::vector<double>& s, bool refine);
+
+// Truncation rank for one unfolding (rule 0: Frobenius tail; rule 1: sigma cut).
+int truncation_rank(const std::vector<double>& s, double tol, int rule, double fro);
+
+// HOSVD (Alg. 1) of one defining tensor stored [k][j][i].  Returns 0, or 1 if
+// max_rank forces a tail above tol.
+int hosvd_component(const std::complex<double>* A, const int n[3], double tol, int rule,
+                    int max_rank, TuckerComponent& out);
+
+// Rows 0..n of the length-2n DFT of the parity-s embedded columns of U (n x r).
+void fourier_factor(const std::vector<std::complex<double>>& U, int n, int r, int s,
+                    std::vector<std::complex<double>>& Uh);
+
+}  // namespace vie

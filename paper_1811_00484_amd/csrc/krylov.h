@@ -1,0 +1,37 @@
+// Launchers of the batched Krylov vector kernels (krylov.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "dev_common.h"
+
+namespace vie {
+
+int krylov_nblk(long n);   // per-system partial count for a vector of n complex elements
+
+// out[a*nvec + v] = <V_v[s], W[s]> = sum conj(V_v) W, s = map[a]
+template <typename TK>
+hipError_t kr_mdot(const c2<TK>* V, long vstride, long sstride, int nvec, const c2<TK>* W, long wvoff, long n,
+                   const int* map, int nact, c2<double>* partial, c2<double>* out, hipStream_t st);
+// W[s] += sign * sum_v V_v[s] coef[a*cstride + v]
+template <typename TK>
+hipError_t kr_maxpy(c2<TK>* W, long wvoff, long wsstride, const c2<TK>* V, long vstride, long sstride, int nvec,
+                    int cstride, const c2<double>* coef, double sign, long n, const int* map, int nact,
+                    hipStream_t st);
+// out[a].x = ||W[s]||^2
+template <typename TK>
+hipError_t kr_norm2(const c2<TK>* W, long wvoff, long sstride, long n, const int* map, int nact,
+                    c2<double>* partial, c2<double>* out, hipStream_t st);
+// dst[s] = src[s] / sqrt(norm2[a].x)
+template <typename TK>
+hipError_t kr_scale_norm(c2<TK>* dst, long dvoff, const c2<TK>* src, long svoff, long sstride,
+                         const c2<double>* norm2, long n, const int* map, int nact, hipStream_t st);
+// R[s] = B[s] - R[s]
+template <typename TK>
+hipError_t kr_residual(c2<TK>* R, const c2<TK>* B, long sstride, long n, const int* map, int nact, hipStream_t st);
+template <typename TO, typename TI>
+hipError_t kr_convert(c2<TO>* dst, const c2<TI>* src, long n, hipStream_t st);
+// g = sum_q conj(z_q) E_q per voxel
+template <typename T>
+hipError_t kr_field_gradient(const c2<T>* z, const c2<T>* E, c2<T>* g, long V, hipStream_t st);
+
+}  // namespace vie

@@ -1,0 +1,407 @@
+// C ABI of the Tucker-compressed FFT-VIE library: operator construction,
+// matvecs and test entry points.  The GMRES driver is in solve.cpp.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vie.h"
+#include "host_compress.h"
+#include "vie_internal.h"
+
+namespace vie {
+
+thread_local std::string g_last_error;
+
+vie_status fail(vie_status st, const std::string& msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+vie_status hip_fail(hipError_t e, const char* where)
+{
+    return fail(VIE_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+static bool make_plan(int L, FftPlan& p)
+{
+    p.L = L;
+    p.nst = 0;
+    int rem = L;
+    const int order[] = {8, 4, 2, 3, 5, 7};
+    for (int R : order) {
+        while (rem % R == 0) {
+            if (p.nst >= 12) return false;
+            // avoid a radix-4/8 that would leave a lone factor of 2 unusable: fine either way
+            p.rad[p.nst++] = R;
+            rem /= R;
+        }
+    }
+    return rem == 1;
+}
+
+static void free_op(DeviceOp& d)
+{
+    (void)hipFree(d.d64.core);
+    (void)hipFree(d.d64.fac);
+    (void)hipFree(d.d32.core);
+    (void)hipFree(d.d32.fac);
+    (void)hipFree(d.b16.core);
+    (void)hipFree(d.b16.fac);
+    for (int a = 0; a < 3; ++a) {
+        (void)hipFree(d.tw64[a]);
+        (void)hipFree(d.tw32[a]);
+    }
+    (void)hipFree(d.dense32);
+    (void)hipFree(d.dense64);
+}
+
+static unsigned short to_bf16(float f)
+{
+    unsigned int u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);   // inf / nan
+    unsigned int lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;                                                        // round to nearest even
+    return (unsigned short)(u >> 16);
+}
+
+}  // namespace vie
+
+using namespace vie;
+
+extern "C" {
+
+const char* vie_last_error(void) { return g_last_error.c_str(); }
+
+const char* vie_version(void) { return "vie-gfx950 0.1"; }
+
+vie_status vie_compress(const int n[3], const double* green, const vie_compress_opts* opts, vie_op** out,
+                        vie_compress_info* info)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!n || !green || !out) return fail(VIE_E_ARG, "vie_compress: null argument");
+    for (int a = 0; a < 3; ++a)
+        if (n[a] < 1 || n[a] > 256) return fail(VIE_E_UNSUPPORTED, "vie_compress: n_i must be in [1, 256]");
+    double tol = opts ? opts->tol : 1e-6;
+    int rule = opts ? opts->trunc_rule : 0;
+    int max_rank = opts ? opts->max_rank : 0;
+    if (!(tol > 0.0) || !std::isfinite(tol) || (rule != 0 && rule != 1) || max_rank < 0)
+        return fail(VIE_E_ARG, "vie_compress: bad options");
+    const long V = (long)n[0] * n[1] * n[2];
+    FftPlan plans[3];
+    for (int a = 0; a < 3; ++a)
+        if (!make_plan(2 * n[a], plans[a]))
+            return fail(VIE_E_UNSUPPORTED, "vie_compress: 2 n_i must factor into 2, 3, 5, 7");
+    for (long t = 0; t < 12 * V; ++t)
+        if (!std::isfinite(green[t])) return fail(VIE_E_NONFINITE, "vie_compress: non-finite Green's tensor");
+
+    using cd = std::complex<double>;
+    TuckerComponent tc[6];
+    std::vector<cd> A(V);
+    const int odd[6][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+    for (int c = 0; c < 6; ++c) {
+        const double* g = green + 2 * (size_t)c * V;
+        for (long t = 0; t < V; ++t) A[t] = cd(g[2 * t], g[2 * t + 1]);
+        // an odd component vanishes at zero offset along its odd axes
+        for (int k = 0; k < n[2]; ++k)
+            for (int j = 0; j < n[1]; ++j)
+                for (int i = 0; i < n[0]; ++i)
+                    if ((odd[c][0] && i == 0) || (odd[c][1] && j == 0) || (odd[c][2] && k == 0))
+                        A[((long)k * n[1] + j) * n[0] + i] = 0.0;
+        int rc = hosvd_component(A.data(), n, tol, rule, max_rank, tc[c]);
+        if (rc != 0) return fail(VIE_E_UNSUPPORTED, "vie_compress: max_rank too small for tol");
+    }
+    // pack cores (scaled by 1/M) and Fourier factors
+    DeviceOp d;
+    OpView& v = d.view;
+    int rmax = 1;
+    int core_tot = 0, fac_tot = 0;
+    for (int a = 0; a < 3; ++a) {
+        v.n[a] = n[a];
+        v.L[a] = 2 * n[a];
+        d.plan[a] = plans[a];
+    }
+    for (int c = 0; c < 6; ++c) {
+        for (int a = 0; a < 3; ++a) {
+            v.r[c][a] = tc[c].r[a];
+            rmax = std::max(rmax, tc[c].r[a]);
+        }
+        v.core_off[c] = core_tot;
+        core_tot += tc[c].r[0] * tc[c].r[1] * tc[c].r[2];
+        for (int a = 0; a < 3; ++a) {
+            v.fac_off[c][a] = fac_tot;
+            fac_tot += (n[a] + 1) * tc[c].r[a];
+        }
+    }
+    v.rmax = rmax;
+    if (rmax > 64) return fail(VIE_E_UNSUPPORTED, "vie_compress: Tucker rank above 64");
+    const double invM = 1.0 / (8.0 * (double)V);
+    std::vector<cd> hcore(core_tot), hfac(fac_tot);
+    for (int c = 0; c < 6; ++c) {
+        for (size_t t = 0; t < tc[c].G.size(); ++t) hcore[v.core_off[c] + t] = tc[c].G[t] * invM;
+        for (int a = 0; a < 3; ++a) {
+            std::vector<cd> Uh;
+            fourier_factor(tc[c].U[a], n[a], tc[c].r[a], odd[c][a] ? -1 : 1, Uh);
+            std::copy(Uh.begin(), Uh.end(), hfac.begin() + v.fac_off[c][a]);
+        }
+    }
+    // device upload
+    hipError_t e;
+    e = hipGetDevice(&d.device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, d.device) == hipSuccess && lds > 0)
+        d.max_lds = (size_t)lds;
+    auto upload = [&](const std::vector<cd>& src, void** dst64, void** dst32, void** dst16) -> hipError_t {
+        size_t m = src.size();
+        std::vector<c2<double>> h64(m);
+        std::vector<c2<float>> h32(m);
+        std::vector<unsigned short> h16(2 * m);
+        for (size_t t = 0; t < m; ++t) {
+            h64[t].x = src[t].real();
+            h64[t].y = src[t].imag();
+            h32[t].x = (float)src[t].real();
+            h32[t].y = (float)src[t].imag();
+            h16[2 * t] = to_bf16((float)src[t].real());
+            h16[2 * t + 1] = to_bf16((float)src[t].imag());
+        }
+        hipError_t er;
+        if ((er = hipMalloc(dst64, m * sizeof(c2<double>))) != hipSuccess) return er;
+        if ((er = hipMalloc(dst32, m * sizeof(c2<float>))) != hipSuccess) return er;
+        if ((er = hipMalloc(dst16, m * 4)) != hipSuccess) return er;
+        if ((er = hipMemcpy(*dst64, h64.data(), m * sizeof(c2<double>), hipMemcpyHostToDevice)) != hipSuccess)
+            return er;
+        if ((er = hipMemcpy(*dst32, h32.data(), m * sizeof(c2<float>), hipMemcpyHostToDevice)) != hipSuccess)
+            return er;
+        return hipMemcpy(*dst16, h16.data(), m * 4, hipMemcpyHostToDevice);
+    };
+    e = upload(hcore, (void**)&d.d64.core, (void**)&d.d32.core, (void**)&d.b16.core);
+    if (e == hipSuccess) e = upload(hfac, (void**)&d.d64.fac, (void**)&d.d32.fac, (void**)&d.b16.fac);
+    for (int a = 0; a < 3 && e == hipSuccess; ++a) {
+        int L = v.L[a];
+        std::vector<c2<double>> t64(L);
+        std::vector<c2<float>> t32(L);
+        for (int m = 0; m < L; ++m) {
+            double ang = -2.0 * M_PI * (double)m / (double)L;
+            t64[m].x = std::cos(ang);
+            t64[m].y = std::sin(ang);
+            t32[m].x = (float)t64[m].x;
+            t32[m].y = (float)t64[m].y;
+        }
+        e = hipMalloc((void**)&d.tw64[a], L * sizeof(c2<double>));
+        if (e == hipSuccess) e = hipMalloc((void**)&d.tw32[a], L * sizeof(c2<float>));
+        if (e == hipSuccess) e = hipMemcpy(d.tw64[a], t64.data(), L * sizeof(c2<double>), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d.tw32[a], t32.data(), L * sizeof(c2<float>), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        free_op(d);
+        return e == hipErrorOutOfMemory ? fail(VIE_E_NOMEM, "vie_compress: device allocation failed")
+                                        : hip_fail(e, "vie_compress upload");
+    }
+    d.tucker_bytes = (size_t)(core_tot + fac_tot) * sizeof(c2<float>);
+    vie_op* op = new vie_op;
+    op->d = d;
+    *out = op;
+    if (info) {
+        for (int c = 0; c < 6; ++c) {
+            for (int a = 0; a < 3; ++a) info->ranks[c][a] = tc[c].r[a];
+            info->tail_bound[c] = tc[c].tail_rel;
+            info->fro_norm[c] = tc[c].fro;
+        }
+        info->tucker_bytes_c64 = d.tucker_bytes;
+        info->dense_bytes_c64 = (size_t)6 * 8 * (size_t)V * sizeof(c2<float>);
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return VIE_OK;
+}
+
+vie_status vie_op_destroy(vie_op* op)
+{
+    if (!op) return VIE_OK;
+    free_op(op->d);
+    delete op;
+    return VIE_OK;
+}
+
+vie_status vie_op_query(const vie_op* op, int n[3], int ranks[6][3])
+{
+    if (!op) return fail(VIE_E_ARG, "vie_op_query: null op");
+    if (n)
+        for (int a = 0; a < 3; ++a) n[a] = op->d.view.n[a];
+    if (ranks)
+        for (int c = 0; c < 6; ++c)
+            for (int a = 0; a < 3; ++a) ranks[c][a] = op->d.view.r[c][a];
+    return VIE_OK;
+}
+
+vie_status vie_op_densify(vie_op* op, int with_c128)
+{
+    if (!op) return fail(VIE_E_ARG, "vie_op_densify: null op");
+    hipError_t e = launch_densify(op->d, with_c128, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "vie_op_densify");
+    return VIE_OK;
+}
+
+vie_status vie_op_set_nhat(vie_op* op, int source)
+{
+    if (!op || (source != VIE_NHAT_TUCKER && source != VIE_NHAT_DENSE))
+        return fail(VIE_E_ARG, "vie_op_set_nhat: bad argument");
+    if (source == VIE_NHAT_DENSE && !op->d.dense32)
+        return fail(VIE_E_ARG, "vie_op_set_nhat: call vie_op_densify first");
+    op->d.nhat_source = source;
+    return VIE_OK;
+}
+
+size_t vie_workspace_bytes(const vie_op* op, int dtype, int nrhs)
+{
+    if (!op || nrhs < 1) return 0;
+    size_t el = dtype == VIE_C128 ? sizeof(c2<double>) : sizeof(c2<float>);
+    return matvec_ws_elems(op->d, nrhs) * el;
+}
+
+}  // extern "C"
+
+namespace vie {
+
+vie_status matvec_common(const vie_op* op, int mode, int dtype, int recon, const void* eps, const void* x,
+                         void* y, int nrhs, void* ws, size_t ws_bytes, void* stream, const int* rhs_map)
+{
+    if (!op || !x || !y || !ws || nrhs < 1) return fail(VIE_E_ARG, "vie_matvec: null argument or nrhs < 1");
+    bool needs_eps = (mode == MODE_A || mode == MODE_AH);
+    if (needs_eps && !eps) return fail(VIE_E_ARG, "vie_matvec: eps_c is required for VIE_OP_A");
+    if (dtype != VIE_C64 && dtype != VIE_C128) return fail(VIE_E_ARG, "vie_matvec: bad dtype");
+    if (recon < VIE_RECON_AUTO || recon > VIE_RECON_FP64) return fail(VIE_E_ARG, "vie_matvec: bad recon");
+    if (dtype == VIE_C64 && recon == VIE_RECON_FP64)
+        return fail(VIE_E_UNSUPPORTED, "vie_matvec: FP64 reconstruction needs VIE_C128");
+    if (dtype == VIE_C128 && (recon == VIE_RECON_FP32 || recon == VIE_RECON_BF16))
+        return fail(VIE_E_UNSUPPORTED, "vie_matvec: reduced reconstruction needs VIE_C64");
+    if (recon == VIE_RECON_BF16) return fail(VIE_E_UNSUPPORTED, "vie_matvec: BF16 reconstruction not built");
+    size_t need = vie_workspace_bytes(op, dtype, nrhs);
+    if (ws_bytes < need) return fail(VIE_E_ARG, "vie_matvec: workspace too small");
+    const OpView& v = op->d.view;
+    size_t vbytes = (size_t)nrhs * 3 * v.n[0] * v.n[1] * v.n[2] * (dtype == VIE_C128 ? 16 : 8);
+    const char* xb = (const char*)x;
+    const char* yb = (const char*)y;
+    if (!(xb + vbytes <= yb || yb + vbytes <= xb)) return fail(VIE_E_ARG, "vie_matvec: x and y overlap");
+    hipStream_t s = (hipStream_t)stream;
+    std::string err;
+    hipError_t e;
+    if (dtype == VIE_C128)
+        e = launch_matvec<double, double>(op->d, mode, 0, (const c2<double>*)eps, (const c2<double>*)x,
+                                          (c2<double>*)y, nrhs, (c2<double>*)ws, s, rhs_map, err);
+    else
+        e = launch_matvec<float, float>(op->d, mode, 0, (const c2<float>*)eps, (const c2<float>*)x,
+                                        (c2<float>*)y, nrhs, (c2<float>*)ws, s, rhs_map, err);
+    if (e != hipSuccess) {
+        if (!err.empty()) return fail(VIE_E_UNSUPPORTED, "vie_matvec: " + err);
+        return hip_fail(e, "vie_matvec launch");
+    }
+    return VIE_OK;
+}
+
+}  // namespace vie
+
+extern "C" {
+
+vie_status vie_matvec(const vie_op* op, int kind, int dtype, int recon, const void* eps_c, const void* x, void* y,
+                      int nrhs, void* ws, size_t ws_bytes, void* stream)
+{
+    if (kind != VIE_OP_A && kind != VIE_OP_N) return fail(VIE_E_ARG, "vie_matvec: bad kind");
+    return matvec_common(op, kind == VIE_OP_A ? MODE_A : MODE_N, dtype, recon, eps_c, x, y, nrhs, ws, ws_bytes,
+                         stream, nullptr);
+}
+
+vie_status vie_matvec_adjoint(const vie_op* op, int kind, int dtype, int recon, const void* eps_c, const void* x,
+                              void* y, int nrhs, void* ws, size_t ws_bytes, void* stream)
+{
+    if (kind != VIE_OP_A && kind != VIE_OP_N) return fail(VIE_E_ARG, "vie_matvec_adjoint: bad kind");
+    return matvec_common(op, kind == VIE_OP_A ? MODE_AH : MODE_NH, dtype, recon, eps_c, x, y, nrhs, ws, ws_bytes,
+                         stream, nullptr);
+}
+
+vie_status vie_debug_nhat(const vie_op* op, int dtype, int recon, const int* idx, int count, double* out)
+{
+    if (!op || !idx || !out || count < 0) return fail(VIE_E_ARG, "vie_debug_nhat: bad argument");
+    (void)recon;
+    if (count == 0) return VIE_OK;
+    const OpView& v = op->d.view;
+    for (int m = 0; m < count; ++m) {
+        if (idx[4 * m] < 0 || idx[4 * m] > 5) return fail(VIE_E_ARG, "vie_debug_nhat: bad component");
+        for (int a = 0; a < 3; ++a)
+            if (idx[4 * m + 1 + a] < 0 || idx[4 * m + 1 + a] >= v.L[a])
+                return fail(VIE_E_ARG, "vie_debug_nhat: index out of range");
+    }
+    int* didx = nullptr;
+    double* dout = nullptr;
+    hipError_t e = hipMalloc((void**)&didx, sizeof(int) * 4 * count);
+    if (e == hipSuccess) e = hipMalloc((void**)&dout, sizeof(double) * 2 * count);
+    if (e == hipSuccess) e = hipMemcpy(didx, idx, sizeof(int) * 4 * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_nhat_samples(op->d, dtype == VIE_C128 ? 1 : 0, didx, count, dout, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, dout, sizeof(double) * 2 * count, hipMemcpyDeviceToHost);
+    (void)hipFree(didx);
+    (void)hipFree(dout);
+    if (e != hipSuccess) return hip_fail(e, "vie_debug_nhat");
+    return VIE_OK;
+}
+
+vie_status vie_debug_hosvd(const int n[3], const double* tensor, double tol, int rule, int ranks[3], double* svals,
+                           double* recon, double* tail)
+{
+    if (!n || !tensor || !ranks) return fail(VIE_E_ARG, "vie_debug_hosvd: null argument");
+    for (int a = 0; a < 3; ++a)
+        if (n[a] < 1 || n[a] > 512) return fail(VIE_E_ARG, "vie_debug_hosvd: bad size");
+    if (!(tol > 0) || (rule != 0 && rule != 1)) return fail(VIE_E_ARG, "vie_debug_hosvd: bad tol/rule");
+    using cd = std::complex<double>;
+    long V = (long)n[0] * n[1] * n[2];
+    std::vector<cd> A(V);
+    for (long t = 0; t < V; ++t) A[t] = cd(tensor[2 * t], tensor[2 * t + 1]);
+    TuckerComponent tc;
+    hosvd_component(A.data(), n, tol, rule, 0, tc);
+    for (int a = 0; a < 3; ++a) ranks[a] = tc.r[a];
+    if (svals) {
+        int off = 0;
+        for (int a = 0; a < 3; ++a)
+            for (int k = 0; k < n[a]; ++k) svals[off++] = tc.sv[a][k];
+    }
+    if (tail) *tail = tc.tail_rel;
+    if (recon) {
+        int r1 = tc.r[0], r2 = tc.r[1], r3 = tc.r[2];
+        for (int k = 0; k < n[2]; ++k)
+            for (int j = 0; j < n[1]; ++j)
+                for (int i = 0; i < n[0]; ++i) {
+                    cd acc = 0;
+                    for (int al = 0; al < r1; ++al)
+                        for (int be = 0; be < r2; ++be)
+                            for (int ga = 0; ga < r3; ++ga)
+                                acc += tc.G[((size_t)al * r2 + be) * r3 + ga] * tc.U[0][(size_t)i * r1 + al] *
+                                       tc.U[1][(size_t)j * r2 + be] * tc.U[2][(size_t)k * r3 + ga];
+                    long t = ((long)k * n[1] + j) * n[0] + i;
+                    recon[2 * t] = acc.real();
+                    recon[2 * t + 1] = acc.imag();
+                }
+    }
+    return VIE_OK;
+}
+
+vie_status vie_profile_enable(int on)
+{
+    prof_enable(on);
+    return VIE_OK;
+}
+
+vie_status vie_profile_collect(double ms[5], int counts[5])
+{
+    if (!ms || !counts) return fail(VIE_E_ARG, "vie_profile_collect: null argument");
+    int bad = prof_collect(ms, counts, 5);
+    if (bad) return fail(VIE_E_HIP, "vie_profile_collect: event query failed");
+    return VIE_OK;
+}
+
+}  // extern "C"

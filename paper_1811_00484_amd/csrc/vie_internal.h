@@ -1,0 +1,89 @@
+// Internal types shared by the C ABI layer and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "dev_common.h"
+
+namespace vie {
+
+// Device view of the compressed operator (passed to kernels by value).
+// Fourier factors of component c along axis a: rows 0..n_a of the DFT of the
+// embedded factor columns, row-major (n_a + 1) x r_a, at fac + fac_off[c][a].
+// Cores: [r1][r2][r3] (r3 fastest) at core + core_off[c], scaled by
+// 1 / (8 n1 n2 n3) so the inverse FFTs can stay unnormalised.
+struct OpView {
+    int n[3];
+    int L[3];
+    int r[6][3];
+    int core_off[6];
+    int fac_off[6][3];
+    int rmax;
+};
+
+template <typename T>
+struct OpBuffers {
+    c2<T>* core = nullptr;
+    c2<T>* fac = nullptr;
+};
+
+struct BF16Buffers {
+    // interleaved (re, im) bf16 pairs, same offsets as OpView
+    unsigned short* core = nullptr;
+    unsigned short* fac = nullptr;
+};
+
+struct DeviceOp {
+    OpView view;
+    FftPlan plan[3];
+    OpBuffers<double> d64;
+    OpBuffers<float> d32;
+    BF16Buffers b16;
+    // twiddle tables exp(-2 pi i m / L_a), m < L_a, per axis
+    c2<double>* tw64[3] = {nullptr, nullptr, nullptr};
+    c2<float>* tw32[3] = {nullptr, nullptr, nullptr};
+    // dense half-spectrum stores [c][k2][k1][k3] over (n1+1)(n2+1)(n3+1)
+    c2<float>* dense32 = nullptr;
+    c2<double>* dense64 = nullptr;
+    int nhat_source = 0;
+    size_t tucker_bytes = 0;
+    int device = 0;
+    size_t max_lds = 65536;
+};
+
+// matvec modes
+enum { MODE_A = 0, MODE_AH = 1, MODE_N = 2, MODE_NH = 3 };
+
+// Launch the five-pass matvec.  TV: vector element type, T: compute type.
+// recon: 0 = same as T, 1 = BF16 (T = float only).
+template <typename TV, typename T>
+hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* eps, const c2<TV>* x,
+                         c2<TV>* y, int nrhs, c2<T>* ws, hipStream_t s, const int* rhs_map,
+                         std::string& err);
+
+// Sampled Fourier-domain tensor values for tests.
+hipError_t launch_nhat_samples(const DeviceOp& op, int prec, const int* idx_dev, int count,
+                               double* out_dev, hipStream_t s);
+
+// Materialise dense half-spectrum stores.
+hipError_t launch_densify(DeviceOp& op, int with_c128, hipStream_t s);
+
+size_t matvec_ws_elems(const DeviceOp& op, int nrhs);   // complex elements per workspace
+
+// per-pass event timing (passes 0..4 = X+, Y+, Z*, Y-, X-)
+void prof_enable(int on);
+int prof_collect(double* ms, int* counts, int npass);
+
+// Krylov helpers (batched over systems); T = double or float.
+template <typename T>
+struct KrylovArgs;
+
+}  // namespace vie
+
+// opaque handle of the C ABI
+struct vie_op {
+    vie::DeviceOp d;
+};
+

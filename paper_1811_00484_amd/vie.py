@@ -1,0 +1,316 @@
+"""ctypes binding of libvie.so (argument marshalling only).
+
+Every numerical step runs inside the HIP library; this module converts
+torch tensors and numpy arrays to the plain pointers of the C ABI declared in
+``include/vie.h`` and raises on negative status codes.  There is no fallback:
+if the shared library is missing or fails to load, every call raises.
+
+Tensor conventions: vectors are complex torch tensors of shape
+(nrhs, 3, n3, n2, n1) (or (3, n3, n2, n1) for one right-hand side) on the
+current HIP device, complex64 or complex128, contiguous; eps_c is
+(n3, n2, n1) of the same dtype.  Work is enqueued on
+``torch.cuda.current_stream()``.
+"""
+import ctypes
+import os
+import warnings
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvie.so")
+
+VIE_OK, VIE_NOT_CONVERGED = 0, 1
+VIE_E_ARG, VIE_E_NOMEM, VIE_E_HIP, VIE_E_NONFINITE, VIE_E_UNSUPPORTED = -1, -2, -3, -4, -5
+VIE_C64, VIE_C128 = 0, 1
+VIE_RECON_AUTO, VIE_RECON_FP32, VIE_RECON_BF16, VIE_RECON_FP64 = 0, 1, 2, 3
+VIE_OP_A, VIE_OP_N = 0, 1
+VIE_NHAT_TUCKER, VIE_NHAT_DENSE = 0, 1
+
+_RECON = {"auto": VIE_RECON_AUTO, "fp32": VIE_RECON_FP32, "bf16": VIE_RECON_BF16, "fp64": VIE_RECON_FP64}
+
+
+class VieError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("vie status %d: %s" % (status, msg))
+        self.status = status
+
+
+class CompressOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("trunc_rule", ctypes.c_int), ("max_rank", ctypes.c_int)]
+
+
+class CompressInfo(ctypes.Structure):
+    _fields_ = [("ranks", (ctypes.c_int * 3) * 6), ("tail_bound", ctypes.c_double * 6),
+                ("fro_norm", ctypes.c_double * 6), ("tucker_bytes_c64", ctypes.c_size_t),
+                ("dense_bytes_c64", ctypes.c_size_t), ("seconds", ctypes.c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_outer", ctypes.c_int),
+                ("adjoint", ctypes.c_int), ("refine", ctypes.c_int), ("inner_recon", ctypes.c_int),
+                ("inner_tol", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("matvecs", ctypes.c_int), ("matvecs_fp64", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("refine_steps", ctypes.c_int), ("converged", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double)),
+                ("hist_cap", ctypes.c_int), ("hist_len", ctypes.c_int)]
+
+
+# exported symbols and their ctypes signatures (kept in step with include/vie.h)
+_P = ctypes.c_void_p
+_SIGS = {
+    "vie_compress": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.POINTER(CompressOpts),
+                                    ctypes.POINTER(_P), ctypes.POINTER(CompressInfo)]),
+    "vie_op_destroy": (ctypes.c_int, [_P]),
+    "vie_op_query": (ctypes.c_int, [_P, _P, _P]),
+    "vie_op_densify": (ctypes.c_int, [_P, ctypes.c_int]),
+    "vie_op_set_nhat": (ctypes.c_int, [_P, ctypes.c_int]),
+    "vie_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int, ctypes.c_int]),
+    "vie_matvec": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, ctypes.c_int, _P,
+                                  ctypes.c_size_t, _P]),
+    "vie_matvec_adjoint": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, ctypes.c_int,
+                                          _P, ctypes.c_size_t, _P]),
+    "vie_solve_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SolveOpts)]),
+    "vie_solve": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int, ctypes.POINTER(SolveOpts),
+                                 ctypes.POINTER(SolveInfo), _P, ctypes.c_size_t, _P]),
+    "vie_field_gradient": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
+    "vie_debug_nhat": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int, _P]),
+    "vie_debug_hosvd": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.c_double, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_int), _P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "vie_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "vie_profile_collect": (ctypes.c_int, [_P, _P]),
+    "vie_last_error": (ctypes.c_char_p, []),
+    "vie_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load libvie.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libvie.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status, what):
+    if status < 0:
+        msg = load().vie_last_error().decode(errors="replace")
+        raise VieError(status, "%s: %s" % (what, msg))
+    return status
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dt(t):
+    if t.dtype == torch.complex64:
+        return VIE_C64
+    if t.dtype == torch.complex128:
+        return VIE_C128
+    raise TypeError("complex64 or complex128 expected, got %s" % t.dtype)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Operator:
+    """Device-resident Tucker-compressed Green's operator (owns a vie_op)."""
+
+    def __init__(self, handle, n, info):
+        self._h = handle
+        self.n = tuple(n)
+        self.ranks = [tuple(info.ranks[c][a] for a in range(3)) for c in range(6)]
+        self.tail_bound = [info.tail_bound[c] for c in range(6)]
+        self.fro_norm = [info.fro_norm[c] for c in range(6)]
+        self.tucker_bytes_c64 = int(info.tucker_bytes_c64)
+        self.dense_bytes_c64 = int(info.dense_bytes_c64)
+        self.compress_seconds = float(info.seconds)
+        self._ws = {}
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("operator destroyed")
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            load().vie_op_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, nbytes, device):
+        key = (device, nbytes)
+        ws = self._ws.get(key)
+        if ws is None:
+            self._ws.clear()
+            ws = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+            self._ws[key] = ws
+        return ws
+
+
+def compress(green, tol=1e-6, trunc_rule=0, max_rank=0):
+    """HOSVD-compress the six defining tensors (numpy complex128,
+    shape (6, n3, n2, n1)) and upload the operator to the current device."""
+    lib = load()
+    g = np.ascontiguousarray(green, dtype=np.complex128)
+    if g.ndim != 4 or g.shape[0] != 6:
+        raise ValueError("green must have shape (6, n3, n2, n1)")
+    n = (ctypes.c_int * 3)(g.shape[3], g.shape[2], g.shape[1])
+    opts = CompressOpts(float(tol), int(trunc_rule), int(max_rank))
+    info = CompressInfo()
+    h = ctypes.c_void_p()
+    _check(lib.vie_compress(n, g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts), ctypes.byref(h),
+                            ctypes.byref(info)), "vie_compress")
+    return Operator(h, (g.shape[3], g.shape[2], g.shape[1]), info)
+
+
+def _as_batch(x, op):
+    n1, n2, n3 = op.n
+    if x.dim() == 4:
+        x = x.unsqueeze(0)
+    if x.dim() != 5 or tuple(x.shape[1:]) != (3, n3, n2, n1):
+        raise ValueError("vector shape must be (nrhs, 3, %d, %d, %d)" % (n3, n2, n1))
+    if not x.is_contiguous():
+        raise ValueError("vectors must be contiguous")
+    return x
+
+
+def matvec(op, x, eps_c=None, kind="A", adjoint=False, recon="auto", out=None):
+    """y = A x, N x (kind 'N'), or their adjoints, for a batch of vectors."""
+    lib = load()
+    squeeze = x.dim() == 4
+    xb = _as_batch(x, op)
+    dt = _dt(xb)
+    k = VIE_OP_A if kind == "A" else VIE_OP_N
+    if k == VIE_OP_A:
+        if eps_c is None:
+            raise ValueError("eps_c required for kind 'A'")
+        if eps_c.dtype != xb.dtype or not eps_c.is_contiguous() or tuple(eps_c.shape) != xb.shape[2:]:
+            raise ValueError("eps_c must be contiguous (n3, n2, n1) of the vector dtype")
+    y = torch.empty_like(xb) if out is None else _as_batch(out, op)
+    nbytes = lib.vie_workspace_bytes(op.handle, dt, xb.shape[0])
+    ws = op.workspace(nbytes, xb.device)
+    fn = lib.vie_matvec_adjoint if adjoint else lib.vie_matvec
+    _check(fn(op.handle, k, dt, _RECON[recon], _ptr(eps_c) if k == VIE_OP_A else None, _ptr(xb), _ptr(y),
+              xb.shape[0], _ptr(ws), nbytes, _stream()), "vie_matvec")
+    return y[0] if squeeze and out is None else y
+
+
+def solve(op, b, eps_c, x0=None, tol=1e-6, restart=50, max_outer=200, adjoint=False, refine=False,
+          inner_tol=1e-4, inner_recon="fp32", history=64):
+    """GMRES solve of A x = b (or A^H x = b).  Returns (x, infos, status)."""
+    lib = load()
+    squeeze = b.dim() == 4
+    bb = _as_batch(b, op)
+    dt = _dt(bb)
+    nrhs = bb.shape[0]
+    x = torch.zeros_like(bb) if x0 is None else _as_batch(x0, op).clone()
+    opts = SolveOpts(float(tol), int(restart), int(max_outer), int(bool(adjoint)), int(bool(refine)),
+                     _RECON[inner_recon], float(inner_tol))
+    infos = (SolveInfo * nrhs)()
+    hist = [(ctypes.c_double * history)() for _ in range(nrhs)]
+    for s in range(nrhs):
+        infos[s].history = ctypes.cast(hist[s], ctypes.POINTER(ctypes.c_double))
+        infos[s].hist_cap = history
+    nbytes = lib.vie_solve_workspace_bytes(op.handle, dt, nrhs, ctypes.byref(opts))
+    if nbytes == 0:
+        raise VieError(VIE_E_ARG, "vie_solve_workspace_bytes rejected the options")
+    ws = op.workspace(nbytes, bb.device)
+    st = _check(lib.vie_solve(op.handle, dt, _ptr(eps_c), _ptr(bb), _ptr(x), nrhs, ctypes.byref(opts), infos,
+                              _ptr(ws), nbytes, _stream()), "vie_solve")
+    out = []
+    for s in range(nrhs):
+        i = infos[s]
+        out.append({"matvecs": i.matvecs, "matvecs_fp64": i.matvecs_fp64, "restarts": i.restarts,
+                    "refine_steps": i.refine_steps, "converged": bool(i.converged),
+                    "rel_residual": i.rel_residual, "history": [hist[s][t] for t in range(i.hist_len)]})
+    if st == VIE_NOT_CONVERGED:
+        warnings.warn("vie_solve: not every system reached tol %g" % tol)
+    return (x[0] if squeeze else x), out, st
+
+
+def field_gradient(op, z, E):
+    """g = sum_q conj(z_q) E_q per voxel (z, E of shape (3, n3, n2, n1))."""
+    lib = load()
+    if z.shape != E.shape or z.dtype != E.dtype or z.dim() != 4:
+        raise ValueError("z and E must both be (3, n3, n2, n1) of one dtype")
+    g = torch.empty(z.shape[1:], dtype=z.dtype, device=z.device)
+    _check(lib.vie_field_gradient(op.handle, _dt(z), _ptr(z), _ptr(E), _ptr(g), _stream()), "vie_field_gradient")
+    return g
+
+
+def densify(op, with_c128=False):
+    _check(load().vie_op_densify(op.handle, int(with_c128)), "vie_op_densify")
+
+
+def set_nhat(op, source):
+    _check(load().vie_op_set_nhat(op.handle, VIE_NHAT_DENSE if source == "dense" else VIE_NHAT_TUCKER),
+           "vie_op_set_nhat")
+
+
+def debug_nhat(op, idx, dtype=torch.complex64):
+    """Fourier-domain tensor values at (c, k1, k2, k3) rows of ``idx``,
+    including the 1/(8 n1 n2 n3) scale carried by the device core."""
+    lib = load()
+    a = np.ascontiguousarray(idx, dtype=np.int32).reshape(-1, 4)
+    out = np.empty((a.shape[0], 2), dtype=np.float64)
+    dt = VIE_C128 if dtype == torch.complex128 else VIE_C64
+    _check(lib.vie_debug_nhat(op.handle, dt, VIE_RECON_AUTO, a.ctypes.data_as(ctypes.c_void_p), a.shape[0],
+                              out.ctypes.data_as(ctypes.c_void_p)), "vie_debug_nhat")
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def debug_hosvd(tensor, tol, rule=0, want_recon=True):
+    """Host-only HOSVD of one defining tensor (numpy complex128 (n3, n2, n1)):
+    returns (ranks, [s1, s2, s3], reconstruction, tail).  No device work."""
+    lib = load()
+    a = np.ascontiguousarray(tensor, dtype=np.complex128)
+    n3, n2, n1 = a.shape
+    n = (ctypes.c_int * 3)(n1, n2, n3)
+    ranks = (ctypes.c_int * 3)()
+    sv = np.empty(n1 + n2 + n3)
+    rec = np.empty(a.shape, dtype=np.complex128) if want_recon else None
+    tail = ctypes.c_double()
+    _check(lib.vie_debug_hosvd(n, a.ctypes.data_as(ctypes.c_void_p), float(tol), int(rule), ranks,
+                               sv.ctypes.data_as(ctypes.c_void_p),
+                               rec.ctypes.data_as(ctypes.c_void_p) if want_recon else None,
+                               ctypes.byref(tail)), "vie_debug_hosvd")
+    return tuple(ranks), [sv[:n1], sv[n1:n1 + n2], sv[n1 + n2:]], rec, tail.value
+
+
+def profile_enable(on=True):
+    _check(load().vie_profile_enable(int(bool(on))), "vie_profile_enable")
+
+
+def profile_collect():
+    """Summed per-pass milliseconds and launch counts since the last collect."""
+    ms = (ctypes.c_double * 5)()
+    cnt = (ctypes.c_int * 5)()
+    _check(load().vie_profile_collect(ctypes.cast(ms, ctypes.c_void_p), ctypes.cast(cnt, ctypes.c_void_p)),
+           "vie_profile_collect")
+    return list(ms), list(cnt)
+
+
+def exported_symbols():
+    return list(_SIGS)

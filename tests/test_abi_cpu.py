@@ -1,0 +1,104 @@
+"""CPU checks of the C ABI library: it loads, exports every function that
+include/vie.h declares, rejects bad arguments before touching a device, and
+its host-side HOSVD (the compression half of vie_compress) agrees with the
+oracle's SVD-based HOSVD."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import vie_inputs as vi
+from oracle import tucker
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vie.h")
+
+
+def _lib():
+    from paper_1811_00484_amd import vie
+    if not os.path.exists(vie.LIB_PATH):
+        from paper_1811_00484_amd import build
+        build.build()
+    return vie
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vie_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("vie_compress", "vie_matvec", "vie_matvec_adjoint", "vie_solve"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    vie = _lib()
+    lib = vie.load()
+    names = _declared_functions()
+    for name in names:
+        assert hasattr(lib, name), name
+    # the ctypes signature table covers the header exactly
+    assert sorted(vie.exported_symbols()) == names
+
+
+def test_argument_errors_before_any_device_work():
+    import ctypes
+    vie = _lib()
+    lib = vie.load()
+    assert lib.vie_compress(None, None, None, None, None) == vie.VIE_E_ARG
+    assert b"null" in lib.vie_last_error()
+    assert lib.vie_matvec(None, 0, 0, 0, None, None, None, 1, None, 0, None) == vie.VIE_E_ARG
+    assert lib.vie_solve(None, 0, None, None, None, 1, None, None, None, 0, None) == vie.VIE_E_ARG
+    assert lib.vie_op_destroy(None) == vie.VIE_OK
+    assert lib.vie_workspace_bytes(None, 0, 1) == 0
+    n = (ctypes.c_int * 3)(4, 4, 300)
+    g = np.zeros(12)
+    assert lib.vie_compress(n, g.ctypes.data_as(ctypes.c_void_p), None, ctypes.byref(ctypes.c_void_p()),
+                            None) == vie.VIE_E_UNSUPPORTED
+    n = (ctypes.c_int * 3)(11, 4, 4)            # 2 * 11 has the prime factor 11
+    g = np.zeros(12 * 11 * 16)
+    assert lib.vie_compress(n, g.ctypes.data_as(ctypes.c_void_p), None, ctypes.byref(ctypes.c_void_p()),
+                            None) == vie.VIE_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("c", [0, 3, 5])
+@pytest.mark.parametrize("tol", [1e-6, 1e-8])
+def test_host_hosvd_matches_oracle(c, tol):
+    vie = _lib()
+    n = (14, 12, 10)
+    G = vi.green_tensor(n, 0.004, vi.wavenumber(298e6))
+    A = G[c]
+    ranks, sv, rec, tail = vie.debug_hosvd(A, tol)
+    Gc, Us, s = tucker.hosvd(tucker.from_storage(A), tol)
+    assert list(ranks) == [U.shape[1] for U in Us]
+    for a in range(3):
+        np.testing.assert_allclose(sv[a], s[a], rtol=0, atol=1e-13 * s[a][0])
+    rec_o = tucker.to_storage(tucker.tucker_reconstruct(Gc, *Us))
+    assert np.linalg.norm(rec - rec_o) <= 1e-12 * np.linalg.norm(rec_o)
+    assert np.linalg.norm(rec - A) <= tol * np.linalg.norm(A)
+    assert tail <= tol
+
+
+def test_host_hosvd_exact_low_rank():
+    vie = _lib()
+    rng = np.random.default_rng(0)
+    n = (9, 8, 7)
+    core = rng.standard_normal((3, 4, 2)) + 1j * rng.standard_normal((3, 4, 2))
+    Us = [np.linalg.qr(rng.standard_normal((m, r)) + 1j * rng.standard_normal((m, r)))[0]
+          for m, r in zip(n, core.shape)]
+    A = tucker.to_storage(tucker.tucker_reconstruct(core, *Us))
+    ranks, sv, rec, tail = vie.debug_hosvd(A, 1e-10)
+    assert ranks == (3, 4, 2)
+    assert np.linalg.norm(rec - A) <= 1e-13 * np.linalg.norm(A)
+
+
+def test_literal_truncation_rule():
+    vie = _lib()
+    G = vi.green_tensor((10, 9, 8), 0.004, vi.wavenumber(298e6))
+    ranks, sv, _, _ = vie.debug_hosvd(G[1], 1e-5, rule=1, want_recon=False)
+    for a in range(3):
+        assert ranks[a] == max(1, int(np.sum(sv[a] >= 1e-5 / np.sqrt(3) * sv[a][0])))

@@ -1,0 +1,137 @@
+"""GPU parity of the matvec through the C ABI against the FP64 oracle.
+
+Tolerances: complex64 path (FP32 FFTs, FP32 Tucker reconstruction) within a
+relative L2 error of 1e-5 of the oracle on the same Tucker operator;
+complex128 path within 1e-12 (FP64 FFT rounding on these sizes is ~1e-15; the
+two HOSVDs agree to ~1e-14 relative).  Index maps (padding, cropping, the
+parity signs of the mirrored pencils) are checked bit-exactly with
+integer-valued data in test_gpu_exact.py."""
+import numpy as np
+import pytest
+import torch
+
+import vie_inputs as vi
+from gpu_common import F, K0, device, problem, rel, say, to_dev
+from oracle import circulant, operator as opm
+from paper_1811_00484_amd import vie
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [
+    (16, 16, 16),      # tiny workload grid
+    (12, 10, 9),       # ragged, radix 8/4/3/2 mixes
+    (20, 15, 18),      # radix 5 and 3 (L = 40, 30, 36)
+    (16, 14, 7),       # radix 7 (L = 28, 14)
+    (5, 3, 2),         # tiny odd
+    (1, 1, 1),         # single voxel
+    (35, 4, 6),        # pencil counts not multiples of the tile width (L1 = 70 = 2*5*7)
+]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("mode", ["A", "AH", "N"])
+def test_matvec_c64_matches_oracle(n, mode):
+    say("matvec c64", n, mode)
+    G, epsc, ref = problem(n)
+    u = vi.random_field(n, 100)
+    op = vie.compress(G, tol=1e-6)
+    assert op.ranks == ref.ranks
+    y_ref = opm.matvec(ref, epsc, u, mode)
+    x = to_dev(u, torch.complex64)
+    e = to_dev(epsc, torch.complex64)
+    kind = "N" if mode == "N" else "A"
+    y = vie.matvec(op, x, e, kind=kind, adjoint=(mode == "AH")).cpu().numpy()
+    err = rel(y.astype(np.complex128), y_ref)
+    say("   rel err", err)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("n", [(16, 16, 16), (12, 10, 9), (20, 15, 18), (1, 1, 1)])
+@pytest.mark.parametrize("mode", ["A", "AH"])
+def test_matvec_c128_matches_oracle(n, mode):
+    say("matvec c128", n, mode)
+    G, epsc, ref = problem(n, tol=1e-8)
+    u = vi.random_field(n, 101)
+    op = vie.compress(G, tol=1e-8)
+    assert op.ranks == ref.ranks
+    y_ref = opm.matvec(ref, epsc, u, mode)
+    y = vie.matvec(op, to_dev(u, torch.complex128), to_dev(epsc, torch.complex128),
+                   adjoint=(mode == "AH")).cpu().numpy()
+    err = rel(y, y_ref)
+    say("   rel err", err)
+    assert err <= 1e-12
+
+
+def test_batched_rhs_equal_single_rhs():
+    n = (12, 10, 9)
+    G, epsc, ref = problem(n)
+    op = vie.compress(G, tol=1e-6)
+    u = vi.random_field(n, 7, nrhs=3)
+    x = to_dev(u, torch.complex64)
+    e = to_dev(epsc, torch.complex64)
+    yb = vie.matvec(op, x, e).cpu().numpy()
+    for s in range(3):
+        ys = vie.matvec(op, x[s].contiguous(), e).cpu().numpy()
+        np.testing.assert_array_equal(yb[s], ys)          # same kernels, same order: bitwise
+        assert rel(yb[s].astype(np.complex128), opm.matvec(ref, epsc, u[s], "A")) <= 1e-5
+
+
+def test_adjoint_identity_on_device():
+    n = (20, 15, 18)
+    G, epsc, _ = problem(n)
+    op = vie.compress(G, tol=1e-6)
+    x = to_dev(vi.random_field(n, 1), torch.complex128)
+    y = to_dev(vi.random_field(n, 2), torch.complex128)
+    e = to_dev(epsc, torch.complex128)
+    Ax = vie.matvec(op, x, e)
+    AHy = vie.matvec(op, y, e, adjoint=True)
+    lhs = torch.vdot(y.flatten(), Ax.flatten()).item()
+    rhs = torch.vdot(AHy.flatten(), x.flatten()).item()
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_fourier_tensor_samples_match_oracle():
+    # N^_c(k1, k2, k3) from the device Tucker form (including the mirrored
+    # half of the spectrum) against the oracle's densely reconstructed
+    # Fourier-domain tensor; the device core carries 1/(8 n1 n2 n3)
+    n = (12, 10, 9)
+    G, epsc, _ = problem(n, tol=1e-8)
+    ref = opm.tucker_operator(G, 1e-8)
+    op = vie.compress(G, tol=1e-8)
+    rng = np.random.default_rng(3)
+    L = (24, 20, 18)
+    idx = np.stack([rng.integers(0, 6, 400), rng.integers(0, L[0], 400), rng.integers(0, L[1], 400),
+                    rng.integers(0, L[2], 400)], axis=1)
+    idx = np.concatenate([idx, [[c, 12, 10, 9] for c in range(6)], [[c, 0, 0, 0] for c in range(6)]])
+    got = vie.debug_nhat(op, idx, torch.complex128) * (8 * 12 * 10 * 9)
+    want = np.array([ref.nhat[c][k1, k2, k3] for c, k1, k2, k3 in idx])
+    scale = max(np.abs(ref.nhat[c]).max() for c in range(6))
+    assert np.abs(got - want).max() <= 1e-12 * scale
+
+
+def test_dense_spectrum_path_equals_tucker_path():
+    n = (16, 14, 12)
+    G, epsc, _ = problem(n)
+    op = vie.compress(G, tol=1e-6)
+    x = to_dev(vi.random_field(n, 9), torch.complex64)
+    e = to_dev(epsc, torch.complex64)
+    y_t = vie.matvec(op, x, e).cpu().numpy()
+    vie.densify(op)
+    vie.set_nhat(op, "dense")
+    y_d = vie.matvec(op, x, e).cpu().numpy()
+    vie.set_nhat(op, "tucker")
+    assert rel(y_d, y_t) <= 1e-6
+
+
+def test_rejects_bad_arguments_on_device():
+    n = (4, 4, 4)
+    G, epsc, _ = problem(n)
+    op = vie.compress(G, tol=1e-6)
+    x = to_dev(vi.random_field(n, 1), torch.complex64)
+    e = to_dev(epsc, torch.complex64)
+    with pytest.raises(vie.VieError):
+        vie.matvec(op, x, e, out=x.unsqueeze(0))                      # aliasing
+    with pytest.raises(vie.VieError):
+        vie.matvec(op, x, e, recon="fp64")                            # FP64 recon on c64
+    with pytest.raises(ValueError):
+        vie.matvec(op, x, None)                                       # A needs eps_c
