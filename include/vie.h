@@ -202,14 +202,38 @@ vie_status vie_solve(const vie_op* op, int dtype, const void* eps_c, const void*
                      size_t ws_bytes, void* stream);
 
 /*
- * vie_field_gradient -- g_n = sum_q conj(z_q(n)) E_q(n) for every voxel n
- * (the voxel-wise factor of the adjoint gradient: dL/d eps_r = Re g,
- * dL/d sigma = Im g / (omega eps0)).
- *   z, E   DEVICE [3][n3][n2][n1] complex (dtype);  g DEVICE [n3][n2][n1] complex.
- * Asynchronous.
+ * Helpers of the differentiable forward model (voxel-wise, asynchronous on
+ * `stream`; dtype VIE_C64 with float real maps or VIE_C128 with double).
+ * omega_eps0 = 2 pi f eps0 > 0.
+ *
+ * vie_problem_setup -- eps_c = eps_r - i sigma / (omega eps0) (exp(+i omega t)
+ *   convention) and the right-hand side b = c_e chi e_inc, c_e = i omega eps0,
+ *   chi = eps_c - 1 (eq. 1-2).  eps_r, sigma DEVICE real [n3][n2][n1];
+ *   e_inc, b DEVICE complex [3][n3][n2][n1]; eps_c DEVICE complex [n3][n2][n1].
  */
-vie_status vie_field_gradient(const vie_op* op, int dtype, const void* z, const void* E, void* g,
-                              void* stream);
+vie_status vie_problem_setup(const vie_op* op, int dtype, const void* eps_r, const void* sigma, const void* e_inc,
+                             double omega_eps0, void* eps_c, void* b, void* stream);
+/*
+ * vie_total_field -- E = e_inc + (N u - u) / c_e: the total field of the
+ *   polarisation current u = c_e chi E (eq. 3).  Nu = vie_matvec(VIE_OP_N, u).
+ *   All DEVICE complex [3][n3][n2][n1].
+ */
+vie_status vie_total_field(const vie_op* op, int dtype, const void* e_inc, const void* u, const void* Nu,
+                           double omega_eps0, void* E, void* stream);
+/*
+ * vie_adjoint_source -- t = N^H g - g, the right-hand side A^H z = (N - I)^H g
+ *   of the adjoint solve for an objective gradient g = dL/dRe(E) + i dL/dIm(E).
+ */
+vie_status vie_adjoint_source(const vie_op* op, int dtype, const void* g, const void* NHg, void* t, void* stream);
+/*
+ * vie_field_gradient -- with X_n = sum_q conj(z_q(n)) E_q(n):
+ *   g_eps[n] = Re X_n = dL/d eps_r(n),  g_sigma[n] = Im X_n / (omega eps0) = dL/d sigma(n),
+ *   where z solves A^H z = N^H g - g (chi_n = eps_r - 1 - i sigma/(omega eps0), so
+ *   d chi/d eps_r = 1 and d chi/d sigma = -i/(omega eps0)).
+ *   z, E DEVICE complex [3][n3][n2][n1]; g_eps, g_sigma DEVICE real [n3][n2][n1].
+ */
+vie_status vie_field_gradient(const vie_op* op, int dtype, const void* z, const void* E, double omega_eps0,
+                              void* g_eps, void* g_sigma, void* stream);
 
 /*
  * Debug / test entry points (bit-exact checks of indexing).
@@ -248,6 +272,14 @@ vie_status vie_debug_hosvd(const int n[3], const double* tensor, double tol, int
  */
 vie_status vie_profile_enable(int on);
 vie_status vie_profile_collect(double ms[5], int counts[5]);
+
+/*
+ * Kernel selection (for tests that compare the two implementations): 0 =
+ * default (register-FFT kernels for FFT lengths 128, 256, 512, LDS-staged
+ * mixed-radix kernels otherwise), 1 = mixed-radix kernels for every pass.
+ * Process-wide.
+ */
+vie_status vie_set_kernel_path(int path);
 
 const char* vie_last_error(void);
 /* library version string */

@@ -30,8 +30,20 @@ template <typename TK>
 hipError_t kr_residual(c2<TK>* R, const c2<TK>* B, long sstride, long n, const int* map, int nact, hipStream_t st);
 template <typename TO, typename TI>
 hipError_t kr_convert(c2<TO>* dst, const c2<TI>* src, long n, hipStream_t st);
-// g = sum_q conj(z_q) E_q per voxel
+// g_eps = Re X, g_sigma = Im X / oe0 with X = sum_q conj(z_q) E_q per voxel
 template <typename T>
-hipError_t kr_field_gradient(const c2<T>* z, const c2<T>* E, c2<T>* g, long V, hipStream_t st);
+hipError_t kr_field_gradient(const c2<T>* z, const c2<T>* E, T* g_eps, T* g_sig, double oe0, long V,
+                             hipStream_t st);
+// eps_c = eps_r - i sigma / oe0, b = i oe0 (eps_c - 1) e_inc   (oe0 = omega eps0)
+template <typename T>
+hipError_t kr_problem(const T* eps_r, const T* sigma, const c2<T>* e_inc, c2<T>* eps_c, c2<T>* b, double oe0, long V,
+                      hipStream_t st);
+// E = e_inc + (Nu - u) / (i oe0)
+template <typename T>
+hipError_t kr_total_field(const c2<T>* e_inc, const c2<T>* u, const c2<T>* Nu, c2<T>* E, double oe0, long n,
+                          hipStream_t st);
+// t = NHg - g
+template <typename T>
+hipError_t kr_adjoint_source(const c2<T>* g, const c2<T>* NHg, c2<T>* t, long n, hipStream_t st);
 
 }  // namespace vie

@@ -170,15 +170,55 @@ __global__ void __launch_bounds__(KB) k_convert(c2<TO>* __restrict__ dst, const 
     if (i < n) dst[i] = cvt<TO>(src[i]);
 }
 
+// g_eps = Re X, g_sigma = Im X / (omega eps0), X = sum_q conj(z_q) E_q
 template <typename T>
 __global__ void __launch_bounds__(KB) k_field_gradient(const c2<T>* __restrict__ z, const c2<T>* __restrict__ E,
-                                                       c2<T>* __restrict__ g, long V)
+                                                       T* __restrict__ g_eps, T* __restrict__ g_sig, double oe0,
+                                                       long V)
 {
     long i = (long)blockIdx.x * KB + threadIdx.x;
     if (i >= V) return;
     c2<T> acc = mk<T>(0, 0);
     for (int q = 0; q < 3; ++q) acc = acc + mulc(E[q * V + i], z[q * V + i]);   // conj(z) E
-    g[i] = acc;
+    g_eps[i] = acc.x;
+    g_sig[i] = (T)(acc.y / oe0);
+}
+
+// eps_c = eps_r - i sigma / (omega eps0);  b_q = i omega eps0 (eps_c - 1) e_q
+template <typename T>
+__global__ void __launch_bounds__(KB) k_problem(const T* __restrict__ eps_r, const T* __restrict__ sigma,
+                                                const c2<T>* __restrict__ e_inc, c2<T>* __restrict__ eps_c,
+                                                c2<T>* __restrict__ b, double oe0, long V)
+{
+    long i = (long)blockIdx.x * KB + threadIdx.x;
+    if (i >= V) return;
+    c2<T> ec = mk<T>(eps_r[i], (T)(-(double)sigma[i] / oe0));
+    eps_c[i] = ec;
+    c2<T> ce_chi = mk<T>((T)(-oe0 * (double)ec.y), (T)(oe0 * ((double)ec.x - 1.0)));   // i oe0 (eps_c - 1)
+    for (int q = 0; q < 3; ++q) b[q * V + i] = ce_chi * e_inc[q * V + i];
+}
+
+// E = e_inc + (Nu - u) / (i omega eps0)
+template <typename T>
+__global__ void __launch_bounds__(KB) k_total_field(const c2<T>* __restrict__ e_inc, const c2<T>* __restrict__ u,
+                                                    const c2<T>* __restrict__ Nu, c2<T>* __restrict__ E, double oe0,
+                                                    long n)
+{
+    long i = (long)blockIdx.x * KB + threadIdx.x;
+    if (i >= n) return;
+    c2<T> d = Nu[i] - u[i];
+    // d / (i oe0) = -i d / oe0
+    E[i] = mk<T>(e_inc[i].x + (T)((double)d.y / oe0), e_inc[i].y - (T)((double)d.x / oe0));
+}
+
+// t = N^H g - g
+template <typename T>
+__global__ void __launch_bounds__(KB) k_adjoint_source(const c2<T>* __restrict__ g, const c2<T>* __restrict__ NHg,
+                                                       c2<T>* __restrict__ t, long n)
+{
+    long i = (long)blockIdx.x * KB + threadIdx.x;
+    if (i >= n) return;
+    t[i] = NHg[i] - g[i];
 }
 
 // ---------------------------- launchers ---------------------------------
@@ -241,9 +281,33 @@ hipError_t kr_convert(c2<TO>* dst, const c2<TI>* src, long n, hipStream_t st)
 }
 
 template <typename T>
-hipError_t kr_field_gradient(const c2<T>* z, const c2<T>* E, c2<T>* g, long V, hipStream_t st)
+hipError_t kr_field_gradient(const c2<T>* z, const c2<T>* E, T* g_eps, T* g_sig, double oe0, long V,
+                             hipStream_t st)
 {
-    hipLaunchKernelGGL(k_field_gradient<T>, dim3((V + KB - 1) / KB), dim3(KB), 0, st, z, E, g, V);
+    hipLaunchKernelGGL(k_field_gradient<T>, dim3((V + KB - 1) / KB), dim3(KB), 0, st, z, E, g_eps, g_sig, oe0, V);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t kr_problem(const T* eps_r, const T* sigma, const c2<T>* e_inc, c2<T>* eps_c, c2<T>* b, double oe0, long V,
+                      hipStream_t st)
+{
+    hipLaunchKernelGGL(k_problem<T>, dim3((V + KB - 1) / KB), dim3(KB), 0, st, eps_r, sigma, e_inc, eps_c, b, oe0, V);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t kr_total_field(const c2<T>* e_inc, const c2<T>* u, const c2<T>* Nu, c2<T>* E, double oe0, long n,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_total_field<T>, dim3((n + KB - 1) / KB), dim3(KB), 0, st, e_inc, u, Nu, E, oe0, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t kr_adjoint_source(const c2<T>* g, const c2<T>* NHg, c2<T>* t, long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adjoint_source<T>, dim3((n + KB - 1) / KB), dim3(KB), 0, st, g, NHg, t, n);
     return hipGetLastError();
 }
 
@@ -257,7 +321,12 @@ hipError_t kr_field_gradient(const c2<T>* z, const c2<T>* E, c2<T>* g, long V, h
     template hipError_t kr_scale_norm<TK>(c2<TK>*, long, const c2<TK>*, long, long, const c2<double>*, long,     \
                                           const int*, int, hipStream_t);                                         \
     template hipError_t kr_residual<TK>(c2<TK>*, const c2<TK>*, long, long, const int*, int, hipStream_t);       \
-    template hipError_t kr_field_gradient<TK>(const c2<TK>*, const c2<TK>*, c2<TK>*, long, hipStream_t);
+    template hipError_t kr_field_gradient<TK>(const c2<TK>*, const c2<TK>*, TK*, TK*, double, long, hipStream_t); \
+    template hipError_t kr_problem<TK>(const TK*, const TK*, const c2<TK>*, c2<TK>*, c2<TK>*, double, long,        \
+                                       hipStream_t);                                                             \
+    template hipError_t kr_total_field<TK>(const c2<TK>*, const c2<TK>*, const c2<TK>*, c2<TK>*, double, long,     \
+                                           hipStream_t);                                                         \
+    template hipError_t kr_adjoint_source<TK>(const c2<TK>*, const c2<TK>*, c2<TK>*, long, hipStream_t);
 
 VIE_KR_INST(float)
 VIE_KR_INST(double)

@@ -39,6 +39,8 @@ namespace vie {
 
 static constexpr int NT = 256;   // threads per block in every pass
 
+int g_kernel_path = 0;
+
 // component parities: s_a(c) = -1 iff c is off-diagonal and a is one of its axes
 __device__ __forceinline__ int comp_sign(int c, int f1, int f2, int f3)
 {
@@ -504,9 +506,13 @@ hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* 
     constexpr int MAXE_XY = 32;   // W * L <= MAXE * NT for W*L <= 8192
     constexpr int MAXE_Z = 24;    // 3 * G * L3 <= 6144
 
+    const bool allow_fast = g_kernel_path == 0;
     // ---- X+
     {
         PassTimer timer(0, s);
+        if (allow_fast && xy_pass_fast<TV, T>(0, L1, nullptr, S1, x, eps, tw[0], n1, n2, n3, L1, L2, mode, nrhs,
+                                              rhs_map, s)) {
+        } else {
         int W = tile_width<T>(op.max_lds, L1);
         if ((size_t)W * L1 > (size_t)MAXE_XY * NT) { err = "x length too large"; return hipErrorInvalidValue; }
         size_t lds = (size_t)(W + 1) * L1 * sizeof(c2<T>) + (size_t)L1 * sizeof(c2<T>);
@@ -517,10 +523,14 @@ hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* 
             hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, x, eps, S1, op.plan[0], tw[0], n1, n2, n3, mode,
                                rhs_map);
         });
+        }
     }
     // ---- Y+
     {
         PassTimer timer(1, s);
+        if (allow_fast && xy_pass_fast<TV, T>(1, L2, S1, S2, x, eps, tw[1], n1, n2, n3, L1, L2, mode, nrhs,
+                                              rhs_map, s)) {
+        } else {
         int W = tile_width<T>(op.max_lds, L2);
         if ((size_t)W * L2 > (size_t)MAXE_XY * NT) { err = "y length too large"; return hipErrorInvalidValue; }
         size_t lds = (size_t)(W + 1) * L2 * sizeof(c2<T>) + (size_t)L2 * sizeof(c2<T>);
@@ -530,10 +540,17 @@ hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* 
             (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S1, S2, op.plan[1], tw[1], L1, n2, n3);
         });
+        }
     }
     // ---- Z*
+    if (op.nhat_source == 1 && dense == nullptr) {
+        err = "dense spectrum not materialised";
+        return hipErrorInvalidValue;
+    }
     {
         PassTimer timer(2, s);
+        if (allow_fast && z_pass_fast<T>(op, mode, nrhs, S2, tw[2], core, fac, dense, s)) {
+        } else {
         int G = 4;
         while (G > 1 && z_lds_bytes<T>(v, G) > op.max_lds) G /= 2;
         size_t lds = z_lds_bytes<T>(v, G);
@@ -550,10 +567,14 @@ hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* 
         auto kern = k_zmid<T, MAXE_Z>;
         (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S2, op.plan[2], tw[2], za, core, fac, dense);
+        }
     }
     // ---- Y-
     {
         PassTimer timer(3, s);
+        if (allow_fast && xy_pass_fast<TV, T>(2, L2, S2, S1, x, eps, tw[1], n1, n2, n3, L1, L2, mode, nrhs,
+                                              rhs_map, s)) {
+        } else {
         int W = tile_width<T>(op.max_lds, L2);
         size_t lds = (size_t)(W + 1) * L2 * sizeof(c2<T>) + (size_t)L2 * sizeof(c2<T>);
         dim3 grid((n3 + W - 1) / W, L1, nrhs * 3);
@@ -562,10 +583,14 @@ hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* 
             (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S2, S1, op.plan[1], tw[1], L1, n2, n3);
         });
+        }
     }
     // ---- X-
     {
         PassTimer timer(4, s);
+        if (allow_fast && xy_pass_fast<TV, T>(3, L1, S1, y, x, eps, tw[0], n1, n2, n3, L1, L2, mode, nrhs,
+                                              rhs_map, s)) {
+        } else {
         int W = tile_width<T>(op.max_lds, L1);
         size_t lds = (size_t)(W + 1) * L1 * sizeof(c2<T>) + (size_t)L1 * sizeof(c2<T>);
         dim3 grid((n2 + W - 1) / W, n3, nrhs * 3);
@@ -575,6 +600,7 @@ hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* 
             hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S1, x, eps, y, op.plan[0], tw[0], n1, n2, n3, mode,
                                rhs_map);
         });
+        }
     }
     return hipGetLastError();
 }

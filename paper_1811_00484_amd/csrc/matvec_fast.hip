@@ -1,0 +1,508 @@
+// Register-FFT kernels of the five matvec passes for power-of-two FFT
+// lengths (L = 64 ... 512), the sizes of the workloads that matter for
+// throughput.  Same data layouts and results as the generic LDS-staged
+// kernels in matvec.hip (which remain the path for lengths with factors 3,
+// 5, 7), but each thread keeps its pencil elements in registers across the
+// radix-8/4 stages (reg_fft.h) and LDS only carries the transposes between
+// stages.
+//
+// X/Y passes: a block owns W pencils of one tile; global rows are staged
+// through per-pencil LDS slices (stride PL = L + L/8 + 1 complex, odd so
+// that both row-wise and pencil-wise walks are free of bank conflicts).
+//
+// Z pass: a block owns one canonical k2 (and its mirror L2 - k2) and a
+// chunk of k1 quads.  W_c(k2) = G_c x2 U2_c(k2, :) is built once per block;
+// per quad V_c = U1_c(k1, :) W_c and N^_c(k1, k2, k3) = sum_g V_c[g]
+// U3_c(k3, g) for k3 in [0, n3] go to LDS, and each thread transforms the
+// three components of its pencil in registers, so the 3 x 3 component
+// product is thread-local.
+#include <hip/hip_runtime.h>
+
+#include "reg_fft.h"
+#include "vie_internal.h"
+
+namespace vie {
+
+// ---------------------------------------------------------------------------
+// plans: forward plan and its reverse for the inverse
+template <int L>
+struct Pow2Plan;
+template <>
+struct Pow2Plan<512> {
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void fwd(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    {
+        reg_fft<512, TPP, NSEQ, DIR, T, 8, 8, 8>(v, lds, st, t, tw);
+    }
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void inv(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    {
+        reg_fft<512, TPP, NSEQ, DIR, T, 8, 8, 8>(v, lds, st, t, tw);
+    }
+    static constexpr int RF0 = 8, RFL = 8, RI0 = 8, RIL = 8;
+};
+template <>
+struct Pow2Plan<256> {
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void fwd(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    {
+        reg_fft<256, TPP, NSEQ, DIR, T, 8, 8, 4>(v, lds, st, t, tw);
+    }
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void inv(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    {
+        reg_fft<256, TPP, NSEQ, DIR, T, 4, 8, 8>(v, lds, st, t, tw);
+    }
+    static constexpr int RF0 = 8, RFL = 4, RI0 = 4, RIL = 8;
+};
+template <>
+struct Pow2Plan<128> {
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void fwd(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    {
+        reg_fft<128, TPP, NSEQ, DIR, T, 8, 4, 4>(v, lds, st, t, tw);
+    }
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void inv(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    {
+        reg_fft<128, TPP, NSEQ, DIR, T, 4, 4, 8>(v, lds, st, t, tw);
+    }
+    static constexpr int RF0 = 8, RFL = 4, RI0 = 4, RIL = 8;
+};
+template <>
+struct Pow2Plan<64> {
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void fwd(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    {
+        reg_fft<64, TPP, NSEQ, DIR, T, 8, 8>(v, lds, st, t, tw);
+    }
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void inv(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    {
+        reg_fft<64, TPP, NSEQ, DIR, T, 8, 8>(v, lds, st, t, tw);
+    }
+    static constexpr int RF0 = 8, RFL = 8, RI0 = 8, RIL = 8;
+};
+
+template <int L>
+struct PL {
+    static constexpr int value = L + L / 8 + 1;
+};
+
+// ---------------------------------------------------------------------------
+// X/Y passes.  KIND: 0 = X+, 1 = Y+, 2 = Y-, 3 = X-.
+struct XYArgs {
+    int n1, n2, n3, L1, L2;
+    int mode;
+};
+
+template <typename TV, typename T, int L, int E, int W, int KIND>
+__global__ void __launch_bounds__(W*(L / E)) k_xy_fast(const void* __restrict__ in_, void* __restrict__ out_,
+                                                       const c2<TV>* __restrict__ x, const c2<TV>* __restrict__ eps,
+                                                       const c2<T>* __restrict__ tw, XYArgs a,
+                                                       const int* __restrict__ rhs_map)
+{
+    constexpr int TPP = L / E;
+    constexpr int NT = W * TPP;
+    constexpr int P = PL<L>::value;
+    using Plan = Pow2Plan<L>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    c2<T>* buf = reinterpret_cast<c2<T>*>(smem_raw);           // [W][P]
+    c2<T>* tws = buf + (size_t)W * P;                           // [L]
+    const int tid = threadIdx.x;
+    for (int m = tid; m < L; m += NT) tws[m] = tw[m];
+
+    const int n1 = a.n1, n2 = a.n2, n3 = a.n3, L1 = a.L1, L2 = a.L2;
+    const int zq = blockIdx.z, q = zq % 3, bl = zq / 3;
+    const long bqc = (long)bl * 3 + q;                           // compact (workspace) index
+    const int b = rhs_map ? rhs_map[bl] : bl;
+    const long bqv = (long)b * 3 + q;                           // vector index
+    const int p0 = blockIdx.x * W;                              // first pencil of the tile
+    const int row = blockIdx.y;
+    // number of valid pencils in the tile and the transform's input length
+    int npen, nin;
+    if (KIND == 0) { npen = n2; nin = n1; }
+    else if (KIND == 1) { npen = n3; nin = n2; }
+    else if (KIND == 2) { npen = n3; nin = L2; }
+    else { npen = n2; nin = L1; }
+
+    const int w = tid / TPP, t = tid % TPP;
+    const int pw = p0 + w;                                      // my pencil
+    c2<T>* slice = buf + w * P;
+    c2<T> v[E];
+
+    if (KIND == 0 || KIND == 1) {
+        // ---- rows contiguous per pencil: straight into the registers of
+        //      the first stage (zero padding beyond nin)
+        constexpr int R0 = Plan::RF0;
+#pragma unroll
+        for (int u = 0; u < E / R0; ++u)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                const int pos = t + TPP * u + r * (L / R0);
+                c2<T> val = mk<T>(0, 0);
+                if (pw < npen && pos < nin) {
+                    if (KIND == 0) {
+                        long idx = ((bqv * n3 + row) * n2 + pw) * n1 + pos;
+                        val = cvt<T>(x[idx]);
+                        if (a.mode == MODE_AH) {
+                            c2<T> ep = cvt<T>(eps[((long)row * n2 + pw) * n1 + pos]);
+                            val = mk<T>(ep.x - (T)1, -ep.y) * val;
+                        }
+                    } else {
+                        const c2<T>* S1 = reinterpret_cast<const c2<T>*>(in_);
+                        val = S1[((bqc * n3 + pw) * L1 + row) * n2 + pos];
+                    }
+                }
+                v[u * R0 + r] = val;
+            }
+        Plan::template fwd<T, TPP, 1, -1>(v, slice, 0, t, tws);
+        reg_store<L, TPP, Plan::RFL, L / Plan::RFL>(v, slice, t);
+        __syncthreads();
+        // ---- transposed output [m][p0 + w], all L frequencies
+        c2<T>* S = reinterpret_cast<c2<T>*>(out_);
+        for (int e = tid; e < W * L; e += NT) {
+            int ww = e % W, m = e / W;
+            int p = p0 + ww;
+            if (p >= npen) continue;
+            c2<T> val = buf[ww * P + lds_pad(m)];
+            if (KIND == 0) S[((bqc * n3 + row) * L1 + m) * n2 + p] = val;
+            else S[((bqc * L2 + m) * L1 + row) * n3 + p] = val;
+        }
+    } else {
+        // ---- transposed input: element m of pencil ww at [m][p0 + ww]
+        for (int e = tid; e < W * L; e += NT) {
+            int ww = e % W, m = e / W;
+            int p = p0 + ww;
+            c2<T> val = mk<T>(0, 0);
+            if (p < npen) {
+                const c2<T>* S = reinterpret_cast<const c2<T>*>(in_);
+                if (KIND == 2) val = S[((bqc * L2 + m) * L1 + row) * n3 + p];
+                else val = S[((bqc * n3 + row) * L1 + m) * n2 + p];
+            }
+            buf[ww * P + lds_pad(m)] = val;
+        }
+        __syncthreads();
+        reg_load<L, TPP, Plan::RI0>(v, slice, t);
+        __syncthreads();
+        Plan::template inv<T, TPP, 1, 1>(v, slice, 0, t, tws);
+        // ---- cropped rows straight from the registers of the last stage
+        constexpr int RL = Plan::RIL;
+        const int nout = KIND == 2 ? n2 : n1;
+        if (pw < npen) {
+#pragma unroll
+            for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+                for (int r = 0; r < RL; ++r) {
+                    const int m = t + TPP * u + r * (L / RL);
+                    if (m >= nout) continue;
+                    const c2<T> rr = v[u * RL + r];
+                    if (KIND == 2) {
+                        c2<T>* S3 = reinterpret_cast<c2<T>*>(out_);
+                        S3[((bqc * n3 + pw) * L1 + row) * n2 + m] = rr;
+                    } else {
+                        c2<TV>* y = reinterpret_cast<c2<TV>*>(out_);
+                        long idx = ((bqv * n3 + row) * n2 + pw) * n1 + m;
+                        c2<T> o;
+                        if (a.mode == MODE_A || a.mode == MODE_AH) {
+                            c2<T> u0 = cvt<T>(x[idx]);
+                            c2<T> ep = cvt<T>(eps[((long)row * n2 + pw) * n1 + m]);
+                            if (a.mode == MODE_A) o = ep * u0 - mk<T>(ep.x - (T)1, ep.y) * rr;
+                            else o = conj(ep) * u0 - rr;
+                        } else {
+                            o = rr;
+                        }
+                        y[idx] = cvt<TV>(o);
+                    }
+                }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Z pass
+struct ZFastArgs {
+    OpView v;
+    int conj;
+    int dense;
+    int chunk;     // k1 quads per block
+};
+
+__device__ __forceinline__ int zsign(int c, int f1, int f2, int f3)
+{
+    int odd1 = (c == 3 || c == 4), odd2 = (c == 3 || c == 5), odd3 = (c == 4 || c == 5);
+    return ((odd1 & f1) ^ (odd2 & f2) ^ (odd3 & f3)) ? -1 : 1;
+}
+
+template <typename T, int L3>
+__global__ void __launch_bounds__(4 * (L3 / 8)) k_z_fast(c2<T>* __restrict__ S2, const c2<T>* __restrict__ tw,
+                                                         ZFastArgs a, const c2<T>* __restrict__ core,
+                                                         const c2<T>* __restrict__ fac,
+                                                         const c2<T>* __restrict__ dense)
+{
+    constexpr int E = 8;
+    constexpr int TPP = L3 / E;
+    constexpr int NT = 4 * TPP;
+    constexpr int P = PL<L3>::value;
+    constexpr int N3 = L3 / 2;
+    using Plan = Pow2Plan<L3>;
+    const OpView& v = a.v;
+    const int n1 = v.n[0], n2 = v.n[1];
+    const int L1 = v.L[0], L2 = v.L[1];
+    const int rmax = v.rmax;
+    const int tid = threadIdx.x;
+    const int pe = tid / TPP, t = tid % TPP;
+    const int s1 = pe & 1, s2 = pe >> 1;
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    // X: per-pencil FFT transpose slices [4][P]; after the forward FFT the
+    // same region holds the quad's N^ table [6][N3+1] (6 (N3+1) <= 4 P)
+    c2<T>* X = reinterpret_cast<c2<T>*>(smem_raw);
+    c2<T>* NTt = X;
+    c2<T>* Wc = X + 4 * P;                                      // [6][rmax*rmax]
+    c2<T>* Vc = Wc + 6 * rmax * rmax;                           // [6][rmax]
+    c2<T>* tws = Vc + 6 * rmax;                                 // [L3]
+    for (int m = tid; m < L3; m += NT) tws[m] = tw[m];
+
+    const int k2 = blockIdx.x % (n2 + 1);
+    const int k1b = (blockIdx.x / (n2 + 1)) * a.chunk;
+    const int k1e = min(n1 + 1, k1b + a.chunk);
+    const int b = blockIdx.y;
+    const bool m2 = k2 > 0 && k2 < n2;
+
+    // ---- W_c(k2) = G_c x2 U2_c(k2, :) for the six components
+    if (!a.dense) {
+        for (int c = 0; c < 6; ++c) {
+            const int r1 = v.r[c][0], r2 = v.r[c][1], r3 = v.r[c][2];
+            const c2<T>* G = core + v.core_off[c];
+            const c2<T>* U2 = fac + v.fac_off[c][1] + (long)k2 * r2;
+            for (int e = tid; e < r1 * r3; e += NT) {
+                int al = e / r3, ga = e - al * r3;
+                c2<T> acc = mk<T>(0, 0);
+                for (int be = 0; be < r2; ++be) fma_c(acc, G[((long)al * r2 + be) * r3 + ga], U2[be]);
+                Wc[c * rmax * rmax + e] = acc;
+            }
+        }
+    }
+    __syncthreads();
+
+    for (int k1 = k1b; k1 < k1e; ++k1) {
+        const bool m1 = k1 > 0 && k1 < n1;
+        const bool exists = (s1 == 0 || m1) && (s2 == 0 || m2);
+        const int pk1 = s1 ? L1 - k1 : k1;
+        const int pk2 = s2 ? L2 - k2 : k2;
+
+        // ---- V_c = U1_c(k1, :) W_c
+        if (!a.dense) {
+            for (int e = tid; e < 6 * rmax; e += NT) {
+                int c = e / rmax, ga = e - c * rmax;
+                const int r1 = v.r[c][0], r3 = v.r[c][2];
+                if (ga < r3) {
+                    const c2<T>* U1 = fac + v.fac_off[c][0] + (long)k1 * r1;
+                    c2<T> acc = mk<T>(0, 0);
+                    for (int al = 0; al < r1; ++al) fma_c(acc, U1[al], Wc[c * rmax * rmax + al * r3 + ga]);
+                    Vc[e] = acc;
+                }
+            }
+        }
+
+        // ---- load the three components of my pencil (input layout of the
+        //      forward plan; positions >= n3 are the zero padding)
+        c2<T> d[3][E];
+        constexpr int R0 = Plan::RF0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const c2<T>* src = S2 + ((((long)b * 3 + q) * L2 + pk2) * L1 + pk1) * N3;
+#pragma unroll
+            for (int u = 0; u < E / R0; ++u)
+#pragma unroll
+                for (int r = 0; r < R0; ++r) {
+                    int pos = t + TPP * u + r * (L3 / R0);
+                    d[q][u * R0 + r] = (exists && r < R0 / 2) ? src[pos] : mk<T>(0, 0);
+                }
+        }
+        // ---- forward FFT of each component (LDS slice per pencil)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) Plan::template fwd<T, TPP, 1, -1>(d[q], X + pe * P, 0, t, tws);
+        __syncthreads();   // slices free, Vc complete
+
+        // ---- N^_c(k1, k2, k3), k3 in [0, n3], into the freed slices
+        if (!a.dense) {
+            for (int e = tid; e < 6 * (N3 + 1); e += NT) {
+                int c = e / (N3 + 1), kk = e - c * (N3 + 1);
+                const int r3 = v.r[c][2];
+                const c2<T>* U3 = fac + v.fac3t_off[c] + kk;
+                c2<T> acc = mk<T>(0, 0);
+                for (int ga = 0; ga < r3; ++ga) fma_c(acc, Vc[c * rmax + ga], U3[(long)ga * (N3 + 1)]);
+                NTt[e] = acc;
+            }
+        } else {
+            const long per = (long)(n1 + 1) * (n2 + 1) * (N3 + 1);
+            for (int e = tid; e < 6 * (N3 + 1); e += NT) {
+                int c = e / (N3 + 1), kk = e - c * (N3 + 1);
+                NTt[e] = dense[c * per + ((long)k2 * (n1 + 1) + k1) * (N3 + 1) + kk];
+            }
+        }
+        __syncthreads();   // NTt complete
+
+        // ---- 3x3 component product; output layout of the forward plan
+        constexpr int RL = Plan::RFL;
+#pragma unroll
+        for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int m = t + TPP * u + r * (L3 / RL);
+                const int f3 = m > N3;
+                const int kk = f3 ? L3 - m : m;
+                c2<T> Nc[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    c2<T> tv = NTt[c * (N3 + 1) + kk];
+                    if (zsign(c, s1 ? 1 : 0, s2 ? 1 : 0, f3) < 0) tv = mk<T>(-tv.x, -tv.y);
+                    Nc[c] = a.conj ? conj(tv) : tv;
+                }
+                const int i = u * RL + r;
+                c2<T> x0 = d[0][i], x1 = d[1][i], x2 = d[2][i];
+                d[0][i] = Nc[0] * x0 + Nc[3] * x1 + Nc[4] * x2;
+                d[1][i] = Nc[3] * x0 + Nc[1] * x1 + Nc[5] * x2;
+                d[2][i] = Nc[4] * x0 + Nc[5] * x1 + Nc[2] * x2;
+            }
+        __syncthreads();   // NTt consumed: the slices are reused by the inverse FFT
+
+        // ---- inverse FFT and cropped store (output layout of the inverse plan)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) Plan::template inv<T, TPP, 1, 1>(d[q], X + pe * P, 0, t, tws);
+        constexpr int RIL = Plan::RIL;
+        if (exists) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                c2<T>* dst = S2 + ((((long)b * 3 + q) * L2 + pk2) * L1 + pk1) * N3;
+#pragma unroll
+                for (int u = 0; u < E / RIL; ++u)
+#pragma unroll
+                    for (int r = 0; r < RIL / 2; ++r) dst[t + TPP * u + r * (L3 / RIL)] = d[q][u * RIL + r];
+            }
+        }
+        __syncthreads();   // Vc and the slices are reused by the next quad
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host dispatch
+
+template <typename T>
+static constexpr int xy_E()
+{
+    return sizeof(T) == 4 ? 32 : 16;
+}
+
+template <typename T, int L>
+static constexpr int xy_W()
+{
+    // 256 threads per block
+    return 256 / (L / xy_E<T>());
+}
+
+template <typename TV, typename T, int L, int KIND>
+static void launch_xy(const void* in, void* out, const c2<TV>* x, const c2<TV>* eps, const c2<T>* tw,
+                      const XYArgs& a, int grid_x, int grid_y, int nz, const int* rhs_map, hipStream_t s)
+{
+    constexpr int E = xy_E<T>();
+    constexpr int W = xy_W<T, L>();
+    constexpr int NT = W * (L / E);
+    size_t lds = sizeof(c2<T>) * ((size_t)W * PL<L>::value + L);
+    auto kern = k_xy_fast<TV, T, L, E, W, KIND>;
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, dim3((grid_x + W - 1) / W, grid_y, nz), dim3(NT), lds, s, in, out, x, eps, tw, a,
+                       rhs_map);
+}
+
+template <typename TV, typename T, int KIND>
+static bool dispatch_xy(int L, const void* in, void* out, const c2<TV>* x, const c2<TV>* eps, const c2<T>* tw,
+                        const XYArgs& a, int gx, int gy, int nz, const int* rhs_map, hipStream_t s)
+{
+    switch (L) {
+    case 512: launch_xy<TV, T, 512, KIND>(in, out, x, eps, tw, a, gx, gy, nz, rhs_map, s); return true;
+    case 256: launch_xy<TV, T, 256, KIND>(in, out, x, eps, tw, a, gx, gy, nz, rhs_map, s); return true;
+    case 128: launch_xy<TV, T, 128, KIND>(in, out, x, eps, tw, a, gx, gy, nz, rhs_map, s); return true;
+    default: return false;
+    }
+}
+
+template <typename T, int L3>
+static size_t zfast_lds(const OpView& v)
+{
+    static_assert(6 * (L3 / 2 + 1) <= 4 * PL<L3>::value, "N^ table must fit in the FFT slices");
+    return sizeof(c2<T>) * ((size_t)4 * PL<L3>::value + 6 * (size_t)v.rmax * v.rmax + 6 * v.rmax + L3);
+}
+
+template <typename T, int L3>
+static hipError_t launch_z(const DeviceOp& op, int mode, int nrhs, c2<T>* S2, const c2<T>* tw,
+                           const c2<T>* core, const c2<T>* fac, const c2<T>* dense, hipStream_t s)
+{
+    const OpView& v = op.view;
+    ZFastArgs za;
+    za.v = v;
+    za.conj = (mode == MODE_AH || mode == MODE_NH);
+    za.dense = op.nhat_source == 1;
+    za.chunk = 16;
+    int nchunk = (v.n[0] + 1 + za.chunk - 1) / za.chunk;
+    size_t lds = zfast_lds<T, L3>(v);
+    if (lds > op.max_lds) return hipErrorInvalidValue;
+    auto kern = k_z_fast<T, L3>;
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, dim3((v.n[1] + 1) * nchunk, nrhs), dim3(4 * (L3 / 8)), lds, s, S2, tw, za, core, fac,
+                       dense);
+    return hipGetLastError();
+}
+
+// Entry points used by launch_matvec (matvec.hip), one per pass; each
+// returns false when its FFT length has no register-FFT kernel.
+template <typename TV, typename T>
+bool xy_pass_fast(int kind, int L, const void* in, void* out, const c2<TV>* x, const c2<TV>* eps, const c2<T>* tw,
+                  int n1, int n2, int n3, int L1, int L2, int mode, int nrhs, const int* rhs_map, hipStream_t s)
+{
+    XYArgs a{n1, n2, n3, L1, L2, mode};
+    const int nz = nrhs * 3;
+    switch (kind) {
+    case 0: return dispatch_xy<TV, T, 0>(L, in, out, x, eps, tw, a, n2, n3, nz, rhs_map, s);
+    case 1: return dispatch_xy<TV, T, 1>(L, in, out, x, eps, tw, a, n3, L1, nz, rhs_map, s);
+    case 2: return dispatch_xy<TV, T, 2>(L, in, out, x, eps, tw, a, n3, L1, nz, rhs_map, s);
+    default: return dispatch_xy<TV, T, 3>(L, in, out, x, eps, tw, a, n2, n3, nz, rhs_map, s);
+    }
+}
+
+template <typename T>
+bool z_pass_fast(const DeviceOp& op, int mode, int nrhs, c2<T>* S2, const c2<T>* tw, const c2<T>* core,
+                 const c2<T>* fac, const c2<T>* dense, hipStream_t s)
+{
+    const OpView& v = op.view;
+    switch (v.L[2]) {
+    case 512:
+        if (zfast_lds<T, 512>(v) > op.max_lds) return false;
+        launch_z<T, 512>(op, mode, nrhs, S2, tw, core, fac, dense, s);
+        return true;
+    case 256:
+        if (zfast_lds<T, 256>(v) > op.max_lds) return false;
+        launch_z<T, 256>(op, mode, nrhs, S2, tw, core, fac, dense, s);
+        return true;
+    case 128:
+        if (zfast_lds<T, 128>(v) > op.max_lds) return false;
+        launch_z<T, 128>(op, mode, nrhs, S2, tw, core, fac, dense, s);
+        return true;
+    default: return false;
+    }
+}
+
+#define VIE_XYF_INST(TV, T)                                                                                        \
+    template bool xy_pass_fast<TV, T>(int, int, const void*, void*, const c2<TV>*, const c2<TV>*, const c2<T>*, int, \
+                                      int, int, int, int, int, int, const int*, hipStream_t);
+VIE_XYF_INST(float, float)
+VIE_XYF_INST(double, double)
+VIE_XYF_INST(double, float)
+template bool z_pass_fast<float>(const DeviceOp&, int, int, c2<float>*, const c2<float>*, const c2<float>*,
+                                 const c2<float>*, const c2<float>*, hipStream_t);
+template bool z_pass_fast<double>(const DeviceOp&, int, int, c2<double>*, const c2<double>*, const c2<double>*,
+                                  const c2<double>*, const c2<double>*, hipStream_t);
+
+}  // namespace vie

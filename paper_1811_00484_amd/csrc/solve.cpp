@@ -399,21 +399,79 @@ vie_status vie_solve(const vie_op* op, int dtype, const void* eps_c, const void*
                                info, (char*)ws, Lt, st);
 }
 
-vie_status vie_field_gradient(const vie_op* op, int dtype, const void* z, const void* E, void* g, void* stream)
+vie_status vie_field_gradient(const vie_op* op, int dtype, const void* z, const void* E, double omega_eps0,
+                              void* g_eps, void* g_sigma, void* stream)
 {
-    if (!op || !z || !E || !g) return fail(VIE_E_ARG, "vie_field_gradient: null argument");
+    if (!op || !z || !E || !g_eps || !g_sigma || !(omega_eps0 > 0))
+        return fail(VIE_E_ARG, "vie_field_gradient: bad argument");
     const OpView& v = op->d.view;
     long V = (long)v.n[0] * v.n[1] * v.n[2];
     hipError_t e;
     if (dtype == VIE_C128)
-        e = kr_field_gradient<double>((const c2<double>*)z, (const c2<double>*)E, (c2<double>*)g, V,
-                                      (hipStream_t)stream);
+        e = kr_field_gradient<double>((const c2<double>*)z, (const c2<double>*)E, (double*)g_eps, (double*)g_sigma,
+                                      omega_eps0, V, (hipStream_t)stream);
     else if (dtype == VIE_C64)
-        e = kr_field_gradient<float>((const c2<float>*)z, (const c2<float>*)E, (c2<float>*)g, V,
-                                     (hipStream_t)stream);
+        e = kr_field_gradient<float>((const c2<float>*)z, (const c2<float>*)E, (float*)g_eps, (float*)g_sigma,
+                                     omega_eps0, V, (hipStream_t)stream);
     else
         return fail(VIE_E_ARG, "vie_field_gradient: bad dtype");
     if (e != hipSuccess) return hip_fail(e, "vie_field_gradient");
+    return VIE_OK;
+}
+
+vie_status vie_problem_setup(const vie_op* op, int dtype, const void* eps_r, const void* sigma, const void* e_inc,
+                             double omega_eps0, void* eps_c, void* b, void* stream)
+{
+    if (!op || !eps_r || !sigma || !e_inc || !eps_c || !b || !(omega_eps0 > 0))
+        return fail(VIE_E_ARG, "vie_problem_setup: bad argument");
+    const OpView& v = op->d.view;
+    long V = (long)v.n[0] * v.n[1] * v.n[2];
+    hipError_t e;
+    if (dtype == VIE_C128)
+        e = kr_problem<double>((const double*)eps_r, (const double*)sigma, (const c2<double>*)e_inc,
+                               (c2<double>*)eps_c, (c2<double>*)b, omega_eps0, V, (hipStream_t)stream);
+    else if (dtype == VIE_C64)
+        e = kr_problem<float>((const float*)eps_r, (const float*)sigma, (const c2<float>*)e_inc, (c2<float>*)eps_c,
+                              (c2<float>*)b, omega_eps0, V, (hipStream_t)stream);
+    else
+        return fail(VIE_E_ARG, "vie_problem_setup: bad dtype");
+    if (e != hipSuccess) return hip_fail(e, "vie_problem_setup");
+    return VIE_OK;
+}
+
+vie_status vie_total_field(const vie_op* op, int dtype, const void* e_inc, const void* u, const void* Nu,
+                           double omega_eps0, void* E, void* stream)
+{
+    if (!op || !e_inc || !u || !Nu || !E || !(omega_eps0 > 0)) return fail(VIE_E_ARG, "vie_total_field: bad argument");
+    const OpView& v = op->d.view;
+    long n = 3L * v.n[0] * v.n[1] * v.n[2];
+    hipError_t e;
+    if (dtype == VIE_C128)
+        e = kr_total_field<double>((const c2<double>*)e_inc, (const c2<double>*)u, (const c2<double>*)Nu,
+                                   (c2<double>*)E, omega_eps0, n, (hipStream_t)stream);
+    else if (dtype == VIE_C64)
+        e = kr_total_field<float>((const c2<float>*)e_inc, (const c2<float>*)u, (const c2<float>*)Nu, (c2<float>*)E,
+                                  omega_eps0, n, (hipStream_t)stream);
+    else
+        return fail(VIE_E_ARG, "vie_total_field: bad dtype");
+    if (e != hipSuccess) return hip_fail(e, "vie_total_field");
+    return VIE_OK;
+}
+
+vie_status vie_adjoint_source(const vie_op* op, int dtype, const void* g, const void* NHg, void* t, void* stream)
+{
+    if (!op || !g || !NHg || !t) return fail(VIE_E_ARG, "vie_adjoint_source: bad argument");
+    const OpView& v = op->d.view;
+    long n = 3L * v.n[0] * v.n[1] * v.n[2];
+    hipError_t e;
+    if (dtype == VIE_C128)
+        e = kr_adjoint_source<double>((const c2<double>*)g, (const c2<double>*)NHg, (c2<double>*)t, n,
+                                      (hipStream_t)stream);
+    else if (dtype == VIE_C64)
+        e = kr_adjoint_source<float>((const c2<float>*)g, (const c2<float>*)NHg, (c2<float>*)t, n, (hipStream_t)stream);
+    else
+        return fail(VIE_E_ARG, "vie_adjoint_source: bad dtype");
+    if (e != hipSuccess) return hip_fail(e, "vie_adjoint_source");
     return VIE_OK;
 }
 

@@ -139,6 +139,11 @@ vie_status vie_compress(const int n[3], const double* green, const vie_compress_
             fac_tot += (n[a] + 1) * tc[c].r[a];
         }
     }
+    // z factors also stored transposed ([g][k3]) for coalesced pencil-wise reads
+    for (int c = 0; c < 6; ++c) {
+        v.fac3t_off[c] = fac_tot;
+        fac_tot += (n[2] + 1) * tc[c].r[2];
+    }
     v.rmax = rmax;
     if (rmax > 64) return fail(VIE_E_UNSUPPORTED, "vie_compress: Tucker rank above 64");
     const double invM = 1.0 / (8.0 * (double)V);
@@ -149,6 +154,11 @@ vie_status vie_compress(const int n[3], const double* green, const vie_compress_
             std::vector<cd> Uh;
             fourier_factor(tc[c].U[a], n[a], tc[c].r[a], odd[c][a] ? -1 : 1, Uh);
             std::copy(Uh.begin(), Uh.end(), hfac.begin() + v.fac_off[c][a]);
+            if (a == 2) {
+                const int r3 = tc[c].r[2];
+                for (int k = 0; k <= n[2]; ++k)
+                    for (int g = 0; g < r3; ++g) hfac[v.fac3t_off[c] + (size_t)g * (n[2] + 1) + k] = Uh[(size_t)k * r3 + g];
+            }
         }
     }
     // device upload
@@ -401,6 +411,13 @@ vie_status vie_profile_collect(double ms[5], int counts[5])
     if (!ms || !counts) return fail(VIE_E_ARG, "vie_profile_collect: null argument");
     int bad = prof_collect(ms, counts, 5);
     if (bad) return fail(VIE_E_HIP, "vie_profile_collect: event query failed");
+    return VIE_OK;
+}
+
+vie_status vie_set_kernel_path(int path)
+{
+    if (path != 0 && path != 1) return fail(VIE_E_ARG, "vie_set_kernel_path: 0 or 1");
+    g_kernel_path = path;
     return VIE_OK;
 }
 

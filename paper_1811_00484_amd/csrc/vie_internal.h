@@ -11,7 +11,9 @@ namespace vie {
 
 // Device view of the compressed operator (passed to kernels by value).
 // Fourier factors of component c along axis a: rows 0..n_a of the DFT of the
-// embedded factor columns, row-major (n_a + 1) x r_a, at fac + fac_off[c][a].
+// embedded factor columns, row-major (n_a + 1) x r_a, at fac + fac_off[c][a];
+// the z factor again column-major ((n3 + 1) contiguous per column) at
+// fac + fac3t_off[c].
 // Cores: [r1][r2][r3] (r3 fastest) at core + core_off[c], scaled by
 // 1 / (8 n1 n2 n3) so the inverse FFTs can stay unnormalised.
 struct OpView {
@@ -20,6 +22,7 @@ struct OpView {
     int r[6][3];
     int core_off[6];
     int fac_off[6][3];
+    int fac3t_off[6];   // z factor transposed: [r3][n3 + 1]
     int rmax;
 };
 
@@ -71,6 +74,16 @@ hipError_t launch_nhat_samples(const DeviceOp& op, int prec, const int* idx_dev,
 hipError_t launch_densify(DeviceOp& op, int with_c128, hipStream_t s);
 
 size_t matvec_ws_elems(const DeviceOp& op, int nrhs);   // complex elements per workspace
+
+// register-FFT variants of the passes (matvec_fast.hip); false = not available
+template <typename TV, typename T>
+bool xy_pass_fast(int kind, int L, const void* in, void* out, const c2<TV>* x, const c2<TV>* eps, const c2<T>* tw,
+                  int n1, int n2, int n3, int L1, int L2, int mode, int nrhs, const int* rhs_map, hipStream_t s);
+template <typename T>
+bool z_pass_fast(const DeviceOp& op, int mode, int nrhs, c2<T>* S2, const c2<T>* tw, const c2<T>* core,
+                 const c2<T>* fac, const c2<T>* dense, hipStream_t s);
+// 0 = choose per pass (register FFT where the length allows), 1 = generic kernels only
+extern int g_kernel_path;
 
 // per-pass event timing (passes 0..4 = X+, Y+, Z*, Y-, X-)
 void prof_enable(int on);

@@ -77,12 +77,16 @@ _SIGS = {
     "vie_solve_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SolveOpts)]),
     "vie_solve": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int, ctypes.POINTER(SolveOpts),
                                  ctypes.POINTER(SolveInfo), _P, ctypes.c_size_t, _P]),
-    "vie_field_gradient": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
+    "vie_field_gradient": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_double, _P, _P, _P]),
+    "vie_problem_setup": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_double, _P, _P, _P]),
+    "vie_total_field": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_double, _P, _P]),
+    "vie_adjoint_source": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
     "vie_debug_nhat": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int, _P]),
     "vie_debug_hosvd": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.c_double, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_int), _P, _P, ctypes.POINTER(ctypes.c_double)]),
     "vie_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "vie_profile_collect": (ctypes.c_int, [_P, _P]),
+    "vie_set_kernel_path": (ctypes.c_int, [ctypes.c_int]),
     "vie_last_error": (ctypes.c_char_p, []),
     "vie_version": (ctypes.c_char_p, []),
 }
@@ -250,14 +254,66 @@ def solve(op, b, eps_c, x0=None, tol=1e-6, restart=50, max_outer=200, adjoint=Fa
     return (x[0] if squeeze else x), out, st
 
 
-def field_gradient(op, z, E):
-    """g = sum_q conj(z_q) E_q per voxel (z, E of shape (3, n3, n2, n1))."""
-    lib = load()
-    if z.shape != E.shape or z.dtype != E.dtype or z.dim() != 4:
-        raise ValueError("z and E must both be (3, n3, n2, n1) of one dtype")
-    g = torch.empty(z.shape[1:], dtype=z.dtype, device=z.device)
-    _check(lib.vie_field_gradient(op.handle, _dt(z), _ptr(z), _ptr(E), _ptr(g), _stream()), "vie_field_gradient")
-    return g
+EPS0 = 8.8541878128e-12
+
+
+def _oe0(freq_hz):
+    return 2.0 * np.pi * float(freq_hz) * EPS0
+
+
+def _vec3(t, op, name):
+    n1, n2, n3 = op.n
+    if tuple(t.shape) != (3, n3, n2, n1) or not t.is_contiguous():
+        raise ValueError("%s must be contiguous (3, %d, %d, %d)" % (name, n3, n2, n1))
+    return t
+
+
+def problem_setup(op, eps_r, sigma, e_inc, freq_hz):
+    """eps_c = eps_r - i sigma/(omega eps0) and b = i omega eps0 (eps_c - 1) e_inc
+    (real maps float32/float64 matching complex64/complex128 e_inc)."""
+    _vec3(e_inc, op, "e_inc")
+    rdt = torch.float32 if e_inc.dtype == torch.complex64 else torch.float64
+    if eps_r.dtype != rdt or sigma.dtype != rdt or not eps_r.is_contiguous() or not sigma.is_contiguous():
+        raise ValueError("eps_r and sigma must be contiguous %s" % rdt)
+    eps_c = torch.empty(e_inc.shape[1:], dtype=e_inc.dtype, device=e_inc.device)
+    b = torch.empty_like(e_inc)
+    _check(load().vie_problem_setup(op.handle, _dt(e_inc), _ptr(eps_r), _ptr(sigma), _ptr(e_inc), _oe0(freq_hz),
+                                    _ptr(eps_c), _ptr(b), _stream()), "vie_problem_setup")
+    return eps_c, b
+
+
+def total_field(op, e_inc, u, Nu, freq_hz):
+    """E = e_inc + (N u - u) / (i omega eps0)."""
+    for t, nm in ((e_inc, "e_inc"), (u, "u"), (Nu, "Nu")):
+        _vec3(t, op, nm)
+    E = torch.empty_like(u)
+    _check(load().vie_total_field(op.handle, _dt(u), _ptr(e_inc), _ptr(u), _ptr(Nu), _oe0(freq_hz), _ptr(E),
+                                  _stream()), "vie_total_field")
+    return E
+
+
+def adjoint_source(op, g, NHg):
+    """t = N^H g - g."""
+    _vec3(g, op, "g")
+    _vec3(NHg, op, "NHg")
+    t = torch.empty_like(g)
+    _check(load().vie_adjoint_source(op.handle, _dt(g), _ptr(g), _ptr(NHg), _ptr(t), _stream()),
+           "vie_adjoint_source")
+    return t
+
+
+def field_gradient(op, z, E, freq_hz):
+    """(dL/d eps_r, dL/d sigma) per voxel from the adjoint field z and the total field E."""
+    _vec3(z, op, "z")
+    _vec3(E, op, "E")
+    if z.dtype != E.dtype:
+        raise ValueError("z and E must share a dtype")
+    rdt = torch.float32 if z.dtype == torch.complex64 else torch.float64
+    ge = torch.empty(z.shape[1:], dtype=rdt, device=z.device)
+    gs = torch.empty_like(ge)
+    _check(load().vie_field_gradient(op.handle, _dt(z), _ptr(z), _ptr(E), _oe0(freq_hz), _ptr(ge), _ptr(gs),
+                                     _stream()), "vie_field_gradient")
+    return ge, gs
 
 
 def densify(op, with_c128=False):
@@ -310,6 +366,11 @@ def profile_collect():
     _check(load().vie_profile_collect(ctypes.cast(ms, ctypes.c_void_p), ctypes.cast(cnt, ctypes.c_void_p)),
            "vie_profile_collect")
     return list(ms), list(cnt)
+
+
+def set_kernel_path(path):
+    """0 = default kernel choice, 1 = mixed-radix LDS kernels only."""
+    _check(load().vie_set_kernel_path(int(path)), "vie_set_kernel_path")
 
 
 def exported_symbols():

@@ -42,3 +42,10 @@ def to_dev(a, dtype):
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@functools.lru_cache(maxsize=8)
+def library_operator(n, h=0.005, tol=1e-6, phantom="sphere", seed=2):
+    from paper_1811_00484_amd import vie
+    G, _, _ = problem(n, h, tol, phantom, seed)
+    return vie.compress(G, tol=tol)
