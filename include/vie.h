@@ -202,6 +202,45 @@ vie_status vie_solve(const vie_op* op, int dtype, const void* eps_c, const void*
                      size_t ws_bytes, void* stream);
 
 /*
+ * Batches of several grids (instances) of uneven size: every pass of the
+ * matvec runs as ONE launch over all instances' tiles (the work of each
+ * block is looked up in a device table of instances).  Each instance has its
+ * own operator, eps_c, vectors and right-hand-side count.
+ */
+typedef struct {
+    const vie_op* op;     /* operator of this instance's grid */
+    const void* eps_c;    /* DEVICE [n3][n2][n1] complex (dtype); may be NULL for VIE_OP_N */
+    const void* x;        /* DEVICE [nrhs][3][n3][n2][n1] */
+    void* y;              /* DEVICE, same shape, no overlap with x */
+    int nrhs;
+} vie_instance;
+
+/* Workspace (bytes) of vie_matvec_multi for this batch. */
+size_t vie_matvec_multi_workspace_bytes(const vie_instance* inst, int count, int dtype);
+/* y = A x (kind VIE_OP_A) or N x (VIE_OP_N), or their adjoints (adjoint = 1),
+ * for every instance; asynchronous on `stream`.  Mixed-radix kernels, any
+ * supported grid per instance; Tucker operators only. */
+vie_status vie_matvec_multi(const vie_instance* inst, int count, int kind, int adjoint, int dtype, void* ws,
+                            size_t ws_bytes, void* stream);
+
+typedef struct {
+    const vie_op* op;
+    const void* eps_c;      /* DEVICE [n3][n2][n1] complex (dtype) */
+    const void* b;          /* DEVICE [nrhs][3][n3][n2][n1] */
+    void* x;                /* DEVICE, same shape: initial guess in, solution out */
+    int nrhs;
+    vie_solve_info* info;   /* HOST array of nrhs, may be NULL */
+} vie_solve_instance;
+
+/* Workspace (bytes) of vie_solve_multi. */
+size_t vie_solve_multi_workspace_bytes(const vie_solve_instance* inst, int count, int dtype, const vie_solve_opts* opts);
+/* GMRES on every system of every instance in lockstep (as vie_solve): each
+ * Arnoldi step issues one multi-instance matvec for all unconverged systems.
+ * Returns VIE_OK if every system converged, else VIE_NOT_CONVERGED. */
+vie_status vie_solve_multi(const vie_solve_instance* inst, int count, int dtype, const vie_solve_opts* opts, void* ws,
+                           size_t ws_bytes, void* stream);
+
+/*
  * Helpers of the differentiable forward model (voxel-wise, asynchronous on
  * `stream`; dtype VIE_C64 with float real maps or VIE_C128 with double).
  * omega_eps0 = 2 pi f eps0 > 0.

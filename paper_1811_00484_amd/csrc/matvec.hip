@@ -30,6 +30,7 @@
 // dense is stored).
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <cstdio>
 
 #include "fft_device.h"
@@ -58,17 +59,17 @@ __device__ __forceinline__ void load_tw(c2<T>* dst, const c2<T>* src, int L, int
 
 // ------------------------------- pass X+ --------------------------------
 template <typename TV, typename T, int W, int MAXE>
-__global__ void __launch_bounds__(NT) k_xfwd(const c2<TV>* __restrict__ x, const c2<TV>* __restrict__ eps,
+__device__ __forceinline__ void xfwd_body(const c2<TV>* __restrict__ x, const c2<TV>* __restrict__ eps,
                                              c2<T>* __restrict__ S1, FftPlan pl, const c2<T>* __restrict__ tw,
-                                             int n1, int n2, int n3, int mode, const int* __restrict__ rhs_map)
+                                             int n1, int n2, int n3, int mode, const int* __restrict__ rhs_map, int bx, int by, int bz)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T>* buf = reinterpret_cast<c2<T>*>(smem_raw);
     const int L1 = pl.L;
     c2<T>* tws = buf + (size_t)L1 * (W + 1);
     const int tid = threadIdx.x;
-    const int j0 = blockIdx.x * W, k = blockIdx.y;
-    const int zq = blockIdx.z;               // launch rhs * 3 + q
+    const int j0 = bx * W, k = by;
+    const int zq = bz;               // launch rhs * 3 + q
     const int q = zq % 3, bl = zq / 3;
     const int b = rhs_map ? rhs_map[bl] : bl;
     const long bq = (long)b * 3 + q;
@@ -106,16 +107,16 @@ __global__ void __launch_bounds__(NT) k_xfwd(const c2<TV>* __restrict__ x, const
 
 // ------------------------------- pass Y+ --------------------------------
 template <typename T, int W, int MAXE>
-__global__ void __launch_bounds__(NT) k_yfwd(const c2<T>* __restrict__ S1, c2<T>* __restrict__ S2, FftPlan pl,
-                                             const c2<T>* __restrict__ tw, int L1, int n2, int n3)
+__device__ __forceinline__ void yfwd_body(const c2<T>* __restrict__ S1, c2<T>* __restrict__ S2, FftPlan pl,
+                                             const c2<T>* __restrict__ tw, int L1, int n2, int n3, int bx, int by, int bz)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T>* buf = reinterpret_cast<c2<T>*>(smem_raw);
     const int L2 = pl.L;
     c2<T>* tws = buf + (size_t)L2 * (W + 1);
     const int tid = threadIdx.x;
-    const int k0 = blockIdx.x * W, i = blockIdx.y;
-    const long bq = blockIdx.z;
+    const int k0 = bx * W, i = by;
+    const long bq = bz;
     load_tw(tws, tw, L2, tid);
     for (int e = tid; e < W * n2; e += NT) {
         int w = e / n2, j = e - w * n2;
@@ -139,16 +140,16 @@ __global__ void __launch_bounds__(NT) k_yfwd(const c2<T>* __restrict__ S1, c2<T>
 
 // ------------------------------- pass Y- --------------------------------
 template <typename T, int W, int MAXE>
-__global__ void __launch_bounds__(NT) k_yinv(const c2<T>* __restrict__ S2, c2<T>* __restrict__ S3, FftPlan pl,
-                                             const c2<T>* __restrict__ tw, int L1, int n2, int n3)
+__device__ __forceinline__ void yinv_body(const c2<T>* __restrict__ S2, c2<T>* __restrict__ S3, FftPlan pl,
+                                             const c2<T>* __restrict__ tw, int L1, int n2, int n3, int bx, int by, int bz)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T>* buf = reinterpret_cast<c2<T>*>(smem_raw);
     const int L2 = pl.L;
     c2<T>* tws = buf + (size_t)L2 * (W + 1);
     const int tid = threadIdx.x;
-    const int k0 = blockIdx.x * W, i = blockIdx.y;
-    const long bq = blockIdx.z;
+    const int k0 = bx * W, i = by;
+    const long bq = bz;
     load_tw(tws, tw, L2, tid);
     for (int e = tid; e < W * L2; e += NT) {
         int w = e % W, j = e / W;
@@ -168,18 +169,18 @@ __global__ void __launch_bounds__(NT) k_yinv(const c2<T>* __restrict__ S2, c2<T>
 
 // ------------------------------- pass X- --------------------------------
 template <typename TV, typename T, int W, int MAXE>
-__global__ void __launch_bounds__(NT) k_xinv(const c2<T>* __restrict__ S3, const c2<TV>* __restrict__ x,
+__device__ __forceinline__ void xinv_body(const c2<T>* __restrict__ S3, const c2<TV>* __restrict__ x,
                                              const c2<TV>* __restrict__ eps, c2<TV>* __restrict__ y, FftPlan pl,
                                              const c2<T>* __restrict__ tw, int n1, int n2, int n3, int mode,
-                                             const int* __restrict__ rhs_map)
+                                             const int* __restrict__ rhs_map, int bx, int by, int bz)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T>* buf = reinterpret_cast<c2<T>*>(smem_raw);
     const int L1 = pl.L;
     c2<T>* tws = buf + (size_t)L1 * (W + 1);
     const int tid = threadIdx.x;
-    const int j0 = blockIdx.x * W, k = blockIdx.y;
-    const int zq = blockIdx.z;
+    const int j0 = bx * W, k = by;
+    const int zq = bz;
     const int q = zq % 3, bl = zq / 3;
     const int b = rhs_map ? rhs_map[bl] : bl;
     const long bq_in = (long)bl * 3 + q;
@@ -235,9 +236,9 @@ struct ZFactors {
 };
 
 template <typename T, int MAXE>
-__global__ void __launch_bounds__(NT) k_zmid(c2<T>* __restrict__ S2, FftPlan pl, const c2<T>* __restrict__ tw,
+__device__ __forceinline__ void zmid_body(c2<T>* __restrict__ S2, FftPlan pl, const c2<T>* __restrict__ tw,
                                              ZArgs a, const c2<T>* __restrict__ core,
-                                             const c2<T>* __restrict__ fac, const c2<T>* __restrict__ dense)
+                                             const c2<T>* __restrict__ fac, const c2<T>* __restrict__ dense, int bx, int by, int bz)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const OpView& v = a.v;
@@ -250,7 +251,7 @@ __global__ void __launch_bounds__(NT) k_zmid(c2<T>* __restrict__ S2, FftPlan pl,
     int P = 0;
     int pk1[4], pk2[4], pf1[4], pf2[4];
     {
-        int bidx = blockIdx.x;
+        int bidx = bx;
         if (a.G == 4) {
             k1 = bidx % (n1 + 1);
             k2 = bidx / (n1 + 1);
@@ -278,7 +279,7 @@ __global__ void __launch_bounds__(NT) k_zmid(c2<T>* __restrict__ S2, FftPlan pl,
                 ++P;
             }
     }
-    const int b = blockIdx.y;
+    const int b = by;
 
     // ---- LDS carve-up
     c2<T>* X = reinterpret_cast<c2<T>*>(smem_raw);           // [3*P][L3]
@@ -368,6 +369,118 @@ __global__ void __launch_bounds__(NT) k_zmid(c2<T>* __restrict__ S2, FftPlan pl,
         int q = s / P, pe = s - q * P;
         S2[((((long)b * 3 + q) * L2 + pk2[pe]) * L1 + pk1[pe]) * n3 + m] = X[s * L3 + m];
     }
+}
+
+// ----------------------- single-instance kernels --------------------------
+template <typename TV, typename T, int W, int MAXE>
+__global__ void __launch_bounds__(NT) k_xfwd(const c2<TV>* __restrict__ x, const c2<TV>* __restrict__ eps,
+                                             c2<T>* __restrict__ S1, FftPlan pl, const c2<T>* __restrict__ tw,
+                                             int n1, int n2, int n3, int mode, const int* __restrict__ rhs_map)
+{
+    xfwd_body<TV, T, W, MAXE>(x, eps, S1, pl, tw, n1, n2, n3, mode, rhs_map, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <typename T, int W, int MAXE>
+__global__ void __launch_bounds__(NT) k_yfwd(const c2<T>* __restrict__ S1, c2<T>* __restrict__ S2, FftPlan pl,
+                                             const c2<T>* __restrict__ tw, int L1, int n2, int n3)
+{
+    yfwd_body<T, W, MAXE>(S1, S2, pl, tw, L1, n2, n3, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <typename T, int W, int MAXE>
+__global__ void __launch_bounds__(NT) k_yinv(const c2<T>* __restrict__ S2, c2<T>* __restrict__ S3, FftPlan pl,
+                                             const c2<T>* __restrict__ tw, int L1, int n2, int n3)
+{
+    yinv_body<T, W, MAXE>(S2, S3, pl, tw, L1, n2, n3, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <typename TV, typename T, int W, int MAXE>
+__global__ void __launch_bounds__(NT) k_xinv(const c2<T>* __restrict__ S3, const c2<TV>* __restrict__ x,
+                                             const c2<TV>* __restrict__ eps, c2<TV>* __restrict__ y, FftPlan pl,
+                                             const c2<T>* __restrict__ tw, int n1, int n2, int n3, int mode,
+                                             const int* __restrict__ rhs_map)
+{
+    xinv_body<TV, T, W, MAXE>(S3, x, eps, y, pl, tw, n1, n2, n3, mode, rhs_map, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <typename T, int MAXE>
+__global__ void __launch_bounds__(NT) k_zmid(c2<T>* __restrict__ S2, FftPlan pl, const c2<T>* __restrict__ tw,
+                                             ZArgs a, const c2<T>* __restrict__ core,
+                                             const c2<T>* __restrict__ fac, const c2<T>* __restrict__ dense)
+{
+    zmid_body<T, MAXE>(S2, pl, tw, a, core, fac, dense, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// ------------------------ multi-instance kernels ---------------------------
+// One launch per pass covers every instance of a batch (grids of different
+// sizes): block b belongs to the instance whose [off, off + cnt) range holds
+// it and is decoded into that instance's tile coordinates.
+__device__ __forceinline__ int find_inst(const InstDev* __restrict__ tab, int count, int pass, int b)
+{
+    int i = 0;
+    while (i + 1 < count && b >= tab[i + 1].off[pass]) ++i;
+    return i;
+}
+
+template <typename TV, typename T, int W, int MAXE>
+__global__ void __launch_bounds__(NT) k_xfwd_multi(const InstDev* __restrict__ tab, int count, int mode)
+{
+    const InstDev& I = tab[find_inst(tab, count, 0, blockIdx.x)];
+    const int t = blockIdx.x - I.off[0];
+    const int n1 = I.v.n[0], n2 = I.v.n[1], n3 = I.v.n[2];
+    const int gx = (n2 + W - 1) / W;
+    xfwd_body<TV, T, W, MAXE>((const c2<TV>*)I.x, (const c2<TV>*)I.eps, (c2<T>*)I.S1, I.plan[0],
+                              (const c2<T>*)I.tw[0], n1, n2, n3, mode, I.map, t % gx, (t / gx) % n3,
+                              t / (gx * n3));
+}
+
+template <typename T, int W, int MAXE>
+__global__ void __launch_bounds__(NT) k_yfwd_multi(const InstDev* __restrict__ tab, int count)
+{
+    const InstDev& I = tab[find_inst(tab, count, 1, blockIdx.x)];
+    const int t = blockIdx.x - I.off[1];
+    const int n2 = I.v.n[1], n3 = I.v.n[2], L1 = I.v.L[0];
+    const int gx = (n3 + W - 1) / W;
+    yfwd_body<T, W, MAXE>((const c2<T>*)I.S1, (c2<T>*)I.S2, I.plan[1], (const c2<T>*)I.tw[1], L1, n2, n3, t % gx,
+                          (t / gx) % L1, t / (gx * L1));
+}
+
+template <typename T, int MAXE>
+__global__ void __launch_bounds__(NT) k_zmid_multi(const InstDev* __restrict__ tab, int count, int conj)
+{
+    const InstDev& I = tab[find_inst(tab, count, 2, blockIdx.x)];
+    const int t = blockIdx.x - I.off[2];
+    ZArgs za;
+    za.v = I.v;
+    za.G = I.G;
+    za.conj = conj;
+    za.dense = 0;
+    const int nblk = I.cnt[2] / I.nact;
+    zmid_body<T, MAXE>((c2<T>*)I.S2, I.plan[2], (const c2<T>*)I.tw[2], za, (const c2<T>*)I.core,
+                       (const c2<T>*)I.fac, nullptr, t % nblk, t / nblk, 0);
+}
+
+template <typename T, int W, int MAXE>
+__global__ void __launch_bounds__(NT) k_yinv_multi(const InstDev* __restrict__ tab, int count)
+{
+    const InstDev& I = tab[find_inst(tab, count, 3, blockIdx.x)];
+    const int t = blockIdx.x - I.off[3];
+    const int n2 = I.v.n[1], n3 = I.v.n[2], L1 = I.v.L[0];
+    const int gx = (n3 + W - 1) / W;
+    yinv_body<T, W, MAXE>((const c2<T>*)I.S2, (c2<T>*)I.S1, I.plan[1], (const c2<T>*)I.tw[1], L1, n2, n3, t % gx,
+                          (t / gx) % L1, t / (gx * L1));
+}
+
+template <typename TV, typename T, int W, int MAXE>
+__global__ void __launch_bounds__(NT) k_xinv_multi(const InstDev* __restrict__ tab, int count, int mode)
+{
+    const InstDev& I = tab[find_inst(tab, count, 4, blockIdx.x)];
+    const int t = blockIdx.x - I.off[4];
+    const int n1 = I.v.n[0], n2 = I.v.n[1], n3 = I.v.n[2];
+    const int gx = (n2 + W - 1) / W;
+    xinv_body<TV, T, W, MAXE>((const c2<T>*)I.S1, (const c2<TV>*)I.x, (const c2<TV>*)I.eps, (c2<TV>*)I.y,
+                              I.plan[0], (const c2<T>*)I.tw[0], n1, n2, n3, mode, I.map, t % gx, (t / gx) % n3,
+                              t / (gx * n3));
 }
 
 // ------------------------------- host side ------------------------------
@@ -614,6 +727,115 @@ template hipError_t launch_matvec<double, double>(const DeviceOp&, int, int, con
 template hipError_t launch_matvec<double, float>(const DeviceOp&, int, int, const c2<double>*,
                                                  const c2<double>*, c2<double>*, int, c2<float>*, hipStream_t,
                                                  const int*, std::string&);
+
+// ----------------------- multi-instance launcher ------------------------
+template <typename TV, typename T>
+hipError_t launch_matvec_multi(const std::vector<InstHost>& inst, int mode, InstDev* tab_dev, hipStream_t s,
+                               std::string& err)
+{
+    constexpr int MAXE_XY = 32;
+    constexpr int MAXE_Z = 24;
+    const int count = (int)inst.size();
+    // common tile width and z group: the most restrictive instance decides
+    size_t max_lds = SIZE_MAX;
+    int maxL = 1, maxL3 = 1;
+    for (auto& h : inst) {
+        max_lds = std::min(max_lds, h.op->max_lds);
+        maxL = std::max(maxL, std::max(h.op->view.L[0], h.op->view.L[1]));
+        maxL3 = std::max(maxL3, h.op->view.L[2]);
+    }
+    int W = tile_width<T>(max_lds, maxL);
+    if ((size_t)W * maxL > (size_t)MAXE_XY * NT) { err = "length too large"; return hipErrorInvalidValue; }
+    std::vector<InstDev> tab(count);
+    int G = 4;
+    for (int i = 0; i < count; ++i)
+        while (G > 1 && z_lds_bytes<T>(inst[i].op->view, G) > max_lds) G /= 2;
+    size_t lds_z = 0;
+    for (int i = 0; i < count; ++i) lds_z = std::max(lds_z, z_lds_bytes<T>(inst[i].op->view, G));
+    if (lds_z > max_lds || (size_t)3 * G * maxL3 > (size_t)MAXE_Z * NT) { err = "z pass does not fit"; return hipErrorInvalidValue; }
+    int off[5] = {0, 0, 0, 0, 0};
+    for (int i = 0; i < count; ++i) {
+        const DeviceOp& op = *inst[i].op;
+        const OpView& v = op.view;
+        InstDev& d = tab[i];
+        d.v = v;
+        for (int a = 0; a < 3; ++a) {
+            d.plan[a] = op.plan[a];
+            d.tw[a] = sizeof(T) == 8 ? (const void*)op.tw64[a] : (const void*)op.tw32[a];
+        }
+        d.core = sizeof(T) == 8 ? (const void*)op.d64.core : (const void*)op.d32.core;
+        d.fac = sizeof(T) == 8 ? (const void*)op.d64.fac : (const void*)op.d32.fac;
+        d.x = inst[i].x;
+        d.y = inst[i].y;
+        d.eps = inst[i].eps;
+        d.map = inst[i].map;
+        d.nact = inst[i].nact;
+        d.S2 = inst[i].ws;
+        d.S1 = (char*)inst[i].ws + sizeof(c2<T>) * (size_t)3 * v.L[1] * v.L[0] * v.n[2] * inst[i].nact;
+        d.G = G;
+        const int n1 = v.n[0], n2 = v.n[1], n3 = v.n[2], L1 = v.L[0], L2 = v.L[1];
+        const int nz = inst[i].nact * 3;
+        d.cnt[0] = ((n2 + W - 1) / W) * n3 * nz;
+        d.cnt[1] = ((n3 + W - 1) / W) * L1 * nz;
+        d.cnt[2] = (G == 4 ? (n1 + 1) * (n2 + 1) : (G == 2 ? (n1 + 1) * L2 : L1 * L2)) * inst[i].nact;
+        d.cnt[3] = d.cnt[1];
+        d.cnt[4] = d.cnt[0];
+        for (int p = 0; p < 5; ++p) {
+            d.off[p] = off[p];
+            off[p] += d.cnt[p];
+        }
+    }
+    hipError_t e = hipMemcpyAsync(tab_dev, tab.data(), sizeof(InstDev) * count, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    size_t lds_xy = (size_t)(W + 1) * maxL * sizeof(c2<T>) + (size_t)maxL * sizeof(c2<T>);
+    const int conj = (mode == MODE_AH || mode == MODE_NH);
+    {
+        PassTimer timer(0, s);
+        VIE_W_DISPATCH(W, {
+            auto kern = k_xfwd_multi<TV, T, Wc, MAXE_XY>;
+            (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_xy);
+            hipLaunchKernelGGL(kern, dim3(off[0]), dim3(NT), lds_xy, s, tab_dev, count, mode);
+        });
+    }
+    {
+        PassTimer timer(1, s);
+        VIE_W_DISPATCH(W, {
+            auto kern = k_yfwd_multi<T, Wc, MAXE_XY>;
+            (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_xy);
+            hipLaunchKernelGGL(kern, dim3(off[1]), dim3(NT), lds_xy, s, tab_dev, count);
+        });
+    }
+    {
+        PassTimer timer(2, s);
+        auto kern = k_zmid_multi<T, MAXE_Z>;
+        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_z);
+        hipLaunchKernelGGL(kern, dim3(off[2]), dim3(NT), lds_z, s, tab_dev, count, conj);
+    }
+    {
+        PassTimer timer(3, s);
+        VIE_W_DISPATCH(W, {
+            auto kern = k_yinv_multi<T, Wc, MAXE_XY>;
+            (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_xy);
+            hipLaunchKernelGGL(kern, dim3(off[3]), dim3(NT), lds_xy, s, tab_dev, count);
+        });
+    }
+    {
+        PassTimer timer(4, s);
+        VIE_W_DISPATCH(W, {
+            auto kern = k_xinv_multi<TV, T, Wc, MAXE_XY>;
+            (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_xy);
+            hipLaunchKernelGGL(kern, dim3(off[4]), dim3(NT), lds_xy, s, tab_dev, count, mode);
+        });
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_matvec_multi<float, float>(const std::vector<InstHost>&, int, InstDev*, hipStream_t,
+                                                      std::string&);
+template hipError_t launch_matvec_multi<double, double>(const std::vector<InstHost>&, int, InstDev*, hipStream_t,
+                                                        std::string&);
+template hipError_t launch_matvec_multi<double, float>(const std::vector<InstHost>&, int, InstDev*, hipStream_t,
+                                                       std::string&);
 
 // ----------------------- sampled N^ (tests) ------------------------------
 template <typename T>

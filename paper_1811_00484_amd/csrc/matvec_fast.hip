@@ -156,6 +156,7 @@ __global__ void __launch_bounds__(W*(L / E)) k_xy_fast(const void* __restrict__ 
                 }
                 v[u * R0 + r] = val;
             }
+        __syncthreads();   // twiddle table complete (the FFT stages sync per wavefront only)
         Plan::template fwd<T, TPP, 1, -1>(v, slice, 0, t, tws);
         reg_store<L, TPP, Plan::RFL, L / Plan::RFL>(v, slice, t);
         __syncthreads();
@@ -170,21 +171,32 @@ __global__ void __launch_bounds__(W*(L / E)) k_xy_fast(const void* __restrict__ 
             else S[((bqc * L2 + m) * L1 + row) * n3 + p] = val;
         }
     } else {
-        // ---- transposed input: element m of pencil ww at [m][p0 + ww]
-        for (int e = tid; e < W * L; e += NT) {
-            int ww = e % W, m = e / W;
-            int p = p0 + ww;
-            c2<T> val = mk<T>(0, 0);
-            if (p < npen) {
-                const c2<T>* S = reinterpret_cast<const c2<T>*>(in_);
-                if (KIND == 2) val = S[((bqc * L2 + m) * L1 + row) * n3 + p];
-                else val = S[((bqc * n3 + row) * L1 + m) * n2 + p];
+        // ---- transposed input: element m of pencil ww at [m][p0 + ww];
+        //      all E loads of a thread are issued before the LDS writes
+        {
+            c2<T> tmp[E];
+            const c2<T>* S = reinterpret_cast<const c2<T>*>(in_);
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+                const int e = tid + u * NT;
+                const int ww = e % W, m = e / W;
+                const int p = p0 + ww;
+                c2<T> val = mk<T>(0, 0);
+                if (p < npen) {
+                    if (KIND == 2) val = S[((bqc * L2 + m) * L1 + row) * n3 + p];
+                    else val = S[((bqc * n3 + row) * L1 + m) * n2 + p];
+                }
+                tmp[u] = val;
             }
-            buf[ww * P + lds_pad(m)] = val;
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+                const int e = tid + u * NT;
+                buf[(e % W) * P + lds_pad(e / W)] = tmp[u];
+            }
         }
         __syncthreads();
         reg_load<L, TPP, Plan::RI0>(v, slice, t);
-        __syncthreads();
+        wave_sync();   // the slice is only rewritten by the lanes of this pencil's wavefront
         Plan::template inv<T, TPP, 1, 1>(v, slice, 0, t, tws);
         // ---- cropped rows straight from the registers of the last stage
         constexpr int RL = Plan::RIL;
@@ -234,17 +246,75 @@ __device__ __forceinline__ int zsign(int c, int f1, int f2, int f3)
     return ((odd1 & f1) ^ (odd2 & f2) ^ (odd3 & f3)) ? -1 : 1;
 }
 
+// Load the three components of a pencil into the input layout of the
+// forward plan (positions >= n3 are the zero padding).
+template <typename T, int L3, int TPP, int R0>
+__device__ __forceinline__ void z_load(c2<T> (&d)[3][8], const c2<T>* __restrict__ S2, long base, long cstride, int t,
+                                       bool exists)
+{
+    constexpr int E = 8;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int u = 0; u < E / R0; ++u)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                const int pos = t + TPP * u + r * (L3 / R0);
+                d[q][u * R0 + r] = (exists && r < R0 / 2) ? S2[base + q * cstride + pos] : mk<T>(0, 0);
+            }
+}
+
+// 3x3 component product in the output layout of the forward plan
+template <typename T, int L3, int TPP, int RL>
+__device__ __forceinline__ void z_product(c2<T> (&d)[3][8], const c2<T>* NTt, int t, int f1, int f2, int conj)
+{
+    constexpr int E = 8;
+    constexpr int N3 = L3 / 2;
+#pragma unroll
+    for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const int m = t + TPP * u + r * (L3 / RL);
+            const int f3 = m > N3;
+            const int kk = f3 ? L3 - m : m;
+            c2<T> Nc[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                c2<T> tv = NTt[c * (N3 + 1) + kk];
+                if (zsign(c, f1, f2, f3) < 0) tv = mk<T>(-tv.x, -tv.y);
+                Nc[c] = conj ? vie::conj(tv) : tv;
+            }
+            const int i = u * RL + r;
+            c2<T> x0 = d[0][i], x1 = d[1][i], x2 = d[2][i];
+            d[0][i] = Nc[0] * x0 + Nc[3] * x1 + Nc[4] * x2;
+            d[1][i] = Nc[3] * x0 + Nc[1] * x1 + Nc[5] * x2;
+            d[2][i] = Nc[4] * x0 + Nc[5] * x1 + Nc[2] * x2;
+        }
+}
+
+template <typename T, int L3, int TPP, int RIL>
+__device__ __forceinline__ void z_store(const c2<T> (&d)[3][8], c2<T>* __restrict__ S2, long base, long cstride, int t)
+{
+    constexpr int E = 8;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int u = 0; u < E / RIL; ++u)
+#pragma unroll
+            for (int r = 0; r < RIL / 2; ++r) S2[base + q * cstride + t + TPP * u + r * (L3 / RIL)] = d[q][u * RIL + r];
+}
+
 template <typename T, int L3>
 __global__ void __launch_bounds__(4 * (L3 / 8)) k_z_fast(c2<T>* __restrict__ S2, const c2<T>* __restrict__ tw,
                                                          ZFastArgs a, const c2<T>* __restrict__ core,
                                                          const c2<T>* __restrict__ fac,
                                                          const c2<T>* __restrict__ dense)
 {
-    constexpr int E = 8;
-    constexpr int TPP = L3 / E;
+    constexpr int TPP = L3 / 8;
     constexpr int NT = 4 * TPP;
     constexpr int P = PL<L3>::value;
     constexpr int N3 = L3 / 2;
+    constexpr int NTS = 6 * (N3 + 1);                            // N^ table entries per quad
     using Plan = Pow2Plan<L3>;
     const OpView& v = a.v;
     const int n1 = v.n[0], n2 = v.n[1];
@@ -255,13 +325,14 @@ __global__ void __launch_bounds__(4 * (L3 / 8)) k_z_fast(c2<T>* __restrict__ S2,
     const int s1 = pe & 1, s2 = pe >> 1;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    // X: per-pencil FFT transpose slices [4][P]; after the forward FFT the
-    // same region holds the quad's N^ table [6][N3+1] (6 (N3+1) <= 4 P)
+    // X: per-pencil FFT transpose slices [4][P]; after the forward FFT of the
+    // first quad of a pair the same region holds its N^ table, the second
+    // quad's table has a region of its own
     c2<T>* X = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* NTt = X;
-    c2<T>* Wc = X + 4 * P;                                      // [6][rmax*rmax]
-    c2<T>* Vc = Wc + 6 * rmax * rmax;                           // [6][rmax]
-    c2<T>* tws = Vc + 6 * rmax;                                 // [L3]
+    c2<T>* NTB = X + 4 * P;                                     // [6][N3+1]
+    c2<T>* Wc = NTB + NTS;                                      // [6][rmax*rmax]
+    c2<T>* Vc = Wc + 6 * rmax * rmax;                           // [2][6][rmax]
+    c2<T>* tws = Vc + 12 * rmax;                                // [L3]
     for (int m = tid; m < L3; m += NT) tws[m] = tw[m];
 
     const int k2 = blockIdx.x % (n2 + 1);
@@ -269,6 +340,8 @@ __global__ void __launch_bounds__(4 * (L3 / 8)) k_z_fast(c2<T>* __restrict__ S2,
     const int k1e = min(n1 + 1, k1b + a.chunk);
     const int b = blockIdx.y;
     const bool m2 = k2 > 0 && k2 < n2;
+    const int pk2 = s2 ? L2 - k2 : k2;
+    const long cstride = (long)L2 * L1 * N3;
 
     // ---- W_c(k2) = G_c x2 U2_c(k2, :) for the six components
     if (!a.dense) {
@@ -277,113 +350,119 @@ __global__ void __launch_bounds__(4 * (L3 / 8)) k_z_fast(c2<T>* __restrict__ S2,
             const c2<T>* G = core + v.core_off[c];
             const c2<T>* U2 = fac + v.fac_off[c][1] + (long)k2 * r2;
             for (int e = tid; e < r1 * r3; e += NT) {
-                int al = e / r3, ga = e - al * r3;
+                const int al = e / r3, ga = e - al * r3;
+                const c2<T>* g = G + (long)al * r2 * r3 + ga;
                 c2<T> acc = mk<T>(0, 0);
-                for (int be = 0; be < r2; ++be) fma_c(acc, G[((long)al * r2 + be) * r3 + ga], U2[be]);
+                for (int b0 = 0; b0 < r2; b0 += 8) {
+                    c2<T> gv[8], uv[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const bool ok = b0 + q < r2;
+                        gv[q] = ok ? g[(long)(b0 + q) * r3] : mk<T>(0, 0);
+                        uv[q] = ok ? U2[b0 + q] : mk<T>(0, 0);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) fma_c(acc, gv[q], uv[q]);
+                }
                 Wc[c * rmax * rmax + e] = acc;
             }
         }
     }
     __syncthreads();
 
-    for (int k1 = k1b; k1 < k1e; ++k1) {
-        const bool m1 = k1 > 0 && k1 < n1;
-        const bool exists = (s1 == 0 || m1) && (s2 == 0 || m2);
-        const int pk1 = s1 ? L1 - k1 : k1;
-        const int pk2 = s2 ? L2 - k2 : k2;
-
-        // ---- V_c = U1_c(k1, :) W_c
+    for (int kA = k1b; kA < k1e; kA += 2) {
+        const int kB = kA + 1;
+        const bool hasB = kB < k1e;
+        // ---- V_c = U1_c(k1, :) W_c for both quads of the pair
         if (!a.dense) {
-            for (int e = tid; e < 6 * rmax; e += NT) {
-                int c = e / rmax, ga = e - c * rmax;
+            for (int e = tid; e < 12 * rmax; e += NT) {
+                const int qd = e / (6 * rmax), rem = e - qd * 6 * rmax;
+                const int c = rem / rmax, ga = rem - c * rmax;
                 const int r1 = v.r[c][0], r3 = v.r[c][2];
-                if (ga < r3) {
+                const int k1 = qd ? kB : kA;
+                if (ga < r3 && (qd == 0 || hasB)) {
                     const c2<T>* U1 = fac + v.fac_off[c][0] + (long)k1 * r1;
+                    const c2<T>* w = Wc + c * rmax * rmax + ga;
                     c2<T> acc = mk<T>(0, 0);
-                    for (int al = 0; al < r1; ++al) fma_c(acc, U1[al], Wc[c * rmax * rmax + al * r3 + ga]);
+                    for (int a0 = 0; a0 < r1; a0 += 8) {
+                        c2<T> uv[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) uv[q] = a0 + q < r1 ? U1[a0 + q] : mk<T>(0, 0);
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            if (a0 + q < r1) fma_c(acc, uv[q], w[(a0 + q) * r3]);
+                    }
                     Vc[e] = acc;
                 }
             }
         }
-
-        // ---- load the three components of my pencil (input layout of the
-        //      forward plan; positions >= n3 are the zero padding)
-        c2<T> d[3][E];
-        constexpr int R0 = Plan::RF0;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const c2<T>* src = S2 + ((((long)b * 3 + q) * L2 + pk2) * L1 + pk1) * N3;
-#pragma unroll
-            for (int u = 0; u < E / R0; ++u)
-#pragma unroll
-                for (int r = 0; r < R0; ++r) {
-                    int pos = t + TPP * u + r * (L3 / R0);
-                    d[q][u * R0 + r] = (exists && r < R0 / 2) ? src[pos] : mk<T>(0, 0);
-                }
-        }
-        // ---- forward FFT of each component (LDS slice per pencil)
+        // ---- quad A: load and forward FFT
+        const bool m1A = kA > 0 && kA < n1;
+        const bool exA = (s1 == 0 || m1A) && (s2 == 0 || m2);
+        const long baseA = (((long)b * 3 * L2 + pk2) * L1 + (s1 ? L1 - kA : kA)) * N3;
+        c2<T> d[3][8];
+        z_load<T, L3, TPP, Plan::RF0>(d, S2, baseA, cstride, t, exA);
 #pragma unroll
         for (int q = 0; q < 3; ++q) Plan::template fwd<T, TPP, 1, -1>(d[q], X + pe * P, 0, t, tws);
         __syncthreads();   // slices free, Vc complete
 
-        // ---- N^_c(k1, k2, k3), k3 in [0, n3], into the freed slices
+        // ---- N^ tables of both quads: each z-factor element is loaded once
+        //      and used for the two quads
         if (!a.dense) {
-            for (int e = tid; e < 6 * (N3 + 1); e += NT) {
-                int c = e / (N3 + 1), kk = e - c * (N3 + 1);
+            for (int e = tid; e < NTS; e += NT) {
+                const int c = e / (N3 + 1), kk = e - c * (N3 + 1);
                 const int r3 = v.r[c][2];
                 const c2<T>* U3 = fac + v.fac3t_off[c] + kk;
-                c2<T> acc = mk<T>(0, 0);
-                for (int ga = 0; ga < r3; ++ga) fma_c(acc, Vc[c * rmax + ga], U3[(long)ga * (N3 + 1)]);
-                NTt[e] = acc;
+                const c2<T>* va = Vc + c * rmax;
+                const c2<T>* vb = Vc + 6 * rmax + c * rmax;
+                c2<T> accA = mk<T>(0, 0), accB = mk<T>(0, 0);
+                for (int g0 = 0; g0 < r3; g0 += 8) {
+                    c2<T> uv[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        uv[q] = g0 + q < r3 ? U3[(long)(g0 + q) * (N3 + 1)] : mk<T>(0, 0);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        if (g0 + q < r3) {
+                            fma_c(accA, va[g0 + q], uv[q]);
+                            fma_c(accB, vb[g0 + q], uv[q]);
+                        }
+                    }
+                }
+                X[e] = accA;
+                NTB[e] = accB;
             }
         } else {
             const long per = (long)(n1 + 1) * (n2 + 1) * (N3 + 1);
-            for (int e = tid; e < 6 * (N3 + 1); e += NT) {
-                int c = e / (N3 + 1), kk = e - c * (N3 + 1);
-                NTt[e] = dense[c * per + ((long)k2 * (n1 + 1) + k1) * (N3 + 1) + kk];
+            for (int e = tid; e < NTS; e += NT) {
+                const int c = e / (N3 + 1), kk = e - c * (N3 + 1);
+                const c2<T>* src = dense + c * per + (long)k2 * (n1 + 1) * (N3 + 1) + kk;
+                X[e] = src[(long)kA * (N3 + 1)];
+                if (hasB) NTB[e] = src[(long)kB * (N3 + 1)];
             }
         }
-        __syncthreads();   // NTt complete
-
-        // ---- 3x3 component product; output layout of the forward plan
-        constexpr int RL = Plan::RFL;
-#pragma unroll
-        for (int u = 0; u < E / RL; ++u)
-#pragma unroll
-            for (int r = 0; r < RL; ++r) {
-                const int m = t + TPP * u + r * (L3 / RL);
-                const int f3 = m > N3;
-                const int kk = f3 ? L3 - m : m;
-                c2<T> Nc[6];
-#pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    c2<T> tv = NTt[c * (N3 + 1) + kk];
-                    if (zsign(c, s1 ? 1 : 0, s2 ? 1 : 0, f3) < 0) tv = mk<T>(-tv.x, -tv.y);
-                    Nc[c] = a.conj ? conj(tv) : tv;
-                }
-                const int i = u * RL + r;
-                c2<T> x0 = d[0][i], x1 = d[1][i], x2 = d[2][i];
-                d[0][i] = Nc[0] * x0 + Nc[3] * x1 + Nc[4] * x2;
-                d[1][i] = Nc[3] * x0 + Nc[1] * x1 + Nc[5] * x2;
-                d[2][i] = Nc[4] * x0 + Nc[5] * x1 + Nc[2] * x2;
-            }
-        __syncthreads();   // NTt consumed: the slices are reused by the inverse FFT
-
-        // ---- inverse FFT and cropped store (output layout of the inverse plan)
+        __syncthreads();   // tables complete
+        z_product<T, L3, TPP, Plan::RFL>(d, X, t, s1, s2, a.conj);
+        __syncthreads();   // table A consumed: the slices are reused by the inverse FFT
 #pragma unroll
         for (int q = 0; q < 3; ++q) Plan::template inv<T, TPP, 1, 1>(d[q], X + pe * P, 0, t, tws);
-        constexpr int RIL = Plan::RIL;
-        if (exists) {
+        if (exA) z_store<T, L3, TPP, Plan::RIL>(d, S2, baseA, cstride, t);
+
+        // ---- quad B
+        if (hasB) {
+            const bool m1B = kB > 0 && kB < n1;
+            const bool exB = (s1 == 0 || m1B) && (s2 == 0 || m2);
+            const long baseB = (((long)b * 3 * L2 + pk2) * L1 + (s1 ? L1 - kB : kB)) * N3;
+            // each wavefront now only touches its own pencil slice until the end of the pair
+            z_load<T, L3, TPP, Plan::RF0>(d, S2, baseB, cstride, t, exB);
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                c2<T>* dst = S2 + ((((long)b * 3 + q) * L2 + pk2) * L1 + pk1) * N3;
+            for (int q = 0; q < 3; ++q) Plan::template fwd<T, TPP, 1, -1>(d[q], X + pe * P, 0, t, tws);
+            z_product<T, L3, TPP, Plan::RFL>(d, NTB, t, s1, s2, a.conj);
 #pragma unroll
-                for (int u = 0; u < E / RIL; ++u)
-#pragma unroll
-                    for (int r = 0; r < RIL / 2; ++r) dst[t + TPP * u + r * (L3 / RIL)] = d[q][u * RIL + r];
-            }
+            for (int q = 0; q < 3; ++q) Plan::template inv<T, TPP, 1, 1>(d[q], X + pe * P, 0, t, tws);
+            if (exB) z_store<T, L3, TPP, Plan::RIL>(d, S2, baseB, cstride, t);
         }
-        __syncthreads();   // Vc and the slices are reused by the next quad
+        __syncthreads();   // Vc, NTB and the slices are reused by the next pair
     }
 }
 
@@ -433,7 +512,8 @@ template <typename T, int L3>
 static size_t zfast_lds(const OpView& v)
 {
     static_assert(6 * (L3 / 2 + 1) <= 4 * PL<L3>::value, "N^ table must fit in the FFT slices");
-    return sizeof(c2<T>) * ((size_t)4 * PL<L3>::value + 6 * (size_t)v.rmax * v.rmax + 6 * v.rmax + L3);
+    return sizeof(c2<T>) * ((size_t)4 * PL<L3>::value + 6 * (L3 / 2 + 1) + 6 * (size_t)v.rmax * v.rmax +
+                            12 * v.rmax + L3);
 }
 
 template <typename T, int L3>

@@ -30,6 +30,22 @@ struct RadixList {
 
 __device__ __forceinline__ int lds_pad(int a) { return a + (a >> 3); }
 
+// Make LDS writes of this wavefront visible to its other lanes (a pencil
+// whose threads all sit in one wavefront needs no block-wide barrier).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool WAVE>
+__device__ __forceinline__ void stage_sync()
+{
+    if constexpr (WAVE) wave_sync();
+    else __syncthreads();
+}
+
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft_reg(c2<T>* a)
 {
@@ -103,7 +119,7 @@ struct Prod<R0, Rs...> {
 // Recursive stage driver.  NS = product of the radices already applied.
 // NSEQ pencils are transformed together (thread registers v[s*E ...] and LDS
 // slices lds + s * stride); the barriers are shared.
-template <int L, int TPP, int NSEQ, int DIR, int NS, typename T, int R0, int... Rs>
+template <int L, int TPP, int NSEQ, int DIR, int NS, bool WAVE, typename T, int R0, int... Rs>
 struct RegFFTImpl {
     __device__ __forceinline__ static void run(c2<T>* v, c2<T>* lds, int stride, int t, const c2<T>* tw)
     {
@@ -114,20 +130,24 @@ struct RegFFTImpl {
             constexpr int RN = RadixList<Rs...>::v[0];
 #pragma unroll
             for (int s = 0; s < NSEQ; ++s) reg_store<L, TPP, R0, NS>(v + s * E, lds + s * stride, t);
-            __syncthreads();
+            stage_sync<WAVE>();
 #pragma unroll
             for (int s = 0; s < NSEQ; ++s) reg_load<L, TPP, RN>(v + s * E, lds + s * stride, t);
-            __syncthreads();
-            RegFFTImpl<L, TPP, NSEQ, DIR, NS * R0, T, Rs...>::run(v, lds, stride, t, tw);
+            stage_sync<WAVE>();
+            RegFFTImpl<L, TPP, NSEQ, DIR, NS * R0, WAVE, T, Rs...>::run(v, lds, stride, t, tw);
         }
     }
 };
 
+// WAVE: every pencil's TPP threads lie in one wavefront (TPP divides 64 and
+// pencils are aligned to it), so the inter-stage transposes only need
+// wavefront-level ordering.
 template <int L, int TPP, int NSEQ, int DIR, typename T, int... Rs>
 __device__ __forceinline__ void reg_fft(c2<T>* v, c2<T>* lds, int stride, int t, const c2<T>* tw)
 {
     static_assert(Prod<Rs...>::value == L, "plan does not multiply to L");
-    RegFFTImpl<L, TPP, NSEQ, DIR, 1, T, Rs...>::run(v, lds, stride, t, tw);
+    constexpr bool WAVE = (TPP <= 64) && (64 % TPP == 0);
+    RegFFTImpl<L, TPP, NSEQ, DIR, 1, WAVE, T, Rs...>::run(v, lds, stride, t, tw);
 }
 
 // LDS slice length (elements) for one pencil including the padding

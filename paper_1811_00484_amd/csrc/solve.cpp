@@ -98,246 +98,302 @@ struct SysState {
     double beta0 = 0;
 };
 
-template <typename TK, typename TC>
-vie_status run(const vie_op* opw, int mode, const c2<TK>* eps, const c2<TK>* b, c2<TK>* x, int nrhs,
-               const vie_solve_opts& o, vie_solve_info* info, char* ws, const Layout& Lt, hipStream_t st)
+// Per-instance state of a (possibly multi-instance) batched GMRES solve.
+template <typename TK>
+struct Inst {
+    const DeviceOp* op = nullptr;
+    const c2<TK>* eps = nullptr;
+    const c2<TK>* b = nullptr;
+    c2<TK>* x = nullptr;
+    int nrhs = 0;
+    vie_solve_info* info = nullptr;
+    long n = 0;
+    Layout Lt;
+    char* ws = nullptr;
+    c2<TK>* V = nullptr;
+    c2<TK>* R = nullptr;
+    void* mws = nullptr;
+    c2<double>* partial = nullptr;
+    c2<double>* dh1 = nullptr;
+    c2<double>* dh2 = nullptr;
+    c2<double>* dcoef = nullptr;
+    c2<double>* dnrm = nullptr;
+    int* dmap = nullptr;
+    std::vector<double> bnorm, relres;
+    std::vector<char> conv;
+    std::vector<int> mvs, mv64, cycles;
+    std::vector<SysState> S;
+    std::vector<int> cyc, run;
+};
+
+template <typename TV, typename T>
+hipError_t mv_dispatch(const std::vector<InstHost>& req, int mode, InstDev* tab, hipStream_t st, std::string& err)
 {
-    const DeviceOp& op = opw->d;
-    const OpView& v = op.view;
-    const long n = 3L * v.n[0] * v.n[1] * v.n[2];
+    if (req.empty()) return hipSuccess;
+    if (req.size() == 1) {
+        const InstHost& h = req[0];
+        return launch_matvec<TV, T>(*h.op, mode, 0, (const c2<TV>*)h.eps, (const c2<TV>*)h.x, (c2<TV>*)h.y, h.nact,
+                                    (c2<T>*)h.ws, st, h.map, err);
+    }
+    return launch_matvec_multi<TV, T>(req, mode, tab, st, err);
+}
+
+template <typename TK, typename TC>
+vie_status run_multi(std::vector<Inst<TK>>& I, int mode, const vie_solve_opts& o, InstDev* tab, hipStream_t st)
+{
     const int m = o.restart;
-    const long sstride = n, vstride = (long)nrhs * n;
-    c2<TK>* Vb = (c2<TK>*)(ws + Lt.V);
-    c2<TK>* R = (c2<TK>*)(ws + Lt.R);
-    void* mws = ws + Lt.mws;
-    c2<double>* partial = (c2<double>*)(ws + Lt.partial);
-    c2<double>* dh1 = (c2<double>*)(ws + Lt.h1);
-    c2<double>* dh2 = (c2<double>*)(ws + Lt.h2);
-    c2<double>* dcoef = (c2<double>*)(ws + Lt.coef);
-    c2<double>* dnrm = (c2<double>*)(ws + Lt.nrm);
-    int* dmap = (int*)(ws + Lt.map);
     hipError_t e;
     std::string err;
-
-    auto upload_map = [&](const std::vector<int>& mp) -> hipError_t {
-        hipError_t er = hipMemcpyAsync(dmap, mp.data(), sizeof(int) * mp.size(), hipMemcpyHostToDevice, st);
+    auto upload_map = [&](Inst<TK>& in, const std::vector<int>& mp) -> hipError_t {
+        if (mp.empty()) return hipSuccess;
+        hipError_t er = hipMemcpyAsync(in.dmap, mp.data(), sizeof(int) * mp.size(), hipMemcpyHostToDevice, st);
         if (er != hipSuccess) return er;
         return hipStreamSynchronize(st);
     };
-    // matvec of the working (inner) operator, or of the FP64 residual operator
-    auto mv_inner = [&](const c2<TK>* xin, c2<TK>* yout, int nact) -> hipError_t {
-        return launch_matvec<TK, TC>(op, mode, 0, eps, xin, yout, nact, (c2<TC>*)mws, st, dmap, err);
+    auto fetch = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+        hipError_t er = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st);
+        if (er != hipSuccess) return er;
+        return hipStreamSynchronize(st);
     };
-    auto mv_resid = [&](const c2<TK>* xin, c2<TK>* yout, int nact) -> hipError_t {
-        if (o.refine) {
-            if constexpr (sizeof(TK) == 8)
-                return launch_matvec<double, double>(op, mode, 0, (const c2<double>*)eps, (const c2<double>*)xin,
-                                                     (c2<double>*)yout, nact, (c2<double>*)mws, st, dmap, err);
+    // ---- right-hand side norms, zero right-hand sides
+    for (auto& in : I) {
+        const long n = in.n;
+        std::vector<int> all(in.nrhs);
+        for (int s = 0; s < in.nrhs; ++s) all[s] = s;
+        if ((e = upload_map(in, all)) != hipSuccess) return hip_fail(e, "vie_solve map");
+        if ((e = kr_norm2<TK>(in.b, 0, n, n, in.dmap, in.nrhs, in.partial, in.dnrm, st)) != hipSuccess)
+            return hip_fail(e, "vie_solve norm");
+        std::vector<c2<double>> h(in.nrhs);
+        if ((e = fetch(h.data(), in.dnrm, sizeof(c2<double>) * in.nrhs)) != hipSuccess)
+            return hip_fail(e, "vie_solve norm copy");
+        in.bnorm.assign(in.nrhs, 0.0);
+        in.relres.assign(in.nrhs, INFINITY);
+        in.conv.assign(in.nrhs, 0);
+        in.mvs.assign(in.nrhs, 0);
+        in.mv64.assign(in.nrhs, 0);
+        in.cycles.assign(in.nrhs, 0);
+        in.S.assign(in.nrhs, SysState());
+        for (auto& ss : in.S) {
+            ss.H.assign((size_t)(m + 1) * m, 0.0);
+            ss.g.assign(m + 1, 0.0);
+            ss.cs.assign(m, 0.0);
+            ss.sn.assign(m, 0.0);
         }
-        return mv_inner(xin, yout, nact);
-    };
-
-    std::vector<double> bnorm(nrhs, 0.0);
-    std::vector<int> all(nrhs);
-    for (int s = 0; s < nrhs; ++s) all[s] = s;
-    if ((e = upload_map(all)) != hipSuccess) return hip_fail(e, "vie_solve map");
-    if ((e = kr_norm2<TK>(b, 0, sstride, n, dmap, nrhs, partial, dnrm, st)) != hipSuccess)
-        return hip_fail(e, "vie_solve norm");
-    {
-        std::vector<c2<double>> h(nrhs);
-        e = hipMemcpyAsync(h.data(), dnrm, sizeof(c2<double>) * nrhs, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(e, "vie_solve norm copy");
-        for (int s = 0; s < nrhs; ++s) {
-            bnorm[s] = std::sqrt(h[s].x);
-            if (!std::isfinite(bnorm[s])) return fail(VIE_E_NONFINITE, "vie_solve: non-finite right-hand side");
+        if (in.info)
+            for (int s = 0; s < in.nrhs; ++s) in.info[s].hist_len = 0;
+        for (int s = 0; s < in.nrhs; ++s) {
+            in.bnorm[s] = std::sqrt(h[s].x);
+            if (!std::isfinite(in.bnorm[s])) return fail(VIE_E_NONFINITE, "vie_solve: non-finite right-hand side");
+            if (in.bnorm[s] == 0.0) {
+                in.conv[s] = 1;
+                in.relres[s] = 0.0;
+                (void)hipMemsetAsync(in.x + s * n, 0, sizeof(c2<TK>) * n, st);
+            }
         }
     }
-    std::vector<bool> conv(nrhs, false);
-    std::vector<double> relres(nrhs, INFINITY);
-    std::vector<int> mvs(nrhs, 0), mv64(nrhs, 0), cycles(nrhs, 0), steps(nrhs, 0);
-    if (info)
-        for (int s = 0; s < nrhs; ++s) info[s].hist_len = 0;
-    // b == 0 -> x = 0 solves it
-    for (int s = 0; s < nrhs; ++s)
-        if (bnorm[s] == 0.0) {
-            conv[s] = true;
-            relres[s] = 0.0;
-            (void)hipMemsetAsync(x + s * sstride, 0, sizeof(c2<TK>) * n, st);
-        }
-    std::vector<SysState> S(nrhs);
-    for (auto& ss : S) {
-        ss.H.assign((size_t)(m + 1) * m, 0.0);
-        ss.g.assign(m + 1, 0.0);
-        ss.cs.assign(m, 0.0);
-        ss.sn.assign(m, 0.0);
-    }
-    bool nonfinite = false;
-
+    std::vector<InstHost> req;
     for (int outer = 0;; ++outer) {
-        std::vector<int> act;
-        for (int s = 0; s < nrhs; ++s)
-            if (!conv[s]) act.push_back(s);
-        if (act.empty()) break;
-        int na = (int)act.size();
-        if ((e = upload_map(act)) != hipSuccess) return hip_fail(e, "vie_solve map");
-        // ---- true residual R = b - A x
-        if ((e = mv_resid(x, R, na)) != hipSuccess)
-            return err.empty() ? hip_fail(e, "vie_solve matvec") : fail(VIE_E_UNSUPPORTED, err);
-        for (int s : act) (o.refine ? mv64[s] : mvs[s])++;
-        if ((e = kr_residual<TK>(R, b, sstride, n, dmap, na, st)) != hipSuccess) return hip_fail(e, "residual");
-        if ((e = kr_norm2<TK>(R, 0, sstride, n, dmap, na, partial, dnrm, st)) != hipSuccess)
-            return hip_fail(e, "norm");
-        std::vector<c2<double>> hn(na);
-        e = hipMemcpyAsync(hn.data(), dnrm, sizeof(c2<double>) * na, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(e, "vie_solve copy");
-        std::vector<int> cyc;
-        for (int a = 0; a < na; ++a) {
-            int s = act[a];
-            double beta = std::sqrt(hn[a].x);
-            if (!std::isfinite(beta)) {
-                nonfinite = true;
-                continue;
-            }
-            relres[s] = beta / bnorm[s];
-            if (info && info[s].history && info[s].hist_len < info[s].hist_cap)
-                info[s].history[info[s].hist_len++] = relres[s];
-            if (relres[s] <= o.tol) {
-                conv[s] = true;
-                continue;
-            }
-            if (outer >= o.max_outer) continue;
-            S[s].beta0 = beta;
-            cyc.push_back(s);
+        // ---- true residual R = b - A x for every unconverged system
+        req.clear();
+        std::vector<std::vector<int>> act(I.size());
+        for (size_t i = 0; i < I.size(); ++i) {
+            Inst<TK>& in = I[i];
+            for (int s = 0; s < in.nrhs; ++s)
+                if (!in.conv[s]) act[i].push_back(s);
+            if (act[i].empty()) continue;
+            if ((e = upload_map(in, act[i])) != hipSuccess) return hip_fail(e, "vie_solve map");
+            req.push_back({in.op, in.x, in.R, in.eps, in.dmap, (int)act[i].size(), in.mws});
         }
-        if (nonfinite) return fail(VIE_E_NONFINITE, "vie_solve: non-finite residual");
-        if (cyc.empty()) break;
-        // ---- one GMRES(m) cycle on the systems in `cyc`
-        int nc = (int)cyc.size();
-        if ((e = upload_map(cyc)) != hipSuccess) return hip_fail(e, "vie_solve map");
-        // V0 = R / beta: norms of R for the cyc systems are recomputed in cyc order
-        if ((e = kr_norm2<TK>(R, 0, sstride, n, dmap, nc, partial, dnrm, st)) != hipSuccess)
-            return hip_fail(e, "norm");
-        if ((e = kr_scale_norm<TK>(Vb, 0, R, 0, sstride, dnrm, n, dmap, nc, st)) != hipSuccess)
-            return hip_fail(e, "scale");
-        for (int s : cyc) {
-            SysState& ss = S[s];
-            std::fill(ss.H.begin(), ss.H.end(), cd(0.0));
-            std::fill(ss.g.begin(), ss.g.end(), cd(0.0));
-            ss.g[0] = ss.beta0;
-            ss.k = 0;
-            ss.in_cycle = true;
+        if (req.empty()) break;
+        if (o.refine) {
+            if constexpr (sizeof(TK) == 8) e = mv_dispatch<double, double>(req, mode, tab, st, err);
+        } else {
+            e = mv_dispatch<TK, TC>(req, mode, tab, st, err);
         }
-        std::vector<int> run_list = cyc;
-        for (int j = 0; j < m && !run_list.empty(); ++j) {
-            int nr = (int)run_list.size();
-            if ((e = upload_map(run_list)) != hipSuccess) return hip_fail(e, "vie_solve map");
-            c2<TK>* Vj = Vb + (long)j * vstride;
-            c2<TK>* Vj1 = Vb + (long)(j + 1) * vstride;
-            if ((e = mv_inner(Vj, Vj1, nr)) != hipSuccess)
+        if (e != hipSuccess) return err.empty() ? hip_fail(e, "vie_solve matvec") : fail(VIE_E_UNSUPPORTED, err);
+        bool any_cycle = false;
+        for (size_t i = 0; i < I.size(); ++i) {
+            Inst<TK>& in = I[i];
+            in.cyc.clear();
+            if (act[i].empty()) continue;
+            const int na = (int)act[i].size();
+            const long n = in.n;
+            for (int s : act[i]) (o.refine ? in.mv64[s] : in.mvs[s])++;
+            if ((e = kr_residual<TK>(in.R, in.b, n, n, in.dmap, na, st)) != hipSuccess) return hip_fail(e, "residual");
+            if ((e = kr_norm2<TK>(in.R, 0, n, n, in.dmap, na, in.partial, in.dnrm, st)) != hipSuccess)
+                return hip_fail(e, "norm");
+            std::vector<c2<double>> hn(na);
+            if ((e = fetch(hn.data(), in.dnrm, sizeof(c2<double>) * na)) != hipSuccess) return hip_fail(e, "copy");
+            for (int a = 0; a < na; ++a) {
+                int s = act[i][a];
+                double beta = std::sqrt(hn[a].x);
+                if (!std::isfinite(beta)) return fail(VIE_E_NONFINITE, "vie_solve: non-finite residual");
+                in.relres[s] = beta / in.bnorm[s];
+                if (in.info && in.info[s].history && in.info[s].hist_len < in.info[s].hist_cap)
+                    in.info[s].history[in.info[s].hist_len++] = in.relres[s];
+                if (in.relres[s] <= o.tol) {
+                    in.conv[s] = 1;
+                    continue;
+                }
+                if (outer >= o.max_outer) continue;
+                in.S[s].beta0 = beta;
+                in.cyc.push_back(s);
+            }
+            if (in.cyc.empty()) continue;
+            any_cycle = true;
+            const int nc = (int)in.cyc.size();
+            if ((e = upload_map(in, in.cyc)) != hipSuccess) return hip_fail(e, "vie_solve map");
+            if ((e = kr_norm2<TK>(in.R, 0, n, n, in.dmap, nc, in.partial, in.dnrm, st)) != hipSuccess)
+                return hip_fail(e, "norm");
+            if ((e = kr_scale_norm<TK>(in.V, 0, in.R, 0, n, in.dnrm, n, in.dmap, nc, st)) != hipSuccess)
+                return hip_fail(e, "scale");
+            for (int s : in.cyc) {
+                SysState& ss = in.S[s];
+                std::fill(ss.H.begin(), ss.H.end(), cd(0.0));
+                std::fill(ss.g.begin(), ss.g.end(), cd(0.0));
+                ss.g[0] = ss.beta0;
+                ss.k = 0;
+            }
+            in.run = in.cyc;
+        }
+        if (!any_cycle) break;
+        // ---- one GMRES(m) cycle, all instances in lockstep
+        for (int j = 0; j < m; ++j) {
+            req.clear();
+            for (auto& in : I) {
+                if (in.run.empty()) continue;
+                const long vstride = (long)in.nrhs * in.n;
+                if ((e = upload_map(in, in.run)) != hipSuccess) return hip_fail(e, "vie_solve map");
+                req.push_back({in.op, in.V + (long)j * vstride, in.V + (long)(j + 1) * vstride, in.eps, in.dmap,
+                               (int)in.run.size(), in.mws});
+            }
+            if (req.empty()) break;
+            if ((e = mv_dispatch<TK, TC>(req, mode, tab, st, err)) != hipSuccess)
                 return err.empty() ? hip_fail(e, "vie_solve matvec") : fail(VIE_E_UNSUPPORTED, err);
-            for (int s : run_list) mvs[s]++;
-            // CGS2
-            const long wvoff = (long)(j + 1) * vstride;
-            e = kr_mdot<TK>(Vb, vstride, sstride, j + 1, Vb, wvoff, n, dmap, nr, partial, dh1, st);
-            if (e == hipSuccess)
-                e = kr_maxpy<TK>(Vb, wvoff, sstride, Vb, vstride, sstride, j + 1, j + 1, dh1, -1.0, n, dmap, nr, st);
-            if (e == hipSuccess)
-                e = kr_mdot<TK>(Vb, vstride, sstride, j + 1, Vb, wvoff, n, dmap, nr, partial, dh2, st);
-            if (e == hipSuccess)
-                e = kr_maxpy<TK>(Vb, wvoff, sstride, Vb, vstride, sstride, j + 1, j + 1, dh2, -1.0, n, dmap, nr, st);
-            if (e == hipSuccess) e = kr_norm2<TK>(Vb, wvoff, sstride, n, dmap, nr, partial, dnrm, st);
-            if (e == hipSuccess) e = kr_scale_norm<TK>(Vb, wvoff, Vb, wvoff, sstride, dnrm, n, dmap, nr, st);
-            if (e != hipSuccess) return hip_fail(e, "vie_solve arnoldi");
-            std::vector<c2<double>> h1((size_t)nr * (j + 1)), h2((size_t)nr * (j + 1)), hb(nr);
-            e = hipMemcpyAsync(h1.data(), dh1, sizeof(c2<double>) * h1.size(), hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(h2.data(), dh2, sizeof(c2<double>) * h2.size(), hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipMemcpyAsync(hb.data(), dnrm, sizeof(c2<double>) * nr, hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (e != hipSuccess) return hip_fail(e, "vie_solve copy");
-            std::vector<int> next;
-            for (int a = 0; a < nr; ++a) {
-                int s = run_list[a];
-                SysState& ss = S[s];
-                cd* Hc = &ss.H[(size_t)j * (m + 1)];
-                for (int i = 0; i <= j; ++i) {
-                    c2<double> t1 = h1[(size_t)a * (j + 1) + i], t2 = h2[(size_t)a * (j + 1) + i];
-                    Hc[i] = cd(t1.x + t2.x, t1.y + t2.y);
+            for (auto& in : I) {
+                if (in.run.empty()) continue;
+                const long n = in.n, vstride = (long)in.nrhs * n;
+                const int nr = (int)in.run.size();
+                for (int s : in.run) in.mvs[s]++;
+                const long wvoff = (long)(j + 1) * vstride;
+                e = kr_mdot<TK>(in.V, vstride, n, j + 1, in.V, wvoff, n, in.dmap, nr, in.partial, in.dh1, st);
+                if (e == hipSuccess)
+                    e = kr_maxpy<TK>(in.V, wvoff, n, in.V, vstride, n, j + 1, j + 1, in.dh1, -1.0, n, in.dmap, nr, st);
+                if (e == hipSuccess)
+                    e = kr_mdot<TK>(in.V, vstride, n, j + 1, in.V, wvoff, n, in.dmap, nr, in.partial, in.dh2, st);
+                if (e == hipSuccess)
+                    e = kr_maxpy<TK>(in.V, wvoff, n, in.V, vstride, n, j + 1, j + 1, in.dh2, -1.0, n, in.dmap, nr, st);
+                if (e == hipSuccess) e = kr_norm2<TK>(in.V, wvoff, n, n, in.dmap, nr, in.partial, in.dnrm, st);
+                if (e == hipSuccess) e = kr_scale_norm<TK>(in.V, wvoff, in.V, wvoff, n, in.dnrm, n, in.dmap, nr, st);
+                if (e != hipSuccess) return hip_fail(e, "vie_solve arnoldi");
+                std::vector<c2<double>> h1((size_t)nr * (j + 1)), h2((size_t)nr * (j + 1)), hb(nr);
+                e = hipMemcpyAsync(h1.data(), in.dh1, sizeof(c2<double>) * h1.size(), hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(h2.data(), in.dh2, sizeof(c2<double>) * h2.size(), hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(hb.data(), in.dnrm, sizeof(c2<double>) * nr, hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                if (e != hipSuccess) return hip_fail(e, "vie_solve copy");
+                std::vector<int> next;
+                for (int a = 0; a < nr; ++a) {
+                    int s = in.run[a];
+                    SysState& ss = in.S[s];
+                    cd* Hc = &ss.H[(size_t)j * (m + 1)];
+                    for (int i2 = 0; i2 <= j; ++i2) {
+                        c2<double> t1 = h1[(size_t)a * (j + 1) + i2], t2 = h2[(size_t)a * (j + 1) + i2];
+                        Hc[i2] = cd(t1.x + t2.x, t1.y + t2.y);
+                    }
+                    double beta = std::sqrt(hb[a].x);
+                    Hc[j + 1] = beta;
+                    bool finite = std::isfinite(beta);
+                    for (int i2 = 0; i2 <= j; ++i2)
+                        finite = finite && std::isfinite(Hc[i2].real()) && std::isfinite(Hc[i2].imag());
+                    if (!finite) return fail(VIE_E_NONFINITE, "vie_solve: non-finite Arnoldi quantity");
+                    for (int i2 = 0; i2 < j; ++i2) {
+                        cd aa = Hc[i2], bb = Hc[i2 + 1];
+                        Hc[i2] = ss.cs[i2] * aa + ss.sn[i2] * bb;
+                        Hc[i2 + 1] = -std::conj(ss.sn[i2]) * aa + ss.cs[i2] * bb;
+                    }
+                    givens(Hc[j], Hc[j + 1], ss.cs[j], ss.sn[j]);
+                    cd aa = Hc[j], bb = Hc[j + 1];
+                    Hc[j] = ss.cs[j] * aa + ss.sn[j] * bb;
+                    Hc[j + 1] = 0.0;
+                    ss.g[j + 1] = -std::conj(ss.sn[j]) * ss.g[j];
+                    ss.g[j] = ss.cs[j] * ss.g[j];
+                    ss.k = j + 1;
+                    double est = std::abs(ss.g[j + 1]);
+                    double target = o.tol * in.bnorm[s];
+                    if (o.refine) target = std::max(o.inner_tol * ss.beta0, 0.5 * o.tol * in.bnorm[s]);
+                    bool stop = est <= target || beta == 0.0 || std::abs(Hc[j]) == 0.0;
+                    if (!stop) next.push_back(s);
                 }
-                double beta = std::sqrt(hb[a].x);
-                Hc[j + 1] = beta;
-                bool finite = std::isfinite(beta);
-                for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(Hc[i].real()) && std::isfinite(Hc[i].imag());
-                if (!finite) {
-                    nonfinite = true;
-                    break;
-                }
-                for (int i = 0; i < j; ++i) {
-                    cd aa = Hc[i], bb = Hc[i + 1];
-                    Hc[i] = ss.cs[i] * aa + ss.sn[i] * bb;
-                    Hc[i + 1] = -std::conj(ss.sn[i]) * aa + ss.cs[i] * bb;
-                }
-                givens(Hc[j], Hc[j + 1], ss.cs[j], ss.sn[j]);
-                cd aa = Hc[j], bb = Hc[j + 1];
-                Hc[j] = ss.cs[j] * aa + ss.sn[j] * bb;
-                Hc[j + 1] = 0.0;
-                ss.g[j + 1] = -std::conj(ss.sn[j]) * ss.g[j];
-                ss.g[j] = ss.cs[j] * ss.g[j];
-                ss.k = j + 1;
-                steps[s]++;
-                double est = std::abs(ss.g[j + 1]);
-                double target = o.tol * bnorm[s];
-                if (o.refine) target = std::max(o.inner_tol * ss.beta0, 0.5 * o.tol * bnorm[s]);
-                bool stop = est <= target || beta == 0.0 || std::abs(Hc[j]) == 0.0;
-                if (!stop) next.push_back(s);
+                in.run = next;
             }
-            if (nonfinite) return fail(VIE_E_NONFINITE, "vie_solve: non-finite Arnoldi quantity");
-            run_list = next;
         }
         // ---- x += V y for every system of the cycle
-        int kmax = 0;
-        std::vector<c2<double>> coef((size_t)nc * m);
-        for (int a = 0; a < nc; ++a) {
-            SysState& ss = S[cyc[a]];
-            int k = ss.k;
-            kmax = std::max(kmax, k);
-            std::vector<cd> y(k);
-            for (int i = k - 1; i >= 0; --i) {
-                cd acc = ss.g[i];
-                for (int t = i + 1; t < k; ++t) acc -= ss.H[(size_t)t * (m + 1) + i] * y[t];
-                cd d = ss.H[(size_t)i * (m + 1) + i];
-                y[i] = std::abs(d) > 0.0 ? acc / d : cd(0.0);
+        for (auto& in : I) {
+            if (in.cyc.empty()) continue;
+            const long n = in.n, vstride = (long)in.nrhs * n;
+            const int nc = (int)in.cyc.size();
+            int kmax = 0;
+            std::vector<c2<double>> coef((size_t)nc * m);
+            for (int a = 0; a < nc; ++a) {
+                SysState& ss = in.S[in.cyc[a]];
+                int k = ss.k;
+                kmax = std::max(kmax, k);
+                std::vector<cd> y(k);
+                for (int i2 = k - 1; i2 >= 0; --i2) {
+                    cd acc = ss.g[i2];
+                    for (int t = i2 + 1; t < k; ++t) acc -= ss.H[(size_t)t * (m + 1) + i2] * y[t];
+                    cd d = ss.H[(size_t)i2 * (m + 1) + i2];
+                    y[i2] = std::abs(d) > 0.0 ? acc / d : cd(0.0);
+                }
+                for (int i2 = 0; i2 < m; ++i2) {
+                    cd yy = i2 < k ? y[i2] : cd(0.0);
+                    coef[(size_t)a * m + i2].x = yy.real();
+                    coef[(size_t)a * m + i2].y = yy.imag();
+                }
+                in.cycles[in.cyc[a]]++;
             }
-            for (int i = 0; i < m; ++i) {
-                cd yy = i < k ? y[i] : cd(0.0);
-                coef[(size_t)a * m + i].x = yy.real();
-                coef[(size_t)a * m + i].y = yy.imag();
-            }
-            cycles[cyc[a]]++;
+            if ((e = upload_map(in, in.cyc)) != hipSuccess) return hip_fail(e, "vie_solve map");
+            e = hipMemcpyAsync(in.dcoef, coef.data(), sizeof(c2<double>) * coef.size(), hipMemcpyHostToDevice, st);
+            if (e == hipSuccess && kmax > 0)
+                e = kr_maxpy<TK>(in.x, 0, n, in.V, vstride, n, kmax, m, in.dcoef, 1.0, n, in.dmap, nc, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return hip_fail(e, "vie_solve update");
         }
-        if ((e = upload_map(cyc)) != hipSuccess) return hip_fail(e, "vie_solve map");
-        e = hipMemcpyAsync(dcoef, coef.data(), sizeof(c2<double>) * coef.size(), hipMemcpyHostToDevice, st);
-        if (e == hipSuccess && kmax > 0)
-            e = kr_maxpy<TK>(x, 0, sstride, Vb, vstride, sstride, kmax, m, dcoef, 1.0, n, dmap, nc, st);
-        if (e != hipSuccess) return hip_fail(e, "vie_solve update");
     }
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "vie_solve sync");
     bool all_conv = true;
-    for (int s = 0; s < nrhs; ++s) {
-        all_conv = all_conv && conv[s];
-        if (info) {
-            info[s].matvecs = mvs[s];
-            info[s].matvecs_fp64 = mv64[s];
-            info[s].restarts = cycles[s];
-            info[s].refine_steps = o.refine ? cycles[s] : 0;
-            info[s].converged = conv[s] ? 1 : 0;
-            info[s].rel_residual = relres[s];
+    for (auto& in : I)
+        for (int s = 0; s < in.nrhs; ++s) {
+            all_conv = all_conv && in.conv[s];
+            if (in.info) {
+                in.info[s].matvecs = in.mvs[s];
+                in.info[s].matvecs_fp64 = in.mv64[s];
+                in.info[s].restarts = in.cycles[s];
+                in.info[s].refine_steps = o.refine ? in.cycles[s] : 0;
+                in.info[s].converged = in.conv[s] ? 1 : 0;
+                in.info[s].rel_residual = in.relres[s];
+            }
         }
-    }
     return all_conv ? VIE_OK : VIE_NOT_CONVERGED;
+}
+
+template <typename TK>
+void bind_ws(Inst<TK>& in, char* ws)
+{
+    in.ws = ws;
+    in.V = (c2<TK>*)(ws + in.Lt.V);
+    in.R = (c2<TK>*)(ws + in.Lt.R);
+    in.mws = ws + in.Lt.mws;
+    in.partial = (c2<double>*)(ws + in.Lt.partial);
+    in.dh1 = (c2<double>*)(ws + in.Lt.h1);
+    in.dh2 = (c2<double>*)(ws + in.Lt.h2);
+    in.dcoef = (c2<double>*)(ws + in.Lt.coef);
+    in.dnrm = (c2<double>*)(ws + in.Lt.nrm);
+    in.dmap = (int*)(ws + in.Lt.map);
 }
 
 vie_solve_opts defaults(const vie_solve_opts* o)
@@ -353,6 +409,46 @@ vie_solve_opts defaults(const vie_solve_opts* o)
     return o ? *o : d;
 }
 
+// total workspace of a multi-instance solve: one instance table, then each
+// instance's own layout, 256-byte aligned
+size_t multi_ws_bytes(const vie_solve_instance* in, int count, int dtype, const vie_solve_opts& o)
+{
+    size_t tot = align256(sizeof(InstDev) * (size_t)count);
+    for (int i = 0; i < count; ++i) tot += align256(layout(in[i].op->d, dtype, in[i].nrhs, o.restart, o.refine).total);
+    return tot;
+}
+
+template <typename TK, typename TC>
+vie_status solve_typed(const vie_solve_instance* in, int count, int dtype, const vie_solve_opts& o, int mode, char* ws,
+                       hipStream_t st)
+{
+    std::vector<Inst<TK>> I(count);
+    InstDev* tab = (InstDev*)ws;
+    size_t off = align256(sizeof(InstDev) * (size_t)count);
+    for (int i = 0; i < count; ++i) {
+        Inst<TK>& d = I[i];
+        d.op = &in[i].op->d;
+        d.eps = (const c2<TK>*)in[i].eps_c;
+        d.b = (const c2<TK>*)in[i].b;
+        d.x = (c2<TK>*)in[i].x;
+        d.nrhs = in[i].nrhs;
+        d.info = in[i].info;
+        d.n = 3L * d.op->view.n[0] * d.op->view.n[1] * d.op->view.n[2];
+        d.Lt = layout(*d.op, dtype, d.nrhs, o.restart, o.refine);
+        bind_ws(d, ws + off);
+        off += align256(d.Lt.total);
+    }
+    return run_multi<TK, TC>(I, mode, o, tab, st);
+}
+
+vie_status solve_instances(const vie_solve_instance* in, int count, int dtype, const vie_solve_opts& o, int mode,
+                           char* ws, hipStream_t st)
+{
+    if (dtype == VIE_C64) return solve_typed<float, float>(in, count, dtype, o, mode, ws, st);
+    if (o.refine) return solve_typed<double, float>(in, count, dtype, o, mode, ws, st);
+    return solve_typed<double, double>(in, count, dtype, o, mode, ws, st);
+}
+
 }  // namespace
 }  // namespace vie
 
@@ -365,7 +461,8 @@ size_t vie_solve_workspace_bytes(const vie_op* op, int dtype, int nrhs, const vi
     if (!op || nrhs < 1) return 0;
     vie_solve_opts o = defaults(opts);
     if (o.restart < 1 || o.restart > 200) return 0;
-    return layout(op->d, dtype, nrhs, o.restart, o.refine).total;
+    vie_solve_instance one{op, nullptr, nullptr, nullptr, nrhs, nullptr};
+    return multi_ws_bytes(&one, 1, dtype, o);
 }
 
 vie_status vie_solve(const vie_op* op, int dtype, const void* eps_c, const void* b, void* x, int nrhs,
@@ -380,8 +477,10 @@ vie_status vie_solve(const vie_op* op, int dtype, const void* eps_c, const void*
     if (o.refine && !(o.inner_tol > 0 && o.inner_tol < 1)) return fail(VIE_E_ARG, "vie_solve: inner_tol in (0, 1)");
     if (o.refine && o.inner_recon != VIE_RECON_FP32)
         return fail(VIE_E_UNSUPPORTED, "vie_solve: inner reconstruction must be FP32 in this build");
-    Layout Lt = layout(op->d, dtype, nrhs, o.restart, o.refine);
-    if (ws_bytes < Lt.total) return fail(VIE_E_ARG, "vie_solve: workspace too small");
+    {
+        vie_solve_instance one{op, nullptr, nullptr, nullptr, nrhs, nullptr};
+        if (ws_bytes < multi_ws_bytes(&one, 1, dtype, o)) return fail(VIE_E_ARG, "vie_solve: workspace too small");
+    }
     const OpView& v = op->d.view;
     size_t vbytes = (size_t)nrhs * 3 * v.n[0] * v.n[1] * v.n[2] * (dtype == VIE_C128 ? 16 : 8);
     const char* xb = (const char*)x;
@@ -389,14 +488,8 @@ vie_status vie_solve(const vie_op* op, int dtype, const void* eps_c, const void*
     if (!(xb + vbytes <= bb || bb + vbytes <= xb)) return fail(VIE_E_ARG, "vie_solve: x and b overlap");
     int mode = o.adjoint ? MODE_AH : MODE_A;
     hipStream_t st = (hipStream_t)stream;
-    if (dtype == VIE_C64)
-        return run<float, float>(op, mode, (const c2<float>*)eps_c, (const c2<float>*)b, (c2<float>*)x, nrhs, o,
-                                 info, (char*)ws, Lt, st);
-    if (o.refine)
-        return run<double, float>(op, mode, (const c2<double>*)eps_c, (const c2<double>*)b, (c2<double>*)x, nrhs,
-                                  o, info, (char*)ws, Lt, st);
-    return run<double, double>(op, mode, (const c2<double>*)eps_c, (const c2<double>*)b, (c2<double>*)x, nrhs, o,
-                               info, (char*)ws, Lt, st);
+    vie_solve_instance one{op, eps_c, b, x, nrhs, info};
+    return solve_instances(&one, 1, dtype, o, mode, (char*)ws, st);
 }
 
 vie_status vie_field_gradient(const vie_op* op, int dtype, const void* z, const void* E, double omega_eps0,
@@ -472,6 +565,95 @@ vie_status vie_adjoint_source(const vie_op* op, int dtype, const void* g, const 
     else
         return fail(VIE_E_ARG, "vie_adjoint_source: bad dtype");
     if (e != hipSuccess) return hip_fail(e, "vie_adjoint_source");
+    return VIE_OK;
+}
+
+static vie_status check_solve_opts(const vie_solve_opts& o, int dtype)
+{
+    if (!(o.tol > 0) || o.restart < 1 || o.restart > 200 || o.max_outer < 0 || (o.refine != 0 && o.refine != 1))
+        return fail(VIE_E_ARG, "vie_solve: bad options");
+    if (dtype != VIE_C64 && dtype != VIE_C128) return fail(VIE_E_ARG, "vie_solve: bad dtype");
+    if (o.refine && dtype != VIE_C128) return fail(VIE_E_ARG, "vie_solve: refinement needs VIE_C128 vectors");
+    if (o.refine && !(o.inner_tol > 0 && o.inner_tol < 1)) return fail(VIE_E_ARG, "vie_solve: inner_tol in (0, 1)");
+    if (o.refine && o.inner_recon != VIE_RECON_FP32)
+        return fail(VIE_E_UNSUPPORTED, "vie_solve: inner reconstruction must be FP32 in this build");
+    return VIE_OK;
+}
+
+size_t vie_solve_multi_workspace_bytes(const vie_solve_instance* inst, int count, int dtype, const vie_solve_opts* opts)
+{
+    if (!inst || count < 1) return 0;
+    vie_solve_opts o = defaults(opts);
+    if (o.restart < 1 || o.restart > 200) return 0;
+    for (int i = 0; i < count; ++i)
+        if (!inst[i].op || inst[i].nrhs < 1) return 0;
+    return multi_ws_bytes(inst, count, dtype, o);
+}
+
+vie_status vie_solve_multi(const vie_solve_instance* inst, int count, int dtype, const vie_solve_opts* opts, void* ws,
+                           size_t ws_bytes, void* stream)
+{
+    if (!inst || count < 1 || !ws) return fail(VIE_E_ARG, "vie_solve_multi: bad argument");
+    vie_solve_opts o = defaults(opts);
+    vie_status st = check_solve_opts(o, dtype);
+    if (st != VIE_OK) return st;
+    size_t eb = dtype == VIE_C128 ? 16 : 8;
+    for (int i = 0; i < count; ++i) {
+        const vie_solve_instance& in = inst[i];
+        if (!in.op || !in.eps_c || !in.b || !in.x || in.nrhs < 1) return fail(VIE_E_ARG, "vie_solve_multi: bad instance");
+        const OpView& v = in.op->d.view;
+        size_t vb = (size_t)in.nrhs * 3 * v.n[0] * v.n[1] * v.n[2] * eb;
+        const char* xb = (const char*)in.x;
+        const char* bb = (const char*)in.b;
+        if (!(xb + vb <= bb || bb + vb <= xb)) return fail(VIE_E_ARG, "vie_solve_multi: x and b overlap");
+    }
+    if (ws_bytes < multi_ws_bytes(inst, count, dtype, o)) return fail(VIE_E_ARG, "vie_solve_multi: workspace too small");
+    return solve_instances(inst, count, dtype, o, o.adjoint ? MODE_AH : MODE_A, (char*)ws, (hipStream_t)stream);
+}
+
+size_t vie_matvec_multi_workspace_bytes(const vie_instance* inst, int count, int dtype)
+{
+    if (!inst || count < 1) return 0;
+    size_t el = dtype == VIE_C128 ? 16 : 8;
+    size_t tot = align256(sizeof(InstDev) * (size_t)count);
+    for (int i = 0; i < count; ++i) {
+        if (!inst[i].op || inst[i].nrhs < 1) return 0;
+        tot += align256(matvec_ws_elems(inst[i].op->d, inst[i].nrhs) * el);
+    }
+    return tot;
+}
+
+vie_status vie_matvec_multi(const vie_instance* inst, int count, int kind, int adjoint, int dtype, void* ws,
+                            size_t ws_bytes, void* stream)
+{
+    if (!inst || count < 1 || !ws) return fail(VIE_E_ARG, "vie_matvec_multi: bad argument");
+    if (kind != VIE_OP_A && kind != VIE_OP_N) return fail(VIE_E_ARG, "vie_matvec_multi: bad kind");
+    if (dtype != VIE_C64 && dtype != VIE_C128) return fail(VIE_E_ARG, "vie_matvec_multi: bad dtype");
+    size_t need = vie_matvec_multi_workspace_bytes(inst, count, dtype);
+    if (need == 0 || ws_bytes < need) return fail(VIE_E_ARG, "vie_matvec_multi: workspace too small");
+    int mode = kind == VIE_OP_A ? (adjoint ? MODE_AH : MODE_A) : (adjoint ? MODE_NH : MODE_N);
+    size_t eb = dtype == VIE_C128 ? 16 : 8;
+    std::vector<InstHost> req(count);
+    size_t off = align256(sizeof(InstDev) * (size_t)count);
+    for (int i = 0; i < count; ++i) {
+        const vie_instance& in = inst[i];
+        if (!in.x || !in.y || (kind == VIE_OP_A && !in.eps_c)) return fail(VIE_E_ARG, "vie_matvec_multi: bad instance");
+        if (in.op->d.nhat_source != 0) return fail(VIE_E_UNSUPPORTED, "vie_matvec_multi: Tucker operators only");
+        const OpView& v = in.op->d.view;
+        size_t vb = (size_t)in.nrhs * 3 * v.n[0] * v.n[1] * v.n[2] * eb;
+        const char* xb = (const char*)in.x;
+        const char* yb = (const char*)in.y;
+        if (!(xb + vb <= yb || yb + vb <= xb)) return fail(VIE_E_ARG, "vie_matvec_multi: x and y overlap");
+        req[i] = {&in.op->d, in.x, in.y, in.eps_c, nullptr, in.nrhs, (char*)ws + off};
+        off += align256(matvec_ws_elems(in.op->d, in.nrhs) * eb);
+    }
+    std::string err;
+    hipError_t e;
+    if (dtype == VIE_C128)
+        e = launch_matvec_multi<double, double>(req, mode, (InstDev*)ws, (hipStream_t)stream, err);
+    else
+        e = launch_matvec_multi<float, float>(req, mode, (InstDev*)ws, (hipStream_t)stream, err);
+    if (e != hipSuccess) return err.empty() ? hip_fail(e, "vie_matvec_multi") : fail(VIE_E_UNSUPPORTED, "vie_matvec_multi: " + err);
     return VIE_OK;
 }
 

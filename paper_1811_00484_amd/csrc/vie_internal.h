@@ -56,6 +56,35 @@ struct DeviceOp {
     size_t max_lds = 65536;
 };
 
+// One instance of a multi-instance matvec (several grids, one launch per pass).
+struct InstDev {
+    OpView v;
+    FftPlan plan[3];
+    const void* tw[3];
+    const void* core;
+    const void* fac;
+    const void* x;
+    void* y;
+    const void* eps;
+    const int* map;   // active right-hand sides of this instance (nullptr = 0..nact-1)
+    void* S1;
+    void* S2;
+    int nact;
+    int G;
+    int off[5];       // first block of the instance in each pass
+    int cnt[5];       // blocks of the instance in each pass
+};
+
+struct InstHost {
+    const DeviceOp* op;
+    const void* x;
+    void* y;
+    const void* eps;
+    const int* map;
+    int nact;
+    void* ws;         // matvec workspace of this instance (matvec_ws_elems(op, nact) elements)
+};
+
 // matvec modes
 enum { MODE_A = 0, MODE_AH = 1, MODE_N = 2, MODE_NH = 3 };
 
@@ -65,6 +94,12 @@ template <typename TV, typename T>
 hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* eps, const c2<TV>* x,
                          c2<TV>* y, int nrhs, c2<T>* ws, hipStream_t s, const int* rhs_map,
                          std::string& err);
+
+// Multi-instance matvec: one launch per pass over all instances (mixed-radix
+// LDS kernels).  tab_dev: device scratch for the instance table.
+template <typename TV, typename T>
+hipError_t launch_matvec_multi(const std::vector<InstHost>& inst, int mode, InstDev* tab_dev, hipStream_t s,
+                               std::string& err);
 
 // Sampled Fourier-domain tensor values for tests.
 hipError_t launch_nhat_samples(const DeviceOp& op, int prec, const int* idx_dev, int count,

@@ -60,6 +60,16 @@ class SolveInfo(ctypes.Structure):
                 ("hist_cap", ctypes.c_int), ("hist_len", ctypes.c_int)]
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_void_p), ("eps_c", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("y", ctypes.c_void_p), ("nrhs", ctypes.c_int)]
+
+
+class SolveInstance(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_void_p), ("eps_c", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("nrhs", ctypes.c_int), ("info", ctypes.POINTER(SolveInfo))]
+
+
 # exported symbols and their ctypes signatures (kept in step with include/vie.h)
 _P = ctypes.c_void_p
 _SIGS = {
@@ -77,6 +87,13 @@ _SIGS = {
     "vie_solve_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SolveOpts)]),
     "vie_solve": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int, ctypes.POINTER(SolveOpts),
                                  ctypes.POINTER(SolveInfo), _P, ctypes.c_size_t, _P]),
+    "vie_matvec_multi_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Instance), ctypes.c_int, ctypes.c_int]),
+    "vie_matvec_multi": (ctypes.c_int, [ctypes.POINTER(Instance), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, _P, ctypes.c_size_t, _P]),
+    "vie_solve_multi_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SolveInstance), ctypes.c_int, ctypes.c_int,
+                                                          ctypes.POINTER(SolveOpts)]),
+    "vie_solve_multi": (ctypes.c_int, [ctypes.POINTER(SolveInstance), ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(SolveOpts), _P, ctypes.c_size_t, _P]),
     "vie_field_gradient": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_double, _P, _P, _P]),
     "vie_problem_setup": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_double, _P, _P, _P]),
     "vie_total_field": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_double, _P, _P]),
@@ -252,6 +269,86 @@ def solve(op, b, eps_c, x0=None, tol=1e-6, restart=50, max_outer=200, adjoint=Fa
     if st == VIE_NOT_CONVERGED:
         warnings.warn("vie_solve: not every system reached tol %g" % tol)
     return (x[0] if squeeze else x), out, st
+
+
+_multi_ws = {}
+
+
+def _scratch(nbytes, device):
+    key = (str(device), "multi")
+    t = _multi_ws.get(key)
+    if t is None or t.numel() < nbytes:
+        t = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+        _multi_ws[key] = t
+    return t
+
+
+def matvec_multi(items, kind="A", adjoint=False):
+    """One multi-instance matvec: ``items`` is a list of (op, x, eps_c) with x of
+    shape (nrhs, 3, n3, n2, n1) per instance (grids may differ); returns the
+    list of outputs.  Every pass is one kernel launch over all instances."""
+    lib = load()
+    arr = (Instance * len(items))()
+    outs = []
+    dt = None
+    for i, (op, x, eps_c) in enumerate(items):
+        xb = _as_batch(x, op)
+        dt = _dt(xb) if dt is None else dt
+        if _dt(xb) != dt:
+            raise ValueError("all instances must share a dtype")
+        y = torch.empty_like(xb)
+        outs.append(y)
+        arr[i] = Instance(op.handle, eps_c.data_ptr() if eps_c is not None else None, xb.data_ptr(), y.data_ptr(),
+                          xb.shape[0])
+    k = VIE_OP_A if kind == "A" else VIE_OP_N
+    nbytes = lib.vie_matvec_multi_workspace_bytes(arr, len(items), dt)
+    if nbytes == 0:
+        raise VieError(VIE_E_ARG, "vie_matvec_multi_workspace_bytes rejected the batch")
+    ws = _scratch(nbytes, outs[0].device)
+    _check(lib.vie_matvec_multi(arr, len(items), k, int(bool(adjoint)), dt, _ptr(ws), nbytes, _stream()),
+           "vie_matvec_multi")
+    return outs
+
+
+def solve_multi(items, tol=1e-6, restart=50, max_outer=200, adjoint=False, refine=False, inner_tol=1e-4,
+                history=64):
+    """GMRES on several instances (op, b, eps_c) in lockstep; returns a list
+    of (x, infos) per instance and the overall status."""
+    lib = load()
+    arr = (SolveInstance * len(items))()
+    keep = []
+    xs = []
+    dt = None
+    for i, (op, b, eps_c) in enumerate(items):
+        bb = _as_batch(b, op)
+        dt = _dt(bb) if dt is None else dt
+        x = torch.zeros_like(bb)
+        xs.append(x)
+        infos = (SolveInfo * bb.shape[0])()
+        hist = [(ctypes.c_double * history)() for _ in range(bb.shape[0])]
+        for s_ in range(bb.shape[0]):
+            infos[s_].history = ctypes.cast(hist[s_], ctypes.POINTER(ctypes.c_double))
+            infos[s_].hist_cap = history
+        keep.append((infos, hist, bb))
+        arr[i] = SolveInstance(op.handle, eps_c.data_ptr(), bb.data_ptr(), x.data_ptr(), bb.shape[0],
+                               ctypes.cast(infos, ctypes.POINTER(SolveInfo)))
+    opts = SolveOpts(float(tol), int(restart), int(max_outer), int(bool(adjoint)), int(bool(refine)),
+                     VIE_RECON_FP32, float(inner_tol))
+    nbytes = lib.vie_solve_multi_workspace_bytes(arr, len(items), dt, ctypes.byref(opts))
+    if nbytes == 0:
+        raise VieError(VIE_E_ARG, "vie_solve_multi_workspace_bytes rejected the batch")
+    ws = _scratch(nbytes, xs[0].device)
+    st = _check(lib.vie_solve_multi(arr, len(items), dt, ctypes.byref(opts), _ptr(ws), nbytes, _stream()),
+                "vie_solve_multi")
+    out = []
+    for x, (infos, hist, bb) in zip(xs, keep):
+        lst = []
+        for s_ in range(bb.shape[0]):
+            i_ = infos[s_]
+            lst.append({"matvecs": i_.matvecs, "restarts": i_.restarts, "converged": bool(i_.converged),
+                        "rel_residual": i_.rel_residual, "history": [hist[s_][t] for t in range(i_.hist_len)]})
+        out.append((x, lst))
+    return out, st
 
 
 EPS0 = 8.8541878128e-12
