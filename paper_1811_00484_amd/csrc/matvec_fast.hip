@@ -29,57 +29,97 @@ template <int L>
 struct Pow2Plan;
 template <>
 struct Pow2Plan<512> {
-    template <typename T, int TPP, int NSEQ, int DIR>
-    __device__ static void fwd(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    using TwF = TwTable<512, 1, 8, 8, 8>;
+    using TwI = TwTable<512, 1, 8, 8, 8>;
+    static constexpr int TWI = 0;
+    static constexpr int TW = TWI + TwI::size;   // twiddle-table entries in LDS
+    template <typename T>
+    __device__ static void fill_tw(c2<T>* dst, const c2<T>* tw, int tid, int nt)
     {
-        reg_fft<512, TPP, NSEQ, DIR, T, 8, 8, 8>(v, lds, st, t, tw);
+        TwF::fill(dst, tw, tid, nt);
+        
     }
     template <typename T, int TPP, int NSEQ, int DIR>
-    __device__ static void inv(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    __device__ static void fwd(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tws)
     {
-        reg_fft<512, TPP, NSEQ, DIR, T, 8, 8, 8>(v, lds, st, t, tw);
+        reg_fft<512, TPP, NSEQ, DIR, T, 8, 8, 8>(v, lds, st, t, tws);
+    }
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void inv(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tws)
+    {
+        reg_fft<512, TPP, NSEQ, DIR, T, 8, 8, 8>(v, lds, st, t, tws + TWI);
     }
     static constexpr int RF0 = 8, RFL = 8, RI0 = 8, RIL = 8;
 };
 template <>
 struct Pow2Plan<256> {
-    template <typename T, int TPP, int NSEQ, int DIR>
-    __device__ static void fwd(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    using TwF = TwTable<256, 1, 8, 8, 4>;
+    using TwI = TwTable<256, 1, 4, 8, 8>;
+    static constexpr int TWI = TwF::size;
+    static constexpr int TW = TWI + TwI::size;   // twiddle-table entries in LDS
+    template <typename T>
+    __device__ static void fill_tw(c2<T>* dst, const c2<T>* tw, int tid, int nt)
     {
-        reg_fft<256, TPP, NSEQ, DIR, T, 8, 8, 4>(v, lds, st, t, tw);
+        TwF::fill(dst, tw, tid, nt);
+        TwI::fill(dst + TWI, tw, tid, nt);
     }
     template <typename T, int TPP, int NSEQ, int DIR>
-    __device__ static void inv(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    __device__ static void fwd(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tws)
     {
-        reg_fft<256, TPP, NSEQ, DIR, T, 4, 8, 8>(v, lds, st, t, tw);
+        reg_fft<256, TPP, NSEQ, DIR, T, 8, 8, 4>(v, lds, st, t, tws);
+    }
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void inv(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tws)
+    {
+        reg_fft<256, TPP, NSEQ, DIR, T, 4, 8, 8>(v, lds, st, t, tws + TWI);
     }
     static constexpr int RF0 = 8, RFL = 4, RI0 = 4, RIL = 8;
 };
 template <>
 struct Pow2Plan<128> {
-    template <typename T, int TPP, int NSEQ, int DIR>
-    __device__ static void fwd(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    using TwF = TwTable<128, 1, 8, 4, 4>;
+    using TwI = TwTable<128, 1, 4, 4, 8>;
+    static constexpr int TWI = TwF::size;
+    static constexpr int TW = TWI + TwI::size;   // twiddle-table entries in LDS
+    template <typename T>
+    __device__ static void fill_tw(c2<T>* dst, const c2<T>* tw, int tid, int nt)
     {
-        reg_fft<128, TPP, NSEQ, DIR, T, 8, 4, 4>(v, lds, st, t, tw);
+        TwF::fill(dst, tw, tid, nt);
+        TwI::fill(dst + TWI, tw, tid, nt);
     }
     template <typename T, int TPP, int NSEQ, int DIR>
-    __device__ static void inv(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    __device__ static void fwd(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tws)
     {
-        reg_fft<128, TPP, NSEQ, DIR, T, 4, 4, 8>(v, lds, st, t, tw);
+        reg_fft<128, TPP, NSEQ, DIR, T, 8, 4, 4>(v, lds, st, t, tws);
+    }
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void inv(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tws)
+    {
+        reg_fft<128, TPP, NSEQ, DIR, T, 4, 4, 8>(v, lds, st, t, tws + TWI);
     }
     static constexpr int RF0 = 8, RFL = 4, RI0 = 4, RIL = 8;
 };
 template <>
 struct Pow2Plan<64> {
-    template <typename T, int TPP, int NSEQ, int DIR>
-    __device__ static void fwd(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    using TwF = TwTable<64, 1, 8, 8>;
+    using TwI = TwTable<64, 1, 8, 8>;
+    static constexpr int TWI = 0;
+    static constexpr int TW = TWI + TwI::size;   // twiddle-table entries in LDS
+    template <typename T>
+    __device__ static void fill_tw(c2<T>* dst, const c2<T>* tw, int tid, int nt)
     {
-        reg_fft<64, TPP, NSEQ, DIR, T, 8, 8>(v, lds, st, t, tw);
+        TwF::fill(dst, tw, tid, nt);
+        
     }
     template <typename T, int TPP, int NSEQ, int DIR>
-    __device__ static void inv(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tw)
+    __device__ static void fwd(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tws)
     {
-        reg_fft<64, TPP, NSEQ, DIR, T, 8, 8>(v, lds, st, t, tw);
+        reg_fft<64, TPP, NSEQ, DIR, T, 8, 8>(v, lds, st, t, tws);
+    }
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void inv(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tws)
+    {
+        reg_fft<64, TPP, NSEQ, DIR, T, 8, 8>(v, lds, st, t, tws + TWI);
     }
     static constexpr int RF0 = 8, RFL = 8, RI0 = 8, RIL = 8;
 };
@@ -108,9 +148,9 @@ __global__ void __launch_bounds__(W*(L / E)) k_xy_fast(const void* __restrict__ 
     using Plan = Pow2Plan<L>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T>* buf = reinterpret_cast<c2<T>*>(smem_raw);           // [W][P]
-    c2<T>* tws = buf + (size_t)W * P;                           // [L]
+    c2<T>* tws = buf + (size_t)W * P;                           // [Plan::TW]
     const int tid = threadIdx.x;
-    for (int m = tid; m < L; m += NT) tws[m] = tw[m];
+    Plan::fill_tw(tws, tw, tid, NT);
 
     const int n1 = a.n1, n2 = a.n2, n3 = a.n3, L1 = a.L1, L2 = a.L2;
     const int zq = blockIdx.z, q = zq % 3, bl = zq / 3;
@@ -265,8 +305,8 @@ __device__ __forceinline__ void z_load(c2<T> (&d)[3][8], const c2<T>* __restrict
 }
 
 // 3x3 component product in the output layout of the forward plan
-template <typename T, int L3, int TPP, int RL>
-__device__ __forceinline__ void z_product(c2<T> (&d)[3][8], const c2<T>* NTt, int t, int f1, int f2, int conj)
+template <typename T, int L3, int TPP, int RL, bool CONJ>
+__device__ __forceinline__ void z_product(c2<T> (&d)[3][8], const c2<T>* NTt, int t, int f1, int f2)
 {
     constexpr int E = 8;
     constexpr int N3 = L3 / 2;
@@ -282,7 +322,7 @@ __device__ __forceinline__ void z_product(c2<T> (&d)[3][8], const c2<T>* NTt, in
             for (int c = 0; c < 6; ++c) {
                 c2<T> tv = NTt[c * (N3 + 1) + kk];
                 if (zsign(c, f1, f2, f3) < 0) tv = mk<T>(-tv.x, -tv.y);
-                Nc[c] = conj ? vie::conj(tv) : tv;
+                Nc[c] = CONJ ? vie::conj(tv) : tv;
             }
             const int i = u * RL + r;
             c2<T> x0 = d[0][i], x1 = d[1][i], x2 = d[2][i];
@@ -304,7 +344,7 @@ __device__ __forceinline__ void z_store(const c2<T> (&d)[3][8], c2<T>* __restric
             for (int r = 0; r < RIL / 2; ++r) S2[base + q * cstride + t + TPP * u + r * (L3 / RIL)] = d[q][u * RIL + r];
 }
 
-template <typename T, int L3>
+template <typename T, int L3, bool CONJ>
 __global__ void __launch_bounds__(4 * (L3 / 8)) k_z_fast(c2<T>* __restrict__ S2, const c2<T>* __restrict__ tw,
                                                          ZFastArgs a, const c2<T>* __restrict__ core,
                                                          const c2<T>* __restrict__ fac,
@@ -332,8 +372,8 @@ __global__ void __launch_bounds__(4 * (L3 / 8)) k_z_fast(c2<T>* __restrict__ S2,
     c2<T>* NTB = X + 4 * P;                                     // [6][N3+1]
     c2<T>* Wc = NTB + NTS;                                      // [6][rmax*rmax]
     c2<T>* Vc = Wc + 6 * rmax * rmax;                           // [2][6][rmax]
-    c2<T>* tws = Vc + 12 * rmax;                                // [L3]
-    for (int m = tid; m < L3; m += NT) tws[m] = tw[m];
+    c2<T>* tws = Vc + 12 * rmax;                                // [Plan::TW]
+    Plan::fill_tw(tws, tw, tid, NT);
 
     const int k2 = blockIdx.x % (n2 + 1);
     const int k1b = (blockIdx.x / (n2 + 1)) * a.chunk;
@@ -442,7 +482,7 @@ __global__ void __launch_bounds__(4 * (L3 / 8)) k_z_fast(c2<T>* __restrict__ S2,
             }
         }
         __syncthreads();   // tables complete
-        z_product<T, L3, TPP, Plan::RFL>(d, X, t, s1, s2, a.conj);
+        z_product<T, L3, TPP, Plan::RFL, CONJ>(d, X, t, s1, s2);
         __syncthreads();   // table A consumed: the slices are reused by the inverse FFT
 #pragma unroll
         for (int q = 0; q < 3; ++q) Plan::template inv<T, TPP, 1, 1>(d[q], X + pe * P, 0, t, tws);
@@ -457,7 +497,7 @@ __global__ void __launch_bounds__(4 * (L3 / 8)) k_z_fast(c2<T>* __restrict__ S2,
             z_load<T, L3, TPP, Plan::RF0>(d, S2, baseB, cstride, t, exB);
 #pragma unroll
             for (int q = 0; q < 3; ++q) Plan::template fwd<T, TPP, 1, -1>(d[q], X + pe * P, 0, t, tws);
-            z_product<T, L3, TPP, Plan::RFL>(d, NTB, t, s1, s2, a.conj);
+            z_product<T, L3, TPP, Plan::RFL, CONJ>(d, NTB, t, s1, s2);
 #pragma unroll
             for (int q = 0; q < 3; ++q) Plan::template inv<T, TPP, 1, 1>(d[q], X + pe * P, 0, t, tws);
             if (exB) z_store<T, L3, TPP, Plan::RIL>(d, S2, baseB, cstride, t);
@@ -489,7 +529,7 @@ static void launch_xy(const void* in, void* out, const c2<TV>* x, const c2<TV>* 
     constexpr int E = xy_E<T>();
     constexpr int W = xy_W<T, L>();
     constexpr int NT = W * (L / E);
-    size_t lds = sizeof(c2<T>) * ((size_t)W * PL<L>::value + L);
+    size_t lds = sizeof(c2<T>) * ((size_t)W * PL<L>::value + Pow2Plan<L>::TW);
     auto kern = k_xy_fast<TV, T, L, E, W, KIND>;
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, dim3((grid_x + W - 1) / W, grid_y, nz), dim3(NT), lds, s, in, out, x, eps, tw, a,
@@ -513,7 +553,7 @@ static size_t zfast_lds(const OpView& v)
 {
     static_assert(6 * (L3 / 2 + 1) <= 4 * PL<L3>::value, "N^ table must fit in the FFT slices");
     return sizeof(c2<T>) * ((size_t)4 * PL<L3>::value + 6 * (L3 / 2 + 1) + 6 * (size_t)v.rmax * v.rmax +
-                            12 * v.rmax + L3);
+                            12 * v.rmax + Pow2Plan<L3>::TW);
 }
 
 template <typename T, int L3>
@@ -529,7 +569,7 @@ static hipError_t launch_z(const DeviceOp& op, int mode, int nrhs, c2<T>* S2, co
     int nchunk = (v.n[0] + 1 + za.chunk - 1) / za.chunk;
     size_t lds = zfast_lds<T, L3>(v);
     if (lds > op.max_lds) return hipErrorInvalidValue;
-    auto kern = k_z_fast<T, L3>;
+    auto kern = za.conj ? k_z_fast<T, L3, true> : k_z_fast<T, L3, false>;
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, dim3((v.n[1] + 1) * nchunk, nrhs), dim3(4 * (L3 / 8)), lds, s, S2, tw, za, core, fac,
                        dense);
@@ -560,16 +600,13 @@ bool z_pass_fast(const DeviceOp& op, int mode, int nrhs, c2<T>* S2, const c2<T>*
     switch (v.L[2]) {
     case 512:
         if (zfast_lds<T, 512>(v) > op.max_lds) return false;
-        launch_z<T, 512>(op, mode, nrhs, S2, tw, core, fac, dense, s);
-        return true;
+        return launch_z<T, 512>(op, mode, nrhs, S2, tw, core, fac, dense, s) == hipSuccess;
     case 256:
         if (zfast_lds<T, 256>(v) > op.max_lds) return false;
-        launch_z<T, 256>(op, mode, nrhs, S2, tw, core, fac, dense, s);
-        return true;
+        return launch_z<T, 256>(op, mode, nrhs, S2, tw, core, fac, dense, s) == hipSuccess;
     case 128:
         if (zfast_lds<T, 128>(v) > op.max_lds) return false;
-        launch_z<T, 128>(op, mode, nrhs, S2, tw, core, fac, dense, s);
-        return true;
+        return launch_z<T, 128>(op, mode, nrhs, S2, tw, core, fac, dense, s) == hipSuccess;
     default: return false;
     }
 }

@@ -16,6 +16,11 @@
 // The inverse plan is the forward plan reversed, so a forward transform's
 // output layout is exactly the input layout of the inverse transform and the
 // Fourier-domain product in between needs no data movement.
+//
+// Twiddles come from a per-plan LDS table laid out stage by stage (TwTable):
+// the stage with Ns > 1 owns (R - 1) Ns entries, entry (r - 1) Ns + k =
+// w^(r k L / (Ns R)), so the lanes of a wavefront read consecutive entries
+// (or broadcast one), never several entries of one bank.
 #pragma once
 #include "dev_common.h"
 #include "fft_device.h"
@@ -64,10 +69,9 @@ __device__ __forceinline__ void reg_stage(c2<T>* v, int t, const c2<T>* __restri
         if constexpr (NS > 1) {
             const int j = t + TPP * u;
             const int k = j % NS;
-            constexpr int TS = L / (NS * R);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                c2<T> w = tw[r * k * TS];
+                c2<T> w = tw[(r - 1) * NS + k];
                 v[u * R + r] = (DIR < 0) ? v[u * R + r] * w : mulc(v[u * R + r], w);
             }
         }
@@ -134,7 +138,8 @@ struct RegFFTImpl {
 #pragma unroll
             for (int s = 0; s < NSEQ; ++s) reg_load<L, TPP, RN>(v + s * E, lds + s * stride, t);
             stage_sync<WAVE>();
-            RegFFTImpl<L, TPP, NSEQ, DIR, NS * R0, WAVE, T, Rs...>::run(v, lds, stride, t, tw);
+            constexpr int OWN = NS > 1 ? (R0 - 1) * NS : 0;   // this stage's twiddle entries
+            RegFFTImpl<L, TPP, NSEQ, DIR, NS * R0, WAVE, T, Rs...>::run(v, lds, stride, t, tw + OWN);
         }
     }
 };
@@ -149,6 +154,32 @@ __device__ __forceinline__ void reg_fft(c2<T>* v, c2<T>* lds, int stride, int t,
     constexpr bool WAVE = (TPP <= 64) && (64 % TPP == 0);
     RegFFTImpl<L, TPP, NSEQ, DIR, 1, WAVE, T, Rs...>::run(v, lds, stride, t, tw);
 }
+
+// Stage-ordered twiddle table of a plan (radices Rs applied left to right,
+// NS = product of the radices before them).
+template <int L, int NS, int... Rs>
+struct TwTable {
+    static constexpr int size = 0;
+    template <typename T>
+    __device__ static void fill(c2<T>*, const c2<T>*, int, int)
+    {
+    }
+};
+template <int L, int NS, int R0, int... Rs>
+struct TwTable<L, NS, R0, Rs...> {
+    static constexpr int own = NS > 1 ? (R0 - 1) * NS : 0;
+    static constexpr int size = own + TwTable<L, NS * R0, Rs...>::size;
+    // tw: w^m, m < L, w = exp(-2 pi i / L)
+    template <typename T>
+    __device__ static void fill(c2<T>* dst, const c2<T>* __restrict__ tw, int tid, int nt)
+    {
+        for (int e = tid; e < own; e += nt) {
+            const int r = e / NS + 1, k = e - (r - 1) * NS;
+            dst[e] = tw[r * k * (L / (NS * R0))];
+        }
+        TwTable<L, NS * R0, Rs...>::fill(dst + own, tw, tid, nt);
+    }
+};
 
 // LDS slice length (elements) for one pencil including the padding
 template <int L>
