@@ -26,6 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3   # MI355X vector / dense-MFMA FP32
 
 
 def log(*a):
@@ -39,6 +40,42 @@ PASS_ELEMS_V = [3 + 6, 6 + 12, 12 + 12, 12 + 6, 6 + 3 + 1 + 3]
 
 
 COPY_CAL_BYTES = 1 << 30   # plain copy used to calibrate the HBM byte counters
+
+
+def z_pass_flops(n, ranks):
+    """Algorithmic FP32 flops of one Z-pass launch (one rhs): forward and
+    inverse length-2n3 FFTs of 3 components over the (2n1)(2n2) pencils at
+    5 L log2 L each, the 3x3 complex product (9 complex MACs = 72 flops) at
+    every Fourier point, and the Tucker reconstruction of the half spectrum
+    (N^ tables: (n1+1)(n2+1)(n3+1) r3 complex MACs per component, plus the
+    per-(k1,k2) and per-k2 core contractions)."""
+    n1, n2, n3 = n
+    L1, L2, L3 = 2 * n1, 2 * n2, 2 * n3
+    fft = 2 * 3 * L1 * L2 * 5 * L3 * np.log2(L3)
+    prod = 72.0 * L1 * L2 * L3
+    rec = 0.0
+    for r1, r2, r3 in ranks:
+        rec += 8.0 * ((n1 + 1) * (n2 + 1) * (n3 + 1) * r3 + (n1 + 1) * (n2 + 1) * r1 * r3 + (n2 + 1) * r1 * r2 * r3)
+    return float(fft + prod + rec)
+
+
+def copy_bandwidth(torch, dev, reps=5):
+    """Measured device copy rate (GB/s, read + write) of one elementwise
+    kernel over 1 GiB: what HBM delivers to a plain streaming kernel."""
+    src = torch.ones(COPY_CAL_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * COPY_CAL_BYTES / (ms * 1e-3) / 1e9
 
 
 def kernel_sources_sha256():
@@ -135,11 +172,36 @@ def main():
     e = torch.from_numpy(epsc.astype(np.complex64)).to(dev)
     y = torch.empty_like(x)
 
-    def run(steps):
-        for _ in range(steps):
-            vie.matvec(op, x, e, out=y)
+    st = torch.cuda.current_stream()
 
-    run(args.warmup)
+    def run(steps, recon):
+        for _ in range(steps):
+            vie.matvec(op, x, e, out=y, recon=recon)
+
+    def timed(recon, profile):
+        """ms per matvec over the timed steps (HIP events on the library's
+        stream) and, with ``profile``, the per-pass kernel averages."""
+        run(args.warmup, recon)
+        torch.cuda.synchronize()
+        if profile:
+            vie.profile_enable(True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.time()
+        ev0.record(st)
+        run(args.steps, recon)
+        ev1.record(st)
+        torch.cuda.synchronize()
+        wall = time.time() - w0
+        avg = None
+        if profile:
+            vie.profile_enable(False)
+            pass_ms, pass_cnt = vie.profile_collect()
+            avg = [pass_ms[p] / max(1, pass_cnt[p]) for p in range(5)]
+        return ev0.elapsed_time(ev1) / args.steps, avg, wall
+
+    run(args.warmup, "fp32")
     torch.cuda.synchronize()
     if args.copy_calibration:
         src = torch.ones(COPY_CAL_BYTES // 4, dtype=torch.float32, device=dev)
@@ -147,53 +209,48 @@ def main():
         torch.neg(src, out=dst)   # one elementwise kernel: reads and writes COPY_CAL_BYTES each
         torch.cuda.synchronize()
         del src, dst
-    vie.profile_enable(True)
-    st = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.time()
-    ev0.record(st)
-    run(args.steps)
-    ev1.record(st)
-    torch.cuda.synchronize()
-    wall = time.time() - w0
-    vie.profile_enable(False)
-    pass_ms, pass_cnt = vie.profile_collect()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    ms, avg, wall = timed("fp32", True)
+    y32 = y.clone()
     value = 1000.0 / ms
     alg_bytes = 8.0 * V * sum(PASS_ELEMS_V)
     gbs = alg_bytes / (ms * 1e-3) / 1e9
-    avg = [pass_ms[p] / max(1, pass_cnt[p]) for p in range(5)]
     dom = int(np.argmax(avg))
     dom_bytes = 8.0 * V * PASS_ELEMS_V[dom]
     dom_gbs = dom_bytes / (avg[dom] * 1e-3) / 1e9
     log("matvec: %.3f ms (%.1f matvecs/s, %.0f GB/s algorithmic); passes %s ms" %
         (ms, value, gbs, ["%.3f" % a for a in avg]))
+    zflops = z_pass_flops(n, op.ranks)
+    copy_gbs = copy_bandwidth(torch, dev)
+    log("device copy: %.0f GB/s" % copy_gbs)
 
     extra = {}
+    # BF16 MFMA reconstruction (the inner operator of the refined solve)
+    ms16, avg16, _ = timed("bf16", True)
+    y16 = y.clone()
+    extra["bf16_recon"] = {"ms_per_matvec": ms16, "matvecs_per_s": 1000.0 / ms16,
+                           "alg_GBps": alg_bytes / (ms16 * 1e-3) / 1e9,
+                           "pass_avg_ms": dict(zip(PASS_NAMES, avg16)),
+                           "rel_diff_vs_fp32_recon": float(torch.linalg.vector_norm(y16 - y32) /
+                                                           torch.linalg.vector_norm(y32))}
+    log("bf16-reconstruction matvec: %.3f ms; passes %s ms" % (ms16, ["%.3f" % a for a in avg16]))
     if not args.no_dense:
         vie.densify(op)
         vie.set_nhat(op, "dense")
-        run(args.warmup)
-        torch.cuda.synchronize()
-        d0 = torch.cuda.Event(enable_timing=True)
-        d1 = torch.cuda.Event(enable_timing=True)
-        d0.record(st)
-        run(args.steps)
-        d1.record(st)
-        torch.cuda.synchronize()
-        dms = d0.elapsed_time(d1) / args.steps
+        dms, davg, _ = timed("fp32", True)
         vie.set_nhat(op, "tucker")
         dense_half_bytes = 6 * (N + 1) ** 3 * 8
         extra["dense"] = {"ms_per_matvec": dms, "matvecs_per_s": 1000.0 / dms,
                           "alg_GBps": (alg_bytes + dense_half_bytes) / (dms * 1e-3) / 1e9,
                           "operator_bytes_half_spectrum_c64": dense_half_bytes,
-                          "operator_bytes_full_spectrum_c64": op.dense_bytes_c64}
+                          "operator_bytes_full_spectrum_c64": op.dense_bytes_c64,
+                          "pass_avg_ms": dict(zip(PASS_NAMES, davg))}
         log("dense-spectrum matvec: %.3f ms" % dms)
     extra["memory"] = {"tucker_operator_bytes_c64": op.tucker_bytes_c64,
                        "dense_operator_bytes_c64": op.dense_bytes_c64,
-                       "compression_factor": op.dense_bytes_c64 / op.tucker_bytes_c64}
+                       "compression_factor": op.dense_bytes_c64 / op.tucker_bytes_c64,
+                       "operator_device_bytes_all_copies": op.device_bytes,
+                       "workspace_bytes_per_rhs_c64": vie.workspace_bytes(op, torch.complex64, 1),
+                       "vector_bytes_c64": 3 * V * 8}
 
     if not args.no_solve:
         extra["solve"] = solves(op, b, epsc, dev, vie, torch)
@@ -215,12 +272,17 @@ def main():
                                "HOSVD tol %g, complex64 (FP32 FFT + FP32 Tucker reconstruction), 1 rhs "
                                "(x-polarised plane wave)" % (N, h * 1e3, args.tol),
                    "grid": list(n), "ranks": op.ranks, "alg_bytes_per_matvec": alg_bytes,
-                   "alg_GBps": gbs, "wall_s_timed": wall},
+                   "alg_GBps": gbs, "wall_s_timed": wall, "device_copy_GBps_measured": copy_gbs,
+                   "alg_GBps_frac_of_measured_copy": gbs / copy_gbs},
         "roofline": {"bound": "hbm", "kernel": PASS_NAMES[dom], "achieved": dom_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
                      "traffic": recorded_traffic(PASS_NAMES[dom], N),
                      "avg_ms": avg[dom], "alg_bytes_per_launch": dom_bytes,
-                     "pass_avg_ms": dict(zip(PASS_NAMES, avg))},
+                     "pass_avg_ms": dict(zip(PASS_NAMES, avg)),
+                     "alu": {"kernel": "z_fused", "achieved": zflops / (avg[2] * 1e-3) / 1e12,
+                             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": zflops / (avg[2] * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+                             "alg_flops_per_launch": zflops}},
     }
     result.update(extra)
     if not args.no_cpu_baseline:
@@ -228,27 +290,32 @@ def main():
         log("cpu baseline: timing the FP64 oracle matvec ...")
         cb, y_ref = cpu_baseline(G, epsc, u)
         result["cpu_baseline"] = cb
-        yg = y.cpu().numpy().astype(np.complex128)
-        result["config"]["matvec_rel_err_vs_oracle_dense"] = float(np.linalg.norm(yg - y_ref) /
-                                                                   np.linalg.norm(y_ref))
+        for key, yy in (("matvec_rel_err_vs_oracle_dense", y32), ("bf16_matvec_rel_err_vs_oracle_dense", y16)):
+            yg = yy.cpu().numpy().astype(np.complex128)
+            result["config"][key] = float(np.linalg.norm(yg - y_ref) / np.linalg.norm(y_ref))
     print(json.dumps(result), flush=True)
 
 
 def solves(op, b, epsc, dev, vie, torch):
-    """Seconds per solve to an FP64 true residual of 1e-6: refined
-    (FP64 residual + FP64 Arnoldi, FP32-computed operator) and plain FP32."""
+    """Seconds per solve to an FP64 true residual of 1e-6: refined (FP64
+    residual + FP64 Arnoldi around the FP32-computed operator, with FP32 or
+    BF16-MFMA reconstruction) and plain FP32 (FP32 Arnoldi and residual,
+    checked afterwards in FP64)."""
     out = {}
     bb = torch.from_numpy(b).to(dev)
     ee = torch.from_numpy(epsc).to(dev)
-    torch.cuda.synchronize()
-    t0 = time.time()
-    x, info, st = vie.solve(op, bb, ee, tol=1e-6, restart=50, max_outer=20, refine=True, inner_tol=1e-5)
-    torch.cuda.synchronize()
-    t_ref = time.time() - t0
-    out["refined_fp64_residual"] = {"seconds": t_ref, "converged": info[0]["converged"],
-                                    "rel_residual_fp64": info[0]["rel_residual"],
-                                    "matvecs_fp32": info[0]["matvecs"], "matvecs_fp64": info[0]["matvecs_fp64"]}
-    log("refined solve: %.2f s, %s" % (t_ref, info[0]))
+    for key, rc, itol in (("refined_fp32_recon", "fp32", 1e-5), ("refined_bf16_recon", "bf16", 1e-3)):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        x, info, st = vie.solve(op, bb, ee, tol=1e-6, restart=50, max_outer=20, refine=True, inner_tol=itol,
+                                inner_recon=rc)
+        torch.cuda.synchronize()
+        t = time.time() - t0
+        out[key] = {"seconds": t, "converged": bool(info[0]["converged"]), "inner_tol": itol,
+                    "rel_residual_fp64": info[0]["rel_residual"], "matvecs_inner": info[0]["matvecs"],
+                    "matvecs_fp64": info[0]["matvecs_fp64"], "refine_steps": info[0]["refine_steps"]}
+        log("refined solve (%s reconstruction): %.2f s, %s" % (rc, t, info[0]))
+        del x
     b32 = bb.to(torch.complex64)
     e32 = ee.to(torch.complex64)
     torch.cuda.synchronize()
@@ -258,7 +325,7 @@ def solves(op, b, epsc, dev, vie, torch):
     t_32 = time.time() - t0
     r = vie.matvec(op, x32.to(torch.complex128), ee)
     res64 = (torch.linalg.vector_norm(bb - r) / torch.linalg.vector_norm(bb)).item()
-    out["plain_fp32"] = {"seconds": t_32, "converged_fp32_residual": info32[0]["converged"],
+    out["plain_fp32"] = {"seconds": t_32, "converged_fp32_residual": bool(info32[0]["converged"]),
                          "rel_residual_fp32": info32[0]["rel_residual"], "rel_residual_fp64": res64,
                          "reached_1e-6_fp64": res64 <= 1e-6, "matvecs": info32[0]["matvecs"]}
     log("plain fp32 solve: %.2f s, fp64 residual %.3e, %s" % (t_32, res64, info32[0]))

@@ -83,9 +83,12 @@ typedef struct {
     int ranks[6][3];         /* Tucker ranks (r1, r2, r3) per component */
     double tail_bound[6];    /* sqrt(sum of discarded sigma^2 over the 3 unfoldings) / ||A||_F */
     double fro_norm[6];      /* ||A_c||_F of each defining tensor */
-    size_t tucker_bytes_c64; /* device bytes of cores + Fourier factors at complex64 */
+    size_t tucker_bytes_c64; /* bytes of the cores + Fourier factors (rows 0..n_i), each stored
+                                once, at complex64: the compressed operator */
     size_t dense_bytes_c64;  /* bytes of the 6 dense circulant spectra (8 n1 n2 n3 points each)
                                 at complex64: what the uncompressed method stores */
+    size_t device_bytes;     /* all device memory the operator holds: FP64, FP32 and BF16
+                                copies, the kernels' extra z-factor layouts, twiddles */
     double seconds;          /* host time of the compression */
 } vie_compress_info;
 
@@ -132,7 +135,11 @@ size_t vie_workspace_bytes(const vie_op* op, int dtype, int nrhs);
  * vie_matvec -- y = A x (kind VIE_OP_A) or y = N x (kind VIE_OP_N) for nrhs
  * right-hand sides sharing one operator and one eps_c.
  *   dtype   VIE_C64 or VIE_C128: element type of eps_c, x, y and of the FFTs.
- *   recon   VIE_RECON_*: arithmetic of the Tucker reconstruction.
+ *   recon   VIE_RECON_*: arithmetic of the Tucker reconstruction (eq. 14 per
+ *           k-pencil).  VIE_RECON_BF16 (VIE_C64 only): the z-factor contraction
+ *           runs on MFMA with BF16 inputs and FP32 accumulation, about 1e-3
+ *           relative error in N^; needs 2 n3 in {128, 256, 512} and z ranks
+ *           <= 32, else VIE_E_UNSUPPORTED.
  *   eps_c   DEVICE [n3][n2][n1] complex relative permittivity
  *           eps_r - i sigma/(omega eps0); ignored (may be NULL) for VIE_OP_N.
  *   x       DEVICE [nrhs][3][n3][n2][n1] input.
@@ -162,7 +169,8 @@ typedef struct {
                           residual with the FP64 operator, inner GMRES(m) cycles with FP64
                           Arnoldi on the `inner_recon` operator computed in FP32 (dtype must
                           be VIE_C128) */
-    int inner_recon;   /* refine = 1: VIE_RECON_FP32 or VIE_RECON_BF16 */
+    int inner_recon;   /* refine = 1: VIE_RECON_FP32 or VIE_RECON_BF16 (single-instance
+                          solves; the FP64 residual recovers the BF16 error) */
     double inner_tol;  /* refine = 1: relative reduction asked of each inner cycle */
 } vie_solve_opts;
 

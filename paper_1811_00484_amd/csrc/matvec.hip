@@ -615,7 +615,11 @@ hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* 
         fac = op.d32.fac;
         dense = op.dense32;
     }
-    (void)recon;
+    if (recon == 1 && (sizeof(T) != 4 || g_kernel_path != 0 || !bf16_recon_available(op))) {
+        err = "BF16 reconstruction needs complex64, the register-FFT z pass (2 n3 = 128, 256 or 512) "
+              "and z ranks <= 32";
+        return hipErrorInvalidValue;
+    }
     constexpr int MAXE_XY = 32;   // W * L <= MAXE * NT for W*L <= 8192
     constexpr int MAXE_Z = 24;    // 3 * G * L3 <= 6144
 
@@ -662,7 +666,10 @@ hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* 
     }
     {
         PassTimer timer(2, s);
-        if (allow_fast && z_pass_fast<T>(op, mode, nrhs, S2, tw[2], core, fac, dense, s)) {
+        if (allow_fast && z_pass_fast<T>(op, mode, recon, nrhs, S2, tw[2], core, fac, dense, s)) {
+        } else if (recon == 1) {
+            err = "BF16 z pass could not be launched";
+            return hipErrorInvalidValue;
         } else {
         int G = 4;
         while (G > 1 && z_lds_bytes<T>(v, G) > op.max_lds) G /= 2;

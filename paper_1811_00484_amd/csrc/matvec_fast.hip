@@ -344,11 +344,76 @@ __device__ __forceinline__ void z_store(const c2<T> (&d)[3][8], c2<T>* __restric
             for (int r = 0; r < RIL / 2; ++r) S2[base + q * cstride + t + TPP * u + r * (L3 / RIL)] = d[q][u * RIL + r];
 }
 
-template <typename T, int L3, bool CONJ>
-__global__ void __launch_bounds__(4 * (L3 / 8)) k_z_fast(c2<T>* __restrict__ S2, const c2<T>* __restrict__ tw,
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+// N^ tables of a quad pair from the BF16 z factors on MFMA (FP32 accumulate).
+// Per component the pair's tables are the real product
+//   [Re T_A, Im T_A, Re T_B, Im T_B] (rows k3) = [Re U3 | Im U3] (rows k3, 2 rh)
+//     x [[Re V_A, Im V_A, Re V_B, Im V_B], [-Im V_A, Re V_A, -Im V_B, Re V_B]],
+// done as 16 x 16 x 32 tiles (only the first 4 of the 16 output columns are
+// used).  Each wavefront takes every NWV-th row tile; lane l holds A row
+// l mod 16 and B column l mod 16 with K positions 8 (l / 16) .. +7 of each
+// 32-wide step, and receives output rows 4 (l / 16) .. +3 of column l mod 16.
+template <int L3>
+__device__ __forceinline__ void z_tables_mfma(const OpView& v, const unsigned short* __restrict__ f3m,
+                                              const c2<float>* Vc, c2<float>* tabA, c2<float>* tabB, int tid,
+                                              int nt)
+{
+    constexpr int N3 = L3 / 2;
+    constexpr int NTILE = (N3 + 1 + 15) / 16;
+    const int rmax = v.rmax;
+    const int lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    float* fa = reinterpret_cast<float*>(tabA);
+    float* fb = reinterpret_cast<float*>(tabB);
+    const c2<float>* vq = Vc + ((col >> 1) & 1) * 6 * rmax;
+#pragma unroll 1
+    for (int c = 0; c < 6; ++c) {
+        const int r3 = v.r[c][2], rh = v.rh[c];
+        bf16x8 bop[2];
+#pragma unroll
+        for (int st = 0; st < 2; ++st)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 32 * st + 8 * grp + e;
+                const bool hi = k >= rh;
+                const int g = hi ? k - rh : k;
+                const bool ok = (col < 4) & (k < 2 * rh) & (g < r3);
+                const c2<float> w = vq[c * rmax + (ok ? g : 0)];
+                const float re = hi ? -w.y : w.x, im = hi ? w.x : w.y;
+                bop[st][e] = (__bf16)(ok ? ((col & 1) ? im : re) : 0.f);
+            }
+        const unsigned short* base = f3m + v.fac3m_off[c] + 8 * grp;
+#pragma unroll 1
+        for (int tile = wv; tile < NTILE; tile += nwv) {
+            const unsigned short* row = base + (size_t)(tile * 16 + col) * (2 * rh);
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(row), bop[0], acc, 0, 0,
+                                                          0);
+            if (rh > 16)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(row + 32), bop[1],
+                                                              acc, 0, 0, 0);
+            if (col < 4) {
+                float* dst = (col >> 1) ? fb : fa;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int kk = tile * 16 + 4 * grp + q;
+                    if (kk <= N3) dst[2 * (c * (N3 + 1) + kk) + (col & 1)] = acc[q];
+                }
+            }
+        }
+    }
+}
+
+// REC: 0 = N^ tables in T on the vector ALUs, 1 = BF16 z factors on MFMA
+// (T = float).
+template <typename T, int L3, bool CONJ, int REC>
+__global__ void __launch_bounds__(4 * (L3 / 8), sizeof(T) == 4 ? 3 : 2) k_z_fast(c2<T>* __restrict__ S2, const c2<T>* __restrict__ tw,
                                                          ZFastArgs a, const c2<T>* __restrict__ core,
                                                          const c2<T>* __restrict__ fac,
-                                                         const c2<T>* __restrict__ dense)
+                                                         const c2<T>* __restrict__ dense,
+                                                         const unsigned short* __restrict__ f3m)
 {
     constexpr int TPP = L3 / 8;
     constexpr int NT = 4 * TPP;
@@ -448,7 +513,9 @@ __global__ void __launch_bounds__(4 * (L3 / 8)) k_z_fast(c2<T>* __restrict__ S2,
 
         // ---- N^ tables of both quads: each z-factor element is loaded once
         //      and used for the two quads
-        if (!a.dense) {
+        if (!a.dense && REC == 1) {
+            if constexpr (REC == 1) z_tables_mfma<L3>(v, f3m, Vc, X, NTB, tid, NT);
+        } else if (!a.dense) {
             for (int e = tid; e < NTS; e += NT) {
                 const int c = e / (N3 + 1), kk = e - c * (N3 + 1);
                 const int r3 = v.r[c][2];
@@ -557,7 +624,7 @@ static size_t zfast_lds(const OpView& v)
 }
 
 template <typename T, int L3>
-static hipError_t launch_z(const DeviceOp& op, int mode, int nrhs, c2<T>* S2, const c2<T>* tw,
+static hipError_t launch_z(const DeviceOp& op, int mode, int recon, int nrhs, c2<T>* S2, const c2<T>* tw,
                            const c2<T>* core, const c2<T>* fac, const c2<T>* dense, hipStream_t s)
 {
     const OpView& v = op.view;
@@ -569,10 +636,13 @@ static hipError_t launch_z(const DeviceOp& op, int mode, int nrhs, c2<T>* S2, co
     int nchunk = (v.n[0] + 1 + za.chunk - 1) / za.chunk;
     size_t lds = zfast_lds<T, L3>(v);
     if (lds > op.max_lds) return hipErrorInvalidValue;
-    auto kern = za.conj ? k_z_fast<T, L3, true> : k_z_fast<T, L3, false>;
+    auto kern = za.conj ? k_z_fast<T, L3, true, 0> : k_z_fast<T, L3, false, 0>;
+    if constexpr (sizeof(T) == 4) {
+        if (recon == 1) kern = za.conj ? k_z_fast<T, L3, true, 1> : k_z_fast<T, L3, false, 1>;
+    }
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, dim3((v.n[1] + 1) * nchunk, nrhs), dim3(4 * (L3 / 8)), lds, s, S2, tw, za, core, fac,
-                       dense);
+                       dense, (const unsigned short*)op.b16.fac3m);
     return hipGetLastError();
 }
 
@@ -592,21 +662,32 @@ bool xy_pass_fast(int kind, int L, const void* in, void* out, const c2<TV>* x, c
     }
 }
 
+bool bf16_recon_available(const DeviceOp& op)
+{
+    const OpView& v = op.view;
+    if (!op.b16.fac3m) return false;
+    if (v.L[2] != 512 && v.L[2] != 256 && v.L[2] != 128) return false;
+    for (int c = 0; c < 6; ++c)
+        if (v.rh[c] == 0) return false;
+    return true;
+}
+
 template <typename T>
-bool z_pass_fast(const DeviceOp& op, int mode, int nrhs, c2<T>* S2, const c2<T>* tw, const c2<T>* core,
+bool z_pass_fast(const DeviceOp& op, int mode, int recon, int nrhs, c2<T>* S2, const c2<T>* tw, const c2<T>* core,
                  const c2<T>* fac, const c2<T>* dense, hipStream_t s)
 {
     const OpView& v = op.view;
+    if (recon == 1 && (sizeof(T) != 4 || !bf16_recon_available(op))) return false;
     switch (v.L[2]) {
     case 512:
         if (zfast_lds<T, 512>(v) > op.max_lds) return false;
-        return launch_z<T, 512>(op, mode, nrhs, S2, tw, core, fac, dense, s) == hipSuccess;
+        return launch_z<T, 512>(op, mode, recon, nrhs, S2, tw, core, fac, dense, s) == hipSuccess;
     case 256:
         if (zfast_lds<T, 256>(v) > op.max_lds) return false;
-        return launch_z<T, 256>(op, mode, nrhs, S2, tw, core, fac, dense, s) == hipSuccess;
+        return launch_z<T, 256>(op, mode, recon, nrhs, S2, tw, core, fac, dense, s) == hipSuccess;
     case 128:
         if (zfast_lds<T, 128>(v) > op.max_lds) return false;
-        return launch_z<T, 128>(op, mode, nrhs, S2, tw, core, fac, dense, s) == hipSuccess;
+        return launch_z<T, 128>(op, mode, recon, nrhs, S2, tw, core, fac, dense, s) == hipSuccess;
     default: return false;
     }
 }
@@ -617,9 +698,9 @@ bool z_pass_fast(const DeviceOp& op, int mode, int nrhs, c2<T>* S2, const c2<T>*
 VIE_XYF_INST(float, float)
 VIE_XYF_INST(double, double)
 VIE_XYF_INST(double, float)
-template bool z_pass_fast<float>(const DeviceOp&, int, int, c2<float>*, const c2<float>*, const c2<float>*,
+template bool z_pass_fast<float>(const DeviceOp&, int, int, int, c2<float>*, const c2<float>*, const c2<float>*,
                                  const c2<float>*, const c2<float>*, hipStream_t);
-template bool z_pass_fast<double>(const DeviceOp&, int, int, c2<double>*, const c2<double>*, const c2<double>*,
-                                  const c2<double>*, const c2<double>*, hipStream_t);
+template bool z_pass_fast<double>(const DeviceOp&, int, int, int, c2<double>*, const c2<double>*,
+                                  const c2<double>*, const c2<double>*, const c2<double>*, hipStream_t);
 
 }  // namespace vie

@@ -126,14 +126,20 @@ struct Inst {
     std::vector<int> cyc, run;
 };
 
+// recon 1: BF16 MFMA reconstruction (single-instance register-FFT path only)
 template <typename TV, typename T>
-hipError_t mv_dispatch(const std::vector<InstHost>& req, int mode, InstDev* tab, hipStream_t st, std::string& err)
+hipError_t mv_dispatch(const std::vector<InstHost>& req, int mode, InstDev* tab, hipStream_t st, std::string& err,
+                       int recon = 0)
 {
     if (req.empty()) return hipSuccess;
     if (req.size() == 1) {
         const InstHost& h = req[0];
-        return launch_matvec<TV, T>(*h.op, mode, 0, (const c2<TV>*)h.eps, (const c2<TV>*)h.x, (c2<TV>*)h.y, h.nact,
-                                    (c2<T>*)h.ws, st, h.map, err);
+        return launch_matvec<TV, T>(*h.op, mode, recon, (const c2<TV>*)h.eps, (const c2<TV>*)h.x, (c2<TV>*)h.y,
+                                    h.nact, (c2<T>*)h.ws, st, h.map, err);
+    }
+    if (recon != 0) {
+        err = "BF16 reconstruction is not available for multi-instance batches";
+        return hipErrorInvalidValue;
     }
     return launch_matvec_multi<TV, T>(req, mode, tab, st, err);
 }
@@ -142,6 +148,7 @@ template <typename TK, typename TC>
 vie_status run_multi(std::vector<Inst<TK>>& I, int mode, const vie_solve_opts& o, InstDev* tab, hipStream_t st)
 {
     const int m = o.restart;
+    const int inner_recon = (o.refine && o.inner_recon == VIE_RECON_BF16) ? 1 : 0;
     hipError_t e;
     std::string err;
     auto upload_map = [&](Inst<TK>& in, const std::vector<int>& mp) -> hipError_t {
@@ -268,7 +275,7 @@ vie_status run_multi(std::vector<Inst<TK>>& I, int mode, const vie_solve_opts& o
                                (int)in.run.size(), in.mws});
             }
             if (req.empty()) break;
-            if ((e = mv_dispatch<TK, TC>(req, mode, tab, st, err)) != hipSuccess)
+            if ((e = mv_dispatch<TK, TC>(req, mode, tab, st, err, inner_recon)) != hipSuccess)
                 return err.empty() ? hip_fail(e, "vie_solve matvec") : fail(VIE_E_UNSUPPORTED, err);
             for (auto& in : I) {
                 if (in.run.empty()) continue;
@@ -475,8 +482,8 @@ vie_status vie_solve(const vie_op* op, int dtype, const void* eps_c, const void*
     if (dtype != VIE_C64 && dtype != VIE_C128) return fail(VIE_E_ARG, "vie_solve: bad dtype");
     if (o.refine && dtype != VIE_C128) return fail(VIE_E_ARG, "vie_solve: refinement needs VIE_C128 vectors");
     if (o.refine && !(o.inner_tol > 0 && o.inner_tol < 1)) return fail(VIE_E_ARG, "vie_solve: inner_tol in (0, 1)");
-    if (o.refine && o.inner_recon != VIE_RECON_FP32)
-        return fail(VIE_E_UNSUPPORTED, "vie_solve: inner reconstruction must be FP32 in this build");
+    if (o.refine && o.inner_recon != VIE_RECON_FP32 && o.inner_recon != VIE_RECON_BF16)
+        return fail(VIE_E_ARG, "vie_solve: inner_recon must be VIE_RECON_FP32 or VIE_RECON_BF16");
     {
         vie_solve_instance one{op, nullptr, nullptr, nullptr, nrhs, nullptr};
         if (ws_bytes < multi_ws_bytes(&one, 1, dtype, o)) return fail(VIE_E_ARG, "vie_solve: workspace too small");
@@ -575,8 +582,8 @@ static vie_status check_solve_opts(const vie_solve_opts& o, int dtype)
     if (dtype != VIE_C64 && dtype != VIE_C128) return fail(VIE_E_ARG, "vie_solve: bad dtype");
     if (o.refine && dtype != VIE_C128) return fail(VIE_E_ARG, "vie_solve: refinement needs VIE_C128 vectors");
     if (o.refine && !(o.inner_tol > 0 && o.inner_tol < 1)) return fail(VIE_E_ARG, "vie_solve: inner_tol in (0, 1)");
-    if (o.refine && o.inner_recon != VIE_RECON_FP32)
-        return fail(VIE_E_UNSUPPORTED, "vie_solve: inner reconstruction must be FP32 in this build");
+    if (o.refine && o.inner_recon != VIE_RECON_FP32 && o.inner_recon != VIE_RECON_BF16)
+        return fail(VIE_E_ARG, "vie_solve: inner_recon must be VIE_RECON_FP32 or VIE_RECON_BF16");
     return VIE_OK;
 }
 

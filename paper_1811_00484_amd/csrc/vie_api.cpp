@@ -53,6 +53,7 @@ static void free_op(DeviceOp& d)
     (void)hipFree(d.d32.fac);
     (void)hipFree(d.b16.core);
     (void)hipFree(d.b16.fac);
+    (void)hipFree(d.b16.fac3m);
     for (int a = 0; a < 3; ++a) {
         (void)hipFree(d.tw64[a]);
         (void)hipFree(d.tw32[a]);
@@ -139,6 +140,7 @@ vie_status vie_compress(const int n[3], const double* green, const vie_compress_
             fac_tot += (n[a] + 1) * tc[c].r[a];
         }
     }
+    const int fac_unique = fac_tot;
     // z factors also stored transposed ([g][k3]) for coalesced pencil-wise reads
     for (int c = 0; c < 6; ++c) {
         v.fac3t_off[c] = fac_tot;
@@ -160,6 +162,27 @@ vie_status vie_compress(const int n[3], const double* green, const vie_compress_
                     for (int g = 0; g < r3; ++g) hfac[v.fac3t_off[c] + (size_t)g * (n[2] + 1) + k] = Uh[(size_t)k * r3 + g];
             }
         }
+    }
+    // BF16 z factors in the row layout of the MFMA reconstruction
+    const int ntile3 = (n[2] + 1 + 15) / 16;
+    int m3_tot = 0;
+    for (int c = 0; c < 6; ++c) {
+        const int r3 = tc[c].r[2];
+        v.rh[c] = r3 <= 16 ? 16 : (r3 <= 32 ? 32 : 0);
+        v.fac3m_off[c] = m3_tot;
+        m3_tot += ntile3 * 16 * 2 * v.rh[c];
+    }
+    std::vector<unsigned short> h3m((size_t)std::max(m3_tot, 1), 0);
+    for (int c = 0; c < 6; ++c) {
+        const int r3 = tc[c].r[2], rh = v.rh[c];
+        if (rh == 0) continue;
+        for (int k = 0; k <= n[2]; ++k)
+            for (int g = 0; g < r3; ++g) {
+                const cd u = hfac[v.fac_off[c][2] + (size_t)k * r3 + g];
+                unsigned short* row = h3m.data() + v.fac3m_off[c] + (size_t)k * 2 * rh;
+                row[g] = to_bf16((float)u.real());
+                row[rh + g] = to_bf16((float)u.imag());
+            }
     }
     // device upload
     hipError_t e;
@@ -193,6 +216,9 @@ vie_status vie_compress(const int n[3], const double* green, const vie_compress_
     };
     e = upload(hcore, (void**)&d.d64.core, (void**)&d.d32.core, (void**)&d.b16.core);
     if (e == hipSuccess) e = upload(hfac, (void**)&d.d64.fac, (void**)&d.d32.fac, (void**)&d.b16.fac);
+    if (e == hipSuccess) e = hipMalloc((void**)&d.b16.fac3m, h3m.size() * sizeof(unsigned short));
+    if (e == hipSuccess)
+        e = hipMemcpy(d.b16.fac3m, h3m.data(), h3m.size() * sizeof(unsigned short), hipMemcpyHostToDevice);
     for (int a = 0; a < 3 && e == hipSuccess; ++a) {
         int L = v.L[a];
         std::vector<c2<double>> t64(L);
@@ -214,7 +240,11 @@ vie_status vie_compress(const int n[3], const double* green, const vie_compress_
         return e == hipErrorOutOfMemory ? fail(VIE_E_NOMEM, "vie_compress: device allocation failed")
                                         : hip_fail(e, "vie_compress upload");
     }
-    d.tucker_bytes = (size_t)(core_tot + fac_tot) * sizeof(c2<float>);
+    d.tucker_bytes = (size_t)(core_tot + fac_unique) * sizeof(c2<float>);
+    size_t twb = 0;
+    for (int a = 0; a < 3; ++a) twb += (size_t)v.L[a] * (sizeof(c2<double>) + sizeof(c2<float>));
+    d.device_bytes = (size_t)(core_tot + fac_tot) * (sizeof(c2<double>) + sizeof(c2<float>) + 4) +
+                     h3m.size() * sizeof(unsigned short) + twb;
     vie_op* op = new vie_op;
     op->d = d;
     *out = op;
@@ -226,6 +256,7 @@ vie_status vie_compress(const int n[3], const double* green, const vie_compress_
         }
         info->tucker_bytes_c64 = d.tucker_bytes;
         info->dense_bytes_c64 = (size_t)6 * 8 * (size_t)V * sizeof(c2<float>);
+        info->device_bytes = d.device_bytes;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return VIE_OK;
@@ -292,7 +323,6 @@ vie_status matvec_common(const vie_op* op, int mode, int dtype, int recon, const
         return fail(VIE_E_UNSUPPORTED, "vie_matvec: FP64 reconstruction needs VIE_C128");
     if (dtype == VIE_C128 && (recon == VIE_RECON_FP32 || recon == VIE_RECON_BF16))
         return fail(VIE_E_UNSUPPORTED, "vie_matvec: reduced reconstruction needs VIE_C64");
-    if (recon == VIE_RECON_BF16) return fail(VIE_E_UNSUPPORTED, "vie_matvec: BF16 reconstruction not built");
     size_t need = vie_workspace_bytes(op, dtype, nrhs);
     if (ws_bytes < need) return fail(VIE_E_ARG, "vie_matvec: workspace too small");
     const OpView& v = op->d.view;
@@ -307,7 +337,8 @@ vie_status matvec_common(const vie_op* op, int mode, int dtype, int recon, const
         e = launch_matvec<double, double>(op->d, mode, 0, (const c2<double>*)eps, (const c2<double>*)x,
                                           (c2<double>*)y, nrhs, (c2<double>*)ws, s, rhs_map, err);
     else
-        e = launch_matvec<float, float>(op->d, mode, 0, (const c2<float>*)eps, (const c2<float>*)x,
+        e = launch_matvec<float, float>(op->d, mode, recon == VIE_RECON_BF16 ? 1 : 0, (const c2<float>*)eps,
+                                        (const c2<float>*)x,
                                         (c2<float>*)y, nrhs, (c2<float>*)ws, s, rhs_map, err);
     if (e != hipSuccess) {
         if (!err.empty()) return fail(VIE_E_UNSUPPORTED, "vie_matvec: " + err);

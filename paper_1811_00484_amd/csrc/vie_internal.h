@@ -24,6 +24,11 @@ struct OpView {
     int fac_off[6][3];
     int fac3t_off[6];   // z factor transposed: [r3][n3 + 1]
     int rmax;
+    // BF16 z factor for the MFMA reconstruction: per component 16 * ceil((n3 + 1) / 16)
+    // rows k3 of 2 rh bf16 values [Re U3(k3, 0..rh) | Im U3(k3, 0..rh)], zero beyond
+    // r3 and beyond row n3; rh = 16 ceil(r3 / 16) (0 when r3 > 32: not available)
+    int rh[6];
+    int fac3m_off[6];
 };
 
 template <typename T>
@@ -36,6 +41,7 @@ struct BF16Buffers {
     // interleaved (re, im) bf16 pairs, same offsets as OpView
     unsigned short* core = nullptr;
     unsigned short* fac = nullptr;
+    unsigned short* fac3m = nullptr;   // MFMA layout of the z factors (OpView::fac3m_off)
 };
 
 struct DeviceOp {
@@ -51,7 +57,8 @@ struct DeviceOp {
     c2<float>* dense32 = nullptr;
     c2<double>* dense64 = nullptr;
     int nhat_source = 0;
-    size_t tucker_bytes = 0;
+    size_t tucker_bytes = 0;   // cores + factors, each once, complex64
+    size_t device_bytes = 0;   // everything the operator holds on the device
     int device = 0;
     size_t max_lds = 65536;
 };
@@ -114,9 +121,12 @@ size_t matvec_ws_elems(const DeviceOp& op, int nrhs);   // complex elements per 
 template <typename TV, typename T>
 bool xy_pass_fast(int kind, int L, const void* in, void* out, const c2<TV>* x, const c2<TV>* eps, const c2<T>* tw,
                   int n1, int n2, int n3, int L1, int L2, int mode, int nrhs, const int* rhs_map, hipStream_t s);
+// recon 1: N^ tables from the BF16 z factors on MFMA (T = float only)
 template <typename T>
-bool z_pass_fast(const DeviceOp& op, int mode, int nrhs, c2<T>* S2, const c2<T>* tw, const c2<T>* core,
+bool z_pass_fast(const DeviceOp& op, int mode, int recon, int nrhs, c2<T>* S2, const c2<T>* tw, const c2<T>* core,
                  const c2<T>* fac, const c2<T>* dense, hipStream_t s);
+// whether the BF16 MFMA reconstruction can run for this operator
+bool bf16_recon_available(const DeviceOp& op);
 // 0 = choose per pass (register FFT where the length allows), 1 = generic kernels only
 extern int g_kernel_path;
 

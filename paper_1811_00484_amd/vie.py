@@ -44,7 +44,8 @@ class CompressOpts(ctypes.Structure):
 class CompressInfo(ctypes.Structure):
     _fields_ = [("ranks", (ctypes.c_int * 3) * 6), ("tail_bound", ctypes.c_double * 6),
                 ("fro_norm", ctypes.c_double * 6), ("tucker_bytes_c64", ctypes.c_size_t),
-                ("dense_bytes_c64", ctypes.c_size_t), ("seconds", ctypes.c_double)]
+                ("dense_bytes_c64", ctypes.c_size_t), ("device_bytes", ctypes.c_size_t),
+                ("seconds", ctypes.c_double)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -160,6 +161,7 @@ class Operator:
         self.fro_norm = [info.fro_norm[c] for c in range(6)]
         self.tucker_bytes_c64 = int(info.tucker_bytes_c64)
         self.dense_bytes_c64 = int(info.dense_bytes_c64)
+        self.device_bytes = int(info.device_bytes)
         self.compress_seconds = float(info.seconds)
         self._ws = {}
 
@@ -215,6 +217,14 @@ def _as_batch(x, op):
     if not x.is_contiguous():
         raise ValueError("vectors must be contiguous")
     return x
+
+
+def workspace_bytes(op, dtype, nrhs=1):
+    """Device workspace (bytes) of vie_matvec for ``nrhs`` right-hand sides of
+    torch ``dtype`` (complex64 or complex128)."""
+    import torch
+    dt = VIE_C128 if dtype == torch.complex128 else VIE_C64
+    return int(load().vie_workspace_bytes(op.handle, dt, int(nrhs)))
 
 
 def matvec(op, x, eps_c=None, kind="A", adjoint=False, recon="auto", out=None):
