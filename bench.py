@@ -201,6 +201,8 @@ def main():
             avg = [pass_ms[p] / max(1, pass_cnt[p]) for p in range(5)]
         return ev0.elapsed_time(ev1) / args.steps, avg, wall
 
+    tuned, tune_ms = vie.autotune(op, torch.complex64, 1)
+    log("autotune: %d quads per z workgroup (%s ms)" % (tuned, tune_ms))
     run(args.warmup, "fp32")
     torch.cuda.synchronize()
     if args.copy_calibration:
@@ -219,6 +221,22 @@ def main():
     dom_gbs = dom_bytes / (avg[dom] * 1e-3) / 1e9
     log("matvec: %.3f ms (%.1f matvecs/s, %.0f GB/s algorithmic); passes %s ms" %
         (ms, value, gbs, ["%.3f" % a for a in avg]))
+    # the same matvec captured once into a HIP graph and replayed
+    graph = vie.MatvecGraph(op, x, e)
+    for _ in range(args.warmup):
+        graph.launch()
+    g0 = torch.cuda.Event(enable_timing=True)
+    g1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    g0.record(st)
+    for _ in range(args.steps):
+        graph.launch()
+    g1.record(st)
+    torch.cuda.synchronize()
+    graph_ms = g0.elapsed_time(g1) / args.steps
+    graph_same = bool(torch.equal(graph.y[0], y32))
+    graph.close()
+    log("graph-replayed matvec: %.3f ms (identical to eager: %s)" % (graph_ms, graph_same))
     zflops = z_pass_flops(n, op.ranks)
     copy_gbs = copy_bandwidth(torch, dev)
     log("device copy: %.0f GB/s" % copy_gbs)
@@ -273,7 +291,9 @@ def main():
                                "(x-polarised plane wave)" % (N, h * 1e3, args.tol),
                    "grid": list(n), "ranks": op.ranks, "alg_bytes_per_matvec": alg_bytes,
                    "alg_GBps": gbs, "wall_s_timed": wall, "device_copy_GBps_measured": copy_gbs,
-                   "alg_GBps_frac_of_measured_copy": gbs / copy_gbs},
+                   "alg_GBps_frac_of_measured_copy": gbs / copy_gbs,
+                   "z_quads_per_workgroup_autotuned": tuned, "autotune_z_ms": tune_ms,
+                   "graph_ms_per_matvec": graph_ms, "graph_equals_eager": graph_same},
         "roofline": {"bound": "hbm", "kernel": PASS_NAMES[dom], "achieved": dom_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
                      "traffic": recorded_traffic(PASS_NAMES[dom], N),

@@ -328,6 +328,42 @@ vie_status vie_profile_collect(double ms[5], int counts[5]);
  */
 vie_status vie_set_kernel_path(int path);
 
+/*
+ * vie_autotune -- pick the launch shape of the fused z pass for this operator
+ * by timing the candidates on the device: the number of consecutive k1
+ * mirror quads a workgroup takes (4, 8, 16 or 32; fewer means more
+ * workgroups, more means the per-k2 core contraction W_c(k2) is shared by
+ * more quads).  The choice is stored in the operator and used by every later
+ * matvec and solve on it.
+ *   dtype   VIE_C64 or VIE_C128 (the arithmetic tuned for).
+ *   nrhs    right-hand sides per launch to tune for.
+ *   ws      DEVICE workspace of at least vie_workspace_bytes(op, dtype, nrhs);
+ *           overwritten (zeroed, then used as the z-pass buffer).
+ *   ms      HOST double[4] out (may be NULL): milliseconds per z pass of the
+ *           candidates 4, 8, 16, 32 (0 where not applicable).
+ *   chosen  HOST int out (may be NULL): the chosen quads per workgroup.
+ * Synchronous.  Only the register-FFT z pass (2 n3 = 128, 256, 512) has a
+ * tunable shape; for other lengths it returns VIE_OK and changes nothing.
+ */
+vie_status vie_autotune(vie_op* op, int dtype, int nrhs, void* ws, size_t ws_bytes, void* stream,
+                        double ms[4], int* chosen);
+
+/*
+ * Captured matvecs: vie_matvec_graph records one vie_matvec /
+ * vie_matvec_adjoint (same arguments; adjoint selects which) into a HIP graph
+ * on a private stream and instantiates it; vie_graph_launch replays it on
+ * `stream` — the same five launches on the same buffers, with one launch
+ * call.  The buffers (eps_c, x, y, ws) must stay allocated while the graph
+ * exists and their contents are read at replay time.  The operator must not
+ * be destroyed or re-tuned while the graph exists.  Per-pass profiling must
+ * be off while capturing.
+ */
+typedef struct vie_graph vie_graph;
+vie_status vie_matvec_graph(const vie_op* op, int kind, int adjoint, int dtype, int recon, const void* eps_c,
+                            const void* x, void* y, int nrhs, void* ws, size_t ws_bytes, vie_graph** out);
+vie_status vie_graph_launch(vie_graph* g, void* stream);
+vie_status vie_graph_destroy(vie_graph* g);
+
 const char* vie_last_error(void);
 /* library version string */
 const char* vie_version(void);

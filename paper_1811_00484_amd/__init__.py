@@ -5,5 +5,5 @@ The product path is ``libvie.so`` (HIP kernels + C ABI, ``include/vie.h``);
 ``torch.autograd.Function`` built on it.
 """
 from . import vie  # noqa: F401
-from .vie import (Operator, VieError, compress, debug_nhat, densify, field_gradient, matvec, set_nhat,  # noqa: F401
-                  solve)
+from .vie import (MatvecGraph, Operator, VieError, autotune, compress, debug_nhat, densify,  # noqa: F401
+                  field_gradient, matvec, set_nhat, solve)

@@ -535,6 +535,8 @@ void prof_enable(int on)
     g_prof = on != 0;
 }
 
+bool prof_is_enabled() { return g_prof; }
+
 int prof_collect(double* ms, int* counts, int npass)
 {
     for (int p = 0; p < npass; ++p) {

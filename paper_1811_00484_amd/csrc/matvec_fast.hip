@@ -632,7 +632,7 @@ static hipError_t launch_z(const DeviceOp& op, int mode, int recon, int nrhs, c2
     za.v = v;
     za.conj = (mode == MODE_AH || mode == MODE_NH);
     za.dense = op.nhat_source == 1;
-    za.chunk = 16;
+    za.chunk = op.zchunk;
     int nchunk = (v.n[0] + 1 + za.chunk - 1) / za.chunk;
     size_t lds = zfast_lds<T, L3>(v);
     if (lds > op.max_lds) return hipErrorInvalidValue;

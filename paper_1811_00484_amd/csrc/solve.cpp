@@ -99,6 +99,12 @@ struct SysState {
 };
 
 // Per-instance state of a (possibly multi-instance) batched GMRES solve.
+// Selective re-orthogonalisation threshold: the second Gram-Schmidt pass is
+// skipped when ||w'|| >= kReorthEta ||w||.  Used for FP64 bases when the
+// cycle's target is loose enough (refinement inner cycles, or tol >= 1e-10)
+// that an orthogonality loss of ~1e-13 per vector cannot matter.
+constexpr double kReorthEta = 1e-3;
+
 template <typename TK>
 struct Inst {
     const DeviceOp* op = nullptr;
@@ -124,6 +130,7 @@ struct Inst {
     std::vector<int> mvs, mv64, cycles;
     std::vector<SysState> S;
     std::vector<int> cyc, run;
+    int reorth_steps = 0;   // Arnoldi steps that took the second Gram-Schmidt pass
 };
 
 // recon 1: BF16 MFMA reconstruction (single-instance register-FFT path only)
@@ -149,6 +156,7 @@ vie_status run_multi(std::vector<Inst<TK>>& I, int mode, const vie_solve_opts& o
 {
     const int m = o.restart;
     const int inner_recon = (o.refine && o.inner_recon == VIE_RECON_BF16) ? 1 : 0;
+    const bool selective = sizeof(TK) == 8 && (o.refine || o.tol >= 1e-10);
     hipError_t e;
     std::string err;
     auto upload_map = [&](Inst<TK>& in, const std::vector<int>& mp) -> hipError_t {
@@ -283,31 +291,55 @@ vie_status run_multi(std::vector<Inst<TK>>& I, int mode, const vie_solve_opts& o
                 const int nr = (int)in.run.size();
                 for (int s : in.run) in.mvs[s]++;
                 const long wvoff = (long)(j + 1) * vstride;
-                e = kr_mdot<TK>(in.V, vstride, n, j + 1, in.V, wvoff, n, in.dmap, nr, in.partial, in.dh1, st);
+                // classical Gram-Schmidt; the first pass also returns ||w||^2
+                // (w is basis slot j + 1, so it is the last of the j + 2 dots)
+                e = kr_mdot<TK>(in.V, vstride, n, j + 2, in.V, wvoff, n, in.dmap, nr, in.partial, in.dh1, st);
                 if (e == hipSuccess)
-                    e = kr_maxpy<TK>(in.V, wvoff, n, in.V, vstride, n, j + 1, j + 1, in.dh1, -1.0, n, in.dmap, nr, st);
-                if (e == hipSuccess)
-                    e = kr_mdot<TK>(in.V, vstride, n, j + 1, in.V, wvoff, n, in.dmap, nr, in.partial, in.dh2, st);
-                if (e == hipSuccess)
-                    e = kr_maxpy<TK>(in.V, wvoff, n, in.V, vstride, n, j + 1, j + 1, in.dh2, -1.0, n, in.dmap, nr, st);
+                    e = kr_maxpy<TK>(in.V, wvoff, n, in.V, vstride, n, j + 1, j + 2, in.dh1, -1.0, n, in.dmap, nr, st);
                 if (e == hipSuccess) e = kr_norm2<TK>(in.V, wvoff, n, n, in.dmap, nr, in.partial, in.dnrm, st);
-                if (e == hipSuccess) e = kr_scale_norm<TK>(in.V, wvoff, in.V, wvoff, n, in.dnrm, n, in.dmap, nr, st);
-                if (e != hipSuccess) return hip_fail(e, "vie_solve arnoldi");
-                std::vector<c2<double>> h1((size_t)nr * (j + 1)), h2((size_t)nr * (j + 1)), hb(nr);
-                e = hipMemcpyAsync(h1.data(), in.dh1, sizeof(c2<double>) * h1.size(), hipMemcpyDeviceToHost, st);
+                std::vector<c2<double>> h1((size_t)nr * (j + 2)), h2((size_t)nr * (j + 1)), hb(nr);
                 if (e == hipSuccess)
-                    e = hipMemcpyAsync(h2.data(), in.dh2, sizeof(c2<double>) * h2.size(), hipMemcpyDeviceToHost, st);
+                    e = hipMemcpyAsync(h1.data(), in.dh1, sizeof(c2<double>) * h1.size(), hipMemcpyDeviceToHost, st);
                 if (e == hipSuccess)
                     e = hipMemcpyAsync(hb.data(), in.dnrm, sizeof(c2<double>) * nr, hipMemcpyDeviceToHost, st);
                 if (e == hipSuccess) e = hipStreamSynchronize(st);
-                if (e != hipSuccess) return hip_fail(e, "vie_solve copy");
+                if (e != hipSuccess) return hip_fail(e, "vie_solve arnoldi");
+                // second pass (re-orthogonalisation) unless the first one lost
+                // little of w to cancellation: ||w'|| >= eta ||w|| bounds the
+                // loss of orthogonality of the new vector by ~ unit roundoff / eta
+                // (the Daniel-Gragg-Kaufman-Stewart criterion).  FP32 bases
+                // always take both passes.
+                bool reorth = !selective;
+                for (int a = 0; a < nr && !reorth; ++a) {
+                    const double w0 = std::sqrt(std::max(h1[(size_t)a * (j + 2) + j + 1].x, 0.0));
+                    const double w1 = std::sqrt(std::max(hb[a].x, 0.0));
+                    reorth = !(w1 >= kReorthEta * w0);
+                }
+                if (reorth) {
+                    ++in.reorth_steps;
+                    e = kr_mdot<TK>(in.V, vstride, n, j + 1, in.V, wvoff, n, in.dmap, nr, in.partial, in.dh2, st);
+                    if (e == hipSuccess)
+                        e = kr_maxpy<TK>(in.V, wvoff, n, in.V, vstride, n, j + 1, j + 1, in.dh2, -1.0, n, in.dmap, nr,
+                                         st);
+                    if (e == hipSuccess) e = kr_norm2<TK>(in.V, wvoff, n, n, in.dmap, nr, in.partial, in.dnrm, st);
+                    if (e == hipSuccess)
+                        e = hipMemcpyAsync(h2.data(), in.dh2, sizeof(c2<double>) * h2.size(), hipMemcpyDeviceToHost,
+                                           st);
+                    if (e == hipSuccess)
+                        e = hipMemcpyAsync(hb.data(), in.dnrm, sizeof(c2<double>) * nr, hipMemcpyDeviceToHost, st);
+                } else {
+                    std::fill(h2.begin(), h2.end(), mk<double>(0, 0));
+                }
+                if (e == hipSuccess) e = kr_scale_norm<TK>(in.V, wvoff, in.V, wvoff, n, in.dnrm, n, in.dmap, nr, st);
+                if (e == hipSuccess && reorth) e = hipStreamSynchronize(st);
+                if (e != hipSuccess) return hip_fail(e, "vie_solve arnoldi");
                 std::vector<int> next;
                 for (int a = 0; a < nr; ++a) {
                     int s = in.run[a];
                     SysState& ss = in.S[s];
                     cd* Hc = &ss.H[(size_t)j * (m + 1)];
                     for (int i2 = 0; i2 <= j; ++i2) {
-                        c2<double> t1 = h1[(size_t)a * (j + 1) + i2], t2 = h2[(size_t)a * (j + 1) + i2];
+                        c2<double> t1 = h1[(size_t)a * (j + 2) + i2], t2 = h2[(size_t)a * (j + 1) + i2];
                         Hc[i2] = cd(t1.x + t2.x, t1.y + t2.y);
                     }
                     double beta = std::sqrt(hb[a].x);

@@ -452,4 +452,125 @@ vie_status vie_set_kernel_path(int path)
     return VIE_OK;
 }
 
+vie_status vie_autotune(vie_op* op, int dtype, int nrhs, void* ws, size_t ws_bytes, void* stream, double ms[4],
+                        int* chosen)
+{
+    if (!op || !ws || nrhs < 1) return fail(VIE_E_ARG, "vie_autotune: null argument or nrhs < 1");
+    if (dtype != VIE_C64 && dtype != VIE_C128) return fail(VIE_E_ARG, "vie_autotune: bad dtype");
+    if (ws_bytes < vie_workspace_bytes(op, dtype, nrhs)) return fail(VIE_E_ARG, "vie_autotune: workspace too small");
+    if (ms)
+        for (int k = 0; k < 4; ++k) ms[k] = 0.0;
+    DeviceOp& d = op->d;
+    const OpView& v = d.view;
+    if (chosen) *chosen = d.zchunk;
+    if (g_kernel_path != 0 || (v.L[2] != 128 && v.L[2] != 256 && v.L[2] != 512)) return VIE_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t el = dtype == VIE_C128 ? sizeof(c2<double>) : sizeof(c2<float>);
+    const size_t s2 = (size_t)3 * v.L[1] * v.L[0] * v.n[2] * nrhs;
+    hipError_t e = hipMemsetAsync(ws, 0, s2 * el, s);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const int cand[4] = {4, 8, 16, 32};
+    const int keep = d.zchunk;
+    int best_c = keep;
+    double best = 1e300;
+    auto run = [&]() -> bool {
+        if (dtype == VIE_C128)
+            return z_pass_fast<double>(d, MODE_A, 0, nrhs, (c2<double>*)ws, d.tw64[2], d.d64.core, d.d64.fac,
+                                       d.dense64, s);
+        return z_pass_fast<float>(d, MODE_A, 0, nrhs, (c2<float>*)ws, d.tw32[2], d.d32.core, d.d32.fac, d.dense32,
+                                  s);
+    };
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+        d.zchunk = cand[k];
+        if (!run()) continue;   // shape not launchable (LDS): leave 0
+        e = hipEventRecord(e0, s);
+        const int reps = 3;
+        bool ok = true;
+        for (int r = 0; r < reps && ok; ++r) ok = run();
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess || !ok) break;
+        const double per = (double)t / reps;
+        if (ms) ms[k] = per;
+        if (per < best) {
+            best = per;
+            best_c = cand[k];
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    d.zchunk = e == hipSuccess ? best_c : keep;
+    if (e != hipSuccess) return hip_fail(e, "vie_autotune");
+    if (chosen) *chosen = d.zchunk;
+    return VIE_OK;
+}
+
+}  // extern "C"
+
+struct vie_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+vie_status vie_matvec_graph(const vie_op* op, int kind, int adjoint, int dtype, int recon, const void* eps_c,
+                            const void* x, void* y, int nrhs, void* ws, size_t ws_bytes, vie_graph** out)
+{
+    if (!out) return fail(VIE_E_ARG, "vie_matvec_graph: null output");
+    *out = nullptr;
+    if (kind != VIE_OP_A && kind != VIE_OP_N) return fail(VIE_E_ARG, "vie_matvec_graph: bad kind");
+    if (prof_is_enabled()) return fail(VIE_E_ARG, "vie_matvec_graph: disable per-pass profiling before capturing");
+    const int mode = kind == VIE_OP_A ? (adjoint ? MODE_AH : MODE_A) : (adjoint ? MODE_NH : MODE_N);
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "vie_matvec_graph stream");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "vie_matvec_graph capture");
+    }
+    vie_status st = matvec_common(op, mode, dtype, recon, eps_c, x, y, nrhs, ws, ws_bytes, cs, nullptr);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (st < 0) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess || !g) return hip_fail(e == hipSuccess ? hipErrorUnknown : e, "vie_matvec_graph end");
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "vie_matvec_graph instantiate");
+    }
+    vie_graph* h = new vie_graph;
+    h->graph = g;
+    h->exec = ge;
+    *out = h;
+    return VIE_OK;
+}
+
+vie_status vie_graph_launch(vie_graph* g, void* stream)
+{
+    if (!g || !g->exec) return fail(VIE_E_ARG, "vie_graph_launch: null graph");
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "vie_graph_launch");
+    return VIE_OK;
+}
+
+vie_status vie_graph_destroy(vie_graph* g)
+{
+    if (!g) return VIE_OK;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return VIE_OK;
+}
+
 }  // extern "C"

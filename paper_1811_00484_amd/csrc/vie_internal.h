@@ -61,6 +61,7 @@ struct DeviceOp {
     size_t device_bytes = 0;   // everything the operator holds on the device
     int device = 0;
     size_t max_lds = 65536;
+    int zchunk = 16;   // k1 mirror quads per z-pass workgroup (vie_autotune)
 };
 
 // One instance of a multi-instance matvec (several grids, one launch per pass).
@@ -132,6 +133,7 @@ extern int g_kernel_path;
 
 // per-pass event timing (passes 0..4 = X+, Y+, Z*, Y-, X-)
 void prof_enable(int on);
+bool prof_is_enabled();
 int prof_collect(double* ms, int* counts, int npass);
 
 // Krylov helpers (batched over systems); T = double or float.

@@ -105,6 +105,12 @@ _SIGS = {
     "vie_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "vie_profile_collect": (ctypes.c_int, [_P, _P]),
     "vie_set_kernel_path": (ctypes.c_int, [ctypes.c_int]),
+    "vie_autotune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t, _P, _P,
+                                    ctypes.POINTER(ctypes.c_int)]),
+    "vie_matvec_graph": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P,
+                                        ctypes.c_int, _P, ctypes.c_size_t, ctypes.POINTER(_P)]),
+    "vie_graph_launch": (ctypes.c_int, [_P, _P]),
+    "vie_graph_destroy": (ctypes.c_int, [_P]),
     "vie_last_error": (ctypes.c_char_p, []),
     "vie_version": (ctypes.c_char_p, []),
 }
@@ -478,6 +484,63 @@ def profile_collect():
 def set_kernel_path(path):
     """0 = default kernel choice, 1 = mixed-radix LDS kernels only."""
     _check(load().vie_set_kernel_path(int(path)), "vie_set_kernel_path")
+
+
+def autotune(op, dtype=None, nrhs=1):
+    """Time the z-pass launch shapes on the device and keep the fastest in the
+    operator (vie_autotune).  Returns (quads per workgroup, {candidate: ms})."""
+    lib = load()
+    dtype = torch.complex64 if dtype is None else dtype
+    dt = VIE_C128 if dtype == torch.complex128 else VIE_C64
+    dev = torch.device("cuda", torch.cuda.current_device())
+    nbytes = lib.vie_workspace_bytes(op.handle, dt, int(nrhs))
+    ws = op.workspace(nbytes, dev)
+    ms = (ctypes.c_double * 4)()
+    chosen = ctypes.c_int(0)
+    _check(lib.vie_autotune(op.handle, dt, int(nrhs), _ptr(ws), nbytes, _stream(), ctypes.cast(ms, ctypes.c_void_p),
+                            ctypes.byref(chosen)), "vie_autotune")
+    return int(chosen.value), {c: float(ms[i]) for i, c in enumerate((4, 8, 16, 32))}
+
+
+class MatvecGraph:
+    """One matvec captured into a HIP graph (vie_matvec_graph) on fixed
+    tensors: write new input into ``x`` in place, call ``launch()``, read
+    ``y``.  Owns its workspace; keeps x, y, eps_c and the operator alive."""
+
+    def __init__(self, op, x, eps_c=None, kind="A", adjoint=False, recon="auto", out=None):
+        lib = load()
+        self._lib = lib
+        self.handle = None
+        xb = _as_batch(x, op)
+        dt = _dt(xb)
+        k = VIE_OP_A if kind == "A" else VIE_OP_N
+        if k == VIE_OP_A and (eps_c is None or eps_c.dtype != xb.dtype or not eps_c.is_contiguous()
+                              or tuple(eps_c.shape) != xb.shape[2:]):
+            raise ValueError("eps_c must be contiguous (n3, n2, n1) of the vector dtype")
+        y = torch.empty_like(xb) if out is None else _as_batch(out, op)
+        nbytes = lib.vie_workspace_bytes(op.handle, dt, xb.shape[0])
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=xb.device)
+        self.op, self.x, self.y, self.eps_c = op, xb, y, eps_c
+        h = ctypes.c_void_p()
+        _check(lib.vie_matvec_graph(op.handle, k, int(bool(adjoint)), dt, _RECON[recon],
+                                    _ptr(eps_c) if k == VIE_OP_A else None, _ptr(xb), _ptr(y), xb.shape[0],
+                                    _ptr(self.ws), nbytes, ctypes.byref(h)), "vie_matvec_graph")
+        self.handle = h
+
+    def launch(self):
+        _check(self._lib.vie_graph_launch(self.handle, _stream()), "vie_graph_launch")
+        return self.y
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            self._lib.vie_graph_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def exported_symbols():
