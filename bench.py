@@ -135,6 +135,11 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-workload", action="store_true",
+                    help="also run the batching workload: 6 head phantoms of seeded sizes at 2 mm, 16 dipole "
+                         "fields each, multi-instance matvec and lockstep GMRES")
+    ap.add_argument("--grad-workload", action="store_true",
+                    help="also run the differentiation workload: 128^3 adjoint gradient vs central differences")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 1 GiB (untimed) so that counter runs can "
                          "calibrate FETCH_SIZE / WRITE_SIZE")
@@ -305,6 +310,14 @@ def main():
                              "alg_flops_per_launch": zflops}},
     }
     result.update(extra)
+    for flag, key, fn in ((args.batch_workload, "batch_workload", batch_workload),
+                          (args.grad_workload, "grad_workload", grad_workload)):
+        if flag:
+            try:
+                result[key] = fn(vie, torch, dev, args)
+            except Exception as exc:   # the headline line is printed regardless
+                log("%s failed: %r" % (key, exc))
+                result[key] = {"error": repr(exc)}
     if not args.no_cpu_baseline:
         u = b
         log("cpu baseline: timing the FP64 oracle matvec ...")
@@ -349,6 +362,177 @@ def solves(op, b, epsc, dev, vie, torch):
                          "rel_residual_fp32": info32[0]["rel_residual"], "rel_residual_fp64": res64,
                          "reached_1e-6_fp64": res64 <= 1e-6, "matvecs": info32[0]["matvecs"]}
     log("plain fp32 solve: %.2f s, fp64 residual %.3e, %s" % (t_32, res64, info32[0]))
+    return out
+
+
+def batch_workload(vie, torch, dev, args):
+    """Six nested-ellipsoid head phantoms (jitter seeds 100+i) with grid
+    sizes drawn by default_rng(4) from {48^3, 64x80x96, 96x112x128, 128^3}
+    at 2 mm, 16 z-dipole fields each on a 150 mm cylinder (seeds 400+i,
+    z within half the skin semi-axis), complex64, HOSVD tol 1e-6.  Operators
+    depend only on the grid, so each distinct grid is compressed once and
+    shared.  Reports batched matvecs/s (all 96 right-hand sides, one launch
+    per pass over every instance) beside per-instance launches, and the
+    lockstep GMRES solve of all 96 systems to 1e-6."""
+    import vie_inputs as vi
+    f = 298e6
+    h = 0.002
+    k0 = vi.wavenumber(f)
+    sizes = [(48, 48, 48), (64, 80, 96), (96, 112, 128), (128, 128, 128)]
+    draw = np.random.default_rng(4).integers(0, 4, 6)
+    ops = {}
+    items = []
+    t0 = time.time()
+    for i, k in enumerate(draw):
+        n = sizes[int(k)]
+        if n not in ops:
+            ops[n] = vie.compress(vi.green_tensor(n, h, k0), tol=1e-6)
+            vie.autotune(ops[n], torch.complex64, 16)
+        er, sg, label = vi.head_phantom(n, h, seed=100 + i)
+        epsc = vi.complex_permittivity(er, sg, f)
+        mask = label >= 0
+        half_z = vi.head_semi_axes(n, h, 100 + i)[0, 2] / 2
+        dips = vi.dipole_cylinder(16, 0.15, half_z, seed=400 + i)
+        b = np.stack([vi.rhs_from_field(epsc, vi.dipole_field(n, h, f, p, mask), f) for p in dips])
+        items.append((ops[n], torch.from_numpy(b.astype(np.complex64)).to(dev),
+                      torch.from_numpy(epsc.astype(np.complex64)).to(dev)))
+    log("batch workload: inputs for grids %s in %.1f s" % ([sizes[int(k)] for k in draw], time.time() - t0))
+    nrhs = sum(it[1].shape[0] for it in items)
+    st = torch.cuda.current_stream()
+
+    def timed(fn, steps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(steps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    steps = max(3, args.steps // 4)
+    ms_each = timed(lambda: vie.matvec_multi(items), steps)   # default: per-instance register-FFT launches
+    vie.set_batch_mode(1)
+    try:
+        ms_multi = timed(lambda: vie.matvec_multi(items), steps)   # one mixed-radix launch per pass
+    finally:
+        vie.set_batch_mode(0)
+    vox = sum(it[1].shape[0] * it[1][0, 0].numel() for it in items)
+    out = {"grids": [list(sizes[int(k)]) for k in draw], "rhs_total": nrhs, "voxels_x_rhs": vox,
+           "ranks": {"x".join(map(str, n)): op.ranks for n, op in ops.items()},
+           "multi_launch": {"ms_per_step": ms_multi, "matvecs_per_s": nrhs * 1000.0 / ms_multi,
+                            "alg_GBps": 664.0 * vox / (ms_multi * 1e-3) / 1e9},
+           "per_instance_launch": {"ms_per_step": ms_each, "matvecs_per_s": nrhs * 1000.0 / ms_each,
+                                   "alg_GBps": 664.0 * vox / (ms_each * 1e-3) / 1e9}}
+    log("batch workload: %d rhs, multi-instance %.2f ms/step (%.0f matvecs/s), per-instance %.2f ms/step "
+        "(%.0f matvecs/s)" % (nrhs, ms_multi, nrhs * 1000.0 / ms_multi, ms_each, nrhs * 1000.0 / ms_each))
+    # restarted GMRES in calls of a few cycles each, every call warm-started
+    # from the previous iterate (the same iteration as one long call; each
+    # call re-evaluates the true residual first)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    x0 = None
+    its = [0] * nrhs
+    conv = False
+    for call in range(40):
+        res, stt = vie.solve_multi(items, tol=1e-6, restart=20, max_outer=3, x0=x0)
+        x0 = [x for x, _ in res]
+        infos = [i for _, inf in res for i in inf]
+        its = [a + i["matvecs"] for a, i in zip(its, infos)]
+        conv = all(i["converged"] for i in infos)
+        log("batch workload: solve call %d, %.1f s, worst residual %.3e" %
+            (call, time.time() - t0, max(i["rel_residual"] for i in infos)))
+        if conv:
+            break
+    torch.cuda.synchronize()
+    t = time.time() - t0
+    out["solve_all_lockstep"] = {"seconds": t, "tol": 1e-6, "restart": 20, "all_converged": conv,
+                                 "matvecs_min": min(its), "matvecs_max": max(its),
+                                 "seconds_per_system": t / nrhs}
+    log("batch workload: lockstep solve of %d systems in %.1f s (matvecs %d..%d, converged %s)"
+        % (nrhs, t, min(its), max(its), conv))
+    return out
+
+
+def grad_workload(vie, torch, dev, args):
+    """Differentiation at 128^3, 2 mm, head phantom seed 2, x-polarised plane
+    wave: L = sum over 500 tissue targets (seed 50) of |E_x - E*|^2 with E*
+    from the 5%-perturbed phantom (seed 51) solved in complex128 to 1e-10.
+    The adjoint gradient (complex64 forward and adjoint solves to 1e-6, and
+    the refined variant) is compared with central differences (relative step
+    1e-4, complex128 solves to 1e-12) on 20 tissue voxels (seed 52) x
+    {eps_r, sigma}."""
+    import vie_inputs as vi
+    from paper_1811_00484_amd.autograd import total_field
+    f = 298e6
+    n = (128, 128, 128)
+    h = 0.002
+    k0 = vi.wavenumber(f)
+    op = vie.compress(vi.green_tensor(n, h, k0), tol=1e-6)
+    vie.autotune(op, torch.complex64, 1)
+    er, sg, label = vi.head_phantom(n, h, seed=2)
+    e_inc = vi.plane_wave(n, h, f)
+    tissue = np.nonzero(label.ravel() >= 0)[0]
+    targets = np.sort(np.random.default_rng(50).choice(tissue, 500, replace=False))
+    rng = np.random.default_rng(51)
+    tm = label >= 0
+    er_t = er * np.where(tm, 1 + 0.05 * rng.uniform(-1, 1, er.shape), 1.0)
+    sg_t = sg * np.where(tm, 1 + 0.05 * rng.uniform(-1, 1, sg.shape), 1.0)
+    ee = torch.from_numpy(e_inc).to(dev)
+    tg = torch.from_numpy(targets).to(dev)
+
+    def field(er_, sg_, tol, dtype=torch.complex128):
+        eps_c, b = vie.problem_setup(op, torch.from_numpy(er_).to(dev), torch.from_numpy(sg_).to(dev),
+                                     ee.to(dtype), f)
+        u, info, _ = vie.solve(op, b, eps_c, tol=tol, restart=60, max_outer=100)
+        return vie.total_field(op, ee.to(dtype), u, vie.matvec(op, u, kind="N"), f)
+
+    E_t = field(er_t, sg_t, 1e-10)[0].reshape(-1)[tg]
+
+    def loss_of(E):
+        return torch.sum(torch.abs(E[0].reshape(-1)[tg] - E_t.to(E.dtype)) ** 2)
+
+    out = {"grid": list(n), "targets": 500}
+    grads = {}
+    for key, cdt, rdt, refine in (("c64", torch.complex64, torch.float32, False),
+                                  ("c64_refined", torch.complex128, torch.float64, True)):
+        e_r = torch.from_numpy(er).to(dev, rdt).requires_grad_(True)
+        s_g = torch.from_numpy(sg).to(dev, rdt).requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        E = total_field(op, e_r, s_g, ee.to(cdt), f, tol=1e-6 if not refine else 1e-10, refine=refine)
+        L = loss_of(E)
+        L.backward()
+        torch.cuda.synchronize()
+        grads[key] = (e_r.grad.double().cpu().numpy(), s_g.grad.double().cpu().numpy())
+        out[key] = {"seconds_forward_backward": time.time() - t0, "loss": float(L.item())}
+    picks = np.random.default_rng(52).choice(tissue, 20, replace=False)
+    fd, ad = [], {k: [] for k in grads}
+    t0 = time.time()
+    for vox in picks:
+        idx = np.unravel_index(vox, er.shape)
+        for which, base in ((0, er), (1, sg)):
+            step = 1e-4 * base[idx]
+            p = base.copy()
+            m = base.copy()
+            p[idx] += step
+            m[idx] -= step
+            args_p = (p, sg) if which == 0 else (er, p)
+            args_m = (m, sg) if which == 0 else (er, m)
+            lp = loss_of(field(*args_p, 1e-12)).item()
+            lm = loss_of(field(*args_m, 1e-12)).item()
+            fd.append((lp - lm) / (2 * step))
+            for k in grads:
+                ad[k].append(grads[k][which][idx])
+    fd = np.array(fd)
+    out["fd_seconds"] = time.time() - t0
+    for k in grads:
+        a = np.array(ad[k])
+        out[k]["rel_err_vs_fd"] = float(np.linalg.norm(a - fd) / np.linalg.norm(fd))
+    log("grad workload: %s" % out)
     return out
 
 

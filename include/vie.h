@@ -329,6 +329,16 @@ vie_status vie_profile_collect(double ms[5], int counts[5]);
 vie_status vie_set_kernel_path(int path);
 
 /*
+ * Execution of multi-instance batches (vie_matvec_multi, vie_solve_multi,
+ * and every matvec step of their solves): 0 = default, each instance's five
+ * passes on its own launches (register-FFT kernels where the lengths allow),
+ * all back to back on the caller's stream; 1 = one launch per pass covering
+ * every instance (mixed-radix LDS kernels, per-instance plans from a device
+ * table).  Same results up to rounding.  Process-wide.
+ */
+vie_status vie_set_batch_mode(int mode);
+
+/*
  * vie_autotune -- pick the launch shape of the fused z pass for this operator
  * by timing the candidates on the device: the number of consecutive k1
  * mirror quads a workgroup takes (4, 8, 16 or 32; fewer means more

@@ -41,6 +41,7 @@ namespace vie {
 static constexpr int NT = 256;   // threads per block in every pass
 
 int g_kernel_path = 0;
+int g_batch_mode = 0;
 
 // component parities: s_a(c) = -1 iff c is off-diagonal and a is one of its axes
 __device__ __forceinline__ int comp_sign(int c, int f1, int f2, int f3)
@@ -946,5 +947,33 @@ hipError_t launch_densify(DeviceOp& op, int with_c128, hipStream_t s)
     }
     return hipGetLastError();
 }
+
+template <typename TV, typename T>
+hipError_t launch_batch(const std::vector<InstHost>& req, int mode, int recon, InstDev* tab, hipStream_t st,
+                        std::string& err)
+{
+    if (req.empty()) return hipSuccess;
+    if (req.size() == 1 || g_batch_mode == 0) {
+        for (const InstHost& h : req) {
+            hipError_t e = launch_matvec<TV, T>(*h.op, mode, recon, (const c2<TV>*)h.eps, (const c2<TV>*)h.x,
+                                                (c2<TV>*)h.y, h.nact, (c2<T>*)h.ws, st, h.map, err);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    if (recon != 0) {
+        err = "BF16 reconstruction is not available in the single-launch batch mode";
+        return hipErrorInvalidValue;
+    }
+    return launch_matvec_multi<TV, T>(req, mode, tab, st, err);
+}
+
+template hipError_t launch_batch<float, float>(const std::vector<InstHost>&, int, int, InstDev*, hipStream_t,
+                                               std::string&);
+template hipError_t launch_batch<double, double>(const std::vector<InstHost>&, int, int, InstDev*, hipStream_t,
+                                                 std::string&);
+template hipError_t launch_batch<double, float>(const std::vector<InstHost>&, int, int, InstDev*, hipStream_t,
+                                                std::string&);
+
 
 }  // namespace vie

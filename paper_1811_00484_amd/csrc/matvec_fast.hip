@@ -1,6 +1,6 @@
-// Register-FFT kernels of the five matvec passes for power-of-two FFT
-// lengths (L = 64 ... 512), the sizes of the workloads that matter for
-// throughput.  Same data layouts and results as the generic LDS-staged
+// Register-FFT kernels of the five matvec passes for the FFT lengths of the
+// workloads that matter for throughput: 128, 256, 512 (radix 8/4) on every
+// axis, and 192, 224 (radix 8/4/3, 7/4/2) for the x and y passes.  Same data layouts and results as the generic LDS-staged
 // kernels in matvec.hip (which remain the path for lengths with factors 3,
 // 5, 7), but each thread keeps its pencil elements in registers across the
 // radix-8/4 stages (reg_fft.h) and LDS only carries the transposes between
@@ -26,9 +26,9 @@ namespace vie {
 // ---------------------------------------------------------------------------
 // plans: forward plan and its reverse for the inverse
 template <int L>
-struct Pow2Plan;
+struct RegPlan;
 template <>
-struct Pow2Plan<512> {
+struct RegPlan<512> {
     using TwF = TwTable<512, 1, 8, 8, 8>;
     using TwI = TwTable<512, 1, 8, 8, 8>;
     static constexpr int TWI = 0;
@@ -52,7 +52,7 @@ struct Pow2Plan<512> {
     static constexpr int RF0 = 8, RFL = 8, RI0 = 8, RIL = 8;
 };
 template <>
-struct Pow2Plan<256> {
+struct RegPlan<256> {
     using TwF = TwTable<256, 1, 8, 8, 4>;
     using TwI = TwTable<256, 1, 4, 8, 8>;
     static constexpr int TWI = TwF::size;
@@ -76,7 +76,7 @@ struct Pow2Plan<256> {
     static constexpr int RF0 = 8, RFL = 4, RI0 = 4, RIL = 8;
 };
 template <>
-struct Pow2Plan<128> {
+struct RegPlan<128> {
     using TwF = TwTable<128, 1, 8, 4, 4>;
     using TwI = TwTable<128, 1, 4, 4, 8>;
     static constexpr int TWI = TwF::size;
@@ -100,7 +100,7 @@ struct Pow2Plan<128> {
     static constexpr int RF0 = 8, RFL = 4, RI0 = 4, RIL = 8;
 };
 template <>
-struct Pow2Plan<64> {
+struct RegPlan<64> {
     using TwF = TwTable<64, 1, 8, 8>;
     using TwI = TwTable<64, 1, 8, 8>;
     static constexpr int TWI = 0;
@@ -124,6 +124,55 @@ struct Pow2Plan<64> {
     static constexpr int RF0 = 8, RFL = 8, RI0 = 8, RIL = 8;
 };
 
+template <>
+struct RegPlan<192> {
+    using TwF = TwTable<192, 1, 8, 8, 3>;
+    using TwI = TwTable<192, 1, 3, 8, 8>;
+    static constexpr int TWI = TwF::size;
+    static constexpr int TW = TWI + TwI::size;   // twiddle-table entries in LDS
+    template <typename T>
+    __device__ static void fill_tw(c2<T>* dst, const c2<T>* tw, int tid, int nt)
+    {
+        TwF::fill(dst, tw, tid, nt);
+        TwI::fill(dst + TWI, tw, tid, nt);
+    }
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void fwd(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tws)
+    {
+        reg_fft<192, TPP, NSEQ, DIR, T, 8, 8, 3>(v, lds, st, t, tws);
+    }
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void inv(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tws)
+    {
+        reg_fft<192, TPP, NSEQ, DIR, T, 3, 8, 8>(v, lds, st, t, tws + TWI);
+    }
+    static constexpr int RF0 = 8, RFL = 3, RI0 = 3, RIL = 8;
+};
+template <>
+struct RegPlan<224> {
+    using TwF = TwTable<224, 1, 7, 4, 4, 2>;
+    using TwI = TwTable<224, 1, 2, 4, 4, 7>;
+    static constexpr int TWI = TwF::size;
+    static constexpr int TW = TWI + TwI::size;   // twiddle-table entries in LDS
+    template <typename T>
+    __device__ static void fill_tw(c2<T>* dst, const c2<T>* tw, int tid, int nt)
+    {
+        TwF::fill(dst, tw, tid, nt);
+        TwI::fill(dst + TWI, tw, tid, nt);
+    }
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void fwd(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tws)
+    {
+        reg_fft<224, TPP, NSEQ, DIR, T, 7, 4, 4, 2>(v, lds, st, t, tws);
+    }
+    template <typename T, int TPP, int NSEQ, int DIR>
+    __device__ static void inv(c2<T>* v, c2<T>* lds, int st, int t, const c2<T>* tws)
+    {
+        reg_fft<224, TPP, NSEQ, DIR, T, 2, 4, 4, 7>(v, lds, st, t, tws + TWI);
+    }
+    static constexpr int RF0 = 7, RFL = 2, RI0 = 2, RIL = 7;
+};
+
 template <int L>
 struct PL {
     static constexpr int value = L + L / 8 + 1;
@@ -145,7 +194,7 @@ __global__ void __launch_bounds__(W*(L / E)) k_xy_fast(const void* __restrict__ 
     constexpr int TPP = L / E;
     constexpr int NT = W * TPP;
     constexpr int P = PL<L>::value;
-    using Plan = Pow2Plan<L>;
+    using Plan = RegPlan<L>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T>* buf = reinterpret_cast<c2<T>*>(smem_raw);           // [W][P]
     c2<T>* tws = buf + (size_t)W * P;                           // [Plan::TW]
@@ -420,7 +469,7 @@ __global__ void __launch_bounds__(4 * (L3 / 8), sizeof(T) == 4 ? 3 : 2) k_z_fast
     constexpr int P = PL<L3>::value;
     constexpr int N3 = L3 / 2;
     constexpr int NTS = 6 * (N3 + 1);                            // N^ table entries per quad
-    using Plan = Pow2Plan<L3>;
+    using Plan = RegPlan<L3>;
     const OpView& v = a.v;
     const int n1 = v.n[0], n2 = v.n[1];
     const int L1 = v.L[0], L2 = v.L[1];
@@ -576,27 +625,31 @@ __global__ void __launch_bounds__(4 * (L3 / 8), sizeof(T) == 4 ? 3 : 2) k_z_fast
 // ---------------------------------------------------------------------------
 // host dispatch
 
-template <typename T>
+// elements per thread: every radix of the plan must divide it; 8 threads per
+// pencil for the mixed-radix lengths 192 = 8 8 3 and 224 = 7 4 4 2
+template <typename T, int L>
 static constexpr int xy_E()
 {
-    return sizeof(T) == 4 ? 32 : 16;
+    if constexpr (L == 192) return 24;
+    else if constexpr (L == 224) return 28;
+    else return sizeof(T) == 4 ? 32 : 16;
 }
 
 template <typename T, int L>
 static constexpr int xy_W()
 {
     // 256 threads per block
-    return 256 / (L / xy_E<T>());
+    return 256 / (L / xy_E<T, L>());
 }
 
 template <typename TV, typename T, int L, int KIND>
 static void launch_xy(const void* in, void* out, const c2<TV>* x, const c2<TV>* eps, const c2<T>* tw,
                       const XYArgs& a, int grid_x, int grid_y, int nz, const int* rhs_map, hipStream_t s)
 {
-    constexpr int E = xy_E<T>();
+    constexpr int E = xy_E<T, L>();
     constexpr int W = xy_W<T, L>();
     constexpr int NT = W * (L / E);
-    size_t lds = sizeof(c2<T>) * ((size_t)W * PL<L>::value + Pow2Plan<L>::TW);
+    size_t lds = sizeof(c2<T>) * ((size_t)W * PL<L>::value + RegPlan<L>::TW);
     auto kern = k_xy_fast<TV, T, L, E, W, KIND>;
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, dim3((grid_x + W - 1) / W, grid_y, nz), dim3(NT), lds, s, in, out, x, eps, tw, a,
@@ -611,6 +664,8 @@ static bool dispatch_xy(int L, const void* in, void* out, const c2<TV>* x, const
     case 512: launch_xy<TV, T, 512, KIND>(in, out, x, eps, tw, a, gx, gy, nz, rhs_map, s); return true;
     case 256: launch_xy<TV, T, 256, KIND>(in, out, x, eps, tw, a, gx, gy, nz, rhs_map, s); return true;
     case 128: launch_xy<TV, T, 128, KIND>(in, out, x, eps, tw, a, gx, gy, nz, rhs_map, s); return true;
+    case 192: launch_xy<TV, T, 192, KIND>(in, out, x, eps, tw, a, gx, gy, nz, rhs_map, s); return true;
+    case 224: launch_xy<TV, T, 224, KIND>(in, out, x, eps, tw, a, gx, gy, nz, rhs_map, s); return true;
     default: return false;
     }
 }
@@ -620,7 +675,7 @@ static size_t zfast_lds(const OpView& v)
 {
     static_assert(6 * (L3 / 2 + 1) <= 4 * PL<L3>::value, "N^ table must fit in the FFT slices");
     return sizeof(c2<T>) * ((size_t)4 * PL<L3>::value + 6 * (L3 / 2 + 1) + 6 * (size_t)v.rmax * v.rmax +
-                            12 * v.rmax + Pow2Plan<L3>::TW);
+                            12 * v.rmax + RegPlan<L3>::TW);
 }
 
 template <typename T, int L3>

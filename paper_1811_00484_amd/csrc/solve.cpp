@@ -133,22 +133,12 @@ struct Inst {
     int reorth_steps = 0;   // Arnoldi steps that took the second Gram-Schmidt pass
 };
 
-// recon 1: BF16 MFMA reconstruction (single-instance register-FFT path only)
+// recon 1: BF16 MFMA reconstruction
 template <typename TV, typename T>
 hipError_t mv_dispatch(const std::vector<InstHost>& req, int mode, InstDev* tab, hipStream_t st, std::string& err,
                        int recon = 0)
 {
-    if (req.empty()) return hipSuccess;
-    if (req.size() == 1) {
-        const InstHost& h = req[0];
-        return launch_matvec<TV, T>(*h.op, mode, recon, (const c2<TV>*)h.eps, (const c2<TV>*)h.x, (c2<TV>*)h.y,
-                                    h.nact, (c2<T>*)h.ws, st, h.map, err);
-    }
-    if (recon != 0) {
-        err = "BF16 reconstruction is not available for multi-instance batches";
-        return hipErrorInvalidValue;
-    }
-    return launch_matvec_multi<TV, T>(req, mode, tab, st, err);
+    return launch_batch<TV, T>(req, mode, recon, tab, st, err);
 }
 
 template <typename TK, typename TC>
@@ -689,9 +679,9 @@ vie_status vie_matvec_multi(const vie_instance* inst, int count, int kind, int a
     std::string err;
     hipError_t e;
     if (dtype == VIE_C128)
-        e = launch_matvec_multi<double, double>(req, mode, (InstDev*)ws, (hipStream_t)stream, err);
+        e = launch_batch<double, double>(req, mode, 0, (InstDev*)ws, (hipStream_t)stream, err);
     else
-        e = launch_matvec_multi<float, float>(req, mode, (InstDev*)ws, (hipStream_t)stream, err);
+        e = launch_batch<float, float>(req, mode, 0, (InstDev*)ws, (hipStream_t)stream, err);
     if (e != hipSuccess) return err.empty() ? hip_fail(e, "vie_matvec_multi") : fail(VIE_E_UNSUPPORTED, "vie_matvec_multi: " + err);
     return VIE_OK;
 }

@@ -452,6 +452,13 @@ vie_status vie_set_kernel_path(int path)
     return VIE_OK;
 }
 
+vie_status vie_set_batch_mode(int mode)
+{
+    if (mode != 0 && mode != 1) return fail(VIE_E_ARG, "vie_set_batch_mode: 0 or 1");
+    g_batch_mode = mode;
+    return VIE_OK;
+}
+
 vie_status vie_autotune(vie_op* op, int dtype, int nrhs, void* ws, size_t ws_bytes, void* stream, double ms[4],
                         int* chosen)
 {

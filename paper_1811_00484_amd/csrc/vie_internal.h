@@ -130,6 +130,16 @@ bool z_pass_fast(const DeviceOp& op, int mode, int recon, int nrhs, c2<T>* S2, c
 bool bf16_recon_available(const DeviceOp& op);
 // 0 = choose per pass (register FFT where the length allows), 1 = generic kernels only
 extern int g_kernel_path;
+// multi-instance batches: 0 = each instance's passes on its own (register-FFT)
+// launches, back to back on the stream; 1 = one launch per pass over every
+// instance (mixed-radix LDS kernels)
+extern int g_batch_mode;
+
+// Matvec of a multi-instance batch under g_batch_mode (recon: single-launch
+// mode supports FP32/FP64 reconstruction only).
+template <typename TV, typename T>
+hipError_t launch_batch(const std::vector<InstHost>& inst, int mode, int recon, InstDev* tab_dev, hipStream_t s,
+                        std::string& err);
 
 // per-pass event timing (passes 0..4 = X+, Y+, Z*, Y-, X-)
 void prof_enable(int on);

@@ -105,6 +105,7 @@ _SIGS = {
     "vie_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "vie_profile_collect": (ctypes.c_int, [_P, _P]),
     "vie_set_kernel_path": (ctypes.c_int, [ctypes.c_int]),
+    "vie_set_batch_mode": (ctypes.c_int, [ctypes.c_int]),
     "vie_autotune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t, _P, _P,
                                     ctypes.POINTER(ctypes.c_int)]),
     "vie_matvec_graph": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P,
@@ -327,9 +328,10 @@ def matvec_multi(items, kind="A", adjoint=False):
 
 
 def solve_multi(items, tol=1e-6, restart=50, max_outer=200, adjoint=False, refine=False, inner_tol=1e-4,
-                history=64):
+                history=64, x0=None):
     """GMRES on several instances (op, b, eps_c) in lockstep; returns a list
-    of (x, infos) per instance and the overall status."""
+    of (x, infos) per instance and the overall status.  ``x0``: optional list
+    of initial guesses (one tensor per instance, shape of its b)."""
     lib = load()
     arr = (SolveInstance * len(items))()
     keep = []
@@ -338,7 +340,7 @@ def solve_multi(items, tol=1e-6, restart=50, max_outer=200, adjoint=False, refin
     for i, (op, b, eps_c) in enumerate(items):
         bb = _as_batch(b, op)
         dt = _dt(bb) if dt is None else dt
-        x = torch.zeros_like(bb)
+        x = torch.zeros_like(bb) if x0 is None else _as_batch(x0[i], op).clone()
         xs.append(x)
         infos = (SolveInfo * bb.shape[0])()
         hist = [(ctypes.c_double * history)() for _ in range(bb.shape[0])]
@@ -484,6 +486,12 @@ def profile_collect():
 def set_kernel_path(path):
     """0 = default kernel choice, 1 = mixed-radix LDS kernels only."""
     _check(load().vie_set_kernel_path(int(path)), "vie_set_kernel_path")
+
+
+def set_batch_mode(mode):
+    """0 = per-instance register-FFT launches (default), 1 = one mixed-radix
+    launch per pass over every instance."""
+    _check(load().vie_set_batch_mode(int(mode)), "vie_set_batch_mode")
 
 
 def autotune(op, dtype=None, nrhs=1):

@@ -30,10 +30,17 @@ def _instances(nrhs=3):
     return out
 
 
+@pytest.fixture(params=[0, 1], ids=["per_instance_launches", "one_launch_per_pass"])
+def batch_mode(request):
+    vie.set_batch_mode(request.param)
+    yield request.param
+    vie.set_batch_mode(0)
+
+
 @pytest.mark.parametrize("dt", [torch.complex64, torch.complex128])
 @pytest.mark.parametrize("mode", ["A", "AH"])
-def test_multi_matvec_matches_oracle_and_single(dt, mode):
-    say("multi matvec", dt, mode)
+def test_multi_matvec_matches_oracle_and_single(dt, mode, batch_mode):
+    say("multi matvec", dt, mode, "batch mode", batch_mode)
     insts = _instances()
     items = []
     us = []
@@ -52,7 +59,7 @@ def test_multi_matvec_matches_oracle_and_single(dt, mode):
         assert rel(y, y1) <= (1e-6 if dt == torch.complex64 else 1e-13)
 
 
-def test_multi_solve_all_systems():
+def test_multi_solve_all_systems(batch_mode):
     insts = _instances()
     items = [(op, to_dev(b, torch.complex128), to_dev(epsc, torch.complex128))
              for (n, G, epsc, b, ref, op) in insts]
@@ -68,3 +75,18 @@ def test_multi_solve_all_systems():
     xs, infos, _ = vie.solve(op, to_dev(b, torch.complex128), to_dev(epsc, torch.complex128), tol=1e-9, restart=20)
     assert rel(res[2][0].cpu().numpy(), xs.cpu().numpy()) <= 1e-10
     assert [i["matvecs"] for i in infos] == [i["matvecs"] for i in res[2][1]]
+
+
+def test_multi_solve_warm_start_continues():
+    # restarted GMRES split over two calls (the second warm-started from the
+    # first's iterate) reaches the same tolerance
+    insts = _instances(nrhs=2)
+    items = [(op, to_dev(b, torch.complex128), to_dev(epsc, torch.complex128))
+             for (n, G, epsc, b, ref, op) in insts]
+    res1, st1 = vie.solve_multi(items, tol=1e-9, restart=5, max_outer=2)
+    res2, st2 = vie.solve_multi(items, tol=1e-9, restart=20, x0=[x for x, _ in res1])
+    assert st2 == 0
+    for (x, infos), (n, G, epsc, b, ref, op) in zip(res2, insts):
+        xh = x.cpu().numpy()
+        for s in range(b.shape[0]):
+            assert rel(opm.matvec(ref, epsc, xh[s], "A"), b[s]) <= 1.01e-9

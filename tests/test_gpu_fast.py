@@ -12,7 +12,11 @@ from paper_1811_00484_amd import vie
 
 pytestmark = pytest.mark.gpu
 
-FAST_SIZES = [(64, 64, 64), (64, 20, 64), (64, 48, 128), (128, 40, 64), (36, 64, 256)]
+# register-FFT lengths on each axis: 128, 256, 512 everywhere, 192 (8 8 3) and
+# 224 (7 4 4 2) on x and y; partial tiles, and axes that fall back to the
+# mixed-radix kernels (e.g. 2 n2 = 40, 2 n3 = 32)
+FAST_SIZES = [(64, 64, 64), (64, 20, 64), (64, 48, 128), (128, 40, 64), (36, 64, 256), (96, 112, 16),
+              (40, 112, 64), (96, 20, 64)]
 
 
 @pytest.mark.parametrize("n", FAST_SIZES)
