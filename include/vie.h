@@ -110,6 +110,25 @@ typedef struct {
 vie_status vie_compress(const int n[3], const double* green, const vie_compress_opts* opts,
                         vie_op** out, vie_compress_info* info);
 
+/*
+ * vie_op_from_tucker -- build an operator from a Tucker form of the six
+ * defining tensors computed elsewhere (eq. 13-14: another truncation, a cross
+ * approximation, a stored decomposition).  The factor columns are embedded
+ * and transformed (Sec. V-A) and uploaded exactly as in vie_compress.
+ *   n        HOST int[3], 1 <= n_i <= 256, 2 n_i a product of 2, 3, 5, 7.
+ *   ranks    HOST int[6][3], 1 <= r_a <= min(n_a, 64).
+ *   cores    HOST complex128, the six cores one after another, each
+ *            [r1][r2][r3] (r3 fastest), unscaled (Nt_c = G x1 U1 x2 U2 x3 U3).
+ *   factors  HOST complex128, for c = 0..5 and a = 0..2 in that order the
+ *            real-space factor U_a of component c, n_a x r_a row-major.
+ *            For xy, xz, yz the factors along their two odd axes must have a
+ *            zero row 0 (the odd tensor vanishes at zero offset; VIE_E_ARG).
+ *   out      receives the new operator; info (may be NULL) as in vie_compress
+ *            with tail_bound and fro_norm set to 0.
+ */
+vie_status vie_op_from_tucker(const int n[3], const int ranks[6][3], const double* cores, const double* factors,
+                              vie_op** out, vie_compress_info* info);
+
 /* Release the operator's device memory.  NULL is accepted. */
 vie_status vie_op_destroy(vie_op* op);
 

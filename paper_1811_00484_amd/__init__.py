@@ -6,4 +6,4 @@ The product path is ``libvie.so`` (HIP kernels + C ABI, ``include/vie.h``);
 """
 from . import vie  # noqa: F401
 from .vie import (MatvecGraph, Operator, VieError, autotune, compress, debug_nhat, densify,  # noqa: F401
-                  field_gradient, matvec, set_nhat, solve)
+                  field_gradient, from_tucker, matvec, set_nhat, solve)

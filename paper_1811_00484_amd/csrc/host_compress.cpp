@@ -381,14 +381,27 @@ int hosvd_component(const cd* A, const int n[3], double tol, int rule, int max_r
 
 // Rows 0..n of the DFT (length 2n, exp(-2 pi i m k / 2n)) of the embedded
 // columns e[m] = U[m] (m < n), e[n] = 0, e[2n - m] = s U[m] (1 <= m < n).
+cd twiddle(long m, long L)
+{
+    m %= L;
+    if (m < 0) m += L;
+    if ((4 * m) % L == 0) {
+        switch ((4 * m) / L) {
+        case 0: return cd(1.0, 0.0);
+        case 1: return cd(0.0, -1.0);
+        case 2: return cd(-1.0, 0.0);
+        default: return cd(0.0, 1.0);
+        }
+    }
+    const double ang = -2.0 * M_PI * (double)m / (double)L;
+    return cd(std::cos(ang), std::sin(ang));
+}
+
 void fourier_factor(const std::vector<cd>& U, int n, int r, int s, std::vector<cd>& Uh)
 {
     int L = 2 * n;
     std::vector<cd> w(L);
-    for (int m = 0; m < L; ++m) {
-        double ang = -2.0 * M_PI * (double)m / (double)L;
-        w[m] = cd(std::cos(ang), std::sin(ang));
-    }
+    for (int m = 0; m < L; ++m) w[m] = twiddle(m, L);
     Uh.assign((size_t)(n + 1) * r, 0);
     for (int k = 0; k <= n; ++k)
         for (int c = 0; c < r; ++c) {

@@ -29,6 +29,9 @@ int truncation_rank(const std::vector<double>& s, double tol, int rule, double f
 int hosvd_component(const std::complex<double>* A, const int n[3], double tol, int rule,
                     int max_rank, TuckerComponent& out);
 
+// exp(-2 pi i m / L), exact (0, +-1) at the multiples of a quarter turn.
+std::complex<double> twiddle(long m, long L);
+
 // Rows 0..n of the length-2n DFT of the parity-s embedded columns of U (n x r).
 void fourier_factor(const std::vector<std::complex<double>>& U, int n, int r, int s,
                     std::vector<std::complex<double>>& Uh);

@@ -72,52 +72,12 @@ static unsigned short to_bf16(float f)
     return (unsigned short)(u >> 16);
 }
 
-}  // namespace vie
-
-using namespace vie;
-
-extern "C" {
-
-const char* vie_last_error(void) { return g_last_error.c_str(); }
-
-const char* vie_version(void) { return "vie-gfx950 0.1"; }
-
-vie_status vie_compress(const int n[3], const double* green, const vie_compress_opts* opts, vie_op** out,
-                        vie_compress_info* info)
+static vie_status build_operator(const int n[3], const FftPlan plans[3], TuckerComponent tc[6], vie_op** out,
+                                 vie_compress_info* info, std::chrono::steady_clock::time_point t0)
 {
-    auto t0 = std::chrono::steady_clock::now();
-    if (!n || !green || !out) return fail(VIE_E_ARG, "vie_compress: null argument");
-    for (int a = 0; a < 3; ++a)
-        if (n[a] < 1 || n[a] > 256) return fail(VIE_E_UNSUPPORTED, "vie_compress: n_i must be in [1, 256]");
-    double tol = opts ? opts->tol : 1e-6;
-    int rule = opts ? opts->trunc_rule : 0;
-    int max_rank = opts ? opts->max_rank : 0;
-    if (!(tol > 0.0) || !std::isfinite(tol) || (rule != 0 && rule != 1) || max_rank < 0)
-        return fail(VIE_E_ARG, "vie_compress: bad options");
-    const long V = (long)n[0] * n[1] * n[2];
-    FftPlan plans[3];
-    for (int a = 0; a < 3; ++a)
-        if (!make_plan(2 * n[a], plans[a]))
-            return fail(VIE_E_UNSUPPORTED, "vie_compress: 2 n_i must factor into 2, 3, 5, 7");
-    for (long t = 0; t < 12 * V; ++t)
-        if (!std::isfinite(green[t])) return fail(VIE_E_NONFINITE, "vie_compress: non-finite Green's tensor");
-
     using cd = std::complex<double>;
-    TuckerComponent tc[6];
-    std::vector<cd> A(V);
+    const long V = (long)n[0] * n[1] * n[2];
     const int odd[6][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
-    for (int c = 0; c < 6; ++c) {
-        const double* g = green + 2 * (size_t)c * V;
-        for (long t = 0; t < V; ++t) A[t] = cd(g[2 * t], g[2 * t + 1]);
-        // an odd component vanishes at zero offset along its odd axes
-        for (int k = 0; k < n[2]; ++k)
-            for (int j = 0; j < n[1]; ++j)
-                for (int i = 0; i < n[0]; ++i)
-                    if ((odd[c][0] && i == 0) || (odd[c][1] && j == 0) || (odd[c][2] && k == 0))
-                        A[((long)k * n[1] + j) * n[0] + i] = 0.0;
-        int rc = hosvd_component(A.data(), n, tol, rule, max_rank, tc[c]);
-        if (rc != 0) return fail(VIE_E_UNSUPPORTED, "vie_compress: max_rank too small for tol");
-    }
     // pack cores (scaled by 1/M) and Fourier factors
     DeviceOp d;
     OpView& v = d.view;
@@ -224,9 +184,9 @@ vie_status vie_compress(const int n[3], const double* green, const vie_compress_
         std::vector<c2<double>> t64(L);
         std::vector<c2<float>> t32(L);
         for (int m = 0; m < L; ++m) {
-            double ang = -2.0 * M_PI * (double)m / (double)L;
-            t64[m].x = std::cos(ang);
-            t64[m].y = std::sin(ang);
+            const cd w = twiddle(m, L);
+            t64[m].x = w.real();
+            t64[m].y = w.imag();
             t32[m].x = (float)t64[m].x;
             t32[m].y = (float)t64[m].y;
         }
@@ -260,6 +220,99 @@ vie_status vie_compress(const int n[3], const double* green, const vie_compress_
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return VIE_OK;
+}
+
+}  // namespace vie
+
+using namespace vie;
+
+extern "C" {
+
+const char* vie_last_error(void) { return g_last_error.c_str(); }
+
+const char* vie_version(void) { return "vie-gfx950 0.1"; }
+
+vie_status vie_compress(const int n[3], const double* green, const vie_compress_opts* opts, vie_op** out,
+                        vie_compress_info* info)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!n || !green || !out) return fail(VIE_E_ARG, "vie_compress: null argument");
+    for (int a = 0; a < 3; ++a)
+        if (n[a] < 1 || n[a] > 256) return fail(VIE_E_UNSUPPORTED, "vie_compress: n_i must be in [1, 256]");
+    double tol = opts ? opts->tol : 1e-6;
+    int rule = opts ? opts->trunc_rule : 0;
+    int max_rank = opts ? opts->max_rank : 0;
+    if (!(tol > 0.0) || !std::isfinite(tol) || (rule != 0 && rule != 1) || max_rank < 0)
+        return fail(VIE_E_ARG, "vie_compress: bad options");
+    const long V = (long)n[0] * n[1] * n[2];
+    FftPlan plans[3];
+    for (int a = 0; a < 3; ++a)
+        if (!make_plan(2 * n[a], plans[a]))
+            return fail(VIE_E_UNSUPPORTED, "vie_compress: 2 n_i must factor into 2, 3, 5, 7");
+    for (long t = 0; t < 12 * V; ++t)
+        if (!std::isfinite(green[t])) return fail(VIE_E_NONFINITE, "vie_compress: non-finite Green's tensor");
+
+    using cd = std::complex<double>;
+    TuckerComponent tc[6];
+    std::vector<cd> A(V);
+    const int odd[6][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+    for (int c = 0; c < 6; ++c) {
+        const double* g = green + 2 * (size_t)c * V;
+        for (long t = 0; t < V; ++t) A[t] = cd(g[2 * t], g[2 * t + 1]);
+        // an odd component vanishes at zero offset along its odd axes
+        for (int k = 0; k < n[2]; ++k)
+            for (int j = 0; j < n[1]; ++j)
+                for (int i = 0; i < n[0]; ++i)
+                    if ((odd[c][0] && i == 0) || (odd[c][1] && j == 0) || (odd[c][2] && k == 0))
+                        A[((long)k * n[1] + j) * n[0] + i] = 0.0;
+        int rc = hosvd_component(A.data(), n, tol, rule, max_rank, tc[c]);
+        if (rc != 0) return fail(VIE_E_UNSUPPORTED, "vie_compress: max_rank too small for tol");
+    }
+    return build_operator(n, plans, tc, out, info, t0);
+}
+
+vie_status vie_op_from_tucker(const int n[3], const int ranks[6][3], const double* cores, const double* factors,
+                              vie_op** out, vie_compress_info* info)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!n || !ranks || !cores || !factors || !out) return fail(VIE_E_ARG, "vie_op_from_tucker: null argument");
+    for (int a = 0; a < 3; ++a)
+        if (n[a] < 1 || n[a] > 256) return fail(VIE_E_UNSUPPORTED, "vie_op_from_tucker: n_i must be in [1, 256]");
+    FftPlan plans[3];
+    for (int a = 0; a < 3; ++a)
+        if (!make_plan(2 * n[a], plans[a]))
+            return fail(VIE_E_UNSUPPORTED, "vie_op_from_tucker: 2 n_i must factor into 2, 3, 5, 7");
+    using cd = std::complex<double>;
+    const int odd[6][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+    TuckerComponent tc[6];
+    size_t co = 0, fo = 0;
+    for (int c = 0; c < 6; ++c) {
+        for (int a = 0; a < 3; ++a) {
+            const int r = ranks[c][a];
+            if (r < 1 || r > n[a] || r > 64) return fail(VIE_E_ARG, "vie_op_from_tucker: ranks must be in [1, min(n_a, 64)]");
+            tc[c].r[a] = r;
+        }
+        const size_t ng = (size_t)tc[c].r[0] * tc[c].r[1] * tc[c].r[2];
+        tc[c].G.resize(ng);
+        for (size_t t = 0; t < ng; ++t) tc[c].G[t] = cd(cores[2 * (co + t)], cores[2 * (co + t) + 1]);
+        co += ng;
+        for (int a = 0; a < 3; ++a) {
+            const size_t nu = (size_t)n[a] * tc[c].r[a];
+            tc[c].U[a].resize(nu);
+            for (size_t t = 0; t < nu; ++t) tc[c].U[a][t] = cd(factors[2 * (fo + t)], factors[2 * (fo + t) + 1]);
+            fo += nu;
+            if (odd[c][a])
+                for (int g = 0; g < tc[c].r[a]; ++g)
+                    if (tc[c].U[a][g] != cd(0.0))
+                        return fail(VIE_E_ARG, "vie_op_from_tucker: an off-diagonal component's factor along one of "
+                                               "its odd axes must have a zero row 0");
+        }
+    }
+    for (size_t t = 0; t < 2 * co; ++t)
+        if (!std::isfinite(cores[t])) return fail(VIE_E_NONFINITE, "vie_op_from_tucker: non-finite core");
+    for (size_t t = 0; t < 2 * fo; ++t)
+        if (!std::isfinite(factors[t])) return fail(VIE_E_NONFINITE, "vie_op_from_tucker: non-finite factor");
+    return build_operator(n, plans, tc, out, info, t0);
 }
 
 vie_status vie_op_destroy(vie_op* op)

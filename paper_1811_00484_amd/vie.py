@@ -76,6 +76,8 @@ _P = ctypes.c_void_p
 _SIGS = {
     "vie_compress": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.POINTER(CompressOpts),
                                     ctypes.POINTER(_P), ctypes.POINTER(CompressInfo)]),
+    "vie_op_from_tucker": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _P, _P,
+                                          ctypes.POINTER(_P), ctypes.POINTER(CompressInfo)]),
     "vie_op_destroy": (ctypes.c_int, [_P]),
     "vie_op_query": (ctypes.c_int, [_P, _P, _P]),
     "vie_op_densify": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -213,6 +215,32 @@ def compress(green, tol=1e-6, trunc_rule=0, max_rank=0):
     _check(lib.vie_compress(n, g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts), ctypes.byref(h),
                             ctypes.byref(info)), "vie_compress")
     return Operator(h, (g.shape[3], g.shape[2], g.shape[1]), info)
+
+
+def from_tucker(n, cores, factors):
+    """Operator from a Tucker form computed elsewhere (vie_op_from_tucker):
+    ``n`` = (n1, n2, n3); ``cores[c]`` complex (r1, r2, r3); ``factors[c]`` =
+    (U1, U2, U3) real-space factors, U_a of shape (n_a, r_a)."""
+    lib = load()
+    nn = (ctypes.c_int * 3)(*[int(v) for v in n])
+    ranks = (ctypes.c_int * 18)()
+    cflat, fflat = [], []
+    for c in range(6):
+        G = np.ascontiguousarray(cores[c], dtype=np.complex128)
+        for a in range(3):
+            U = np.ascontiguousarray(factors[c][a], dtype=np.complex128)
+            if U.shape != (n[a], G.shape[a]):
+                raise ValueError("factor %d of component %d must be (n_a, r_a)" % (a, c))
+            ranks[3 * c + a] = G.shape[a]
+            fflat.append(U.ravel())
+        cflat.append(G.ravel())
+    cb = np.ascontiguousarray(np.concatenate(cflat))
+    fb = np.ascontiguousarray(np.concatenate(fflat))
+    info = CompressInfo()
+    h = ctypes.c_void_p()
+    _check(lib.vie_op_from_tucker(nn, ranks, cb.ctypes.data_as(ctypes.c_void_p), fb.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.byref(h), ctypes.byref(info)), "vie_op_from_tucker")
+    return Operator(h, tuple(int(v) for v in n), info)
 
 
 def _as_batch(x, op):

@@ -1,0 +1,109 @@
+"""Bit-exact checks of the index work on the device: padding, cropping, the
+mirror signs of the embedded factors and of the four pencils of a quad, the
+Tucker reconstruction (eq. 14) and the 3x3 component product.
+
+The operator is built with vie_op_from_tucker from integer-valued cores and
+factors (entries in {-1, 0, 1} + i{-1, 0, 1}, ranks <= 2) on grids with
+n_i in {1, 2}: every FFT then has length 2 or 4, whose twiddles are +-1 and
++-i, the 1/(8 n1 n2 n3) scaling is a power of two, and every intermediate
+value is a small dyadic rational.  All arithmetic is exact in FP32 and FP64
+whatever the summation order, so the device must equal the FP64 oracle bit
+for bit in every mode.  A misplaced element, a wrong mirror sign or a wrong
+pad/crop offset changes the result by at least one unit."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import say, to_dev
+from oracle import circulant, operator as opm
+from paper_1811_00484_amd import vie
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = list(itertools.product((1, 2), repeat=3))
+
+
+def _int_complex(rng, shape):
+    return rng.integers(-1, 2, shape) + 1j * rng.integers(-1, 2, shape)
+
+
+def _integer_tucker(n, seed):
+    rng = np.random.default_rng(seed)
+    cores, factors = [], []
+    for c in range(6):
+        signs = circulant.axis_signs(c)
+        r = [int(rng.integers(1, min(n[a], 2) + 1)) for a in range(3)]
+        G = _int_complex(rng, r)
+        Us = []
+        for a in range(3):
+            U = _int_complex(rng, (n[a], r[a]))
+            if signs[a] < 0:
+                U[0, :] = 0   # odd along this axis: zero at zero offset
+            Us.append(U)
+        cores.append(G)
+        factors.append(Us)
+    return cores, factors
+
+
+def _oracle(n, cores, factors):
+    nhat = [circulant.fourier_tensor_tucker(cores[c], factors[c], circulant.axis_signs(c)) for c in range(6)]
+    return opm.FourierOperator(n, nhat)
+
+
+@pytest.mark.parametrize("n", GRIDS)
+@pytest.mark.parametrize("dt", [torch.complex64, torch.complex128])
+def test_integer_tucker_matvec_is_bit_exact(n, dt):
+    cores, factors = _integer_tucker(n, 11 + sum(n))
+    ref = _oracle(n, cores, factors)
+    op = vie.from_tucker(n, cores, factors)
+    rng = np.random.default_rng(5)
+    shape = (3, n[2], n[1], n[0])
+    u = _int_complex(rng, shape)
+    epsc = rng.integers(1, 4, shape[1:]) - 1j * rng.integers(0, 3, shape[1:])
+    x = to_dev(u, dt)
+    e = to_dev(epsc, dt)
+    for mode in ("A", "AH", "N", "NH"):
+        kind = "N" if mode.startswith("N") else "A"
+        y = vie.matvec(op, x, e, kind=kind, adjoint=mode.endswith("H")).cpu().numpy().astype(np.complex128)
+        yo = opm.matvec(ref, epsc, u, mode)
+        bad = int(np.count_nonzero(y != yo))
+        if bad:
+            say("   n", n, dt, mode, "mismatches", bad, "max diff", np.abs(y - yo).max())
+        assert bad == 0, (n, mode)
+
+
+@pytest.mark.parametrize("dt", [torch.complex64, torch.complex128])
+def test_zero_operator_epilogue_is_bit_exact_on_register_fft_path(dt):
+    # N = 0 (zero cores): A u = eps_c u exactly, through all five register-FFT
+    # passes (L = 128, 96 -> 192, 256): checks the x-pass epilogue's indexing
+    # of u, eps_c and y bitwise
+    n = (64, 96, 128)
+    rng = np.random.default_rng(8)
+    cores = [np.zeros((1, 1, 1), complex) for _ in range(6)]
+    factors = []
+    for c in range(6):
+        Us = []
+        for a in range(3):
+            U = np.ones((n[a], 1), complex)
+            if circulant.axis_signs(c)[a] < 0:
+                U[0, 0] = 0
+            Us.append(U)
+        factors.append(Us)
+    op = vie.from_tucker(n, cores, factors)
+    shape = (3, n[2], n[1], n[0])
+    u = _int_complex(rng, shape)
+    epsc = rng.integers(1, 4, shape[1:]) - 1j * rng.integers(0, 3, shape[1:])
+    y = vie.matvec(op, to_dev(u, dt), to_dev(epsc, dt)).cpu().numpy().astype(np.complex128)
+    assert np.array_equal(y, epsc[None] * u)
+    yh = vie.matvec(op, to_dev(u, dt), to_dev(epsc, dt), adjoint=True).cpu().numpy().astype(np.complex128)
+    assert np.array_equal(yh, np.conj(epsc)[None] * u)
+
+
+def test_from_tucker_rejects_nonzero_odd_row():
+    n = (2, 2, 2)
+    cores, factors = _integer_tucker(n, 3)
+    factors[3][0][0, 0] = 1.0   # xy is odd along x
+    with pytest.raises(RuntimeError):
+        vie.from_tucker(n, cores, factors)
