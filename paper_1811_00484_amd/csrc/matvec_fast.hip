@@ -527,6 +527,12 @@ __global__ void __launch_bounds__(4 * (L3 / 8), sizeof(T) == 4 ? 3 : 2) k_z_fast
     for (int kA = k1b; kA < k1e; kA += 2) {
         const int kB = kA + 1;
         const bool hasB = kB < k1e;
+        // ---- quad A's pencils: loads issued first, in flight during the V phase
+        const bool m1A = kA > 0 && kA < n1;
+        const bool exA = (s1 == 0 || m1A) && (s2 == 0 || m2);
+        const long baseA = (((long)b * 3 * L2 + pk2) * L1 + (s1 ? L1 - kA : kA)) * N3;
+        c2<T> d[3][8];
+        z_load<T, L3, TPP, Plan::RF0>(d, S2, baseA, cstride, t, exA);
         // ---- V_c = U1_c(k1, :) W_c for both quads of the pair
         if (!a.dense) {
             for (int e = tid; e < 12 * rmax; e += NT) {
@@ -550,12 +556,7 @@ __global__ void __launch_bounds__(4 * (L3 / 8), sizeof(T) == 4 ? 3 : 2) k_z_fast
                 }
             }
         }
-        // ---- quad A: load and forward FFT
-        const bool m1A = kA > 0 && kA < n1;
-        const bool exA = (s1 == 0 || m1A) && (s2 == 0 || m2);
-        const long baseA = (((long)b * 3 * L2 + pk2) * L1 + (s1 ? L1 - kA : kA)) * N3;
-        c2<T> d[3][8];
-        z_load<T, L3, TPP, Plan::RF0>(d, S2, baseA, cstride, t, exA);
+        // ---- quad A: forward FFT
 #pragma unroll
         for (int q = 0; q < 3; ++q) Plan::template fwd<T, TPP, 1, -1>(d[q], X + pe * P, 0, t, tws);
         __syncthreads();   // slices free, Vc complete
