@@ -299,15 +299,24 @@ def main():
                    "alg_GBps_frac_of_measured_copy": gbs / copy_gbs,
                    "z_quads_per_workgroup_autotuned": tuned, "autotune_z_ms": tune_ms,
                    "graph_ms_per_matvec": graph_ms, "graph_equals_eager": graph_same},
-        "roofline": {"bound": "hbm", "kernel": PASS_NAMES[dom], "achieved": dom_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
+        # The dominant kernel is the fused z pass; at 18 flop per HBM byte with
+        # packed FP32 disabled (vector FP32 then issues 78.6 TFLOP/s at most)
+        # it is bound by the vector ALUs, so that is the primary figure; its
+        # HBM rate is reported beside it.
+        "roofline": {"bound": "alu", "kernel": PASS_NAMES[dom],
+                     "achieved": zflops / (avg[dom] * 1e-3) / 1e12 if dom == 2 else None,
+                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": zflops / (avg[dom] * 1e-3) / 1e12 / FP32_PEAK_TFLOPS if dom == 2 else None,
                      "traffic": recorded_traffic(PASS_NAMES[dom], N),
-                     "avg_ms": avg[dom], "alg_bytes_per_launch": dom_bytes,
+                     "avg_ms": avg[dom], "alg_flops_per_launch": zflops if dom == 2 else None,
+                     "frac_of_nonpacked_fp32_peak": (zflops / (avg[dom] * 1e-3) / 1e12 / (FP32_PEAK_TFLOPS / 2)
+                                                     if dom == 2 else None),
+                     "hbm": {"achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": dom_gbs / HBM_PEAK_GBS, "alg_bytes_per_launch": dom_bytes,
+                             "frac_of_measured_copy": dom_gbs / copy_gbs},
                      "pass_avg_ms": dict(zip(PASS_NAMES, avg)),
-                     "alu": {"kernel": "z_fused", "achieved": zflops / (avg[2] * 1e-3) / 1e12,
-                             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                             "frac": zflops / (avg[2] * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
-                             "alg_flops_per_launch": zflops}},
+                     "pass_hbm_GBps": {p: 8.0 * V * PASS_ELEMS_V[i] / (avg[i] * 1e-3) / 1e9
+                                       for i, p in enumerate(PASS_NAMES)}},
     }
     result.update(extra)
     for flag, key, fn in ((args.batch_workload, "batch_workload", batch_workload),
