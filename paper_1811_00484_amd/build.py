@@ -34,15 +34,17 @@ def _run(cmd):
     return out
 
 
-def build(verbose=False, jobs=None):
-    """Compile every source and link libvie.so; returns the library path."""
+def build(verbose=False, jobs=None, defines=(), out=None):
+    """Compile every source and link libvie.so (or ``out``); ``defines`` are
+    extra -D options (launch-shape overrides); returns the library path."""
+    lib = out or LIB
     objdir = tempfile.mkdtemp(prefix="vie_build_")
     objs = []
     procs = []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src + ".o")
-        cmd = [HIPCC] + COMMON + DEVICE + ["-c", path, "-o", obj]
+        cmd = [HIPCC] + COMMON + ["-D" + d for d in defines] + DEVICE + ["-c", path, "-o", obj]
         if src.endswith(".cpp"):
             cmd = [HIPCC] + COMMON + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-c", path, "-o", obj]
         if verbose:
@@ -61,10 +63,10 @@ def build(verbose=False, jobs=None):
         for cmd, out in failed:
             sys.stderr.write(" ".join(cmd) + "\n" + out + "\n")
         raise RuntimeError("libvie build failed")
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     _run([HIPCC, "-shared", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lpthread"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

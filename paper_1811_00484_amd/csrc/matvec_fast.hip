@@ -202,12 +202,30 @@ __global__ void __launch_bounds__(W*(L / E)) k_xy_fast(const void* __restrict__ 
     Plan::fill_tw(tws, tw, tid, NT);
 
     const int n1 = a.n1, n2 = a.n2, n3 = a.n3, L1 = a.L1, L2 = a.L2;
-    const int zq = blockIdx.z, q = zq % 3, bl = zq / 3;
+    int q, bl, tx, row;
+    if (KIND == 3) {
+        // The three components of one tile read the same eps_c rows in the
+        // epilogue: give them workgroup ids g, g + 8, g + 16, which the
+        // dispatcher sends (round robin over the 8 XCDs) to the same XCD one
+        // after another, so two of the three reads hit its L2.
+        const int lid = blockIdx.x, xcd = lid & 7, slot = lid >> 3;
+        const int tile = (slot / 3) * 8 + xcd;
+        const int ntx = (n2 + W - 1) / W;
+        if (tile >= ntx * n3) return;
+        q = slot % 3;
+        bl = blockIdx.z;
+        tx = tile % ntx;
+        row = tile / ntx;
+    } else {
+        q = blockIdx.z % 3;
+        bl = blockIdx.z / 3;
+        tx = blockIdx.x;
+        row = blockIdx.y;
+    }
     const long bqc = (long)bl * 3 + q;                           // compact (workspace) index
     const int b = rhs_map ? rhs_map[bl] : bl;
     const long bqv = (long)b * 3 + q;                           // vector index
-    const int p0 = blockIdx.x * W;                              // first pencil of the tile
-    const int row = blockIdx.y;
+    const int p0 = tx * W;                                      // first pencil of the tile
     // number of valid pencils in the tile and the transform's input length
     int npen, nin;
     if (KIND == 0) { npen = n2; nin = n1; }
@@ -636,11 +654,23 @@ static constexpr int xy_E()
     else return sizeof(T) == 4 ? 32 : 16;
 }
 
+// pencils per workgroup (256 threads unless overridden at build time)
+#ifndef VIE_XY_W512
+#define VIE_XY_W512 0
+#endif
+#ifndef VIE_XY_W256
+#define VIE_XY_W256 0
+#endif
+#ifndef VIE_XY_W128
+#define VIE_XY_W128 0
+#endif
 template <typename T, int L>
 static constexpr int xy_W()
 {
-    // 256 threads per block
-    return 256 / (L / xy_E<T, L>());
+    if constexpr (L == 512 && VIE_XY_W512 > 0) return VIE_XY_W512;
+    else if constexpr (L == 256 && VIE_XY_W256 > 0) return VIE_XY_W256;
+    else if constexpr (L == 128 && VIE_XY_W128 > 0) return VIE_XY_W128;
+    else return 256 / (L / xy_E<T, L>());
 }
 
 template <typename TV, typename T, int L, int KIND>
@@ -653,8 +683,13 @@ static void launch_xy(const void* in, void* out, const c2<TV>* x, const c2<TV>* 
     size_t lds = sizeof(c2<T>) * ((size_t)W * PL<L>::value + RegPlan<L>::TW);
     auto kern = k_xy_fast<TV, T, L, E, W, KIND>;
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, dim3((grid_x + W - 1) / W, grid_y, nz), dim3(NT), lds, s, in, out, x, eps, tw, a,
-                       rhs_map);
+    dim3 grid((grid_x + W - 1) / W, grid_y, nz);
+    if (KIND == 3) {
+        // one dimension over (tile, component) in XCD-grouped order, z = rhs
+        const long tiles = (long)grid.x * grid.y;
+        grid = dim3((unsigned)(3 * ((tiles + 7) / 8) * 8), 1, nz / 3);
+    }
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, in, out, x, eps, tw, a, rhs_map);
 }
 
 template <typename TV, typename T, int KIND>

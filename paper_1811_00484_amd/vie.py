@@ -19,7 +19,9 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvie.so")
+# VIE_LIBRARY selects another build of the same library (e.g. one compiled
+# with different launch shapes); the default is the in-tree build
+LIB_PATH = os.environ.get("VIE_LIBRARY") or os.path.join(HERE, "libvie.so")
 
 VIE_OK, VIE_NOT_CONVERGED = 0, 1
 VIE_E_ARG, VIE_E_NOMEM, VIE_E_HIP, VIE_E_NONFINITE, VIE_E_UNSUPPORTED = -1, -2, -3, -4, -5
