@@ -349,11 +349,14 @@ vie_status vie_set_kernel_path(int path);
 
 /*
  * Execution of multi-instance batches (vie_matvec_multi, vie_solve_multi,
- * and every matvec step of their solves): 0 = default, each instance's five
- * passes on its own launches (register-FFT kernels where the lengths allow),
- * all back to back on the caller's stream; 1 = one launch per pass covering
- * every instance (mixed-radix LDS kernels, per-instance plans from a device
- * table).  Same results up to rounding.  Process-wide.
+ * and every matvec step of their solves): 0 = default: when every instance
+ * has register-FFT kernels for its lengths (2 n1, 2 n2 in 128, 192, 224, 256,
+ * 512; 2 n3 in 128, 256, 512), one launch per pass and FFT length covers all
+ * instances of that length (descriptors in the kernel arguments, up to 24 / 8
+ * instances per x-y / z launch), bitwise equal to single-instance calls;
+ * otherwise each instance's passes run on their own launches.  1 = one launch
+ * per pass covering every instance with the mixed-radix LDS kernels
+ * (per-instance plans from a device table).  Process-wide.
  */
 vie_status vie_set_batch_mode(int mode);
 

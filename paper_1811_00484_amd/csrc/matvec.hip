@@ -948,11 +948,115 @@ hipError_t launch_densify(DeviceOp& op, int with_c128, hipStream_t s)
     return hipGetLastError();
 }
 
+// Whether every instance has register-FFT kernels for all five passes.
+template <typename T>
+static bool batch_grouped_ok(const std::vector<InstHost>& req, int recon)
+{
+    if (g_kernel_path != 0) return false;
+    for (const InstHost& h : req) {
+        const DeviceOp& op = *h.op;
+        const OpView& v = op.view;
+        if (!xy_fast_length(v.L[0]) || !xy_fast_length(v.L[1]) || !z_fast_length(v.L[2])) return false;
+        if (op.nhat_source == 1 && (sizeof(T) == 8 ? (const void*)op.dense64 : (const void*)op.dense32) == nullptr)
+            return false;
+        if (recon == 1 && (sizeof(T) != 4 || !bf16_recon_available(op))) return false;
+    }
+    return true;
+}
+
+// One launch per pass and FFT length over every instance of the batch
+// (register-FFT kernels; the per-instance descriptors are kernel arguments,
+// at most kXYGroupMax / kZGroupMax instances per launch).
+template <typename TV, typename T>
+static hipError_t launch_batch_grouped(const std::vector<InstHost>& req, int mode, int recon, hipStream_t s,
+                                       std::string& err)
+{
+    const int count = (int)req.size();
+    const int conj = (mode == MODE_AH || mode == MODE_NH);
+    auto tw_of = [](const DeviceOp& op, int axis) -> const c2<T>* {
+        if constexpr (sizeof(T) == 8) return op.tw64[axis];
+        else return op.tw32[axis];
+    };
+    for (int p = 0; p < 5; ++p) {
+        PassTimer timer(p, s);
+        const int kind = p < 2 ? p : p - 1;   // X+, Y+, (Z), Y-, X-
+        const int axis = p == 2 ? 2 : ((kind == 0 || kind == 3) ? 0 : 1);
+        const int gmax = p == 2 ? kZGroupMax : kXYGroupMax;
+        std::vector<char> done(count, 0);
+        for (int i = 0; i < count; ++i) {
+            if (done[i]) continue;
+            const int L = req[i].op->view.L[axis];
+            XYGroup xg;
+            ZGroup zg;
+            xg.n = zg.n = 0;
+            int off = 0, rmax = 0;
+            const c2<T>* tw = tw_of(*req[i].op, axis);
+            for (int j = i; j < count; ++j) {
+                if (done[j] || req[j].op->view.L[axis] != L) continue;
+                if ((p == 2 ? zg.n : xg.n) == gmax) break;   // the next launch takes the rest
+                done[j] = 1;
+                const InstHost& h = req[j];
+                const DeviceOp& op = *h.op;
+                const OpView& v = op.view;
+                c2<T>* S2 = (c2<T>*)h.ws;
+                c2<T>* S1 = S2 + (size_t)3 * v.L[1] * v.L[0] * v.n[2] * h.nact;
+                if (p == 2) {
+                    ZInst& z = zg.e[zg.n++];
+                    z = ZInst{};
+                    z.S2 = S2;
+                    if constexpr (sizeof(T) == 8) {
+                        z.core = op.d64.core;
+                        z.fac = op.d64.fac;
+                        z.dense = op.dense64;
+                    } else {
+                        z.core = op.d32.core;
+                        z.fac = op.d32.fac;
+                        z.dense = op.dense32;
+                    }
+                    z.f3m = op.b16.fac3m;
+                    z.za.v = v;
+                    z.za.conj = conj;
+                    z.za.dense = op.nhat_source == 1;
+                    z.za.chunk = op.zchunk;
+                    z.nbx = (v.n[1] + 1) * ((v.n[0] + 1 + op.zchunk - 1) / op.zchunk);
+                    z.off = off;
+                    off += z.nbx * h.nact;
+                    rmax = std::max(rmax, v.rmax);
+                } else {
+                    const int W = xy_fast_tile<TV, T>(L);
+                    XYInst& e = xg.e[xg.n++];
+                    e = XYInst{};
+                    e.x = h.x;
+                    e.eps = h.eps;
+                    e.map = h.map;
+                    e.a = XYArgs{v.n[0], v.n[1], v.n[2], v.L[0], v.L[1], mode};
+                    if (kind == 0) { e.in = nullptr; e.out = S1; e.ntx = (v.n[1] + W - 1) / W; e.rows = v.n[2]; }
+                    else if (kind == 1) { e.in = S1; e.out = S2; e.ntx = (v.n[2] + W - 1) / W; e.rows = v.L[0]; }
+                    else if (kind == 2) { e.in = S2; e.out = S1; e.ntx = (v.n[2] + W - 1) / W; e.rows = v.L[0]; }
+                    else { e.in = S1; e.out = h.y; e.ntx = (v.n[1] + W - 1) / W; e.rows = v.n[2]; }
+                    e.off = off;
+                    off += e.ntx * e.rows * 3 * h.nact;
+                }
+            }
+            if (off == 0) continue;
+            const bool ok = p == 2 ? z_group_fast<T>(L, conj, recon, rmax, req[i].op->max_lds, zg, off, tw, s)
+                                   : xy_group_fast<TV, T>(kind, L, xg, off, tw, s);
+            if (!ok) {
+                err = "grouped register-FFT launch not available for this batch";
+                return hipErrorInvalidValue;
+            }
+        }
+    }
+    return hipGetLastError();
+}
+
 template <typename TV, typename T>
 hipError_t launch_batch(const std::vector<InstHost>& req, int mode, int recon, InstDev* tab, hipStream_t st,
                         std::string& err)
 {
     if (req.empty()) return hipSuccess;
+    if (req.size() > 1 && g_batch_mode == 0 && batch_grouped_ok<T>(req, recon))
+        return launch_batch_grouped<TV, T>(req, mode, recon, st, err);
     if (req.size() == 1 || g_batch_mode == 0) {
         for (const InstHost& h : req) {
             hipError_t e = launch_matvec<TV, T>(*h.op, mode, recon, (const c2<TV>*)h.eps, (const c2<TV>*)h.x,

@@ -180,16 +180,13 @@ struct PL {
 
 // ---------------------------------------------------------------------------
 // X/Y passes.  KIND: 0 = X+, 1 = Y+, 2 = Y-, 3 = X-.
-struct XYArgs {
-    int n1, n2, n3, L1, L2;
-    int mode;
-};
-
+// One workgroup of an X/Y pass: pencil tile tx, row, component q, compact
+// right-hand side bl (mapped through rhs_map).
 template <typename TV, typename T, int L, int E, int W, int KIND>
-__global__ void __launch_bounds__(W*(L / E)) k_xy_fast(const void* __restrict__ in_, void* __restrict__ out_,
-                                                       const c2<TV>* __restrict__ x, const c2<TV>* __restrict__ eps,
-                                                       const c2<T>* __restrict__ tw, XYArgs a,
-                                                       const int* __restrict__ rhs_map)
+__device__ __forceinline__ void xy_body(const void* __restrict__ in_, void* __restrict__ out_,
+                                        const c2<TV>* __restrict__ x, const c2<TV>* __restrict__ eps,
+                                        const c2<T>* __restrict__ tw, const XYArgs& a,
+                                        const int* __restrict__ rhs_map, int tx, int row, int q, int bl)
 {
     constexpr int TPP = L / E;
     constexpr int NT = W * TPP;
@@ -202,26 +199,6 @@ __global__ void __launch_bounds__(W*(L / E)) k_xy_fast(const void* __restrict__ 
     Plan::fill_tw(tws, tw, tid, NT);
 
     const int n1 = a.n1, n2 = a.n2, n3 = a.n3, L1 = a.L1, L2 = a.L2;
-    int q, bl, tx, row;
-    if (KIND == 3) {
-        // The three components of one tile read the same eps_c rows in the
-        // epilogue: give them workgroup ids g, g + 8, g + 16, which the
-        // dispatcher sends (round robin over the 8 XCDs) to the same XCD one
-        // after another, so two of the three reads hit its L2.
-        const int lid = blockIdx.x, xcd = lid & 7, slot = lid >> 3;
-        const int tile = (slot / 3) * 8 + xcd;
-        const int ntx = (n2 + W - 1) / W;
-        if (tile >= ntx * n3) return;
-        q = slot % 3;
-        bl = blockIdx.z;
-        tx = tile % ntx;
-        row = tile / ntx;
-    } else {
-        q = blockIdx.z % 3;
-        bl = blockIdx.z / 3;
-        tx = blockIdx.x;
-        row = blockIdx.y;
-    }
     const long bqc = (long)bl * 3 + q;                           // compact (workspace) index
     const int b = rhs_map ? rhs_map[bl] : bl;
     const long bqv = (long)b * 3 + q;                           // vector index
@@ -338,15 +315,53 @@ __global__ void __launch_bounds__(W*(L / E)) k_xy_fast(const void* __restrict__ 
     }
 }
 
+template <typename TV, typename T, int L, int E, int W, int KIND>
+__global__ void __launch_bounds__(W*(L / E)) k_xy_fast(const void* __restrict__ in_, void* __restrict__ out_,
+                                                       const c2<TV>* __restrict__ x, const c2<TV>* __restrict__ eps,
+                                                       const c2<T>* __restrict__ tw, XYArgs a,
+                                                       const int* __restrict__ rhs_map)
+{
+    int q, bl, tx, row;
+    if (KIND == 3) {
+        // The three components of one tile read the same eps_c rows in the
+        // epilogue: give them workgroup ids g, g + 8, g + 16, which the
+        // dispatcher sends (round robin over the 8 XCDs) to the same XCD one
+        // after another, so two of the three reads hit its L2.
+        const int lid = blockIdx.x, xcd = lid & 7, slot = lid >> 3;
+        const int tile = (slot / 3) * 8 + xcd;
+        const int ntx = (a.n2 + W - 1) / W;
+        if (tile >= ntx * a.n3) return;
+        q = slot % 3;
+        bl = blockIdx.z;
+        tx = tile % ntx;
+        row = tile / ntx;
+    } else {
+        q = blockIdx.z % 3;
+        bl = blockIdx.z / 3;
+        tx = blockIdx.x;
+        row = blockIdx.y;
+    }
+    xy_body<TV, T, L, E, W, KIND>(in_, out_, x, eps, tw, a, rhs_map, tx, row, q, bl);
+}
+
+// Grouped launch over several instances with the same FFT length: workgroup
+// ids are split by the instances' first-workgroup offsets (ascending); the
+// descriptors are kernel arguments.
+template <typename TV, typename T, int L, int E, int W, int KIND>
+__global__ void __launch_bounds__(W*(L / E)) k_xy_fast_multi(const XYGroup g, const c2<T>* __restrict__ tw)
+{
+    int i = 0;
+    while (i + 1 < g.n && (int)blockIdx.x >= g.e[i + 1].off) ++i;
+    const XYInst& in = g.e[i];
+    const int local = blockIdx.x - in.off;
+    const int tx = local % in.ntx, t2 = local / in.ntx;
+    const int row = t2 % in.rows, zq = t2 / in.rows;
+    xy_body<TV, T, L, E, W, KIND>(in.in, in.out, (const c2<TV>*)in.x, (const c2<TV>*)in.eps, tw, in.a, in.map, tx,
+                                  row, zq % 3, zq / 3);
+}
+
 // ---------------------------------------------------------------------------
 // Z pass
-struct ZFastArgs {
-    OpView v;
-    int conj;
-    int dense;
-    int chunk;     // k1 quads per block
-};
-
 __device__ __forceinline__ int zsign(int c, int f1, int f2, int f3)
 {
     int odd1 = (c == 3 || c == 4), odd2 = (c == 3 || c == 5), odd3 = (c == 4 || c == 5);
@@ -475,12 +490,13 @@ __device__ __forceinline__ void z_tables_mfma(const OpView& v, const unsigned sh
 
 // REC: 0 = N^ tables in T on the vector ALUs, 1 = BF16 z factors on MFMA
 // (T = float).
+// One workgroup of the z pass: bx = canonical k2 + (n2 + 1) * chunk index,
+// b = compact right-hand side.
 template <typename T, int L3, bool CONJ, int REC>
-__global__ void __launch_bounds__(4 * (L3 / 8), sizeof(T) == 4 ? 3 : 2) k_z_fast(c2<T>* __restrict__ S2, const c2<T>* __restrict__ tw,
-                                                         ZFastArgs a, const c2<T>* __restrict__ core,
-                                                         const c2<T>* __restrict__ fac,
-                                                         const c2<T>* __restrict__ dense,
-                                                         const unsigned short* __restrict__ f3m)
+__device__ __forceinline__ void z_body(c2<T>* __restrict__ S2, const c2<T>* __restrict__ tw, const ZFastArgs& a,
+                                       const c2<T>* __restrict__ core, const c2<T>* __restrict__ fac,
+                                       const c2<T>* __restrict__ dense, const unsigned short* __restrict__ f3m,
+                                       int bx, int b)
 {
     constexpr int TPP = L3 / 8;
     constexpr int NT = 4 * TPP;
@@ -507,10 +523,9 @@ __global__ void __launch_bounds__(4 * (L3 / 8), sizeof(T) == 4 ? 3 : 2) k_z_fast
     c2<T>* tws = Vc + 12 * rmax;                                // [Plan::TW]
     Plan::fill_tw(tws, tw, tid, NT);
 
-    const int k2 = blockIdx.x % (n2 + 1);
-    const int k1b = (blockIdx.x / (n2 + 1)) * a.chunk;
+    const int k2 = bx % (n2 + 1);
+    const int k1b = (bx / (n2 + 1)) * a.chunk;
     const int k1e = min(n1 + 1, k1b + a.chunk);
-    const int b = blockIdx.y;
     const bool m2 = k2 > 0 && k2 < n2;
     const int pk2 = s2 ? L2 - k2 : k2;
     const long cstride = (long)L2 * L1 * N3;
@@ -639,6 +654,28 @@ __global__ void __launch_bounds__(4 * (L3 / 8), sizeof(T) == 4 ? 3 : 2) k_z_fast
         }
         __syncthreads();   // Vc, NTB and the slices are reused by the next pair
     }
+}
+
+template <typename T, int L3, bool CONJ, int REC>
+__global__ void __launch_bounds__(4 * (L3 / 8), sizeof(T) == 4 ? 3 : 2)
+    k_z_fast(c2<T>* __restrict__ S2, const c2<T>* __restrict__ tw, ZFastArgs a, const c2<T>* __restrict__ core,
+             const c2<T>* __restrict__ fac, const c2<T>* __restrict__ dense,
+             const unsigned short* __restrict__ f3m)
+{
+    z_body<T, L3, CONJ, REC>(S2, tw, a, core, fac, dense, f3m, blockIdx.x, blockIdx.y);
+}
+
+// Grouped launch over instances with the same z length (offsets ascending).
+template <typename T, int L3, bool CONJ, int REC>
+__global__ void __launch_bounds__(4 * (L3 / 8), sizeof(T) == 4 ? 3 : 2)
+    k_z_fast_multi(const ZGroup g, const c2<T>* __restrict__ tw)
+{
+    int i = 0;
+    while (i + 1 < g.n && (int)blockIdx.x >= g.e[i + 1].off) ++i;
+    const ZInst& in = g.e[i];
+    const int local = blockIdx.x - in.off;
+    z_body<T, L3, CONJ, REC>((c2<T>*)in.S2, tw, in.za, (const c2<T>*)in.core, (const c2<T>*)in.fac,
+                             (const c2<T>*)in.dense, in.f3m, local % in.nbx, local / in.nbx);
 }
 
 // ---------------------------------------------------------------------------
@@ -782,6 +819,106 @@ bool z_pass_fast(const DeviceOp& op, int mode, int recon, int nrhs, c2<T>* S2, c
     default: return false;
     }
 }
+
+// ---- grouped launches (one per pass and FFT length over a batch)
+template <typename TV, typename T, int L, int KIND>
+static void launch_xy_group(const XYGroup& g, int nblocks, const c2<T>* tw, hipStream_t s)
+{
+    constexpr int E = xy_E<T, L>();
+    constexpr int W = xy_W<T, L>();
+    constexpr int NT = W * (L / E);
+    size_t lds = sizeof(c2<T>) * ((size_t)W * PL<L>::value + RegPlan<L>::TW);
+    auto kern = k_xy_fast_multi<TV, T, L, E, W, KIND>;
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), lds, s, g, tw);
+}
+
+template <typename TV, typename T, int KIND>
+static bool dispatch_xy_group(int L, const XYGroup& g, int nblocks, const c2<T>* tw, hipStream_t s)
+{
+    switch (L) {
+    case 512: launch_xy_group<TV, T, 512, KIND>(g, nblocks, tw, s); return true;
+    case 256: launch_xy_group<TV, T, 256, KIND>(g, nblocks, tw, s); return true;
+    case 128: launch_xy_group<TV, T, 128, KIND>(g, nblocks, tw, s); return true;
+    case 192: launch_xy_group<TV, T, 192, KIND>(g, nblocks, tw, s); return true;
+    case 224: launch_xy_group<TV, T, 224, KIND>(g, nblocks, tw, s); return true;
+    default: return false;
+    }
+}
+
+template <typename TV, typename T>
+int xy_fast_tile(int L)
+{
+    switch (L) {
+    case 512: return xy_W<T, 512>();
+    case 256: return xy_W<T, 256>();
+    case 128: return xy_W<T, 128>();
+    case 192: return xy_W<T, 192>();
+    case 224: return xy_W<T, 224>();
+    default: return 0;
+    }
+}
+
+template <typename TV, typename T>
+bool xy_group_fast(int kind, int L, const XYGroup& g, int nblocks, const c2<T>* tw, hipStream_t s)
+{
+    switch (kind) {
+    case 0: return dispatch_xy_group<TV, T, 0>(L, g, nblocks, tw, s);
+    case 1: return dispatch_xy_group<TV, T, 1>(L, g, nblocks, tw, s);
+    case 2: return dispatch_xy_group<TV, T, 2>(L, g, nblocks, tw, s);
+    default: return dispatch_xy_group<TV, T, 3>(L, g, nblocks, tw, s);
+    }
+}
+
+template <typename T, int L3>
+static void launch_z_group(int conj, int recon, int rmax, const ZGroup& g, int nblocks, const c2<T>* tw,
+                           hipStream_t s)
+{
+    OpView dummy{};
+    dummy.rmax = rmax;
+    size_t lds = zfast_lds<T, L3>(dummy);
+    auto kern = conj ? k_z_fast_multi<T, L3, true, 0> : k_z_fast_multi<T, L3, false, 0>;
+    if constexpr (sizeof(T) == 4) {
+        if (recon == 1) kern = conj ? k_z_fast_multi<T, L3, true, 1> : k_z_fast_multi<T, L3, false, 1>;
+    }
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(4 * (L3 / 8)), lds, s, g, tw);
+}
+
+template <typename T>
+bool z_group_fast(int L3, int conj, int recon, int rmax, size_t max_lds, const ZGroup& g, int nblocks,
+                  const c2<T>* tw, hipStream_t s)
+{
+    OpView dummy{};
+    dummy.rmax = rmax;
+    switch (L3) {
+    case 512:
+        if (zfast_lds<T, 512>(dummy) > max_lds) return false;
+        launch_z_group<T, 512>(conj, recon, rmax, g, nblocks, tw, s);
+        return true;
+    case 256:
+        if (zfast_lds<T, 256>(dummy) > max_lds) return false;
+        launch_z_group<T, 256>(conj, recon, rmax, g, nblocks, tw, s);
+        return true;
+    case 128:
+        if (zfast_lds<T, 128>(dummy) > max_lds) return false;
+        launch_z_group<T, 128>(conj, recon, rmax, g, nblocks, tw, s);
+        return true;
+    default: return false;
+    }
+}
+
+bool z_fast_length(int L3) { return L3 == 512 || L3 == 256 || L3 == 128; }
+bool xy_fast_length(int L) { return L == 512 || L == 256 || L == 128 || L == 192 || L == 224; }
+
+template bool xy_group_fast<float, float>(int, int, const XYGroup&, int, const c2<float>*, hipStream_t);
+template bool xy_group_fast<double, double>(int, int, const XYGroup&, int, const c2<double>*, hipStream_t);
+template bool xy_group_fast<double, float>(int, int, const XYGroup&, int, const c2<float>*, hipStream_t);
+template int xy_fast_tile<float, float>(int);
+template int xy_fast_tile<double, double>(int);
+template int xy_fast_tile<double, float>(int);
+template bool z_group_fast<float>(int, int, int, int, size_t, const ZGroup&, int, const c2<float>*, hipStream_t);
+template bool z_group_fast<double>(int, int, int, int, size_t, const ZGroup&, int, const c2<double>*, hipStream_t);
 
 #define VIE_XYF_INST(TV, T)                                                                                        \
     template bool xy_pass_fast<TV, T>(int, int, const void*, void*, const c2<TV>*, const c2<TV>*, const c2<T>*, int, \

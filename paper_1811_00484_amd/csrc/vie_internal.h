@@ -64,6 +64,42 @@ struct DeviceOp {
     int zchunk = 16;   // k1 mirror quads per z-pass workgroup (vie_autotune)
 };
 
+// Arguments of the register-FFT passes.
+struct XYArgs {
+    int n1, n2, n3, L1, L2;
+    int mode;
+};
+struct ZFastArgs {
+    OpView v;
+    int conj;
+    int dense;
+    int chunk;     // k1 quads per workgroup
+};
+
+// Per-instance descriptors of a grouped register-FFT launch (one launch per
+// pass and FFT length over every instance of a batch with that length).
+struct XYInst {
+    const void* in;
+    void* out;
+    const void* x;
+    const void* eps;
+    const int* map;
+    XYArgs a;
+    int off;    // first workgroup of the instance
+    int ntx;    // pencil tiles
+    int rows;   // rows per component
+};
+struct ZInst {
+    void* S2;
+    const void* core;
+    const void* fac;
+    const void* dense;
+    const unsigned short* f3m;
+    ZFastArgs za;
+    int off;    // first workgroup of the instance
+    int nbx;    // workgroups per right-hand side
+};
+
 // One instance of a multi-instance matvec (several grids, one launch per pass).
 struct InstDev {
     OpView v;
@@ -118,6 +154,18 @@ hipError_t launch_densify(DeviceOp& op, int with_c128, hipStream_t s);
 
 size_t matvec_ws_elems(const DeviceOp& op, int nrhs);   // complex elements per workspace
 
+// Instances per grouped launch (descriptors travel in the kernel arguments).
+constexpr int kXYGroupMax = 24;
+constexpr int kZGroupMax = 8;
+struct XYGroup {
+    int n;
+    XYInst e[kXYGroupMax];
+};
+struct ZGroup {
+    int n;
+    ZInst e[kZGroupMax];
+};
+
 // register-FFT variants of the passes (matvec_fast.hip); false = not available
 template <typename TV, typename T>
 bool xy_pass_fast(int kind, int L, const void* in, void* out, const c2<TV>* x, const c2<TV>* eps, const c2<T>* tw,
@@ -128,6 +176,16 @@ bool z_pass_fast(const DeviceOp& op, int mode, int recon, int nrhs, c2<T>* S2, c
                  const c2<T>* fac, const c2<T>* dense, hipStream_t s);
 // whether the BF16 MFMA reconstruction can run for this operator
 bool bf16_recon_available(const DeviceOp& op);
+// grouped register-FFT launches over a batch (instance tables on the device)
+bool xy_fast_length(int L);
+bool z_fast_length(int L3);
+template <typename TV, typename T>
+int xy_fast_tile(int L);   // pencils per workgroup of the X/Y kernels at length L
+template <typename TV, typename T>
+bool xy_group_fast(int kind, int L, const XYGroup& g, int nblocks, const c2<T>* tw, hipStream_t s);
+template <typename T>
+bool z_group_fast(int L3, int conj, int recon, int rmax, size_t max_lds, const ZGroup& g, int nblocks,
+                  const c2<T>* tw, hipStream_t s);
 // 0 = choose per pass (register FFT where the length allows), 1 = generic kernels only
 extern int g_kernel_path;
 // multi-instance batches: 0 = each instance's passes on its own (register-FFT)
