@@ -255,6 +255,17 @@ __device__ __forceinline__ void xy_body(const void* __restrict__ in_, void* __re
             else S[((bqc * L2 + m) * L1 + row) * n3 + p] = val;
         }
     } else {
+        // ---- X- epilogue operands (u, eps_c at the kept rows) are loaded
+        //      together with the transposed input, so their latency is hidden
+        //      behind the FFT (complex64: the LDS already limits the kernel to
+        //      two workgroups per CU, so the registers are free)
+        constexpr int RL = Plan::RIL;
+        constexpr int RH = (RL + 1) / 2;                        // rows m < L/2 sit in r < RH
+        constexpr bool PRE = KIND == 3 && sizeof(TV) == 4 && sizeof(T) == 4;
+        constexpr int NPRE = PRE ? (E / RL) * RH : 1;
+        const int nout = KIND == 2 ? n2 : n1;
+        const bool contrast = a.mode == MODE_A || a.mode == MODE_AH;
+        c2<TV> xpre[NPRE], epre[NPRE];
         // ---- transposed input: element m of pencil ww at [m][p0 + ww];
         //      all E loads of a thread are issued before the LDS writes
         {
@@ -272,6 +283,20 @@ __device__ __forceinline__ void xy_body(const void* __restrict__ in_, void* __re
                 }
                 tmp[u] = val;
             }
+            if constexpr (PRE) {
+                if (contrast && pw < npen) {
+#pragma unroll
+                    for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+                        for (int r = 0; r < RH; ++r) {
+                            const int m = t + TPP * u + r * (L / RL);
+                            if (m < nout) {
+                                xpre[u * RH + r] = x[((bqv * n3 + row) * n2 + pw) * n1 + m];
+                                epre[u * RH + r] = eps[((long)row * n2 + pw) * n1 + m];
+                            }
+                        }
+                }
+            }
 #pragma unroll
             for (int u = 0; u < E; ++u) {
                 const int e = tid + u * NT;
@@ -283,8 +308,6 @@ __device__ __forceinline__ void xy_body(const void* __restrict__ in_, void* __re
         wave_sync();   // the slice is only rewritten by the lanes of this pencil's wavefront
         Plan::template inv<T, TPP, 1, 1>(v, slice, 0, t, tws);
         // ---- cropped rows straight from the registers of the last stage
-        constexpr int RL = Plan::RIL;
-        const int nout = KIND == 2 ? n2 : n1;
         if (pw < npen) {
 #pragma unroll
             for (int u = 0; u < E / RL; ++u)
@@ -300,9 +323,16 @@ __device__ __forceinline__ void xy_body(const void* __restrict__ in_, void* __re
                         c2<TV>* y = reinterpret_cast<c2<TV>*>(out_);
                         long idx = ((bqv * n3 + row) * n2 + pw) * n1 + m;
                         c2<T> o;
-                        if (a.mode == MODE_A || a.mode == MODE_AH) {
-                            c2<T> u0 = cvt<T>(x[idx]);
-                            c2<T> ep = cvt<T>(eps[((long)row * n2 + pw) * n1 + m]);
+                        if (contrast) {
+                            c2<T> u0, ep;
+                            if constexpr (PRE) {
+                                // r < RH holds for every kept row (m < n1 = L/2)
+                                u0 = cvt<T>(xpre[u * RH + (r < RH ? r : 0)]);
+                                ep = cvt<T>(epre[u * RH + (r < RH ? r : 0)]);
+                            } else {
+                                u0 = cvt<T>(x[idx]);
+                                ep = cvt<T>(eps[((long)row * n2 + pw) * n1 + m]);
+                            }
                             if (a.mode == MODE_A) o = ep * u0 - mk<T>(ep.x - (T)1, ep.y) * rr;
                             else o = conj(ep) * u0 - rr;
                         } else {
