@@ -25,6 +25,7 @@ import scipy.fft as sfft
 
 from .circulant import COMPONENTS, axis_signs, component_index, fourier_tensor_dense, \
     fourier_tensor_tucker
+from .cp import fourier_tensor_cp, tucker_cp
 from .tucker import from_storage, hosvd, to_storage
 
 
@@ -69,6 +70,23 @@ def tucker_operator(green, tol, rule=0):
         cores.append(G)
         svals.append(s)
     return FourierOperator(n, nhat, ranks, factors, cores, svals)
+
+
+def tucker_cp_operator(green, tol, R=None, iters=1000, rule=0):
+    """Tucker+CP of each defining tensor (Alg. 2: HOSVD at ``tol``, CP of the
+    core with R terms by alternating least squares), then the Fourier-domain
+    tensor of eq. 17 with the embedded, transformed Tucker+CP factors."""
+    n = (green.shape[3], green.shape[2], green.shape[1])
+    nhat, ranks, factors, errs = [], [], [], []
+    for c in range(6):
+        Ws, G, Us, Vs, e = tucker_cp(from_storage(green[c]), tol, R, iters, rule)
+        nhat.append(fourier_tensor_cp(Ws, axis_signs(c)))
+        ranks.append(tuple(U.shape[1] for U in Us))
+        factors.append(Ws)
+        errs.append(e[-1] if e else 0.0)
+    op = FourierOperator(n, nhat, ranks, factors)
+    op.cp_rel_err = errs
+    return op
 
 
 def apply_N(op, u, conj=False):
