@@ -84,12 +84,15 @@ typedef struct {
     double tail_bound[6];    /* sqrt(sum of discarded sigma^2 over the 3 unfoldings) / ||A||_F */
     double fro_norm[6];      /* ||A_c||_F of each defining tensor */
     size_t tucker_bytes_c64; /* bytes of the cores + Fourier factors (rows 0..n_i), each stored
-                                once, at complex64: the compressed operator */
+                                once, at complex64: the compressed operator (a superdiagonal
+                                Tucker+CP core counts its R diagonal weights only) */
     size_t dense_bytes_c64;  /* bytes of the 6 dense circulant spectra (8 n1 n2 n3 points each)
                                 at complex64: what the uncompressed method stores */
     size_t device_bytes;     /* all device memory the operator holds: FP64, FP32 and BF16
                                 copies, the kernels' extra z-factor layouts, twiddles */
     double seconds;          /* host time of the compression */
+    int cp;                  /* 1 if every core is superdiagonal with r1 = r2 = r3 (a Tucker+CP
+                                form, eq. 17; ranks then hold (R, R, R)), 0 otherwise */
 } vie_compress_info;
 
 /*
@@ -111,6 +114,20 @@ vie_status vie_compress(const int n[3], const double* green, const vie_compress_
                         vie_op** out, vie_compress_info* info);
 
 /*
+ * vie_compress_cp -- Tucker+CP compression (Alg. 2): the HOSVD of vie_compress
+ * (same n, green, opts), then a CP decomposition of each core with cp_rank
+ * terms (0 = the smallest of that core's Tucker ranks) by alternating least
+ * squares, cp_iters sweeps (0 = 1000), started from the leading left singular
+ * vectors of the core's unfoldings; the operator holds the Tucker+CP factors
+ * W^i = U^i V^i (eq. 17) and the z pass builds each N^ pencil from them with
+ * no core contraction.
+ *   cp_rel_err  HOST double[6] out (may be NULL): ||G_c - CP(G_c)||_F / ||G_c||_F.
+ * Errors as vie_compress; VIE_E_ARG for a CP rank above a Tucker rank.
+ */
+vie_status vie_compress_cp(const int n[3], const double* green, const vie_compress_opts* opts, int cp_rank,
+                           int cp_iters, vie_op** out, vie_compress_info* info, double cp_rel_err[6]);
+
+/*
  * vie_op_from_tucker -- build an operator from a Tucker form of the six
  * defining tensors computed elsewhere (eq. 13-14: another truncation, a cross
  * approximation, a stored decomposition).  The factor columns are embedded
@@ -125,6 +142,8 @@ vie_status vie_compress(const int n[3], const double* green, const vie_compress_
  *            zero row 0 (the odd tensor vanishes at zero offset; VIE_E_ARG).
  *   out      receives the new operator; info (may be NULL) as in vie_compress
  *            with tail_bound and fro_norm set to 0.
+ * Superdiagonal cores with r1 = r2 = r3 (a Tucker+CP form) take the same
+ * core-free z-pass branch as vie_compress_cp.
  */
 vie_status vie_op_from_tucker(const int n[3], const int ranks[6][3], const double* cores, const double* factors,
                               vie_op** out, vie_compress_info* info);
@@ -325,6 +344,17 @@ vie_status vie_debug_nhat(const vie_op* op, int dtype, int recon, const int* idx
  */
 vie_status vie_debug_hosvd(const int n[3], const double* tensor, double tol, int rule, int ranks[3],
                            double* svals, double* recon, double* tail);
+
+/*
+ * vie_debug_cp: the CP step of vie_compress_cp (Alg. 2) for ONE core, with no
+ * device work.
+ *   r       HOST int[3], 1 <= r_i <= 64; core HOST complex128 [r1][r2][r3].
+ *   R       CP rank, 1 <= R <= min r_i; iters: ALS sweeps (0 = start only).
+ *   V       HOST complex128 out, V1 [r1][R] then V2 [r2][R] then V3 [r3][R],
+ *           so that core ~ sum_l V1[:, l] (x) V2[:, l] (x) V3[:, l].
+ *   rel_err HOST double out (may be NULL): ||core - CP||_F / ||core||_F.
+ */
+vie_status vie_debug_cp(const int r[3], const double* core, int R, int iters, double* V, double* rel_err);
 
 /*
  * Per-pass timing of the matvec pipeline (for benchmarks).  While enabled,

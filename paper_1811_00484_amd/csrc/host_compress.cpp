@@ -381,6 +381,138 @@ int hosvd_component(const cd* A, const int n[3], double tol, int rule, int max_r
 
 // Rows 0..n of the DFT (length 2n, exp(-2 pi i m k / 2n)) of the embedded
 // columns e[m] = U[m] (m < n), e[n] = 0, e[2n - m] = s U[m] (1 <= m < n).
+// element (a, b, c) of the core, math order, r3 fastest
+static inline cd core_at(const std::vector<cd>& G, const int r[3], int a, int b, int c)
+{
+    return G[((size_t)a * r[1] + b) * r[2] + c];
+}
+
+// Mode-`mode` unfolding of the core with the column order (other axes in
+// increasing axis order, the later one fastest): rows r_mode, columns
+// r_p r_q with (p, q) the other two axes.
+static void core_unfold(const std::vector<cd>& G, const int r[3], int mode, std::vector<cd>& Y)
+{
+    const int p = mode == 0 ? 1 : 0, q = mode == 2 ? 1 : 2;
+    const int nr = r[mode], np = r[p], nq = r[q];
+    Y.assign((size_t)nr * np * nq, 0);
+    for (int i = 0; i < nr; ++i)
+        for (int x = 0; x < np; ++x)
+            for (int y = 0; y < nq; ++y) {
+                int idx[3];
+                idx[mode] = i;
+                idx[p] = x;
+                idx[q] = y;
+                Y[((size_t)i * np + x) * nq + y] = core_at(G, r, idx[0], idx[1], idx[2]);
+            }
+}
+
+// Solve X M = B for X (rows x R) with M (R x R): Gauss-Jordan with partial
+// pivoting on M^T; a (near) singular pivot is replaced by a tiny ridge.
+static void solve_right(std::vector<cd>& B, int rows, const std::vector<cd>& M, int R)
+{
+    std::vector<cd> A((size_t)R * R);   // A = M^T
+    for (int i = 0; i < R; ++i)
+        for (int j = 0; j < R; ++j) A[(size_t)i * R + j] = M[(size_t)j * R + i];
+    // right-hand sides: columns of B^T, i.e. rows of B
+    std::vector<cd> Bt((size_t)R * rows);
+    for (int t = 0; t < rows; ++t)
+        for (int l = 0; l < R; ++l) Bt[(size_t)l * rows + t] = B[(size_t)t * R + l];
+    double scale = 0;
+    for (int i = 0; i < R; ++i) scale = std::max(scale, std::abs(A[(size_t)i * R + i]));
+    for (int k = 0; k < R; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < R; ++i)
+            if (std::abs(A[(size_t)i * R + k]) > std::abs(A[(size_t)piv * R + k])) piv = i;
+        if (piv != k) {
+            for (int j = 0; j < R; ++j) std::swap(A[(size_t)k * R + j], A[(size_t)piv * R + j]);
+            for (int t = 0; t < rows; ++t) std::swap(Bt[(size_t)k * rows + t], Bt[(size_t)piv * rows + t]);
+        }
+        cd d = A[(size_t)k * R + k];
+        if (std::abs(d) <= 1e-14 * scale) d = A[(size_t)k * R + k] = cd(1e-14 * (scale > 0 ? scale : 1.0));
+        for (int i = 0; i < R; ++i) {
+            if (i == k) continue;
+            const cd f = A[(size_t)i * R + k] / d;
+            if (f == cd(0)) continue;
+            for (int j = k; j < R; ++j) A[(size_t)i * R + j] -= f * A[(size_t)k * R + j];
+            for (int t = 0; t < rows; ++t) Bt[(size_t)i * rows + t] -= f * Bt[(size_t)k * rows + t];
+        }
+    }
+    for (int k = 0; k < R; ++k) {
+        const cd d = A[(size_t)k * R + k];
+        for (int t = 0; t < rows; ++t) B[(size_t)t * R + k] = Bt[(size_t)k * rows + t] / d;
+    }
+}
+
+double cp_als(const std::vector<cd>& G, const int r[3], int R, int iters, std::vector<cd> V[3])
+{
+    std::vector<cd> Y;
+    double gn = 0;
+    for (const cd& g : G) gn += std::norm(g);
+    gn = std::sqrt(gn);
+    // start: leading R left singular vectors of each unfolding
+    for (int m = 0; m < 3; ++m) {
+        core_unfold(G, r, m, Y);
+        std::vector<cd> U;
+        std::vector<double> s;
+        const long cols = (long)r[(m + 1) % 3] * r[(m + 2) % 3];
+        if (r[m] <= cols) {
+            svd_left(Y.data(), r[m], cols, U, s, true);
+        } else {
+            U.assign((size_t)r[m] * r[m], 0);
+            for (int i = 0; i < r[m]; ++i) U[(size_t)i * r[m] + i] = 1.0;
+        }
+        V[m].assign((size_t)r[m] * R, 0);
+        for (int i = 0; i < r[m]; ++i)
+            for (int l = 0; l < R; ++l) V[m][(size_t)i * R + l] = U[(size_t)i * r[m] + l];
+    }
+    auto fit_error = [&]() {
+        double e = 0;
+        for (int a = 0; a < r[0]; ++a)
+            for (int b = 0; b < r[1]; ++b)
+                for (int c = 0; c < r[2]; ++c) {
+                    cd acc = 0;
+                    for (int l = 0; l < R; ++l)
+                        acc += V[0][(size_t)a * R + l] * V[1][(size_t)b * R + l] * V[2][(size_t)c * R + l];
+                    e += std::norm(core_at(G, r, a, b, c) - acc);
+                }
+        return gn > 0 ? std::sqrt(e) / gn : 0.0;
+    };
+    std::vector<cd> K, M((size_t)R * R), B;
+    for (int it = 0; it < iters; ++it) {
+        for (int m = 0; m < 3; ++m) {
+            const int p = m == 0 ? 1 : 0, q = m == 2 ? 1 : 2;
+            const int np = r[p], nq = r[q];
+            // K[x nq + y, l] = V_p[x, l] V_q[y, l]
+            K.assign((size_t)np * nq * R, 0);
+            for (int x = 0; x < np; ++x)
+                for (int y = 0; y < nq; ++y)
+                    for (int l = 0; l < R; ++l)
+                        K[((size_t)x * nq + y) * R + l] = V[p][(size_t)x * R + l] * V[q][(size_t)y * R + l];
+            // M = (V_p^T conj V_p) * (V_q^T conj V_q)
+            for (int l = 0; l < R; ++l)
+                for (int k = 0; k < R; ++k) {
+                    cd gp = 0, gq = 0;
+                    for (int x = 0; x < np; ++x) gp += V[p][(size_t)x * R + l] * std::conj(V[p][(size_t)x * R + k]);
+                    for (int y = 0; y < nq; ++y) gq += V[q][(size_t)y * R + l] * std::conj(V[q][(size_t)y * R + k]);
+                    M[(size_t)l * R + k] = gp * gq;
+                }
+            // B = G^(m) conj(K)
+            core_unfold(G, r, m, Y);
+            const long cols = (long)np * nq;
+            B.assign((size_t)r[m] * R, 0);
+            for (int i = 0; i < r[m]; ++i)
+                for (long t = 0; t < cols; ++t) {
+                    const cd y = Y[(size_t)i * cols + t];
+                    if (y == cd(0)) continue;
+                    for (int l = 0; l < R; ++l) B[(size_t)i * R + l] += y * std::conj(K[(size_t)t * R + l]);
+                }
+            solve_right(B, r[m], M, R);
+            V[m] = B;
+        }
+    }
+    return fit_error();
+}
+
 cd twiddle(long m, long L)
 {
     m %= L;

@@ -29,6 +29,16 @@ int truncation_rank(const std::vector<double>& s, double tol, int rule, double f
 int hosvd_component(const std::complex<double>* A, const int n[3], double tol, int rule,
                     int max_rank, TuckerComponent& out);
 
+// CP of a Tucker core G [r1][r2][r3] (r3 fastest) with R <= min r_i terms by
+// alternating least squares (the CP step of Alg. 2): start from the leading R
+// left singular vectors of the core's unfoldings, then `iters` sweeps over
+// modes 1, 2, 3, each the least-squares update V_i = G^(i) conj(K) M^{-1}
+// (K the Khatri-Rao product of the other two factors, M the element-wise
+// product of their Gram matrices).  V[a]: r_a x R row-major.  Returns the
+// relative Frobenius error of the fit.
+double cp_als(const std::vector<std::complex<double>>& G, const int r[3], int R, int iters,
+              std::vector<std::complex<double>> V[3]);
+
 // exp(-2 pi i m / L), exact (0, +-1) at the multiples of a quarter turn.
 std::complex<double> twiddle(long m, long L);
 

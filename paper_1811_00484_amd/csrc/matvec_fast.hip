@@ -560,8 +560,18 @@ __device__ __forceinline__ void z_body(c2<T>* __restrict__ S2, const c2<T>* __re
     const int pk2 = s2 ? L2 - k2 : k2;
     const long cstride = (long)L2 * L1 * N3;
 
-    // ---- W_c(k2) = G_c x2 U2_c(k2, :) for the six components
-    if (!a.dense) {
+    // ---- W_c(k2) = G_c x2 U2_c(k2, :) for the six components; for a
+    //      superdiagonal core (Tucker+CP, eq. 17) only its diagonal
+    //      W_c[l] = G_c[l,l,l] U2_c(k2, l) is nonzero and is all that is kept
+    if (!a.dense && v.cp) {
+        for (int e = tid; e < 6 * rmax; e += NT) {
+            const int c = e / rmax, l = e - c * rmax;
+            const int R = v.r[c][0];
+            if (l < R)
+                Wc[c * rmax * rmax + l] = core[v.core_off[c] + (long)l * (R * R + R + 1)] *
+                                               fac[v.fac_off[c][1] + (long)k2 * R + l];
+        }
+    } else if (!a.dense) {
         for (int c = 0; c < 6; ++c) {
             const int r1 = v.r[c][0], r2 = v.r[c][1], r3 = v.r[c][2];
             const c2<T>* G = core + v.core_off[c];
@@ -596,8 +606,17 @@ __device__ __forceinline__ void z_body(c2<T>* __restrict__ S2, const c2<T>* __re
         const long baseA = (((long)b * 3 * L2 + pk2) * L1 + (s1 ? L1 - kA : kA)) * N3;
         c2<T> d[3][8];
         z_load<T, L3, TPP, Plan::RF0>(d, S2, baseA, cstride, t, exA);
-        // ---- V_c = U1_c(k1, :) W_c for both quads of the pair
-        if (!a.dense) {
+        // ---- V_c = U1_c(k1, :) W_c for both quads of the pair (for a
+        //      superdiagonal core the element-wise product with its diagonal)
+        if (!a.dense && v.cp) {
+            for (int e = tid; e < 12 * rmax; e += NT) {
+                const int qd = e / (6 * rmax), rem = e - qd * 6 * rmax;
+                const int c = rem / rmax, l = rem - c * rmax;
+                const int R = v.r[c][0];
+                if (l < R && (qd == 0 || hasB))
+                    Vc[e] = fac[v.fac_off[c][0] + (long)(qd ? kB : kA) * R + l] * Wc[c * rmax * rmax + l];
+            }
+        } else if (!a.dense) {
             for (int e = tid; e < 12 * rmax; e += NT) {
                 const int qd = e / (6 * rmax), rem = e - qd * 6 * rmax;
                 const int c = rem / rmax, ga = rem - c * rmax;

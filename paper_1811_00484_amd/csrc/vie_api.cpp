@@ -108,6 +108,22 @@ static vie_status build_operator(const int n[3], const FftPlan plans[3], TuckerC
     }
     v.rmax = rmax;
     if (rmax > 64) return fail(VIE_E_UNSUPPORTED, "vie_compress: Tucker rank above 64");
+    // superdiagonal cores (Tucker+CP forms) take the z pass's CP branch
+    v.cp = 1;
+    for (int c = 0; c < 6 && v.cp; ++c) {
+        const int R = tc[c].r[0];
+        if (tc[c].r[1] != R || tc[c].r[2] != R) {
+            v.cp = 0;
+            break;
+        }
+        for (int a = 0; a < R && v.cp; ++a)
+            for (int b = 0; b < R && v.cp; ++b)
+                for (int g = 0; g < R; ++g)
+                    if (!(a == b && b == g) && tc[c].G[((size_t)a * R + b) * R + g] != cd(0.0)) {
+                        v.cp = 0;
+                        break;
+                    }
+    }
     const double invM = 1.0 / (8.0 * (double)V);
     std::vector<cd> hcore(core_tot), hfac(fac_tot);
     for (int c = 0; c < 6; ++c) {
@@ -200,7 +216,14 @@ static vie_status build_operator(const int n[3], const FftPlan plans[3], TuckerC
         return e == hipErrorOutOfMemory ? fail(VIE_E_NOMEM, "vie_compress: device allocation failed")
                                         : hip_fail(e, "vie_compress upload");
     }
-    d.tucker_bytes = (size_t)(core_tot + fac_unique) * sizeof(c2<float>);
+    // a Tucker+CP operator's compressed form is its factors and the R weights
+    // on the core's diagonal
+    size_t core_unique = core_tot;
+    if (v.cp) {
+        core_unique = 0;
+        for (int c = 0; c < 6; ++c) core_unique += tc[c].r[0];
+    }
+    d.tucker_bytes = (core_unique + fac_unique) * sizeof(c2<float>);
     size_t twb = 0;
     for (int a = 0; a < 3; ++a) twb += (size_t)v.L[a] * (sizeof(c2<double>) + sizeof(c2<float>));
     d.device_bytes = (size_t)(core_tot + fac_tot) * (sizeof(c2<double>) + sizeof(c2<float>) + 4) +
@@ -218,6 +241,7 @@ static vie_status build_operator(const int n[3], const FftPlan plans[3], TuckerC
         info->dense_bytes_c64 = (size_t)6 * 8 * (size_t)V * sizeof(c2<float>);
         info->device_bytes = d.device_bytes;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->cp = v.cp;
     }
     return VIE_OK;
 }
@@ -232,8 +256,24 @@ const char* vie_last_error(void) { return g_last_error.c_str(); }
 
 const char* vie_version(void) { return "vie-gfx950 0.1"; }
 
+static vie_status compress_common(const int n[3], const double* green, const vie_compress_opts* opts, int cp_rank,
+                                  int cp_iters, vie_op** out, vie_compress_info* info, double* cp_err);
+
 vie_status vie_compress(const int n[3], const double* green, const vie_compress_opts* opts, vie_op** out,
                         vie_compress_info* info)
+{
+    return compress_common(n, green, opts, -1, 0, out, info, nullptr);
+}
+
+vie_status vie_compress_cp(const int n[3], const double* green, const vie_compress_opts* opts, int cp_rank,
+                           int cp_iters, vie_op** out, vie_compress_info* info, double cp_rel_err[6])
+{
+    if (cp_rank < 0 || cp_iters < 0) return fail(VIE_E_ARG, "vie_compress_cp: negative CP rank or iterations");
+    return compress_common(n, green, opts, cp_rank, cp_iters == 0 ? 1000 : cp_iters, out, info, cp_rel_err);
+}
+
+static vie_status compress_common(const int n[3], const double* green, const vie_compress_opts* opts, int cp_rank,
+                                  int cp_iters, vie_op** out, vie_compress_info* info, double* cp_err)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!n || !green || !out) return fail(VIE_E_ARG, "vie_compress: null argument");
@@ -267,6 +307,36 @@ vie_status vie_compress(const int n[3], const double* green, const vie_compress_
                         A[((long)k * n[1] + j) * n[0] + i] = 0.0;
         int rc = hosvd_component(A.data(), n, tol, rule, max_rank, tc[c]);
         if (rc != 0) return fail(VIE_E_UNSUPPORTED, "vie_compress: max_rank too small for tol");
+    }
+    if (cp_rank >= 0) {
+        // Alg. 2: CP of each core, Tucker+CP factors W^a = U^a V^a, and a
+        // superdiagonal core so that eq. 17 is the Tucker form with it
+        for (int c = 0; c < 6; ++c) {
+            TuckerComponent& t = tc[c];
+            const int rmin = std::min(t.r[0], std::min(t.r[1], t.r[2]));
+            const int R = cp_rank == 0 ? rmin : cp_rank;
+            if (R > rmin) return fail(VIE_E_ARG, "vie_compress_cp: CP rank above the smallest Tucker rank");
+            std::vector<cd> Vf[3];
+            const double e = cp_als(t.G, t.r, R, cp_iters, Vf);
+            if (cp_err) cp_err[c] = e;
+            for (int a = 0; a < 3; ++a) {
+                // row 0 of an odd axis stays exactly zero, as the odd
+                // embedding needs (U's row there is zero up to rounding, and
+                // the large cancelling terms of a near-degenerate CP fit
+                // would amplify that rounding)
+                std::vector<cd> W((size_t)n[a] * R, 0);
+                for (int i = odd[c][a] ? 1 : 0; i < n[a]; ++i)
+                    for (int l = 0; l < R; ++l) {
+                        cd acc = 0;
+                        for (int k = 0; k < t.r[a]; ++k) acc += t.U[a][(size_t)i * t.r[a] + k] * Vf[a][(size_t)k * R + l];
+                        W[(size_t)i * R + l] = acc;
+                    }
+                t.U[a] = W;
+                t.r[a] = R;
+            }
+            t.G.assign((size_t)R * R * R, 0);
+            for (int l = 0; l < R; ++l) t.G[((size_t)l * R + l) * R + l] = 1.0;
+        }
     }
     return build_operator(n, plans, tc, out, info, t0);
 }
@@ -481,6 +551,30 @@ vie_status vie_debug_hosvd(const int n[3], const double* tensor, double tol, int
                     recon[2 * t + 1] = acc.imag();
                 }
     }
+    return VIE_OK;
+}
+
+vie_status vie_debug_cp(const int r[3], const double* core, int R, int iters, double* V, double* rel_err)
+{
+    if (!r || !core || !V) return fail(VIE_E_ARG, "vie_debug_cp: null argument");
+    for (int a = 0; a < 3; ++a)
+        if (r[a] < 1 || r[a] > 64) return fail(VIE_E_ARG, "vie_debug_cp: bad core size");
+    if (R < 1 || R > std::min(r[0], std::min(r[1], r[2])) || iters < 0)
+        return fail(VIE_E_ARG, "vie_debug_cp: bad CP rank or iteration count");
+    using cd = std::complex<double>;
+    const size_t nG = (size_t)r[0] * r[1] * r[2];
+    std::vector<cd> G(nG);
+    for (size_t t = 0; t < nG; ++t) G[t] = cd(core[2 * t], core[2 * t + 1]);
+    std::vector<cd> Vf[3];
+    const double e = cp_als(G, r, R, iters, Vf);
+    size_t off = 0;
+    for (int a = 0; a < 3; ++a)
+        for (const cd& x : Vf[a]) {
+            V[2 * off] = x.real();
+            V[2 * off + 1] = x.imag();
+            ++off;
+        }
+    if (rel_err) *rel_err = e;
     return VIE_OK;
 }
 

@@ -29,6 +29,10 @@ struct OpView {
     // r3 and beyond row n3; rh = 16 ceil(r3 / 16) (0 when r3 > 32: not available)
     int rh[6];
     int fac3m_off[6];
+    // 1: every core is superdiagonal (r1 = r2 = r3 = R, a Tucker+CP form,
+    // eq. 17): the z pass forms V_c(k1, k2, l) = G_c[l,l,l] U1_c(k1, l)
+    // U2_c(k2, l) directly instead of contracting the core
+    int cp;
 };
 
 template <typename T>

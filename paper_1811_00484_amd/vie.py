@@ -47,7 +47,7 @@ class CompressInfo(ctypes.Structure):
     _fields_ = [("ranks", (ctypes.c_int * 3) * 6), ("tail_bound", ctypes.c_double * 6),
                 ("fro_norm", ctypes.c_double * 6), ("tucker_bytes_c64", ctypes.c_size_t),
                 ("dense_bytes_c64", ctypes.c_size_t), ("device_bytes", ctypes.c_size_t),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("cp", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -78,6 +78,8 @@ _P = ctypes.c_void_p
 _SIGS = {
     "vie_compress": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.POINTER(CompressOpts),
                                     ctypes.POINTER(_P), ctypes.POINTER(CompressInfo)]),
+    "vie_compress_cp": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.POINTER(CompressOpts), ctypes.c_int,
+                                       ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(CompressInfo), _P]),
     "vie_op_from_tucker": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _P, _P,
                                           ctypes.POINTER(_P), ctypes.POINTER(CompressInfo)]),
     "vie_op_destroy": (ctypes.c_int, [_P]),
@@ -106,6 +108,8 @@ _SIGS = {
     "vie_debug_nhat": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int, _P]),
     "vie_debug_hosvd": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.c_double, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_int), _P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "vie_debug_cp": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.c_int, ctypes.c_int, _P,
+                                    ctypes.POINTER(ctypes.c_double)]),
     "vie_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "vie_profile_collect": (ctypes.c_int, [_P, _P]),
     "vie_set_kernel_path": (ctypes.c_int, [ctypes.c_int]),
@@ -174,6 +178,7 @@ class Operator:
         self.dense_bytes_c64 = int(info.dense_bytes_c64)
         self.device_bytes = int(info.device_bytes)
         self.compress_seconds = float(info.seconds)
+        self.cp = bool(info.cp)
         self._ws = {}
 
     @property
@@ -217,6 +222,28 @@ def compress(green, tol=1e-6, trunc_rule=0, max_rank=0):
     _check(lib.vie_compress(n, g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts), ctypes.byref(h),
                             ctypes.byref(info)), "vie_compress")
     return Operator(h, (g.shape[3], g.shape[2], g.shape[1]), info)
+
+
+def compress_cp(green, tol=1e-6, cp_rank=0, cp_iters=0, trunc_rule=0, max_rank=0):
+    """Tucker+CP compression (vie_compress_cp): HOSVD at ``tol``, then a CP of
+    each core with ``cp_rank`` terms (0 = its smallest Tucker rank) by
+    ``cp_iters`` ALS sweeps (0 = 1000).  The operator's ``cp_rel_err`` holds
+    the six cores' relative CP fit errors."""
+    lib = load()
+    g = np.ascontiguousarray(green, dtype=np.complex128)
+    if g.ndim != 4 or g.shape[0] != 6:
+        raise ValueError("green must have shape (6, n3, n2, n1)")
+    n = (ctypes.c_int * 3)(g.shape[3], g.shape[2], g.shape[1])
+    opts = CompressOpts(float(tol), int(trunc_rule), int(max_rank))
+    info = CompressInfo()
+    err = np.zeros(6)
+    h = ctypes.c_void_p()
+    _check(lib.vie_compress_cp(n, g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts), int(cp_rank),
+                               int(cp_iters), ctypes.byref(h), ctypes.byref(info), err.ctypes.data_as(ctypes.c_void_p)),
+           "vie_compress_cp")
+    op = Operator(h, (g.shape[3], g.shape[2], g.shape[1]), info)
+    op.cp_rel_err = err
+    return op
 
 
 def from_tucker(n, cores, factors):
@@ -498,6 +525,20 @@ def debug_hosvd(tensor, tol, rule=0, want_recon=True):
                                rec.ctypes.data_as(ctypes.c_void_p) if want_recon else None,
                                ctypes.byref(tail)), "vie_debug_hosvd")
     return tuple(ranks), [sv[:n1], sv[n1:n1 + n2], sv[n1 + n2:]], rec, tail.value
+
+
+def debug_cp(core, R, iters):
+    """Host-only CP-ALS of one core (numpy complex128 (r1, r2, r3)) with R
+    terms and ``iters`` sweeps: returns ([V1, V2, V3], relative error)."""
+    lib = load()
+    G = np.ascontiguousarray(core, dtype=np.complex128)
+    r = (ctypes.c_int * 3)(*G.shape)
+    V = np.empty(sum(G.shape) * R, dtype=np.complex128)
+    err = ctypes.c_double()
+    _check(lib.vie_debug_cp(r, G.ctypes.data_as(ctypes.c_void_p), int(R), int(iters),
+                            V.ctypes.data_as(ctypes.c_void_p), ctypes.byref(err)), "vie_debug_cp")
+    r1, r2, _ = G.shape
+    return [V[:r1 * R].reshape(r1, R), V[r1 * R:(r1 + r2) * R].reshape(r2, R), V[(r1 + r2) * R:].reshape(-1, R)], err.value
 
 
 def profile_enable(on=True):

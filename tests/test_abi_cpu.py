@@ -102,3 +102,44 @@ def test_literal_truncation_rule():
     ranks, sv, _, _ = vie.debug_hosvd(G[1], 1e-5, rule=1, want_recon=False)
     for a in range(3):
         assert ranks[a] == max(1, int(np.sum(sv[a] >= 1e-5 / np.sqrt(3) * sv[a][0])))
+
+
+@pytest.mark.parametrize("c", [0, 4])
+@pytest.mark.parametrize("iters", [1, 20, 200])
+def test_host_cp_als_matches_oracle(c, iters):
+    # the CP step of vie_compress_cp on a real Green's-tensor Tucker core: the
+    # sweeps are equivariant under the column phases of the SVD start, so the
+    # CP tensors of library and oracle agree after every full sweep up to
+    # rounding.  That rounding is amplified: the ALS Gram matrices of these
+    # near-degenerate fits have condition numbers near 1e13, and the library's
+    # pivoted elimination and the oracle's pseudo-inverse round differently,
+    # so the two drift apart by up to ~3e-7 relative over 200 sweeps
+    from oracle import cp
+    vie = _lib()
+    n = (14, 12, 10)
+    G = vi.green_tensor(n, 0.004, vi.wavenumber(298e6))
+    Gc, _, _ = tucker.hosvd(tucker.from_storage(G[c]), 1e-6)
+    R = min(Gc.shape)
+    Vl, el = vie.debug_cp(Gc, R, iters)
+    Vo, eo = cp.cp_als(Gc, R, iters)
+    tight = iters == 1
+    assert abs(el - eo[-1]) <= (1e-9 if tight else 1e-4) * eo[-1]
+    rl, ro = cp.cp_reconstruct(Vl), cp.cp_reconstruct(Vo)
+    assert np.linalg.norm(rl - ro) <= (1e-10 if tight else 2e-6) * np.linalg.norm(ro)
+
+
+def test_host_cp_argument_errors():
+    import ctypes
+    vie = _lib()
+    lib = vie.load()
+    G = np.ones((3, 3, 2), dtype=np.complex128)
+    r = (ctypes.c_int * 3)(3, 3, 2)
+    V = np.empty(64, dtype=np.complex128)
+    p = G.ctypes.data_as(ctypes.c_void_p)
+    assert lib.vie_debug_cp(r, p, 3, 5, V.ctypes.data_as(ctypes.c_void_p), None) == vie.VIE_E_ARG   # R > min r
+    assert lib.vie_debug_cp(r, p, 0, 5, V.ctypes.data_as(ctypes.c_void_p), None) == vie.VIE_E_ARG
+    assert lib.vie_debug_cp(r, None, 2, 5, V.ctypes.data_as(ctypes.c_void_p), None) == vie.VIE_E_ARG
+    n = (ctypes.c_int * 3)(4, 4, 4)
+    g = np.zeros(12 * 64)
+    assert lib.vie_compress_cp(n, g.ctypes.data_as(ctypes.c_void_p), None, -1, 0, ctypes.byref(ctypes.c_void_p()),
+                               None, None) == vie.VIE_E_ARG

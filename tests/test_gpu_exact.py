@@ -107,3 +107,39 @@ def test_from_tucker_rejects_nonzero_odd_row():
     factors[3][0][0, 0] = 1.0   # xy is odd along x
     with pytest.raises(RuntimeError):
         vie.from_tucker(n, cores, factors)
+
+
+@pytest.mark.parametrize("n", [(2, 2, 2), (1, 2, 2), (2, 1, 2), (2, 2, 1)])
+@pytest.mark.parametrize("dt", [torch.complex64, torch.complex128])
+def test_integer_tucker_cp_matvec_is_bit_exact(n, dt):
+    # superdiagonal integer cores (a Tucker+CP form, eq. 17) take the z pass's
+    # CP branch: V = G[l,l,l] U1(k1, l) U2(k2, l) with no core contraction
+    rng = np.random.default_rng(21 + sum(n))
+    cores, factors = [], []
+    for c in range(6):
+        signs = circulant.axis_signs(c)
+        R = 2 if min(n) > 1 else 1
+        G = np.zeros((R, R, R), complex)
+        for l in range(R):
+            G[l, l, l] = _int_complex(rng, ())
+        Us = []
+        for a in range(3):
+            U = _int_complex(rng, (n[a], R))
+            if signs[a] < 0:
+                U[0, :] = 0
+            Us.append(U)
+        cores.append(G)
+        factors.append(Us)
+    ref = _oracle(n, cores, factors)
+    op = vie.from_tucker(n, cores, factors)
+    assert op.cp
+    rng = np.random.default_rng(6)
+    shape = (3, n[2], n[1], n[0])
+    u = _int_complex(rng, shape)
+    epsc = rng.integers(1, 4, shape[1:]) - 1j * rng.integers(0, 3, shape[1:])
+    for mode in ("A", "AH", "N", "NH"):
+        kind = "N" if mode.startswith("N") else "A"
+        y = vie.matvec(op, to_dev(u, dt), to_dev(epsc, dt), kind=kind,
+                       adjoint=mode.endswith("H")).cpu().numpy().astype(np.complex128)
+        yo = opm.matvec(ref, epsc, u, mode)
+        assert int(np.count_nonzero(y != yo)) == 0, (n, mode)
