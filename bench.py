@@ -8,7 +8,7 @@ the full operator A = M_eps - M_chi N (all five passes).  Prints one JSON
 line on stdout; progress goes to stderr.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--grid 256]
-                    [--no-dense] [--no-solve] [--no-cpu-baseline]
+                    [--no-dense] [--no-solve] [--no-cpu-baseline] [--no-cp]
 """
 import argparse
 import glob
@@ -42,20 +42,25 @@ PASS_ELEMS_V = [3 + 6, 6 + 12, 12 + 12, 12 + 6, 6 + 3 + 1 + 3]
 COPY_CAL_BYTES = 1 << 30   # plain copy used to calibrate the HBM byte counters
 
 
-def z_pass_flops(n, ranks):
+def z_pass_flops(n, ranks, cp=False):
     """Algorithmic FP32 flops of one Z-pass launch (one rhs): forward and
     inverse length-2n3 FFTs of 3 components over the (2n1)(2n2) pencils at
     5 L log2 L each, the 3x3 complex product (9 complex MACs = 72 flops) at
     every Fourier point, and the Tucker reconstruction of the half spectrum
     (N^ tables: (n1+1)(n2+1)(n3+1) r3 complex MACs per component, plus the
-    per-(k1,k2) and per-k2 core contractions)."""
+    per-(k1,k2) and per-k2 core contractions; a Tucker+CP operator, ``cp``,
+    has R-term products there instead of contractions)."""
     n1, n2, n3 = n
     L1, L2, L3 = 2 * n1, 2 * n2, 2 * n3
     fft = 2 * 3 * L1 * L2 * 5 * L3 * np.log2(L3)
     prod = 72.0 * L1 * L2 * L3
     rec = 0.0
     for r1, r2, r3 in ranks:
-        rec += 8.0 * ((n1 + 1) * (n2 + 1) * (n3 + 1) * r3 + (n1 + 1) * (n2 + 1) * r1 * r3 + (n2 + 1) * r1 * r2 * r3)
+        rec += 8.0 * (n1 + 1) * (n2 + 1) * (n3 + 1) * r3
+        if cp:
+            rec += 6.0 * ((n1 + 1) * (n2 + 1) * r1 + (n2 + 1) * r1)
+        else:
+            rec += 8.0 * ((n1 + 1) * (n2 + 1) * r1 * r3 + (n2 + 1) * r1 * r2 * r3)
     return float(fft + prod + rec)
 
 
@@ -135,6 +140,7 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cp", action="store_true", help="skip the Tucker+CP leg")
     ap.add_argument("--batch-workload", action="store_true",
                     help="also run the batching workload: 6 head phantoms of seeded sizes at 2 mm, 16 dipole "
                          "fields each, multi-instance matvec and lockstep GMRES")
@@ -278,6 +284,14 @@ def main():
     if not args.no_solve:
         extra["solve"] = solves(op, b, epsc, dev, vie, torch)
 
+    y_cp = None
+    if not args.no_cp:
+        try:
+            extra["tucker_cp"], y_cp = tucker_cp_leg(G, op, x, e, y32, b, epsc, n, args, vie, torch, dev)
+        except Exception as exc:   # the headline line is printed regardless
+            log("tucker_cp leg failed: %r" % (exc,))
+            extra["tucker_cp"] = {"error": repr(exc)}
+
     result = {
         "metric": "VIE matvecs/s (256^3 head phantom, Tucker-compressed operator, 1 rhs)",
         "value": value,
@@ -335,7 +349,77 @@ def main():
         for key, yy in (("matvec_rel_err_vs_oracle_dense", y32), ("bf16_matvec_rel_err_vs_oracle_dense", y16)):
             yg = yy.cpu().numpy().astype(np.complex128)
             result["config"][key] = float(np.linalg.norm(yg - y_ref) / np.linalg.norm(y_ref))
+        if y_cp is not None:
+            yg = y_cp.cpu().numpy().astype(np.complex128)
+            result["tucker_cp"]["matvec_rel_err_vs_oracle_dense"] = float(np.linalg.norm(yg - y_ref) /
+                                                                          np.linalg.norm(y_ref))
     print(json.dumps(result), flush=True)
+
+
+def tucker_cp_leg(G, op_t, x, e, y_t, b, epsc, n, args, vie, torch, dev):
+    """The same workload with the Tucker+CP operator (Alg. 2: HOSVD at the
+    same tolerance, then CP of each core with R = min r_i terms, 1000 ALS
+    sweeps): compression time and fits, operator bytes, matvec time on the
+    z pass's CP branch, its distance from the HOSVD operator's matvec, and a
+    refined solve."""
+    log("vie_compress_cp: HOSVD at tol %g, then CP-ALS (1000 sweeps) of each core ..." % args.tol)
+    t0 = time.time()
+    op = vie.compress_cp(G, tol=args.tol)
+    t_c = time.time() - t0
+    log("vie_compress_cp: %.1f s, CP ranks %s, fit errors %s"
+        % (t_c, [r[0] for r in op.ranks], ["%.2e" % v for v in op.cp_rel_err]))
+    y = torch.empty_like(x)
+    vie.autotune(op, torch.complex64, 1)
+    st = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        vie.matvec(op, x, e, out=y)
+    torch.cuda.synchronize()
+    vie.profile_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(st)
+    for _ in range(args.steps):
+        vie.matvec(op, x, e, out=y)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    vie.profile_enable(False)
+    pass_ms, pass_cnt = vie.profile_collect()
+    avg = [pass_ms[p] / max(1, pass_cnt[p]) for p in range(5)]
+    ms = ev0.elapsed_time(ev1) / args.steps
+    zfl = z_pass_flops(n, op.ranks, cp=True)
+    out = {"compress_seconds": t_c, "cp_ranks": [r[0] for r in op.ranks],
+           "hosvd_ranks": op_t.ranks, "cp_rel_err": list(op.cp_rel_err),
+           "ms_per_matvec": ms, "matvecs_per_s": 1000.0 / ms, "pass_avg_ms": dict(zip(PASS_NAMES, avg)),
+           "z_fused_TFLOPs": zfl / (avg[2] * 1e-3) / 1e12, "z_fused_alg_flops": zfl,
+           "operator_bytes_c64": op.tucker_bytes_c64, "compression_factor": op.dense_bytes_c64 / op.tucker_bytes_c64,
+           "rel_diff_vs_hosvd_matvec": float(torch.linalg.vector_norm(y - y_t) / torch.linalg.vector_norm(y_t))}
+    # the same comparison on a random (non-smooth) field: the CP fit error
+    # shows at its own size there, while the smooth excitation above sits
+    # where the CP error of the Fourier-domain tensor is concentrated
+    import vie_inputs as vi
+    ur = torch.from_numpy(vi.random_field(n, 5).astype(np.complex64)).to(dev)
+    nr_c = vie.matvec(op, ur, kind="N")
+    nr_t = vie.matvec(op_t, ur, kind="N")
+    out["rel_diff_vs_hosvd_N_random_field"] = float(torch.linalg.vector_norm(nr_c - nr_t) /
+                                                    torch.linalg.vector_norm(nr_t))
+    del ur, nr_c, nr_t
+    log("tucker+cp matvec: %.3f ms; passes %s ms; rel diff to HOSVD %.3e"
+        % (ms, ["%.3f" % a for a in avg], out["rel_diff_vs_hosvd_matvec"]))
+    if not args.no_solve:
+        bb = torch.from_numpy(b).to(dev)
+        ee = torch.from_numpy(epsc).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        xs, info, st_ = vie.solve(op, bb, ee, tol=1e-6, restart=50, max_outer=20, refine=True, inner_tol=1e-5)
+        torch.cuda.synchronize()
+        t = time.time() - t0
+        out["refined_solve"] = {"seconds": t, "converged": bool(info[0]["converged"]),
+                                "rel_residual_fp64": info[0]["rel_residual"], "matvecs_inner": info[0]["matvecs"],
+                                "matvecs_fp64": info[0]["matvecs_fp64"]}
+        log("tucker+cp refined solve: %.2f s, %s" % (t, info[0]))
+        del xs
+    op.close()
+    return out, y
 
 
 def solves(op, b, epsc, dev, vie, torch):

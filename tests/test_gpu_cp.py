@@ -38,8 +38,8 @@ from paper_1811_00484_amd import vie
 pytestmark = pytest.mark.gpu
 
 ITERS = 200
-# generic kernels; register-FFT z pass at L3 = 128; L3 = 256 with ragged x/y
-SIZES = [(16, 16, 16), (40, 24, 64), (20, 18, 128)]
+# generic kernels; register-FFT z pass at L3 = 128, 256 and 512 with ragged x/y
+SIZES = [(16, 16, 16), (40, 24, 64), (20, 18, 128), (12, 10, 256)]
 
 _cache = {}
 
