@@ -31,6 +31,9 @@
  *
  * Output layout: out[((c*n3 + k)*n2 + j)*n1 + i] (complex128 interleaved),
  * components c = xx, yy, zz, xy, xz, yz, entry = Nt_c(D = (i, j, k)).
+ *
+ * The same machinery gives the entries of the magnetic operator K of eq. 5
+ * (vie_green_k_fill, below).
  */
 #include <complex.h>
 #include <math.h>
@@ -150,9 +153,33 @@ static inline void vol_weights(const double x[3], const int D[3], double w[4])
     w[3] = d[1] * d[2] * l[0];
 }
 
-/* volume integral of g^ * {tau, lam'lam'lam (3 pairs)} over a unit cell
- * [lo, lo+1]^3 that does not contain the origin in its closure */
-static void vol_cell_regular(const double lo[3], const int D[3], double kappa, int q, cplx acc[4])
+/* weights of the K entries at x: -lam'(x_s - D_s) prod_{i != s} lam(x_i - D_i)
+ * for s = x, y, z in w[0..2] (w[3] = 0), so that the volume integral of
+ * g^ * w[s] is F_s(D) = -int g^ d_s tau_D.  x must lie strictly inside a cell. */
+static inline void vol_weights_k(const double x[3], const int D[3], double w[4])
+{
+    double l[3], d[3];
+    for (int a = 0; a < 3; ++a) {
+        double t = x[a] - D[a];
+        l[a] = lam(t);
+        d[a] = (fabs(t) < 1.0) ? (t > 0 ? -1.0 : 1.0) : 0.0;
+    }
+    w[0] = -d[0] * l[1] * l[2];
+    w[1] = -d[1] * l[0] * l[2];
+    w[2] = -d[2] * l[0] * l[1];
+    w[3] = 0.0;
+}
+
+static inline void cell_weights(int kind, const double x[3], const int D[3], double w[4])
+{
+    if (kind == 0) vol_weights(x, D, w);
+    else vol_weights_k(x, D, w);
+}
+
+/* volume integral of g^ * {tau, lam'lam'lam (3 pairs)} (kind 0) or of the
+ * K weights (kind 1) over a unit cell [lo, lo+1]^3 that does not contain the
+ * origin in its closure */
+static void vol_cell_regular(int kind, const double lo[3], const int D[3], double kappa, int q, cplx acc[4])
 {
     const double *gx = gl_x[q], *gw = gl_w[q];
     for (int ia = 0; ia < q; ++ia)
@@ -163,7 +190,7 @@ static void vol_cell_regular(const double lo[3], const int D[3], double kappa, i
                 double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
                 cplx g = ghat(r, kappa) * w;
                 double wt[4];
-                vol_weights(x, D, wt);
+                cell_weights(kind, x, D, wt);
                 for (int m = 0; m < 4; ++m) acc[m] += g * wt[m];
             }
 }
@@ -172,7 +199,7 @@ static void vol_cell_regular(const double lo[3], const int D[3], double kappa, i
  * {sigma_a * y_a, y in [0,1]^3}; Duffy split into three pyramids with apex
  * at the origin, each mapped to [0,1]^3 with Jacobian s^2, which cancels
  * the 1/r singularity of g^. */
-static void vol_cell_corner(const double sigma[3], const int D[3], double kappa, int q, cplx acc[4])
+static void vol_cell_corner(int kind, const double sigma[3], const int D[3], double kappa, int q, cplx acc[4])
 {
     const double *gx = gl_x[q], *gw = gl_w[q];
     for (int face = 0; face < 3; ++face) {
@@ -190,7 +217,7 @@ static void vol_cell_corner(const double sigma[3], const int D[3], double kappa,
                     double w = gw[is] * gw[ib] * gw[ic] * s * s;
                     cplx g = ghat(r, kappa) * w;
                     double wt[4];
-                    vol_weights(x, D, wt);
+                    cell_weights(kind, x, D, wt);
                     for (int m = 0; m < 4; ++m) acc[m] += g * wt[m];
                 }
         }
@@ -229,10 +256,10 @@ static cplx plane_cell(int p, double c, const double lo2[2], const double sig2[2
     return acc;
 }
 
-static void near_entry(const int D[3], double kappa, int q, cplx out[6])
+/* volume integrals over the 8 unit cells of the support of tau_D, with a
+ * Duffy transform on a cell that has the origin at a corner */
+static void near_volume(int kind, const int D[3], double kappa, int q, cplx vol[4])
 {
-    /* volume part: J0 and the three off-diagonal Jpq */
-    cplx vol[4] = {0, 0, 0, 0};
     for (int cell = 0; cell < 8; ++cell) {
         double lo[3];
         int corner = 1;
@@ -243,9 +270,16 @@ static void near_entry(const int D[3], double kappa, int q, cplx out[6])
             else if (lo[a] == -1.0) sigma[a] = -1.0;
             else corner = 0;
         }
-        if (corner) vol_cell_corner(sigma, D, kappa, q, vol);
-        else vol_cell_regular(lo, D, kappa, q, vol);
+        if (corner) vol_cell_corner(kind, sigma, D, kappa, q, vol);
+        else vol_cell_regular(kind, lo, D, kappa, q, vol);
     }
+}
+
+static void near_entry(const int D[3], double kappa, int q, cplx out[6])
+{
+    /* volume part: J0 and the three off-diagonal Jpq */
+    cplx vol[4] = {0, 0, 0, 0};
+    near_volume(0, D, kappa, q, vol);
     /* plane part: Jpp = sum_s c_s * plane integral at x_p = D_p + s */
     cplx jpp[3];
     for (int p = 0; p < 3; ++p) {
@@ -309,6 +343,85 @@ int vie_green_fill(int n1, int n2, int n3, double kappa, int near_q, int boost,
         if (d <= 1) near_entry(D, kappa, near_q, e);
         else far_entry(D, kappa, far_order(d, boost), e);
         for (int c = 0; c < 6; ++c) {
+            out[2 * (c * V + lin)] = creal(e[c]);
+            out[2 * (c * V + lin) + 1] = cimag(e[c]);
+        }
+    }
+    return 0;
+}
+
+/* ---------------- the K operator (curl of the single-layer potential) ----------------
+ * Entries Kt_pq(D) = <P_D e_p, K P_0 e_q> / vol: observation voxel D, source
+ * voxel 0, so that (K u)_p(m) = sum_m' Kt_pq(m - m') u_q(m') is a
+ * convolution.  With (curl (g e_q))_p = eps_psq d_s g,
+ *   Kt_pq(D) = eps_psq F_s(D),  F_s(D) = int d_s g^(x) tau_D(x) dx
+ *                                      = -int g^(x) d_s tau_D(x) dx,
+ * the second form (integrable 1/r kernel, piecewise constant lam') on the
+ * near shells, the first (smooth kernel d_s g^ = -x_s (1 + i kappa r) g^ / r^2)
+ * on the far ones.  Stored components xy, xz, yz:
+ *   Kt_xy = -F_z, Kt_xz = F_y, Kt_yz = -F_x   (Kt_qp = -Kt_pq, diagonal 0).
+ * Dimensionless: the physical entries are h Kt (the curl brings 1/h, the
+ * kernel and the two volume integrals h^5, the row normalisation 1/h^3). */
+static void k_far_entry(const int D[3], double kappa, int q, cplx F[3])
+{
+    cplx acc[3] = {0, 0, 0};
+    const double *gx = gl_x[q], *gw = gl_w[q];
+    for (int cell = 0; cell < 8; ++cell) {
+        double lo[3];
+        for (int a = 0; a < 3; ++a) lo[a] = ((cell >> a) & 1) ? 0.0 : -1.0;
+        for (int ia = 0; ia < q; ++ia) {
+            double t0 = lo[0] + gx[ia];
+            double w0 = gw[ia] * (1.0 - fabs(t0));
+            double x0 = D[0] + t0;
+            for (int ib = 0; ib < q; ++ib) {
+                double t1 = lo[1] + gx[ib];
+                double w1 = w0 * gw[ib] * (1.0 - fabs(t1));
+                double x1 = D[1] + t1;
+                for (int ic = 0; ic < q; ++ic) {
+                    double t2 = lo[2] + gx[ic];
+                    double w = w1 * gw[ic] * (1.0 - fabs(t2));
+                    double x2 = D[2] + t2;
+                    double r2 = x0 * x0 + x1 * x1 + x2 * x2;
+                    double r = sqrt(r2);
+                    cplx dg = -ghat(r, kappa) * (1.0 + I * kappa * r) / r2;
+                    acc[0] += w * dg * x0;
+                    acc[1] += w * dg * x1;
+                    acc[2] += w * dg * x2;
+                }
+            }
+        }
+    }
+    for (int s = 0; s < 3; ++s) F[s] = acc[s];
+}
+
+/* Fill the K defining tensor: out[((c*n3 + k)*n2 + j)*n1 + i], c = xy, xz, yz,
+ * complex128 interleaved; offsets [lo_lin, hi_lin) as in vie_green_fill. */
+int vie_green_k_fill(int n1, int n2, int n3, double kappa, int near_q, int boost,
+                     double *out, long lo_lin, long hi_lin)
+{
+    gl_init();
+    if (near_q < 2 || near_q > QMAX) return -1;
+    long V = (long)n1 * n2 * n3;
+    if (hi_lin > V) hi_lin = V;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long lin = lo_lin; lin < hi_lin; ++lin) {
+        int D[3] = {(int)(lin % n1), (int)((lin / n1) % n2), (int)(lin / ((long)n1 * n2))};
+        int d = D[0];
+        if (D[1] > d) d = D[1];
+        if (D[2] > d) d = D[2];
+        cplx F[3];
+        if (d <= 1) {
+            cplx vol[4] = {0, 0, 0, 0};
+            near_volume(1, D, kappa, near_q, vol);
+            for (int s = 0; s < 3; ++s) F[s] = vol[s];
+        } else {
+            k_far_entry(D, kappa, far_order(d, boost), F);
+        }
+        /* F_s is odd in D_s: exactly zero on the plane D_s = 0 */
+        for (int s = 0; s < 3; ++s)
+            if (D[s] == 0) F[s] = 0;
+        cplx e[3] = {-F[2], F[1], -F[0]};
+        for (int c = 0; c < 3; ++c) {
             out[2 * (c * V + lin)] = creal(e[c]);
             out[2 * (c * V + lin) + 1] = cimag(e[c]);
         }

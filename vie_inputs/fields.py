@@ -9,7 +9,7 @@ import math
 import numpy as np
 
 from . import _native
-from .constants import EPS0, omega, wavenumber
+from .constants import C0, EPS0, MU0, omega, wavenumber
 from .grid import voxel_centres
 
 
@@ -20,6 +20,17 @@ def plane_wave(n, h, freq_hz, pol=0, amplitude=1.0):
     e = np.zeros((3,) + z.shape, dtype=np.complex128)
     e[pol] = amplitude * np.exp(-1j * wavenumber(freq_hz) * z)
     return e
+
+
+def plane_wave_h(n, h, freq_hz, pol=0, amplitude=1.0):
+    """Magnetic field of ``plane_wave``: H = z-hat x E / eta0 with
+    eta0 = mu0 c0 (exp(+i omega t), travelling along +z).  Shape (3, n3, n2, n1)."""
+    e = plane_wave(n, h, freq_hz, pol, amplitude)
+    eta0 = MU0 * C0
+    hf = np.zeros_like(e)
+    hf[0] = -e[1] / eta0
+    hf[1] = e[0] / eta0
+    return hf
 
 
 def _dyadic(points, k0):
