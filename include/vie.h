@@ -128,6 +128,26 @@ vie_status vie_compress_cp(const int n[3], const double* green, const vie_compre
                            int cp_iters, vie_op** out, vie_compress_info* info, double cp_rel_err[6]);
 
 /*
+ * vie_compress_k -- the magnetic operator K of eq. 5 (curl of the
+ * single-layer potential) as a compressed operator: HOSVD (Alg. 1) of its
+ * three defining tensors and the embedded-factor DFT of Sec. V-A, as
+ * vie_compress.  K's component pair is antisymmetric (K_qp = -K_pq, zero
+ * diagonal) and each component is odd along one axis (xy along z, xz along
+ * y, yz along x); the operator applies
+ *   y_p(m) = sum_q sum_m' K_pq(m - m') x_q(m')
+ * through vie_matvec with kind VIE_OP_N only (no contrast epilogue, no
+ * adjoint: other calls return VIE_E_UNSUPPORTED; it is not accepted by the
+ * solvers, multi-instance calls or vie_autotune).  Its z pass runs on the
+ * mixed-radix kernels.
+ *   green_k HOST complex128 [3][n3][n2][n1]: K_c(offset (i, j, k)) for
+ *           c = xy, xz, yz, observation voxel at the offset, source at 0.
+ *   n, opts, out as vie_compress; info (may be NULL): ranks[0..2] are the
+ *   zero diagonal slots (1, 1, 1), ranks[3..5] the Tucker ranks of xy, xz, yz.
+ */
+vie_status vie_compress_k(const int n[3], const double* green_k, const vie_compress_opts* opts, vie_op** out,
+                          vie_compress_info* info);
+
+/*
  * vie_op_from_tucker -- build an operator from a Tucker form of the six
  * defining tensors computed elsewhere (eq. 13-14: another truncation, a cross
  * approximation, a stored decomposition).  The factor columns are embedded
@@ -305,6 +325,16 @@ vie_status vie_problem_setup(const vie_op* op, int dtype, const void* eps_r, con
  */
 vie_status vie_total_field(const vie_op* op, int dtype, const void* e_inc, const void* u, const void* Nu,
                            double omega_eps0, void* E, void* stream);
+/*
+ * vie_magnetic_field -- H = h_inc + h KJ and |b1+| = mu0 |H_x + i H_y|
+ *   (eq. 18) for the polarisation current J of the electric equation, where
+ *   KJ = vie_matvec(op_k, VIE_OP_N, J) with op_k from vie_compress_k and h
+ *   the voxel edge (the physical K is h times the dimensionless tensor).
+ *   h_inc, KJ, H DEVICE complex [3][n3][n2][n1] (dtype); b1 DEVICE real
+ *   [n3][n2][n1] (float for VIE_C64, double for VIE_C128).
+ */
+vie_status vie_magnetic_field(const vie_op* op_k, int dtype, const void* h_inc, const void* KJ, double h, double mu0,
+                              void* H, void* b1, void* stream);
 /*
  * vie_adjoint_source -- t = N^H g - g, the right-hand side A^H z = (N - I)^H g
  *   of the adjoint solve for an objective gradient g = dL/dRe(E) + i dL/dIm(E).

@@ -44,6 +44,9 @@ hipError_t kr_total_field(const c2<T>* e_inc, const c2<T>* u, const c2<T>* Nu, c
                           hipStream_t st);
 // t = NHg - g
 template <typename T>
+hipError_t kr_magnetic_field(const c2<T>* h_inc, const c2<T>* KJ, double h, double mu0, c2<T>* H, T* b1, long nv,
+                             hipStream_t st);
+template <typename T>
 hipError_t kr_adjoint_source(const c2<T>* g, const c2<T>* NHg, c2<T>* t, long n, hipStream_t st);
 
 }  // namespace vie

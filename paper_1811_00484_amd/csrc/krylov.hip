@@ -211,6 +211,27 @@ __global__ void __launch_bounds__(KB) k_total_field(const c2<T>* __restrict__ e_
     E[i] = mk<T>(e_inc[i].x + (T)((double)d.y / oe0), e_inc[i].y - (T)((double)d.x / oe0));
 }
 
+// H = h_inc + h KJ (the physical K is h times the dimensionless tensor) and
+// |b1+| = mu0 |H_x + i H_y| (eq. 18); nv voxels, components [3][nv]
+template <typename T>
+__global__ void __launch_bounds__(KB) k_magnetic_field(const c2<T>* __restrict__ h_inc, const c2<T>* __restrict__ KJ,
+                                                       double h, double mu0, c2<T>* __restrict__ H, T* __restrict__ b1,
+                                                       long nv)
+{
+    long i = (long)blockIdx.x * KB + threadIdx.x;
+    if (i >= nv) return;
+    c2<T> hq[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const long o = q * nv + i;
+        hq[q] = mk<T>(h_inc[o].x + (T)h * KJ[o].x, h_inc[o].y + (T)h * KJ[o].y);
+        H[o] = hq[q];
+    }
+    // H_x + i H_y
+    const double re = (double)hq[0].x - (double)hq[1].y, im = (double)hq[0].y + (double)hq[1].x;
+    b1[i] = (T)(mu0 * sqrt(re * re + im * im));
+}
+
 // t = N^H g - g
 template <typename T>
 __global__ void __launch_bounds__(KB) k_adjoint_source(const c2<T>* __restrict__ g, const c2<T>* __restrict__ NHg,
@@ -305,6 +326,14 @@ hipError_t kr_total_field(const c2<T>* e_inc, const c2<T>* u, const c2<T>* Nu, c
 }
 
 template <typename T>
+hipError_t kr_magnetic_field(const c2<T>* h_inc, const c2<T>* KJ, double h, double mu0, c2<T>* H, T* b1, long nv,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_magnetic_field<T>, dim3((nv + KB - 1) / KB), dim3(KB), 0, st, h_inc, KJ, h, mu0, H, b1, nv);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t kr_adjoint_source(const c2<T>* g, const c2<T>* NHg, c2<T>* t, long n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_adjoint_source<T>, dim3((n + KB - 1) / KB), dim3(KB), 0, st, g, NHg, t, n);
@@ -326,7 +355,9 @@ hipError_t kr_adjoint_source(const c2<T>* g, const c2<T>* NHg, c2<T>* t, long n,
                                        hipStream_t);                                                             \
     template hipError_t kr_total_field<TK>(const c2<TK>*, const c2<TK>*, const c2<TK>*, c2<TK>*, double, long,     \
                                            hipStream_t);                                                         \
-    template hipError_t kr_adjoint_source<TK>(const c2<TK>*, const c2<TK>*, c2<TK>*, long, hipStream_t);
+    template hipError_t kr_adjoint_source<TK>(const c2<TK>*, const c2<TK>*, c2<TK>*, long, hipStream_t);          \
+    template hipError_t kr_magnetic_field<TK>(const c2<TK>*, const c2<TK>*, double, double, c2<TK>*, TK*, long,   \
+                                              hipStream_t);
 
 VIE_KR_INST(float)
 VIE_KR_INST(double)

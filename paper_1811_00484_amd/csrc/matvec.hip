@@ -44,11 +44,10 @@ int g_kernel_path = 0;
 int g_batch_mode = 0;
 
 // component parities: s_a(c) = -1 iff c is off-diagonal and a is one of its axes
-__device__ __forceinline__ int comp_sign(int c, int f1, int f2, int f3)
+__device__ __forceinline__ int comp_sign(int fam, int c, int f1, int f2, int f3)
 {
     // c: 0 xx, 1 yy, 2 zz, 3 xy, 4 xz, 5 yz
-    int odd1 = (c == 3 || c == 4), odd2 = (c == 3 || c == 5), odd3 = (c == 4 || c == 5);
-    int neg = (odd1 & f1) ^ (odd2 & f2) ^ (odd3 & f3);
+    int neg = (comp_odd(fam, c, 0) & f1) ^ (comp_odd(fam, c, 1) & f2) ^ (comp_odd(fam, c, 2) & f3);
     return neg ? -1 : 1;
 }
 
@@ -350,13 +349,16 @@ __device__ __forceinline__ void zmid_body(c2<T>* __restrict__ S2, FftPlan pl, co
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
             c2<T> t = NTt[c * (n3 + 1) + kk];
-            if (comp_sign(c, pf1[pe], pf2[pe], f3) < 0) t = mk<T>(-t.x, -t.y);
+            if (comp_sign(v.fam, c, pf1[pe], pf2[pe], f3) < 0) t = mk<T>(-t.x, -t.y);
             N[c] = a.conj ? conj(t) : t;
         }
+        // the pair (q, p) below the diagonal is N_pq (symmetric family) or
+        // -K_pq (antisymmetric family)
+        const T lo = v.fam ? (T)-1 : (T)1;
         c2<T> x0 = X[(0 * P + pe) * L3 + m], x1 = X[(1 * P + pe) * L3 + m], x2 = X[(2 * P + pe) * L3 + m];
         c2<T> y0 = N[0] * x0 + N[3] * x1 + N[4] * x2;
-        c2<T> y1 = N[3] * x0 + N[1] * x1 + N[5] * x2;
-        c2<T> y2 = N[4] * x0 + N[5] * x1 + N[2] * x2;
+        c2<T> y1 = lo * (N[3] * x0) + N[1] * x1 + N[5] * x2;
+        c2<T> y2 = lo * (N[4] * x0 + N[5] * x1) + N[2] * x2;
         X[(0 * P + pe) * L3 + m] = y0;
         X[(1 * P + pe) * L3 + m] = y1;
         X[(2 * P + pe) * L3 + m] = y2;
@@ -872,7 +874,7 @@ __global__ void k_nhat_samples(OpView v, const c2<T>* __restrict__ core, const c
             for (int ga = 0; ga < r3; ++ga) fma_c(t, G[((long)al * r2 + be) * r3 + ga], U3[ga]);
             acc = acc + U1[al] * (U2[be] * t);
         }
-    if (comp_sign(c, f[0], f[1], f[2]) < 0) acc = mk<T>(-acc.x, -acc.y);
+    if (comp_sign(v.fam, c, f[0], f[1], f[2]) < 0) acc = mk<T>(-acc.x, -acc.y);
     out[2 * m] = (double)acc.x;
     out[2 * m + 1] = (double)acc.y;
 }
@@ -956,6 +958,7 @@ static bool batch_grouped_ok(const std::vector<InstHost>& req, int recon)
     for (const InstHost& h : req) {
         const DeviceOp& op = *h.op;
         const OpView& v = op.view;
+        if (v.fam != 0) return false;
         if (!xy_fast_length(v.L[0]) || !xy_fast_length(v.L[1]) || !z_fast_length(v.L[2])) return false;
         if (op.nhat_source == 1 && (sizeof(T) == 8 ? (const void*)op.dense64 : (const void*)op.dense32) == nullptr)
             return false;

@@ -842,7 +842,7 @@ bool xy_pass_fast(int kind, int L, const void* in, void* out, const c2<TV>* x, c
 bool bf16_recon_available(const DeviceOp& op)
 {
     const OpView& v = op.view;
-    if (!op.b16.fac3m) return false;
+    if (v.fam != 0 || !op.b16.fac3m) return false;
     if (v.L[2] != 512 && v.L[2] != 256 && v.L[2] != 128) return false;
     for (int c = 0; c < 6; ++c)
         if (v.rh[c] == 0) return false;
@@ -854,6 +854,9 @@ bool z_pass_fast(const DeviceOp& op, int mode, int recon, int nrhs, c2<T>* S2, c
                  const c2<T>* fac, const c2<T>* dense, hipStream_t s)
 {
     const OpView& v = op.view;
+    // the register-FFT z pass has the symmetric (N) product only; K operators
+    // take the generic z kernel
+    if (v.fam != 0) return false;
     if (recon == 1 && (sizeof(T) != 4 || !bf16_recon_available(op))) return false;
     switch (v.L[2]) {
     case 512:

@@ -498,6 +498,7 @@ vie_status vie_solve(const vie_op* op, int dtype, const void* eps_c, const void*
                      const vie_solve_opts* opts, vie_solve_info* info, void* ws, size_t ws_bytes, void* stream)
 {
     if (!op || !eps_c || !b || !x || !ws || nrhs < 1) return fail(VIE_E_ARG, "vie_solve: null argument or nrhs < 1");
+    if (op->d.view.fam != 0) return fail(VIE_E_UNSUPPORTED, "vie_solve: N operators only");
     vie_solve_opts o = defaults(opts);
     if (!(o.tol > 0) || o.restart < 1 || o.restart > 200 || o.max_outer < 0 || (o.refine != 0 && o.refine != 1))
         return fail(VIE_E_ARG, "vie_solve: bad options");
@@ -577,6 +578,27 @@ vie_status vie_total_field(const vie_op* op, int dtype, const void* e_inc, const
     else
         return fail(VIE_E_ARG, "vie_total_field: bad dtype");
     if (e != hipSuccess) return hip_fail(e, "vie_total_field");
+    return VIE_OK;
+}
+
+vie_status vie_magnetic_field(const vie_op* op_k, int dtype, const void* h_inc, const void* KJ, double h, double mu0,
+                              void* H, void* b1, void* stream)
+{
+    if (!op_k || !h_inc || !KJ || !H || !b1 || !(h > 0) || !(mu0 > 0))
+        return fail(VIE_E_ARG, "vie_magnetic_field: bad argument");
+    if (op_k->d.view.fam != 1) return fail(VIE_E_ARG, "vie_magnetic_field: needs a K operator (vie_compress_k)");
+    const OpView& v = op_k->d.view;
+    long nv = (long)v.n[0] * v.n[1] * v.n[2];
+    hipError_t e;
+    if (dtype == VIE_C128)
+        e = kr_magnetic_field<double>((const c2<double>*)h_inc, (const c2<double>*)KJ, h, mu0, (c2<double>*)H,
+                                      (double*)b1, nv, (hipStream_t)stream);
+    else if (dtype == VIE_C64)
+        e = kr_magnetic_field<float>((const c2<float>*)h_inc, (const c2<float>*)KJ, h, mu0, (c2<float>*)H, (float*)b1,
+                                     nv, (hipStream_t)stream);
+    else
+        return fail(VIE_E_ARG, "vie_magnetic_field: bad dtype");
+    if (e != hipSuccess) return hip_fail(e, "vie_magnetic_field");
     return VIE_OK;
 }
 
@@ -668,6 +690,7 @@ vie_status vie_matvec_multi(const vie_instance* inst, int count, int kind, int a
         const vie_instance& in = inst[i];
         if (!in.x || !in.y || (kind == VIE_OP_A && !in.eps_c)) return fail(VIE_E_ARG, "vie_matvec_multi: bad instance");
         if (in.op->d.nhat_source != 0) return fail(VIE_E_UNSUPPORTED, "vie_matvec_multi: Tucker operators only");
+        if (in.op->d.view.fam != 0) return fail(VIE_E_UNSUPPORTED, "vie_matvec_multi: N operators only");
         const OpView& v = in.op->d.view;
         size_t vb = (size_t)in.nrhs * 3 * v.n[0] * v.n[1] * v.n[2] * eb;
         const char* xb = (const char*)in.x;

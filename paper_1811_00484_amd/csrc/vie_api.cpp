@@ -73,14 +73,14 @@ static unsigned short to_bf16(float f)
 }
 
 static vie_status build_operator(const int n[3], const FftPlan plans[3], TuckerComponent tc[6], vie_op** out,
-                                 vie_compress_info* info, std::chrono::steady_clock::time_point t0)
+                                 vie_compress_info* info, std::chrono::steady_clock::time_point t0, int fam = 0)
 {
     using cd = std::complex<double>;
     const long V = (long)n[0] * n[1] * n[2];
-    const int odd[6][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
     // pack cores (scaled by 1/M) and Fourier factors
     DeviceOp d;
     OpView& v = d.view;
+    v.fam = fam;
     int rmax = 1;
     int core_tot = 0, fac_tot = 0;
     for (int a = 0; a < 3; ++a) {
@@ -130,7 +130,7 @@ static vie_status build_operator(const int n[3], const FftPlan plans[3], TuckerC
         for (size_t t = 0; t < tc[c].G.size(); ++t) hcore[v.core_off[c] + t] = tc[c].G[t] * invM;
         for (int a = 0; a < 3; ++a) {
             std::vector<cd> Uh;
-            fourier_factor(tc[c].U[a], n[a], tc[c].r[a], odd[c][a] ? -1 : 1, Uh);
+            fourier_factor(tc[c].U[a], n[a], tc[c].r[a], comp_odd(fam, c, a) ? -1 : 1, Uh);
             std::copy(Uh.begin(), Uh.end(), hfac.begin() + v.fac_off[c][a]);
             if (a == 2) {
                 const int r3 = tc[c].r[2];
@@ -272,6 +272,53 @@ vie_status vie_compress_cp(const int n[3], const double* green, const vie_compre
     return compress_common(n, green, opts, cp_rank, cp_iters == 0 ? 1000 : cp_iters, out, info, cp_rel_err);
 }
 
+vie_status vie_compress_k(const int n[3], const double* green_k, const vie_compress_opts* opts, vie_op** out,
+                          vie_compress_info* info)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!n || !green_k || !out) return fail(VIE_E_ARG, "vie_compress_k: null argument");
+    *out = nullptr;
+    for (int a = 0; a < 3; ++a)
+        if (n[a] < 1 || n[a] > 256) return fail(VIE_E_UNSUPPORTED, "vie_compress_k: n_i must be in [1, 256]");
+    vie_compress_opts o = opts ? *opts : vie_compress_opts{1e-6, 0, 0};
+    if (!(o.tol > 0 && o.tol < 1) || (o.trunc_rule != 0 && o.trunc_rule != 1) || o.max_rank < 0)
+        return fail(VIE_E_ARG, "vie_compress_k: bad options");
+    FftPlan plans[3];
+    for (int a = 0; a < 3; ++a)
+        if (!make_plan(2 * n[a], plans[a]))
+            return fail(VIE_E_UNSUPPORTED, "vie_compress_k: 2 n_i must factor into 2, 3, 5, 7");
+    const long V = (long)n[0] * n[1] * n[2];
+    for (long t = 0; t < 6 * V; ++t)
+        if (!std::isfinite(green_k[t])) return fail(VIE_E_NONFINITE, "vie_compress_k: non-finite tensor");
+    using cd = std::complex<double>;
+    TuckerComponent tc[6];
+    // slots 0..2 (the zero diagonal of an antisymmetric pair): rank-1 zero forms
+    for (int c = 0; c < 3; ++c) {
+        for (int a = 0; a < 3; ++a) {
+            tc[c].r[a] = 1;
+            tc[c].U[a].assign((size_t)n[a], cd(0.0));
+            tc[c].sv[a].assign((size_t)n[a], 0.0);
+        }
+        tc[c].G.assign(1, cd(0.0));
+        tc[c].tail_rel = 0;
+        tc[c].fro = 0;
+    }
+    std::vector<cd> A(V);
+    for (int c = 3; c < 6; ++c) {
+        const double* g = green_k + 2 * (size_t)(c - 3) * V;
+        for (long t = 0; t < V; ++t) A[t] = cd(g[2 * t], g[2 * t + 1]);
+        // the component is odd along one axis: zero at zero offset there
+        for (int k = 0; k < n[2]; ++k)
+            for (int j = 0; j < n[1]; ++j)
+                for (int i = 0; i < n[0]; ++i)
+                    if ((comp_odd(1, c, 0) && i == 0) || (comp_odd(1, c, 1) && j == 0) || (comp_odd(1, c, 2) && k == 0))
+                        A[((long)k * n[1] + j) * n[0] + i] = 0.0;
+        int rc = hosvd_component(A.data(), n, o.tol, o.trunc_rule, o.max_rank, tc[c]);
+        if (rc != 0) return fail(VIE_E_UNSUPPORTED, "vie_compress_k: max_rank too small for tol");
+    }
+    return build_operator(n, plans, tc, out, info, t0, 1);
+}
+
 static vie_status compress_common(const int n[3], const double* green, const vie_compress_opts* opts, int cp_rank,
                                   int cp_iters, vie_op** out, vie_compress_info* info, double* cp_err)
 {
@@ -295,7 +342,9 @@ static vie_status compress_common(const int n[3], const double* green, const vie
     using cd = std::complex<double>;
     TuckerComponent tc[6];
     std::vector<cd> A(V);
-    const int odd[6][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+    int odd[6][3];
+    for (int c = 0; c < 6; ++c)
+        for (int a = 0; a < 3; ++a) odd[c][a] = comp_odd(0, c, a);
     for (int c = 0; c < 6; ++c) {
         const double* g = green + 2 * (size_t)c * V;
         for (long t = 0; t < V; ++t) A[t] = cd(g[2 * t], g[2 * t + 1]);
@@ -353,7 +402,9 @@ vie_status vie_op_from_tucker(const int n[3], const int ranks[6][3], const doubl
         if (!make_plan(2 * n[a], plans[a]))
             return fail(VIE_E_UNSUPPORTED, "vie_op_from_tucker: 2 n_i must factor into 2, 3, 5, 7");
     using cd = std::complex<double>;
-    const int odd[6][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+    int odd[6][3];
+    for (int c = 0; c < 6; ++c)
+        for (int a = 0; a < 3; ++a) odd[c][a] = comp_odd(0, c, a);
     TuckerComponent tc[6];
     size_t co = 0, fo = 0;
     for (int c = 0; c < 6; ++c) {
@@ -438,6 +489,8 @@ vie_status matvec_common(const vie_op* op, int mode, int dtype, int recon, const
                          void* y, int nrhs, void* ws, size_t ws_bytes, void* stream, const int* rhs_map)
 {
     if (!op || !x || !y || !ws || nrhs < 1) return fail(VIE_E_ARG, "vie_matvec: null argument or nrhs < 1");
+    if (op->d.view.fam != 0 && mode != MODE_N)
+        return fail(VIE_E_UNSUPPORTED, "vie_matvec: a K operator has the bare forward product (VIE_OP_N) only");
     bool needs_eps = (mode == MODE_A || mode == MODE_AH);
     if (needs_eps && !eps) return fail(VIE_E_ARG, "vie_matvec: eps_c is required for VIE_OP_A");
     if (dtype != VIE_C64 && dtype != VIE_C128) return fail(VIE_E_ARG, "vie_matvec: bad dtype");
@@ -610,6 +663,7 @@ vie_status vie_autotune(vie_op* op, int dtype, int nrhs, void* ws, size_t ws_byt
                         int* chosen)
 {
     if (!op || !ws || nrhs < 1) return fail(VIE_E_ARG, "vie_autotune: null argument or nrhs < 1");
+    if (op->d.view.fam != 0) return fail(VIE_E_UNSUPPORTED, "vie_autotune: N operators only");
     if (dtype != VIE_C64 && dtype != VIE_C128) return fail(VIE_E_ARG, "vie_autotune: bad dtype");
     if (ws_bytes < vie_workspace_bytes(op, dtype, nrhs)) return fail(VIE_E_ARG, "vie_autotune: workspace too small");
     if (ms)

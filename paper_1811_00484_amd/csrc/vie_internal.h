@@ -16,6 +16,16 @@ namespace vie {
 // fac + fac3t_off[c].
 // Cores: [r1][r2][r3] (r3 fastest) at core + core_off[c], scaled by
 // 1 / (8 n1 n2 n3) so the inverse FFTs can stay unnormalised.
+// Parity of component c (xx, yy, zz, xy, xz, yz) of an operator family
+// along axis a: 1 if the defining tensor is odd along that axis.  N: an
+// off-diagonal component is odd along both of its axes.  K (the curl
+// kernel eps_psq d_s g): xy is odd along z, xz along y, yz along x.
+__host__ __device__ inline int comp_odd(int fam, int c, int a)
+{
+    if (fam == 0) return (c == 3 && a != 2) || (c == 4 && a != 1) || (c == 5 && a != 0);
+    return (c == 3 && a == 2) || (c == 4 && a == 1) || (c == 5 && a == 0);
+}
+
 struct OpView {
     int n[3];
     int L[3];
@@ -29,6 +39,10 @@ struct OpView {
     // r3 and beyond row n3; rh = 16 ceil(r3 / 16) (0 when r3 > 32: not available)
     int rh[6];
     int fac3m_off[6];
+    // operator family: 0 = N (symmetric component pair, six components),
+    // 1 = K (antisymmetric pair: components xy, xz, yz in slots 3..5, slots
+    // 0..2 zero)
+    int fam;
     // 1: every core is superdiagonal (r1 = r2 = r3 = R, a Tucker+CP form,
     // eq. 17): the z pass forms V_c(k1, k2, l) = G_c[l,l,l] U1_c(k1, l)
     // U2_c(k2, l) directly instead of contracting the core

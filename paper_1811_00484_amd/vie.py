@@ -80,6 +80,9 @@ _SIGS = {
                                     ctypes.POINTER(_P), ctypes.POINTER(CompressInfo)]),
     "vie_compress_cp": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.POINTER(CompressOpts), ctypes.c_int,
                                        ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(CompressInfo), _P]),
+    "vie_compress_k": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.POINTER(CompressOpts),
+                                      ctypes.POINTER(_P), ctypes.POINTER(CompressInfo)]),
+    "vie_magnetic_field": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
     "vie_op_from_tucker": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _P, _P,
                                           ctypes.POINTER(_P), ctypes.POINTER(CompressInfo)]),
     "vie_op_destroy": (ctypes.c_int, [_P]),
@@ -244,6 +247,43 @@ def compress_cp(green, tol=1e-6, cp_rank=0, cp_iters=0, trunc_rule=0, max_rank=0
     op = Operator(h, (g.shape[3], g.shape[2], g.shape[1]), info)
     op.cp_rel_err = err
     return op
+
+
+def compress_k(green_k, tol=1e-6, trunc_rule=0, max_rank=0):
+    """HOSVD-compress the three K defining tensors (numpy complex128, shape
+    (3, n3, n2, n1), components xy, xz, yz) into a K operator on the current
+    device (vie_compress_k).  ``op.k_ranks`` holds the Tucker ranks of xy,
+    xz, yz.  Apply it with ``matvec(op, x, kind="N")``."""
+    lib = load()
+    g = np.ascontiguousarray(green_k, dtype=np.complex128)
+    if g.ndim != 4 or g.shape[0] != 3:
+        raise ValueError("green_k must have shape (3, n3, n2, n1)")
+    n = (ctypes.c_int * 3)(g.shape[3], g.shape[2], g.shape[1])
+    opts = CompressOpts(float(tol), int(trunc_rule), int(max_rank))
+    info = CompressInfo()
+    h = ctypes.c_void_p()
+    _check(lib.vie_compress_k(n, g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts), ctypes.byref(h),
+                              ctypes.byref(info)), "vie_compress_k")
+    op = Operator(h, (g.shape[3], g.shape[2], g.shape[1]), info)
+    op.k_ranks = op.ranks[3:]
+    return op
+
+
+def magnetic_field(op_k, j, h_inc, h):
+    """H = h_inc + K j and |b1+| = mu0 |H_x + i H_y| (eq. 18) for a current
+    ``j`` (3, n3, n2, n1) on the device; ``h`` is the voxel edge (m).  The K
+    product runs in the library (vie_matvec, VIE_OP_N) and so does the field
+    and b1+ kernel (vie_magnetic_field).  Returns (H, b1)."""
+    lib = load()
+    kj = matvec(op_k, j, kind="N")
+    if h_inc.dtype != j.dtype or tuple(h_inc.shape) != tuple(j.shape) or not h_inc.is_contiguous():
+        raise ValueError("h_inc must be contiguous, of the shape and dtype of j")
+    H = torch.empty_like(kj)
+    b1 = torch.empty(tuple(j.shape[1:]), dtype=torch.float64 if j.dtype == torch.complex128 else torch.float32,
+                     device=j.device)
+    _check(lib.vie_magnetic_field(op_k.handle, _dt(j), _ptr(h_inc), _ptr(kj), float(h), float(MU0), _ptr(H),
+                                  _ptr(b1), _stream()), "vie_magnetic_field")
+    return H, b1
 
 
 def from_tucker(n, cores, factors):
@@ -427,6 +467,8 @@ def solve_multi(items, tol=1e-6, restart=50, max_outer=200, adjoint=False, refin
 
 
 EPS0 = 8.8541878128e-12
+C0 = 299792458.0
+MU0 = 1.0 / (EPS0 * C0 * C0)
 
 
 def _oe0(freq_hz):
