@@ -141,6 +141,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cp", action="store_true", help="skip the Tucker+CP leg")
+    ap.add_argument("--no-magnetic", action="store_true", help="skip the K operator / b1+ leg")
     ap.add_argument("--batch-workload", action="store_true",
                     help="also run the batching workload: 6 head phantoms of seeded sizes at 2 mm, 16 dipole "
                          "fields each, multi-instance matvec and lockstep GMRES")
@@ -281,8 +282,16 @@ def main():
                        "workspace_bytes_per_rhs_c64": vie.workspace_bytes(op, torch.complex64, 1),
                        "vector_bytes_c64": 3 * V * 8}
 
+    x_sol = None
     if not args.no_solve:
-        extra["solve"] = solves(op, b, epsc, dev, vie, torch)
+        extra["solve"], x_sol = solves(op, b, epsc, dev, vie, torch)
+    if not args.no_magnetic:
+        try:
+            extra["magnetic"] = magnetic_leg(n, h, f, k0, x_sol, args, vie, torch, dev)
+        except Exception as exc:   # the headline line is printed regardless
+            log("magnetic leg failed: %r" % (exc,))
+            extra["magnetic"] = {"error": repr(exc)}
+        del x_sol
 
     y_cp = None
     if not args.no_cp:
@@ -422,6 +431,58 @@ def tucker_cp_leg(G, op_t, x, e, y_t, b, epsc, n, args, vie, torch, dev):
     return out, y
 
 
+def magnetic_leg(n, h, f, k0, x_sol, args, vie, torch, dev):
+    """The magnetic operator K (eq. 5) at the same grid: compression of its
+    three components, the K product (same five passes, antisymmetric 3x3
+    product), and |b1+| (eq. 18) of the refined solution's current."""
+    import vie_inputs as vi
+    t0 = time.time()
+    kt = vi.green_k_tensor(n, h, k0)
+    t_in = time.time() - t0
+    t0 = time.time()
+    opk = vie.compress_k(kt, tol=args.tol)
+    t_c = time.time() - t0
+    del kt
+    log("K tensor %.1f s, vie_compress_k %.1f s, ranks %s" % (t_in, t_c, opk.k_ranks))
+    u = torch.from_numpy(vi.random_field(n, 5).astype(np.complex64)).to(dev)
+    y = torch.empty_like(u)
+    st = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        vie.matvec(opk, u, kind="N", out=y)
+    torch.cuda.synchronize()
+    vie.profile_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(st)
+    for _ in range(args.steps):
+        vie.matvec(opk, u, kind="N", out=y)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    vie.profile_enable(False)
+    pass_ms, pass_cnt = vie.profile_collect()
+    avg = [pass_ms[p] / max(1, pass_cnt[p]) for p in range(5)]
+    ms = ev0.elapsed_time(ev1) / args.steps
+    out = {"k_tensor_seconds": t_in, "compress_seconds": t_c, "ranks": [list(r) for r in opk.k_ranks],
+           "operator_bytes_c64": opk.tucker_bytes_c64, "ms_per_k_matvec": ms,
+           "pass_avg_ms": dict(zip(PASS_NAMES, avg))}
+    log("K matvec: %.3f ms; passes %s ms" % (ms, ["%.3f" % a for a in avg]))
+    del u, y
+    if x_sol is not None:
+        hinc = torch.from_numpy(vi.plane_wave_h(n, h, f)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        H, b1 = vie.magnetic_field(opk, x_sol[0] if x_sol.dim() == 5 else x_sol, hinc, h)
+        torch.cuda.synchronize()
+        out["b1_seconds_complex128"] = time.time() - t0
+        b1n = b1 * vie.C0     # |b1+| in units of the incident plane wave's mu0 |H|
+        out["b1_over_incident"] = {"min": float(b1n.min()), "max": float(b1n.max()), "mean": float(b1n.mean())}
+        log("b1+ of the refined solution: %.3f s, |b1+| / incident in [%.3f, %.3f]"
+            % (out["b1_seconds_complex128"], out["b1_over_incident"]["min"], out["b1_over_incident"]["max"]))
+        del H, b1, hinc
+    opk.close()
+    return out
+
+
 def solves(op, b, epsc, dev, vie, torch):
     """Seconds per solve to an FP64 true residual of 1e-6: refined (FP64
     residual + FP64 Arnoldi around the FP32-computed operator, with FP32 or
@@ -441,6 +502,8 @@ def solves(op, b, epsc, dev, vie, torch):
                     "rel_residual_fp64": info[0]["rel_residual"], "matvecs_inner": info[0]["matvecs"],
                     "matvecs_fp64": info[0]["matvecs_fp64"], "refine_steps": info[0]["refine_steps"]}
         log("refined solve (%s reconstruction): %.2f s, %s" % (rc, t, info[0]))
+        if rc == "fp32":
+            x_keep = x
         del x
     b32 = bb.to(torch.complex64)
     e32 = ee.to(torch.complex64)
@@ -455,7 +518,7 @@ def solves(op, b, epsc, dev, vie, torch):
                          "rel_residual_fp32": info32[0]["rel_residual"], "rel_residual_fp64": res64,
                          "reached_1e-6_fp64": res64 <= 1e-6, "matvecs": info32[0]["matvecs"]}
     log("plain fp32 solve: %.2f s, fp64 residual %.3e, %s" % (t_32, res64, info32[0]))
-    return out
+    return out, x_keep
 
 
 def batch_workload(vie, torch, dev, args):

@@ -137,8 +137,9 @@ vie_status vie_compress_cp(const int n[3], const double* green, const vie_compre
  *   y_p(m) = sum_q sum_m' K_pq(m - m') x_q(m')
  * through vie_matvec with kind VIE_OP_N only (no contrast epilogue, no
  * adjoint: other calls return VIE_E_UNSUPPORTED; it is not accepted by the
- * solvers, multi-instance calls or vie_autotune).  Its z pass runs on the
- * mixed-radix kernels.
+ * solvers, multi-instance calls or vie_autotune).  Its z pass has its own
+ * variant of the register-FFT kernel (z lengths 128, 256, 512) and of the
+ * mixed-radix one.
  *   green_k HOST complex128 [3][n3][n2][n1]: K_c(offset (i, j, k)) for
  *           c = xy, xz, yz, observation voxel at the offset, source at 0.
  *   n, opts, out as vie_compress; info (may be NULL): ranks[0..2] are the

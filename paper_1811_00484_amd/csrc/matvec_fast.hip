@@ -392,10 +392,10 @@ __global__ void __launch_bounds__(W*(L / E)) k_xy_fast_multi(const XYGroup g, co
 
 // ---------------------------------------------------------------------------
 // Z pass
+template <int FAM>
 __device__ __forceinline__ int zsign(int c, int f1, int f2, int f3)
 {
-    int odd1 = (c == 3 || c == 4), odd2 = (c == 3 || c == 5), odd3 = (c == 4 || c == 5);
-    return ((odd1 & f1) ^ (odd2 & f2) ^ (odd3 & f3)) ? -1 : 1;
+    return ((comp_odd(FAM, c, 0) & f1) ^ (comp_odd(FAM, c, 1) & f2) ^ (comp_odd(FAM, c, 2) & f3)) ? -1 : 1;
 }
 
 // Load the three components of a pencil into the input layout of the
@@ -416,8 +416,9 @@ __device__ __forceinline__ void z_load(c2<T> (&d)[3][8], const c2<T>* __restrict
             }
 }
 
-// 3x3 component product in the output layout of the forward plan
-template <typename T, int L3, int TPP, int RL, bool CONJ>
+// 3x3 component product in the output layout of the forward plan; FAM 1
+// (K operators): antisymmetric pair, K's parities, zero diagonal
+template <typename T, int L3, int TPP, int RL, bool CONJ, int FAM>
 __device__ __forceinline__ void z_product(c2<T> (&d)[3][8], const c2<T>* NTt, int t, int f1, int f2)
 {
     constexpr int E = 8;
@@ -431,16 +432,22 @@ __device__ __forceinline__ void z_product(c2<T> (&d)[3][8], const c2<T>* NTt, in
             const int kk = f3 ? L3 - m : m;
             c2<T> Nc[6];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) {
+            for (int c = FAM ? 3 : 0; c < 6; ++c) {
                 c2<T> tv = NTt[c * (N3 + 1) + kk];
-                if (zsign(c, f1, f2, f3) < 0) tv = mk<T>(-tv.x, -tv.y);
+                if (zsign<FAM>(c, f1, f2, f3) < 0) tv = mk<T>(-tv.x, -tv.y);
                 Nc[c] = CONJ ? vie::conj(tv) : tv;
             }
             const int i = u * RL + r;
             c2<T> x0 = d[0][i], x1 = d[1][i], x2 = d[2][i];
-            d[0][i] = Nc[0] * x0 + Nc[3] * x1 + Nc[4] * x2;
-            d[1][i] = Nc[3] * x0 + Nc[1] * x1 + Nc[5] * x2;
-            d[2][i] = Nc[4] * x0 + Nc[5] * x1 + Nc[2] * x2;
+            if constexpr (FAM == 0) {
+                d[0][i] = Nc[0] * x0 + Nc[3] * x1 + Nc[4] * x2;
+                d[1][i] = Nc[3] * x0 + Nc[1] * x1 + Nc[5] * x2;
+                d[2][i] = Nc[4] * x0 + Nc[5] * x1 + Nc[2] * x2;
+            } else {
+                d[0][i] = Nc[3] * x1 + Nc[4] * x2;
+                d[1][i] = Nc[5] * x2 - Nc[3] * x0;
+                d[2][i] = mk<T>(0, 0) - (Nc[4] * x0 + Nc[5] * x1);
+            }
         }
 }
 
@@ -519,7 +526,8 @@ __device__ __forceinline__ void z_tables_mfma(const OpView& v, const unsigned sh
 }
 
 // REC: 0 = N^ tables in T on the vector ALUs, 1 = BF16 z factors on MFMA
-// (T = float).
+// (T = float), 2 = a K operator (antisymmetric product, K parities; tables
+// on the vector ALUs).
 // One workgroup of the z pass: bx = canonical k2 + (n2 + 1) * chunk index,
 // b = compact right-hand side.
 template <typename T, int L3, bool CONJ, int REC>
@@ -681,7 +689,7 @@ __device__ __forceinline__ void z_body(c2<T>* __restrict__ S2, const c2<T>* __re
             }
         }
         __syncthreads();   // tables complete
-        z_product<T, L3, TPP, Plan::RFL, CONJ>(d, X, t, s1, s2);
+        z_product<T, L3, TPP, Plan::RFL, CONJ, REC == 2 ? 1 : 0>(d, X, t, s1, s2);
         __syncthreads();   // table A consumed: the slices are reused by the inverse FFT
 #pragma unroll
         for (int q = 0; q < 3; ++q) Plan::template inv<T, TPP, 1, 1>(d[q], X + pe * P, 0, t, tws);
@@ -696,7 +704,7 @@ __device__ __forceinline__ void z_body(c2<T>* __restrict__ S2, const c2<T>* __re
             z_load<T, L3, TPP, Plan::RF0>(d, S2, baseB, cstride, t, exB);
 #pragma unroll
             for (int q = 0; q < 3; ++q) Plan::template fwd<T, TPP, 1, -1>(d[q], X + pe * P, 0, t, tws);
-            z_product<T, L3, TPP, Plan::RFL, CONJ>(d, NTB, t, s1, s2);
+            z_product<T, L3, TPP, Plan::RFL, CONJ, REC == 2 ? 1 : 0>(d, NTB, t, s1, s2);
 #pragma unroll
             for (int q = 0; q < 3; ++q) Plan::template inv<T, TPP, 1, 1>(d[q], X + pe * P, 0, t, tws);
             if (exB) z_store<T, L3, TPP, Plan::RIL>(d, S2, baseB, cstride, t);
@@ -817,6 +825,7 @@ static hipError_t launch_z(const DeviceOp& op, int mode, int recon, int nrhs, c2
     if constexpr (sizeof(T) == 4) {
         if (recon == 1) kern = za.conj ? k_z_fast<T, L3, true, 1> : k_z_fast<T, L3, false, 1>;
     }
+    if (v.fam == 1) kern = k_z_fast<T, L3, false, 2>;
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, dim3((v.n[1] + 1) * nchunk, nrhs), dim3(4 * (L3 / 8)), lds, s, S2, tw, za, core, fac,
                        dense, (const unsigned short*)op.b16.fac3m);
@@ -854,9 +863,8 @@ bool z_pass_fast(const DeviceOp& op, int mode, int recon, int nrhs, c2<T>* S2, c
                  const c2<T>* fac, const c2<T>* dense, hipStream_t s)
 {
     const OpView& v = op.view;
-    // the register-FFT z pass has the symmetric (N) product only; K operators
-    // take the generic z kernel
-    if (v.fam != 0) return false;
+    // K operators: forward product only (the API rejects the others)
+    if (v.fam != 0 && (mode == MODE_AH || mode == MODE_NH || recon == 1)) return false;
     if (recon == 1 && (sizeof(T) != 4 || !bf16_recon_available(op))) return false;
     switch (v.L[2]) {
     case 512:

@@ -4,8 +4,9 @@
 * K u on the device (vie_compress_k, vie_matvec VIE_OP_N) against the
   oracle's K product with its own HOSVD at the same tolerance: complex64
   <= 1e-5, complex128 <= 1e-11, over grids with ragged tails, every FFT
-  length class and the register-FFT x/y passes (the z pass of a K operator
-  is the mixed-radix kernel);
+  length class, the register-FFT passes (z lengths 128, 256, 512 take the
+  K variant of the register-FFT z kernel) and the mixed-radix ones, which
+  must agree;
 * the field and b1+ kernel against the oracle on a seeded current;
 * end to end on the 16^3 sphere: the library's solve, K product and b1+
   against the oracle's solve, K product and b1+;
@@ -25,7 +26,7 @@ from paper_1811_00484_amd import vie
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [(16, 16, 16), (12, 10, 9), (20, 15, 18), (1, 1, 1), (5, 3, 2), (40, 24, 64), (64, 20, 12)]
+SIZES = [(16, 16, 16), (12, 10, 9), (20, 15, 18), (1, 1, 1), (5, 3, 2), (40, 24, 64), (64, 20, 12), (20, 18, 128)]
 
 
 @pytest.mark.parametrize("n", SIZES)
@@ -46,6 +47,24 @@ def test_k_matvec_matches_oracle(n):
             continue
         err = rel(y, yo)
         say("   ", dt, "rel err", err)
+        assert err <= bound
+
+
+@pytest.mark.parametrize("n", [(40, 24, 64), (20, 18, 128), (12, 10, 256)])
+def test_k_register_fft_equals_mixed_radix(n):
+    kt = vi.green_k_tensor(n, 0.004, K0)
+    op = vie.compress_k(kt, tol=1e-6)
+    u = vi.random_field(n, 46)
+    for dt, bound in ((torch.complex64, 1e-6), (torch.complex128, 1e-13)):
+        x = to_dev(u, dt)
+        yf = vie.matvec(op, x, kind="N").cpu().numpy().astype(np.complex128)
+        vie.set_kernel_path(1)
+        try:
+            yg = vie.matvec(op, x, kind="N").cpu().numpy().astype(np.complex128)
+        finally:
+            vie.set_kernel_path(0)
+        err = rel(yf, yg)
+        say("   ", n, dt, "register-FFT vs mixed-radix", err)
         assert err <= bound
 
 
