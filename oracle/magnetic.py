@@ -16,6 +16,10 @@ along y, Kt_yz along x, and even along the other two.  The FFT evaluation
 embeds each component with these parities (Sec. V-A), and the 3x3 product in
 the Fourier domain uses the antisymmetric pattern.
 
+The full JMVIE operator of eq. 4 (``jm_matvec``) couples the electric and
+magnetic polarisation currents J and M through K, with a magnetic contrast
+chi_h = mu_c - 1 beside the electric one.
+
 Observables: H = H_inc + K J for the polarisation current J of the electric
 equation (u = J, eq. 3; the tissue is non-magnetic, so M = 0 in eq. 1 and
 the second block row only produces the field), and |b1+| = mu0 |H_x + i H_y|
@@ -138,3 +142,24 @@ def magnetic_field(op, u, h_inc, h):
 def b1_plus(H):
     """|b1+| = mu0 |H_x + i H_y| (eq. 18)."""
     return MU0 * np.abs(H[0] + 1j * H[1])
+
+
+def jm_matvec(op_n, op_k, eps_c, mu_c, x, h, freq_hz):
+    """The full JMVIE operator of eq. 4 on x = [J; M] (shape (2, 3, n3, n2, n1)):
+
+        y_J = eps_c J - chi_e N J + c_e chi_e K M
+        y_M = mu_c M - chi_h N M - c_m chi_h K J
+
+    with chi_e = eps_c - 1, chi_h = mu_c - 1, c_e = i omega eps0,
+    c_m = i omega mu0 (eq. 2) and the physical K = h Kt."""
+    from vie_inputs.constants import EPS0, omega
+
+    from .operator import apply_N
+    ce = 1j * omega(freq_hz) * EPS0
+    cm = 1j * omega(freq_hz) * MU0
+    chi_e = np.asarray(eps_c) - 1.0
+    chi_h = np.asarray(mu_c) - 1.0
+    J, M = x[0], x[1]
+    yJ = eps_c[None] * J - chi_e[None] * apply_N(op_n, J) + ce * h * chi_e[None] * apply_K(op_k, M)
+    yM = mu_c[None] * M - chi_h[None] * apply_N(op_n, M) - cm * h * chi_h[None] * apply_K(op_k, J)
+    return np.stack([yJ, yM])

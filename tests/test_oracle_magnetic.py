@@ -197,3 +197,48 @@ def test_magnetic_field_of_a_single_current_voxel():
     grad = -g * (1 + 1j * k0 * gr) / gr ** 2 * r
     Hd = np.cross(grad, np.array([0.0, h ** 3, 0.0]))
     np.testing.assert_allclose(H[:, 0, 0, d], Hd, rtol=2e-3, atol=1e-12 * abs(Hd).max())
+
+
+def _jm_problem(n, h, seed):
+    f = 298e6
+    G = vi.green_tensor(n, h, vi.wavenumber(f))
+    kt = green_k_tensor(n, h, vi.wavenumber(f))
+    rng = np.random.default_rng(seed)
+    shape = tuple(reversed(n))
+    eps_c = 1 + rng.uniform(0, 50, shape) - 1j * rng.uniform(0, 30, shape)
+    mu_c = 1 + rng.uniform(0, 2, shape) - 1j * rng.uniform(0, 0.5, shape)
+    x = np.stack([vi.random_field(n, seed + 1), vi.random_field(n, seed + 2)])
+    return f, G, kt, eps_c, mu_c, x
+
+
+def test_jm_reduces_to_the_electric_operator():
+    # no magnetic contrast and no magnetic current: the first block row is the
+    # electric operator of eq. 4 and the second vanishes
+    from oracle import operator as opm
+    n = (6, 5, 4)
+    h = 0.005
+    f, G, kt, eps_c, _, x = _jm_problem(n, h, 11)
+    x[1] = 0
+    opn, opk = opm.dense_operator(G), mg.dense_k_operator(kt)
+    y = mg.jm_matvec(opn, opk, eps_c, np.ones_like(eps_c), x, h, f)
+    np.testing.assert_allclose(y[0], opm.matvec(opn, eps_c, x[0], "A"), rtol=0, atol=1e-14 * np.abs(y[0]).max())
+    assert not np.any(y[1])
+
+
+def test_jm_duality():
+    # Maxwell duality (E, H, eps, mu) -> (H, -E, mu, eps): with
+    # alpha = -eps0/mu0, A(mu_c, eps_c) [alpha M; J] = [alpha y_M; y_J]; a wrong
+    # sign or coefficient on either coupling block breaks it
+    n = (5, 4, 3)
+    h = 0.004
+    f, G, kt, eps_c, mu_c, x = _jm_problem(n, h, 12)
+    from oracle import operator as opm
+    opn, opk = opm.dense_operator(G), mg.dense_k_operator(kt)
+    y = mg.jm_matvec(opn, opk, eps_c, mu_c, x, h, f)
+    alpha = -vi.EPS0 / vi.MU0
+    yd = mg.jm_matvec(opn, opk, mu_c, eps_c, np.stack([alpha * x[1], x[0]]), h, f)
+    np.testing.assert_allclose(yd[0], alpha * y[1], rtol=1e-12, atol=1e-14 * np.abs(alpha * y[1]).max())
+    np.testing.assert_allclose(yd[1], y[0], rtol=1e-12, atol=1e-14 * np.abs(y[0]).max())
+    # and the coupling is really exercised: K M moves y_J
+    y0 = mg.jm_matvec(opn, opk, eps_c, mu_c, np.stack([x[0], 0 * x[1]]), h, f)
+    assert np.linalg.norm(y0[0] - y[0]) > 1e-6 * np.linalg.norm(y[0])
