@@ -287,7 +287,7 @@ def main():
         extra["solve"], x_sol = solves(op, b, epsc, dev, vie, torch)
     if not args.no_magnetic:
         try:
-            extra["magnetic"] = magnetic_leg(n, h, f, k0, x_sol, args, vie, torch, dev)
+            extra["magnetic"] = magnetic_leg(n, h, f, k0, x_sol, op, args, vie, torch, dev)
         except Exception as exc:   # the headline line is printed regardless
             log("magnetic leg failed: %r" % (exc,))
             extra["magnetic"] = {"error": repr(exc)}
@@ -431,10 +431,11 @@ def tucker_cp_leg(G, op_t, x, e, y_t, b, epsc, n, args, vie, torch, dev):
     return out, y
 
 
-def magnetic_leg(n, h, f, k0, x_sol, args, vie, torch, dev):
+def magnetic_leg(n, h, f, k0, x_sol, opn_for_jm, args, vie, torch, dev):
     """The magnetic operator K (eq. 5) at the same grid: compression of its
     three components, the K product (same five passes, antisymmetric 3x3
-    product), and |b1+| (eq. 18) of the refined solution's current."""
+    product), the full JMVIE operator of eq. 4 with a synthetic magnetic
+    contrast, and |b1+| (eq. 18) of the refined solution's current."""
     import vie_inputs as vi
     t0 = time.time()
     kt = vi.green_k_tensor(n, h, k0)
@@ -467,6 +468,23 @@ def magnetic_leg(n, h, f, k0, x_sol, args, vie, torch, dev):
            "pass_avg_ms": dict(zip(PASS_NAMES, avg))}
     log("K matvec: %.3f ms; passes %s ms" % (ms, ["%.3f" % a for a in avg]))
     del u, y
+    # the full JMVIE operator of eq. 4 with a magnetic contrast (synthetic:
+    # mu_r = 1.5, loss 0.1 inside the head) beside the head's permittivity
+    er, sg, label = vi.head_phantom(n, h, seed=2)
+    eps_c = torch.from_numpy(vi.complex_permittivity(er, sg, f).astype(np.complex64)).to(dev)
+    mu_c = torch.from_numpy(np.where(label >= 0, 1.5 - 0.1j, 1.0 + 0j).astype(np.complex64)).to(dev)
+    xj = torch.from_numpy(np.stack([vi.random_field(n, 6), vi.random_field(n, 7)]).astype(np.complex64)).to(dev)
+    for _ in range(args.warmup):
+        vie.matvec_jm(opn_for_jm, opk, xj, eps_c, mu_c, h, f)
+    torch.cuda.synchronize()
+    ev0.record(st)
+    for _ in range(args.steps):
+        yj = vie.matvec_jm(opn_for_jm, opk, xj, eps_c, mu_c, h, f)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    out["ms_per_jm_matvec"] = ev0.elapsed_time(ev1) / args.steps
+    log("JM matvec (eq. 4, N and K on [J; M] + combine): %.3f ms" % out["ms_per_jm_matvec"])
+    del xj, yj, eps_c, mu_c
     if x_sol is not None:
         hinc = torch.from_numpy(vi.plane_wave_h(n, h, f)).to(dev)
         torch.cuda.synchronize()

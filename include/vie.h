@@ -327,6 +327,24 @@ vie_status vie_problem_setup(const vie_op* op, int dtype, const void* eps_r, con
 vie_status vie_total_field(const vie_op* op, int dtype, const void* e_inc, const void* u, const void* Nu,
                            double omega_eps0, void* E, void* stream);
 /*
+ * vie_matvec_jm -- the full JMVIE operator of eq. 4 on x = [J; M] (electric
+ *   and magnetic polarisation currents):
+ *     y_J = eps_c J - chi_e N J + c_e chi_e K M,
+ *     y_M = mu_c M  - chi_h N M - c_m chi_h K J,
+ *   chi_e = eps_c - 1, chi_h = mu_c - 1, c_e = i omega eps0, c_m = i omega mu0
+ *   (eq. 2), with the N operator op_n (vie_compress) and the K operator op_k
+ *   (vie_compress_k) of the same grid, h the voxel edge (the physical K is h
+ *   times its dimensionless tensor).  J and M go through each operator as
+ *   two right-hand sides (two five-pass products), then one kernel combines.
+ *   x, y DEVICE complex [2][3][n3][n2][n1] (J then M, must not overlap);
+ *   eps_c, mu_c DEVICE complex [n3][n2][n1]; ws DEVICE scratch of at least
+ *   vie_jm_workspace_bytes(op_n, op_k, dtype) bytes.  Asynchronous on stream.
+ */
+size_t vie_jm_workspace_bytes(const vie_op* op_n, const vie_op* op_k, int dtype);
+vie_status vie_matvec_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, double omega, const void* eps_c,
+                         const void* mu_c, const void* x, void* y, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * vie_magnetic_field -- H = h_inc + h KJ and |b1+| = mu0 |H_x + i H_y|
  *   (eq. 18) for the polarisation current J of the electric equation, where
  *   KJ = vie_matvec(op_k, VIE_OP_N, J) with op_k from vie_compress_k and h

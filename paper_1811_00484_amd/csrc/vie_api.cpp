@@ -2,6 +2,7 @@
 // matvecs and test entry points.  The GMRES driver is in solve.cpp.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -11,6 +12,7 @@
 
 #include "../../include/vie.h"
 #include "host_compress.h"
+#include "krylov.h"
 #include "vie_internal.h"
 
 namespace vie {
@@ -541,6 +543,60 @@ vie_status vie_matvec_adjoint(const vie_op* op, int kind, int dtype, int recon, 
     if (kind != VIE_OP_A && kind != VIE_OP_N) return fail(VIE_E_ARG, "vie_matvec_adjoint: bad kind");
     return matvec_common(op, kind == VIE_OP_A ? MODE_AH : MODE_NH, dtype, recon, eps_c, x, y, nrhs, ws, ws_bytes,
                          stream, nullptr);
+}
+
+static size_t align_up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t vie_jm_workspace_bytes(const vie_op* op_n, const vie_op* op_k, int dtype)
+{
+    if (!op_n || !op_k || (dtype != VIE_C64 && dtype != VIE_C128)) return 0;
+    const OpView& v = op_n->d.view;
+    const size_t vec = (size_t)2 * 3 * v.n[0] * v.n[1] * v.n[2] * (dtype == VIE_C128 ? 16 : 8);
+    const size_t mv = std::max(vie_workspace_bytes(op_n, dtype, 2), vie_workspace_bytes(op_k, dtype, 2));
+    return 2 * align_up256(vec) + mv;
+}
+
+vie_status vie_matvec_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, double omega, const void* eps_c,
+                         const void* mu_c, const void* x, void* y, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!op_n || !op_k || !eps_c || !mu_c || !x || !y || !ws || !(h > 0) || !(omega > 0))
+        return fail(VIE_E_ARG, "vie_matvec_jm: bad argument");
+    if (op_n->d.view.fam != 0 || op_k->d.view.fam != 1)
+        return fail(VIE_E_ARG, "vie_matvec_jm: needs an N operator and a K operator");
+    const OpView& v = op_n->d.view;
+    for (int a = 0; a < 3; ++a)
+        if (op_k->d.view.n[a] != v.n[a]) return fail(VIE_E_ARG, "vie_matvec_jm: N and K grids differ");
+    if (dtype != VIE_C64 && dtype != VIE_C128) return fail(VIE_E_ARG, "vie_matvec_jm: bad dtype");
+    const size_t need = vie_jm_workspace_bytes(op_n, op_k, dtype);
+    if (ws_bytes < need) return fail(VIE_E_ARG, "vie_matvec_jm: workspace too small");
+    const long nv = (long)v.n[0] * v.n[1] * v.n[2];
+    const size_t vec = (size_t)2 * 3 * nv * (dtype == VIE_C128 ? 16 : 8);
+    const char* xb = (const char*)x;
+    const char* yb = (const char*)y;
+    if (!(xb + vec <= yb || yb + vec <= xb)) return fail(VIE_E_ARG, "vie_matvec_jm: x and y overlap");
+    char* w = (char*)ws;
+    void* NX = w;
+    void* KX = w + align_up256(vec);
+    void* mw = w + 2 * align_up256(vec);
+    const size_t mb = ws_bytes - 2 * align_up256(vec);
+    // [J; M] as two right-hand sides of each operator
+    vie_status st = matvec_common(op_n, MODE_N, dtype, VIE_RECON_AUTO, nullptr, x, NX, 2, mw, mb, stream, nullptr);
+    if (st != VIE_OK) return st;
+    st = matvec_common(op_k, MODE_N, dtype, VIE_RECON_AUTO, nullptr, x, KX, 2, mw, mb, stream, nullptr);
+    if (st != VIE_OK) return st;
+    const double EPS0 = 8.8541878128e-12, C0 = 299792458.0;
+    const double MU0 = 1.0 / (EPS0 * C0 * C0);
+    hipError_t e;
+    if (dtype == VIE_C128)
+        e = kr_jm_combine<double>((const c2<double>*)eps_c, (const c2<double>*)mu_c, (const c2<double>*)x,
+                                  (const c2<double>*)NX, (const c2<double>*)KX, omega * EPS0 * h, omega * MU0 * h,
+                                  (c2<double>*)y, nv, (hipStream_t)stream);
+    else
+        e = kr_jm_combine<float>((const c2<float>*)eps_c, (const c2<float>*)mu_c, (const c2<float>*)x,
+                                 (const c2<float>*)NX, (const c2<float>*)KX, omega * EPS0 * h, omega * MU0 * h,
+                                 (c2<float>*)y, nv, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "vie_matvec_jm");
+    return VIE_OK;
 }
 
 vie_status vie_debug_nhat(const vie_op* op, int dtype, int recon, const int* idx, int count, double* out)

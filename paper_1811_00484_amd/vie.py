@@ -82,6 +82,9 @@ _SIGS = {
                                        ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(CompressInfo), _P]),
     "vie_compress_k": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.POINTER(CompressOpts),
                                       ctypes.POINTER(_P), ctypes.POINTER(CompressInfo)]),
+    "vie_jm_workspace_bytes": (ctypes.c_size_t, [_P, _P, ctypes.c_int]),
+    "vie_matvec_jm": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P,
+                                     ctypes.c_size_t, _P]),
     "vie_magnetic_field": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
     "vie_op_from_tucker": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _P, _P,
                                           ctypes.POINTER(_P), ctypes.POINTER(CompressInfo)]),
@@ -284,6 +287,25 @@ def magnetic_field(op_k, j, h_inc, h):
     _check(lib.vie_magnetic_field(op_k.handle, _dt(j), _ptr(h_inc), _ptr(kj), float(h), float(MU0), _ptr(H),
                                   _ptr(b1), _stream()), "vie_magnetic_field")
     return H, b1
+
+
+def matvec_jm(op_n, op_k, x, eps_c, mu_c, h, freq_hz):
+    """The full JMVIE operator of eq. 4 (vie_matvec_jm) on x = [J; M] of shape
+    (2, 3, n3, n2, n1); eps_c, mu_c (n3, n2, n1) of the same dtype."""
+    lib = load()
+    n1, n2, n3 = op_n.n
+    if tuple(x.shape) != (2, 3, n3, n2, n1) or not x.is_contiguous():
+        raise ValueError("x must be contiguous (2, 3, n3, n2, n1)")
+    for t in (eps_c, mu_c):
+        if t.dtype != x.dtype or tuple(t.shape) != (n3, n2, n1) or not t.is_contiguous():
+            raise ValueError("eps_c and mu_c must be contiguous (n3, n2, n1) of the vector dtype")
+    dt = _dt(x)
+    nbytes = lib.vie_jm_workspace_bytes(op_n.handle, op_k.handle, dt)
+    ws = _scratch(nbytes, x.device)
+    y = torch.empty_like(x)
+    _check(lib.vie_matvec_jm(op_n.handle, op_k.handle, dt, float(h), 2.0 * np.pi * float(freq_hz), _ptr(eps_c),
+                             _ptr(mu_c), _ptr(x), _ptr(y), _ptr(ws), nbytes, _stream()), "vie_matvec_jm")
+    return y
 
 
 def from_tucker(n, cores, factors):
