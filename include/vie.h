@@ -345,6 +345,24 @@ vie_status vie_matvec_jm(const vie_op* op_n, const vie_op* op_k, int dtype, doub
                          const void* mu_c, const void* x, void* y, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * vie_solve_jm -- GMRES(m) for the full JMVIE system of eq. 4,
+ *   A [J; M] = b, one system, A as in vie_matvec_jm.  The right-hand side of
+ *   eq. 1 is b = [c_e chi_e E_inc; c_m chi_h H_inc].  Plain solves only
+ *   (opts->adjoint and opts->refine must be 0: VIE_E_UNSUPPORTED otherwise);
+ *   tol, restart, max_outer as in vie_solve; x0 = 0; every Arnoldi step
+ *   takes two classical Gram-Schmidt passes with FP64 dot products; restart
+ *   on the true residual.
+ *   b, x DEVICE complex [2][3][n3][n2][n1]; eps_c, mu_c DEVICE complex
+ *   [n3][n2][n1]; info (may be NULL) as in vie_solve (refine fields 0);
+ *   ws DEVICE scratch of vie_solve_jm_workspace_bytes bytes.  Returns VIE_OK,
+ *   or VIE_NOT_CONVERGED with x the last iterate.  Synchronises the stream.
+ */
+size_t vie_solve_jm_workspace_bytes(const vie_op* op_n, const vie_op* op_k, int dtype, const vie_solve_opts* opts);
+vie_status vie_solve_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, double omega, const void* eps_c,
+                        const void* mu_c, const void* b, void* x, const vie_solve_opts* opts, vie_solve_info* info,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/*
  * vie_magnetic_field -- H = h_inc + h KJ and |b1+| = mu0 |H_x + i H_y|
  *   (eq. 18) for the polarisation current J of the electric equation, where
  *   KJ = vie_matvec(op_k, VIE_OP_N, J) with op_k from vie_compress_k and h

@@ -163,3 +163,23 @@ def jm_matvec(op_n, op_k, eps_c, mu_c, x, h, freq_hz):
     yJ = eps_c[None] * J - chi_e[None] * apply_N(op_n, J) + ce * h * chi_e[None] * apply_K(op_k, M)
     yM = mu_c[None] * M - chi_h[None] * apply_N(op_n, M) - cm * h * chi_h[None] * apply_K(op_k, J)
     return np.stack([yJ, yM])
+
+
+def jm_rhs(eps_c, mu_c, e_inc, h_inc, freq_hz):
+    """Right-hand side of eq. 1: [c_e chi_e E_inc; c_m chi_h H_inc]."""
+    from vie_inputs.constants import EPS0, omega
+    ce = 1j * omega(freq_hz) * EPS0
+    cm = 1j * omega(freq_hz) * MU0
+    return np.stack([ce * (np.asarray(eps_c) - 1.0)[None] * e_inc, cm * (np.asarray(mu_c) - 1.0)[None] * h_inc])
+
+
+def solve_jm(op_n, op_k, eps_c, mu_c, b, h, freq_hz, tol=1e-8, restart=50, max_outer=200):
+    """GMRES on the full JMVIE system of eq. 4 (the oracle's GMRES)."""
+    from .gmres import gmres
+    shape = b.shape
+
+    def A(v):
+        return jm_matvec(op_n, op_k, eps_c, mu_c, v.reshape(shape), h, freq_hz).ravel()
+
+    x, info = gmres(A, b, tol=tol, restart=restart, max_outer=max_outer)
+    return x.reshape(shape), info

@@ -85,6 +85,9 @@ _SIGS = {
     "vie_jm_workspace_bytes": (ctypes.c_size_t, [_P, _P, ctypes.c_int]),
     "vie_matvec_jm": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P,
                                      ctypes.c_size_t, _P]),
+    "vie_solve_jm_workspace_bytes": (ctypes.c_size_t, [_P, _P, ctypes.c_int, ctypes.POINTER(SolveOpts)]),
+    "vie_solve_jm": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P,
+                                    ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P, ctypes.c_size_t, _P]),
     "vie_magnetic_field": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
     "vie_op_from_tucker": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _P, _P,
                                           ctypes.POINTER(_P), ctypes.POINTER(CompressInfo)]),
@@ -306,6 +309,37 @@ def matvec_jm(op_n, op_k, x, eps_c, mu_c, h, freq_hz):
     _check(lib.vie_matvec_jm(op_n.handle, op_k.handle, dt, float(h), 2.0 * np.pi * float(freq_hz), _ptr(eps_c),
                              _ptr(mu_c), _ptr(x), _ptr(y), _ptr(ws), nbytes, _stream()), "vie_matvec_jm")
     return y
+
+
+def solve_jm(op_n, op_k, b, eps_c, mu_c, h, freq_hz, tol=1e-6, restart=50, max_outer=200, history=64):
+    """GMRES for the full JMVIE system of eq. 4 (vie_solve_jm): b and the
+    solution have shape (2, 3, n3, n2, n1) ([J; M]).  Returns (x, info dict,
+    status)."""
+    lib = load()
+    n1, n2, n3 = op_n.n
+    if tuple(b.shape) != (2, 3, n3, n2, n1) or not b.is_contiguous():
+        raise ValueError("b must be contiguous (2, 3, n3, n2, n1)")
+    for t in (eps_c, mu_c):
+        if t.dtype != b.dtype or tuple(t.shape) != (n3, n2, n1) or not t.is_contiguous():
+            raise ValueError("eps_c and mu_c must be contiguous (n3, n2, n1) of the vector dtype")
+    dt = _dt(b)
+    opts = SolveOpts(float(tol), int(restart), int(max_outer), 0, 0, VIE_RECON_FP32, 1e-4)
+    nbytes = lib.vie_solve_jm_workspace_bytes(op_n.handle, op_k.handle, dt, ctypes.byref(opts))
+    if nbytes == 0:
+        raise VieError(VIE_E_ARG, "vie_solve_jm_workspace_bytes rejected the options")
+    ws = _scratch(nbytes, b.device)
+    x = torch.empty_like(b)
+    hist = np.zeros(max(1, int(history)))
+    info = SolveInfo()
+    info.history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    info.hist_cap = int(history)
+    st = lib.vie_solve_jm(op_n.handle, op_k.handle, dt, float(h), 2.0 * np.pi * float(freq_hz), _ptr(eps_c),
+                          _ptr(mu_c), _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(info), _ptr(ws), nbytes,
+                          _stream())
+    _check(st, "vie_solve_jm")
+    d = {"matvecs": info.matvecs, "restarts": info.restarts, "converged": bool(info.converged),
+         "rel_residual": info.rel_residual, "history": hist[:info.hist_len].tolist()}
+    return x, d, st
 
 
 def from_tucker(n, cores, factors):

@@ -15,7 +15,8 @@
   includes the 1e-6 truncation);
 * K operators reject the calls they do not support;
 * the full JMVIE operator of eq. 4 (N and K products of [J; M] combined
-  with electric and magnetic contrasts) against the oracle's."""
+  with electric and magnetic contrasts) against the oracle's, and its GMRES
+  solve on a sphere with both contrasts against the oracle's solve."""
 import numpy as np
 import pytest
 import torch
@@ -207,3 +208,38 @@ def test_jm_matvec_matches_oracle(n):
             err = rel(y[blk], yo[blk])
             say("   ", dt, "block", blk, "rel err", err)
             assert err <= bound
+
+
+def test_jm_solve_magnetic_sphere_matches_oracle():
+    # the full JMVIE system with both contrasts: a sphere with eps_r 52,
+    # sigma 0.55 S/m and mu_r = 2 - 0.2i (synthetic magnetic material),
+    # x-polarised plane wave; library GMRES against the oracle's GMRES
+    n = (12, 12, 12)
+    h = 0.005
+    G = vi.green_tensor(n, h, K0)
+    kt = vi.green_k_tensor(n, h, K0)
+    er, sg, _ = vi.sphere_phantom(n, h, 0.4 * 12 * h, 52.0, 0.55)
+    eps_c = vi.complex_permittivity(er, sg, F)
+    mu_c = np.where(er > 1, 2.0 - 0.2j, 1.0 + 0j)
+    b = mg.jm_rhs(eps_c, mu_c, vi.plane_wave(n, h, F), vi.plane_wave_h(n, h, F), F)
+    refn, refk = opm.tucker_operator(G, 1e-10), mg.tucker_k_operator(kt, 1e-10)
+    xo, _ = mg.solve_jm(refn, refk, eps_c, mu_c, b, h, F, tol=1e-11)
+    opn, opk = vie.compress(G, tol=1e-10), vie.compress_k(kt, tol=1e-10)
+    x, info, st = vie.solve_jm(opn, opk, to_dev(b, torch.complex128), to_dev(eps_c, torch.complex128),
+                               to_dev(mu_c, torch.complex128), h, F, tol=1e-11)
+    assert st == 0 and info["converged"]
+    xh = x.cpu().numpy()
+    res = rel(mg.jm_matvec(refn, refk, eps_c, mu_c, xh, h, F), b)
+    say("   JM solve: %d matvecs, oracle residual %.3e" % (info["matvecs"], res))
+    assert res <= 1e-10
+    for blk in range(2):
+        err = rel(xh[blk], xo[blk])
+        say("   block", blk, "rel diff to the oracle's solution", err)
+        assert err <= 1e-8
+    # complex64: plain FP32 GMRES to 1e-5
+    x32, i32, st32 = vie.solve_jm(opn, opk, to_dev(b, torch.complex64), to_dev(eps_c, torch.complex64),
+                                  to_dev(mu_c, torch.complex64), h, F, tol=1e-5)
+    assert st32 == 0
+    r32 = rel(mg.jm_matvec(refn, refk, eps_c, mu_c, x32.cpu().numpy().astype(np.complex128), h, F), b)
+    say("   complex64 JM solve: %d matvecs, oracle residual %.3e" % (i32["matvecs"], r32))
+    assert r32 <= 2e-5

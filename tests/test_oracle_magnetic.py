@@ -242,3 +242,20 @@ def test_jm_duality():
     # and the coupling is really exercised: K M moves y_J
     y0 = mg.jm_matvec(opn, opk, eps_c, mu_c, np.stack([x[0], 0 * x[1]]), h, f)
     assert np.linalg.norm(y0[0] - y[0]) > 1e-6 * np.linalg.norm(y[0])
+
+
+def test_jm_solve_without_magnetic_contrast_is_the_electric_solve():
+    # chi_h = 0: M = 0 solves the second block row, and J solves the electric
+    # equation of the electric-only path
+    from oracle import operator as opm, physics
+    n = (6, 5, 4)
+    h = 0.005
+    f, G, kt, eps_c, _, _ = _jm_problem(n, h, 14)
+    mu_c = np.ones_like(eps_c)
+    opn, opk = opm.dense_operator(G), mg.dense_k_operator(kt)
+    e_inc = vi.plane_wave(n, h, f)
+    b = mg.jm_rhs(eps_c, mu_c, e_inc, vi.plane_wave_h(n, h, f), f)
+    x, info = mg.solve_jm(opn, opk, eps_c, mu_c, b, h, f, tol=1e-11)
+    u, _ = physics.solve_currents(opn, eps_c, e_inc, f, tol=1e-11)
+    assert np.linalg.norm(x[1]) <= 1e-9 * np.linalg.norm(x[0])
+    assert np.linalg.norm(x[0] - u) <= 1e-8 * np.linalg.norm(u)
