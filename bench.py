@@ -484,7 +484,26 @@ def magnetic_leg(n, h, f, k0, x_sol, opn_for_jm, args, vie, torch, dev):
     torch.cuda.synchronize()
     out["ms_per_jm_matvec"] = ev0.elapsed_time(ev1) / args.steps
     log("JM matvec (eq. 4, N and K on [J; M] + combine): %.3f ms" % out["ms_per_jm_matvec"])
-    del xj, yj, eps_c, mu_c
+    del xj, yj
+    if not args.no_solve:
+        # the JM system with this magnetic contrast, plane-wave excitation,
+        # complex64 GMRES(50) to 1e-5 (at most 10 cycles)
+        ce = 1j * 2 * np.pi * f * vie.EPS0
+        cm = 1j * 2 * np.pi * f * vie.MU0
+        e_inc = torch.from_numpy(vi.plane_wave(n, h, f).astype(np.complex64)).to(dev)
+        h_inc = torch.from_numpy(vi.plane_wave_h(n, h, f).astype(np.complex64)).to(dev)
+        bj = torch.stack([ce * (eps_c - 1)[None] * e_inc, cm * (mu_c - 1)[None] * h_inc]).contiguous()
+        del e_inc, h_inc
+        torch.cuda.synchronize()
+        t0 = time.time()
+        xs, info, st_ = vie.solve_jm(opn_for_jm, opk, bj, eps_c, mu_c, h, f, tol=1e-5, restart=50, max_outer=10)
+        torch.cuda.synchronize()
+        out["jm_solve_complex64"] = {"seconds": time.time() - t0, "converged": info["converged"],
+                                     "matvecs": info["matvecs"], "rel_residual": info["rel_residual"],
+                                     "tol": 1e-5}
+        log("JM solve (complex64, tol 1e-5): %.2f s, %s" % (out["jm_solve_complex64"]["seconds"], info))
+        del xs, bj
+    del eps_c, mu_c
     if x_sol is not None:
         hinc = torch.from_numpy(vi.plane_wave_h(n, h, f)).to(dev)
         torch.cuda.synchronize()
