@@ -91,7 +91,7 @@ static void tournament_pairs(int m, int r, std::vector<std::pair<int, int>>& out
 // Left singular vectors (columns of U, m x m, row-major U[i*m + col]) and
 // singular values (descending) of Y (m x N row-major).  `refine` selects the
 // one-sided Jacobi pass on Z = Q^H Y after the Gram eigen-decomposition.
-void svd_left(const cd* Y, int m, long N, std::vector<cd>& U, std::vector<double>& s, bool refine)
+void svd_left(const cd* Y, int m, long N, std::vector<cd>& U, std::vector<double>& s, bool refine, double floor)
 {
     // Gram matrix G = Y Y^H: column chunks in parallel, each thread keeps a
     // private m x m accumulator (upper triangle), summed at the end
@@ -204,6 +204,10 @@ void svd_left(const cd* Y, int m, long N, std::vector<cd>& U, std::vector<double
         double amax = 0;
         for (int i = 0; i < m; ++i) amax = std::max(amax, nrm[i]);
         const double negligible = 1e-24 * amax;
+        // rows count as orthogonal once their cosine is within the rounding
+        // of a length-N dot product (a fixed 4e-16 never settles on long rows)
+        const double rot_eps = 4e-16 * std::max(1.0, std::sqrt((double)N) / 8.0);
+        const double skip_one = floor * amax;
         std::vector<std::pair<int, int>> pairs;
         for (int sweep = 0; sweep < 30 && m > 1; ++sweep) {
             std::atomic<int> rotated(0);
@@ -213,13 +217,14 @@ void svd_left(const cd* Y, int m, long N, std::vector<cd>& U, std::vector<double
                 parallel_for((long)pairs.size(), [&](long b, long e) {
                     for (long t = b; t < e; ++t) {
                         int p = pairs[t].first, q = pairs[t].second;
+                        double a = nrm[p], bb = nrm[q];
+                        if (a < negligible && bb < negligible) continue;
+                        if (a < skip_one || bb < skip_one) continue;
                         cd* zp = &Z[(size_t)p * N];
                         cd* zq = &Z[(size_t)q * N];
                         cd c = 0;
                         for (long n = 0; n < N; ++n) c += zp[n] * std::conj(zq[n]);
-                        double a = nrm[p], bb = nrm[q];
-                        if (a < negligible && bb < negligible) continue;
-                        if (std::abs(c) <= 4e-16 * std::sqrt(a * bb) || std::abs(c) == 0.0) continue;
+                        if (std::abs(c) <= rot_eps * std::sqrt(a * bb) || std::abs(c) == 0.0) continue;
                         rotated.fetch_add(1);
                         double cs, sn;
                         cd ph;
@@ -326,8 +331,13 @@ int hosvd_component(const cd* A, const int n[3], double tol, int rule, int max_r
         // the Gram eigenvectors resolve singular values down to ~1e-8 sigma_max;
         // the Jacobi refinement restores full accuracy when a tight tolerance
         // needs it (and always for small unfoldings, where it is cheap)
-        bool refine = tol < 1e-7 || (long)m * V <= (long)1 << 24;
-        svd_left(Y.data(), m, V / m, Ufull, s, refine);
+        const bool small = (long)m * V <= (long)1 << 24;
+        bool refine = tol < 1e-7 || small;
+        // on large unfoldings, rows far below the truncation level (squared
+        // norm under (1e-3 tol)^2 of the largest: together less than 1e-6 of
+        // the allowed tail) are left out of the rotations
+        const double floor = small ? 0.0 : (1e-3 * tol) * (1e-3 * tol);
+        svd_left(Y.data(), m, V / m, Ufull, s, refine, floor);
         int r = truncation_rank(s, tol, rule, fro);
         int status = 0;
         if (max_rank > 0 && r > max_rank) {

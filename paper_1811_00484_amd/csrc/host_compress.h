@@ -17,9 +17,13 @@ struct TuckerComponent {
 int host_threads();
 
 // Left singular vectors (U, m x m row-major, columns by descending singular
-// value) and singular values of a row-major m x N matrix, m <= N.
+// value) and singular values of a row-major m x N matrix, m <= N.  With
+// `refine`, one-sided Jacobi sweeps on Z = Q^H Y restore full accuracy;
+// floor > 0 leaves out every rotation that involves a row of squared norm
+// below floor * (largest), whose value then stays the row norm (used where
+// such rows cannot change a rank decision).
 void svd_left(const std::complex<double>* Y, int m, long N, std::vector<std::complex<double>>& U,
-              std::vector<double>& s, bool refine);
+              std::vector<double>& s, bool refine, double floor = 0.0);
 
 // Truncation rank for one unfolding (rule 0: Frobenius tail; rule 1: sigma cut).
 int truncation_rank(const std::vector<double>& s, double tol, int rule, double fro);
