@@ -333,10 +333,12 @@ int hosvd_component(const cd* A, const int n[3], double tol, int rule, int max_r
         // needs it (and always for small unfoldings, where it is cheap)
         const bool small = (long)m * V <= (long)1 << 24;
         bool refine = tol < 1e-7 || small;
-        // on large unfoldings, rows far below the truncation level (squared
-        // norm under (1e-3 tol)^2 of the largest: together less than 1e-6 of
-        // the allowed tail) are left out of the rotations
-        const double floor = small ? 0.0 : (1e-3 * tol) * (1e-3 * tol);
+        // on very large unfoldings (more than 2^28 entries times m), rows far
+        // below the truncation level (squared norm under (1e-3 tol)^2 of the
+        // largest: together less than 1e-6 of the allowed tail) are left out
+        // of the rotations; the error bound is unchanged, the kept subspace
+        // then differs from the exact SVD's by far less than tol
+        const double floor = (long)m * V > (long)1 << 28 ? (1e-3 * tol) * (1e-3 * tol) : 0.0;
         svd_left(Y.data(), m, V / m, Ufull, s, refine, floor);
         int r = truncation_rank(s, tol, rule, fro);
         int status = 0;
