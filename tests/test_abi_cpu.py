@@ -143,3 +143,19 @@ def test_host_cp_argument_errors():
     g = np.zeros(12 * 64)
     assert lib.vie_compress_cp(n, g.ctypes.data_as(ctypes.c_void_p), None, -1, 0, ctypes.byref(ctypes.c_void_p()),
                                None, None) == vie.VIE_E_ARG
+
+
+def test_magnetic_and_jm_argument_errors():
+    import ctypes
+    vie = _lib()
+    lib = vie.load()
+    p = ctypes.c_void_p
+    assert lib.vie_compress_k(None, None, None, None, None) == vie.VIE_E_ARG
+    n = (ctypes.c_int * 3)(4, 4, 300)
+    g = np.zeros(6 * 4 * 4 * 300)
+    assert lib.vie_compress_k(n, g.ctypes.data_as(p), None, ctypes.byref(p()), None) == vie.VIE_E_UNSUPPORTED
+    assert lib.vie_magnetic_field(None, 0, None, None, 1.0, 1.0, None, None, None) == vie.VIE_E_ARG
+    assert lib.vie_matvec_jm(None, None, 0, 1.0, 1.0, None, None, None, None, None, 0, None) == vie.VIE_E_ARG
+    assert lib.vie_jm_workspace_bytes(None, None, 0) == 0
+    assert lib.vie_solve_jm_workspace_bytes(None, None, 0, None) == 0
+    assert lib.vie_solve_jm(None, None, 0, 1.0, 1.0, None, None, None, None, None, None, None, 0, None) == vie.VIE_E_ARG
