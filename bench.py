@@ -283,23 +283,27 @@ def main():
                        "vector_bytes_c64": 3 * V * 8}
 
     x_sol = None
+    opk = None
     if not args.no_solve:
         extra["solve"], x_sol = solves(op, b, epsc, dev, vie, torch)
     if not args.no_magnetic:
         try:
-            extra["magnetic"] = magnetic_leg(n, h, f, k0, x_sol, op, args, vie, torch, dev)
+            extra["magnetic"], opk = magnetic_leg(n, h, f, k0, x_sol, op, args, vie, torch, dev)
         except Exception as exc:   # the headline line is printed regardless
             log("magnetic leg failed: %r" % (exc,))
             extra["magnetic"] = {"error": repr(exc)}
-        del x_sol
 
     y_cp = None
     if not args.no_cp:
         try:
-            extra["tucker_cp"], y_cp = tucker_cp_leg(G, op, x, e, y32, b, epsc, n, args, vie, torch, dev)
+            extra["tucker_cp"], y_cp = tucker_cp_leg(G, op, x, e, y32, b, epsc, n, args, vie, torch, dev,
+                                                     obs=(x_sol, opk, sg, label, h, f))
         except Exception as exc:   # the headline line is printed regardless
             log("tucker_cp leg failed: %r" % (exc,))
             extra["tucker_cp"] = {"error": repr(exc)}
+    del x_sol
+    if opk is not None:
+        opk.close()
 
     result = {
         "metric": "VIE matvecs/s (256^3 head phantom, Tucker-compressed operator, 1 rhs)",
@@ -365,7 +369,7 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def tucker_cp_leg(G, op_t, x, e, y_t, b, epsc, n, args, vie, torch, dev):
+def tucker_cp_leg(G, op_t, x, e, y_t, b, epsc, n, args, vie, torch, dev, obs=None):
     """The same workload with the Tucker+CP operator (Alg. 2: HOSVD at the
     same tolerance, then CP of each core with R = min r_i terms, 1000 ALS
     sweeps): compression time and fits, operator bytes, matvec time on the
@@ -426,6 +430,30 @@ def tucker_cp_leg(G, op_t, x, e, y_t, b, epsc, n, args, vie, torch, dev):
                                 "rel_residual_fp64": info[0]["rel_residual"], "matvecs_inner": info[0]["matvecs"],
                                 "matvecs_fp64": info[0]["matvecs_fp64"]}
         log("tucker+cp refined solve: %.2f s, %s" % (t, info[0]))
+        x_t, opk, sg, label, h, f = obs if obs is not None else (None,) * 6
+        if x_t is not None and opk is not None:
+            # the observables of eq. 18 from the Tucker+CP solution against the
+            # HOSVD solution (whose operator is within 5e-6 of the dense one):
+            # p_abs = sigma |E|^2 / 2 and |b1+| over the head's voxels
+            import vie_inputs as vi
+            mask = torch.from_numpy(label >= 0).to(dev)
+            sig = torch.from_numpy(sg).to(dev)
+            einc = torch.from_numpy(vi.plane_wave(n, h, f)).to(dev)
+            hinc = torch.from_numpy(vi.plane_wave_h(n, h, f)).to(dev)
+            obs_v = {}
+            for key, o_, xx in (("hosvd", op_t, x_t), ("tucker_cp", op, xs)):
+                E = vie.total_field(o_, einc, xx, vie.matvec(o_, xx, kind="N"), f)
+                p = 0.5 * sig * (E.abs() ** 2).sum(dim=0)
+                _, b1 = vie.magnetic_field(opk, xx, hinc, h)
+                obs_v[key] = (p[mask], b1[mask])
+                del E
+            for i, nm in ((0, "p_abs"), (1, "b1_plus")):
+                a_, r_ = obs_v["tucker_cp"][i], obs_v["hosvd"][i]
+                out[nm + "_rel_l2_err_vs_hosvd"] = float(torch.linalg.vector_norm(a_ - r_) /
+                                                         torch.linalg.vector_norm(r_))
+            log("tucker+cp observables vs HOSVD: p_abs %.3e, |b1+| %.3e"
+                % (out["p_abs_rel_l2_err_vs_hosvd"], out["b1_plus_rel_l2_err_vs_hosvd"]))
+            del obs_v, einc, hinc
         del xs
     op.close()
     return out, y
@@ -516,8 +544,7 @@ def magnetic_leg(n, h, f, k0, x_sol, opn_for_jm, args, vie, torch, dev):
         log("b1+ of the refined solution: %.3f s, |b1+| / incident in [%.3f, %.3f]"
             % (out["b1_seconds_complex128"], out["b1_over_incident"]["min"], out["b1_over_incident"]["max"]))
         del H, b1, hinc
-    opk.close()
-    return out
+    return out, opk
 
 
 def solves(op, b, epsc, dev, vie, torch):
