@@ -17,6 +17,12 @@
  * (the "component decompression" of Sec. V-B, done per pencil, never into a
  * dense buffer).
  *
+ * Beside it: the Tucker+CP form of Alg. 2 / eq. 17 (vie_compress_cp), the
+ * magnetic operator K of eq. 5 as a compressed operator of its own
+ * (vie_compress_k) with the field and |b1+| of eq. 18
+ * (vie_magnetic_field), and the full JMVIE system of eq. 4 with electric
+ * and magnetic contrasts (vie_matvec_jm, vie_solve_jm).
+ *
  * Conventions shared by every call:
  *  - Complex numbers are interleaved (re, im); complex64 = 2 x float,
  *    complex128 = 2 x double.
