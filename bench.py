@@ -34,7 +34,7 @@ def log(*a):
 
 
 # algorithmic complex elements moved per pass and right-hand side, in units
-# of V = n1 n2 n3 (reads + writes, pruned padding; see DESIGN.md)
+# of V = n1 n2 n3 (reads + writes, pruned padding)
 PASS_NAMES = ["x_fwd", "y_fwd", "z_fused", "y_inv", "x_inv"]
 PASS_ELEMS_V = [3 + 6, 6 + 12, 12 + 12, 12 + 6, 6 + 3 + 1 + 3]
 
@@ -152,8 +152,8 @@ def main():
                          "calibrate FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only; --gpus %d is not supported (the path is single-GPU; "
-              "see DESIGN.md for how it would shard)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only; --gpus %d is not supported (the path runs on one GPU; "
+              "no multi-GPU sharding is built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
