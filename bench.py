@@ -553,7 +553,21 @@ def magnetic_leg(n, h, f, k0, x_sol, opn_for_jm, args, vie, torch, dev):
                                      "matvecs": info["matvecs"], "rel_residual": info["rel_residual"],
                                      "tol": 1e-5}
         log("JM solve (complex64, tol 1e-5): %.2f s, %s" % (out["jm_solve_complex64"]["seconds"], info))
-        del xs, bj
+        del xs
+        # refined: complex128 vectors, FP32 products in the Arnoldi steps,
+        # FP64 restart residuals, to 1e-6
+        e64, m64 = eps_c.to(torch.complex128), mu_c.to(torch.complex128)
+        b64 = bj.to(torch.complex128)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        xs, info, st_ = vie.solve_jm(opn_for_jm, opk, b64, e64, m64, h, f, tol=1e-6, restart=30, max_outer=30,
+                                     refine=True, inner_tol=1e-5)
+        torch.cuda.synchronize()
+        out["jm_solve_refined"] = {"seconds": time.time() - t0, "converged": info["converged"],
+                                   "matvecs_fp32_products": info["matvecs"], "matvecs_fp64": info["matvecs_fp64"],
+                                   "rel_residual": info["rel_residual"], "tol": 1e-6}
+        log("JM solve (refined, tol 1e-6): %.2f s, %s" % (out["jm_solve_refined"]["seconds"], info))
+        del xs, bj, b64, e64, m64
     del eps_c, mu_c
     if x_sol is not None:
         hinc = torch.from_numpy(vi.plane_wave_h(n, h, f)).to(dev)

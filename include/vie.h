@@ -353,13 +353,18 @@ vie_status vie_matvec_jm(const vie_op* op_n, const vie_op* op_k, int dtype, doub
 /*
  * vie_solve_jm -- GMRES(m) for the full JMVIE system of eq. 4,
  *   A [J; M] = b, one system, A as in vie_matvec_jm.  The right-hand side of
- *   eq. 1 is b = [c_e chi_e E_inc; c_m chi_h H_inc].  Plain solves only
- *   (opts->adjoint and opts->refine must be 0: VIE_E_UNSUPPORTED otherwise);
- *   tol, restart, max_outer as in vie_solve; x0 = 0; every Arnoldi step
- *   takes two classical Gram-Schmidt passes with FP64 dot products; restart
- *   on the true residual.
+ *   eq. 1 is b = [c_e chi_e E_inc; c_m chi_h H_inc].  Forward solves only
+ *   (opts->adjoint = 1 gives VIE_E_UNSUPPORTED); tol, restart, max_outer as
+ *   in vie_solve; x0 = 0; every Arnoldi step takes two classical
+ *   Gram-Schmidt passes with FP64 dot products; restart on the true residual.
+ *   opts->refine = 1 (VIE_C128 vectors, else VIE_E_ARG): the Arnoldi steps
+ *   apply the operator with its N and K products computed in FP32, each
+ *   cycle asks for a relative reduction opts->inner_tol, and the restart
+ *   residual uses the FP64 operator, so the solve reaches FP64 accuracy
+ *   (info->matvecs counts the FP32-product applications, matvecs_fp64 the
+ *   residuals, refine_steps the cycles).
  *   b, x DEVICE complex [2][3][n3][n2][n1]; eps_c, mu_c DEVICE complex
- *   [n3][n2][n1]; info (may be NULL) as in vie_solve (refine fields 0);
+ *   [n3][n2][n1]; info (may be NULL) as in vie_solve;
  *   ws DEVICE scratch of vie_solve_jm_workspace_bytes bytes.  Returns VIE_OK,
  *   or VIE_NOT_CONVERGED with x the last iterate.  Synchronises the stream.
  */

@@ -83,9 +83,17 @@ vie_status run_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, d
         hipError_t er = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st);
         return er == hipSuccess ? hipStreamSynchronize(st) : er;
     };
-    auto apply = [&](const c2<TK>* in, c2<TK>* out) {
-        return vie_matvec_jm(op_n, op_k, dtype, h, omega, eps_c, mu_c, in, out, jw, jwb, st);
+    // refinement (o.refine, complex128 vectors): the Arnoldi steps use the
+    // operator with FP32 products, the restart residual the FP64 one
+    const bool refine = o.refine && sizeof(TK) == 8;
+    auto apply_prec = [&](const c2<TK>* in, c2<TK>* out, bool mixed) {
+        jm_mixed_products = mixed;
+        vie_status r = vie_matvec_jm(op_n, op_k, dtype, h, omega, eps_c, mu_c, in, out, jw, jwb, st);
+        jm_mixed_products = false;
+        return r;
     };
+    auto apply = [&](const c2<TK>* in, c2<TK>* out) { return apply_prec(in, out, false); };
+    auto apply_inner = [&](const c2<TK>* in, c2<TK>* out) { return apply_prec(in, out, refine); };
     const int zero = 0;
     if ((e = hipMemcpyAsync(dmap, &zero, sizeof(int), hipMemcpyHostToDevice, st)) != hipSuccess)
         return hip_fail(e, "vie_solve_jm map");
@@ -113,7 +121,8 @@ vie_status run_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, d
         // true residual R = b - A x
         vie_status s = apply(x, R);
         if (s != VIE_OK) return s;
-        inf.matvecs++;
+        if (refine) inf.matvecs_fp64++;
+        else inf.matvecs++;
         if ((e = kr_residual<TK>(R, b, n, n, dmap, 1, st)) != hipSuccess) return hip_fail(e, "residual");
         if ((e = kr_norm2<TK>(R, 0, n, n, dmap, 1, partial, dnrm, st)) != hipSuccess) return hip_fail(e, "norm");
         if ((e = sync_copy(&hn, dnrm, sizeof(hn))) != hipSuccess) return hip_fail(e, "norm copy");
@@ -134,7 +143,7 @@ vie_status run_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, d
         int k = 0;
         for (int j = 0; j < m; ++j) {
             const long wo = (long)(j + 1) * n;
-            if ((s = apply(V + (long)j * n, V + wo)) != VIE_OK) return s;
+            if ((s = apply_inner(V + (long)j * n, V + wo)) != VIE_OK) return s;
             inf.matvecs++;
             // two classical Gram-Schmidt passes; the first also returns ||w||^2
             e = kr_mdot<TK>(V, n, n, j + 2, V, wo, n, dmap, 1, partial, dh1, st);
@@ -183,7 +192,9 @@ vie_status run_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, d
                 g[j] = c * g[j];
             }
             k = j + 1;
-            if (std::abs(g[j + 1]) <= 0.5 * o.tol * bnorm || hj1 == 0.0) break;
+            // refinement: each cycle asks for a relative reduction inner_tol
+            const double stop = refine ? std::max(o.inner_tol * beta, 0.5 * o.tol * bnorm) : 0.5 * o.tol * bnorm;
+            if (std::abs(g[j + 1]) <= stop || hj1 == 0.0) break;
         }
         // y = H(0:k, 0:k)^-1 g(0:k), x += V y
         std::vector<c2<double>> y(k);
@@ -199,6 +210,7 @@ vie_status run_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, d
             return hip_fail(e, "update");
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "update");
         inf.restarts++;
+        if (refine) inf.refine_steps++;
     }
     if (info) *info = inf;
     return status;
@@ -238,8 +250,10 @@ vie_status vie_solve_jm(const vie_op* op_n, const vie_op* op_k, int dtype, doubl
     if (opts) o = *opts;
     if (!(o.tol > 0) || o.restart < 1 || o.restart > 200 || o.max_outer < 0)
         return fail(VIE_E_ARG, "vie_solve_jm: bad options");
-    if (o.adjoint || o.refine) return fail(VIE_E_UNSUPPORTED, "vie_solve_jm: plain forward solves only");
+    if (o.adjoint) return fail(VIE_E_UNSUPPORTED, "vie_solve_jm: forward solves only");
     if (dtype != VIE_C64 && dtype != VIE_C128) return fail(VIE_E_ARG, "vie_solve_jm: bad dtype");
+    if (o.refine && (dtype != VIE_C128 || !(o.inner_tol > 0 && o.inner_tol < 1)))
+        return fail(VIE_E_ARG, "vie_solve_jm: refinement needs VIE_C128 vectors and inner_tol in (0, 1)");
     if (ws_bytes < vie_solve_jm_workspace_bytes(op_n, op_k, dtype, &o))
         return fail(VIE_E_ARG, "vie_solve_jm: workspace too small");
     if (info && info->history && info->hist_cap < 0) return fail(VIE_E_ARG, "vie_solve_jm: bad history capacity");

@@ -18,6 +18,7 @@
 namespace vie {
 
 thread_local std::string g_last_error;
+thread_local bool jm_mixed_products = false;
 
 vie_status fail(vie_status st, const std::string& msg)
 {
@@ -580,10 +581,24 @@ vie_status vie_matvec_jm(const vie_op* op_n, const vie_op* op_k, int dtype, doub
     void* mw = w + 2 * align_up256(vec);
     const size_t mb = ws_bytes - 2 * align_up256(vec);
     // [J; M] as two right-hand sides of each operator
-    vie_status st = matvec_common(op_n, MODE_N, dtype, VIE_RECON_AUTO, nullptr, x, NX, 2, mw, mb, stream, nullptr);
-    if (st != VIE_OK) return st;
-    st = matvec_common(op_k, MODE_N, dtype, VIE_RECON_AUTO, nullptr, x, KX, 2, mw, mb, stream, nullptr);
-    if (st != VIE_OK) return st;
+    vie_status st;
+    if (jm_mixed_products && dtype == VIE_C128) {
+        // FP64 vectors, products computed in FP32 (the inner operator of a
+        // refined solve)
+        std::string err;
+        hipError_t he = launch_matvec<double, float>(op_n->d, MODE_N, 0, nullptr, (const c2<double>*)x,
+                                                     (c2<double>*)NX, 2, (c2<float>*)mw, (hipStream_t)stream,
+                                                     nullptr, err);
+        if (he == hipSuccess)
+            he = launch_matvec<double, float>(op_k->d, MODE_N, 0, nullptr, (const c2<double>*)x, (c2<double>*)KX, 2,
+                                              (c2<float>*)mw, (hipStream_t)stream, nullptr, err);
+        if (he != hipSuccess) return err.empty() ? hip_fail(he, "vie_matvec_jm") : fail(VIE_E_UNSUPPORTED, err);
+    } else {
+        st = matvec_common(op_n, MODE_N, dtype, VIE_RECON_AUTO, nullptr, x, NX, 2, mw, mb, stream, nullptr);
+        if (st != VIE_OK) return st;
+        st = matvec_common(op_k, MODE_N, dtype, VIE_RECON_AUTO, nullptr, x, KX, 2, mw, mb, stream, nullptr);
+        if (st != VIE_OK) return st;
+    }
     const double EPS0 = 8.8541878128e-12, C0 = 299792458.0;
     const double MU0 = 1.0 / (EPS0 * C0 * C0);
     hipError_t e;

@@ -150,6 +150,11 @@ struct InstHost {
 // matvec modes
 enum { MODE_A = 0, MODE_AH = 1, MODE_N = 2, MODE_NH = 3 };
 
+// Set by the refined JM solve around its inner operator applications: the
+// N and K products of vie_matvec_jm then run in FP32 on FP64 vectors
+// (per host thread).
+extern thread_local bool jm_mixed_products;
+
 // Launch the five-pass matvec.  TV: vector element type, T: compute type.
 // recon: 0 = same as T, 1 = BF16 (T = float only).
 template <typename TV, typename T>

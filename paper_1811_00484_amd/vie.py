@@ -311,10 +311,12 @@ def matvec_jm(op_n, op_k, x, eps_c, mu_c, h, freq_hz):
     return y
 
 
-def solve_jm(op_n, op_k, b, eps_c, mu_c, h, freq_hz, tol=1e-6, restart=50, max_outer=200, history=64):
+def solve_jm(op_n, op_k, b, eps_c, mu_c, h, freq_hz, tol=1e-6, restart=50, max_outer=200, history=64,
+             refine=False, inner_tol=1e-5):
     """GMRES for the full JMVIE system of eq. 4 (vie_solve_jm): b and the
-    solution have shape (2, 3, n3, n2, n1) ([J; M]).  Returns (x, info dict,
-    status)."""
+    solution have shape (2, 3, n3, n2, n1) ([J; M]).  ``refine`` (complex128
+    only): FP32 products in the Arnoldi steps, FP64 restart residuals.
+    Returns (x, info dict, status)."""
     lib = load()
     n1, n2, n3 = op_n.n
     if tuple(b.shape) != (2, 3, n3, n2, n1) or not b.is_contiguous():
@@ -323,7 +325,8 @@ def solve_jm(op_n, op_k, b, eps_c, mu_c, h, freq_hz, tol=1e-6, restart=50, max_o
         if t.dtype != b.dtype or tuple(t.shape) != (n3, n2, n1) or not t.is_contiguous():
             raise ValueError("eps_c and mu_c must be contiguous (n3, n2, n1) of the vector dtype")
     dt = _dt(b)
-    opts = SolveOpts(float(tol), int(restart), int(max_outer), 0, 0, VIE_RECON_FP32, 1e-4)
+    opts = SolveOpts(float(tol), int(restart), int(max_outer), 0, int(bool(refine)), VIE_RECON_FP32,
+                     float(inner_tol))
     nbytes = lib.vie_solve_jm_workspace_bytes(op_n.handle, op_k.handle, dt, ctypes.byref(opts))
     if nbytes == 0:
         raise VieError(VIE_E_ARG, "vie_solve_jm_workspace_bytes rejected the options")
@@ -337,7 +340,8 @@ def solve_jm(op_n, op_k, b, eps_c, mu_c, h, freq_hz, tol=1e-6, restart=50, max_o
                           _ptr(mu_c), _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(info), _ptr(ws), nbytes,
                           _stream())
     _check(st, "vie_solve_jm")
-    d = {"matvecs": info.matvecs, "restarts": info.restarts, "converged": bool(info.converged),
+    d = {"matvecs": info.matvecs, "matvecs_fp64": info.matvecs_fp64, "restarts": info.restarts,
+         "refine_steps": info.refine_steps, "converged": bool(info.converged),
          "rel_residual": info.rel_residual, "history": hist[:info.hist_len].tolist()}
     return x, d, st
 

@@ -236,6 +236,17 @@ def test_jm_solve_magnetic_sphere_matches_oracle():
         err = rel(xh[blk], xo[blk])
         say("   block", blk, "rel diff to the oracle's solution", err)
         assert err <= 1e-8
+    # refined: FP32 products in the Arnoldi steps, FP64 restart residuals
+    xr, ir, str_ = vie.solve_jm(opn, opk, to_dev(b, torch.complex128), to_dev(eps_c, torch.complex128),
+                                to_dev(mu_c, torch.complex128), h, F, tol=1e-10, refine=True, inner_tol=1e-5)
+    assert str_ == 0 and ir["converged"] and ir["matvecs_fp64"] >= 2 and ir["refine_steps"] >= 1
+    xrh = xr.cpu().numpy()
+    rr = rel(mg.jm_matvec(refn, refk, eps_c, mu_c, xrh, h, F), b)
+    say("   refined JM solve: %d FP32-product + %d FP64 matvecs, oracle residual %.3e"
+        % (ir["matvecs"], ir["matvecs_fp64"], rr))
+    assert rr <= 1.01e-10
+    for blk in range(2):
+        assert rel(xrh[blk], xo[blk]) <= 1e-8
     # complex64: plain FP32 GMRES to 1e-5
     x32, i32, st32 = vie.solve_jm(opn, opk, to_dev(b, torch.complex64), to_dev(eps_c, torch.complex64),
                                   to_dev(mu_c, torch.complex64), h, F, tol=1e-5)
