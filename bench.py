@@ -7,8 +7,17 @@ side (the x-polarised plane-wave excitation).  A step is one application of
 the full operator A = M_eps - M_chi N (all five passes).  Prints one JSON
 line on stdout; progress goes to stderr.
 
+Beside the headline the line carries: the HIP-graph replay, the BF16
+reconstruction, the dense-spectrum (uncompressed) matvec and solve, the
+refined and plain solves, the Tucker+CP operator (compression, matvec,
+solve, accuracy and the observables of eq. 18 against the HOSVD solution),
+the magnetic operator K with |b1+| and the coupled JMVIE operator and
+solves, and the FP64 oracle timed on the host (cpu_baseline).
+
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--grid 256]
                     [--no-dense] [--no-solve] [--no-cpu-baseline] [--no-cp]
+                    [--no-magnetic] [--batch-workload] [--grad-workload]
+                    [--copy-calibration]
 """
 import argparse
 import glob
