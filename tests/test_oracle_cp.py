@@ -69,3 +69,29 @@ def test_tucker_cp_error_bound_and_factor_algebra():
     s = circulant.axis_signs(0)
     assert np.allclose(cp.fourier_tensor_cp(Ws, s), circulant.fourier_tensor_dense(Atcp, s),
                        atol=1e-11 * np.abs(Atcp).sum())
+
+
+def test_tucker_cp_operator_exact_on_cp_tensors():
+    # defining tensors that are exactly of CP rank 2 (each component with its
+    # parity: zero at offset 0 along its odd axes): the Tucker+CP operator of
+    # Alg. 2 / eq. 17 reproduces the dense operator's product
+    from oracle import circulant, operator as opm
+    rng = np.random.default_rng(9)
+    n = (6, 5, 4)
+    green = np.zeros((6, n[2], n[1], n[0]), complex)
+    for c in range(6):
+        signs = circulant.axis_signs(c)
+        Vs = []
+        for a in range(3):
+            V = _cplx(rng, (n[a], 2))
+            if signs[a] < 0:
+                V[0, :] = 0
+            Vs.append(V)
+        green[c] = tucker.to_storage(cp.cp_reconstruct(Vs))
+    dense = opm.dense_operator(green)
+    op = opm.tucker_cp_operator(green, 1e-12, R=2, iters=300)
+    assert max(op.cp_rel_err) <= 1e-9
+    u = vi.random_field(n, 3)
+    y = opm.apply_N(op, u)
+    yd = opm.apply_N(dense, u)
+    assert np.linalg.norm(y - yd) <= 1e-8 * np.linalg.norm(yd)
