@@ -93,42 +93,44 @@ static void tournament_pairs(int m, int r, std::vector<std::pair<int, int>>& out
 // one-sided Jacobi pass on Z = Q^H Y after the Gram eigen-decomposition.
 void svd_left(const cd* Y, int m, long N, std::vector<cd>& U, std::vector<double>& s, bool refine, double floor)
 {
-    // Gram matrix G = Y Y^H: column chunks in parallel, each thread keeps a
-    // private m x m accumulator (upper triangle), summed at the end
+    // Gram matrix G = Y Y^H.  The columns are cut into chunks of CH and the
+    // chunks into NG contiguous groups whose count does not depend on the
+    // thread count; each group is summed chunk by chunk in order into its
+    // own m x m accumulator (upper triangle) by one thread, and the groups
+    // are then added in group order.  The rounding is therefore the same
+    // for any number of threads.
     const long CH = 512;
     long nch = (N + CH - 1) / CH;
-    int nt = std::max(1, std::min<int>(host_threads(), (int)nch));
-    std::vector<std::vector<cd>> part(nt, std::vector<cd>((size_t)m * m, cd(0)));
-    {
-        std::vector<std::thread> th;
-        for (int t = 0; t < nt; ++t)
-            th.emplace_back([&, t]() {
-                std::vector<cd>& P = part[t];
-                for (long c = t; c < nch; c += nt) {
-                    long b = c * CH, e = std::min(N, b + CH);
-                    for (int i = 0; i < m; ++i) {
-                        const cd* yi = Y + (size_t)i * N;
-                        for (int j = i; j < m; ++j) {
-                            const cd* yj = Y + (size_t)j * N;
-                            double re = 0, im = 0;
-                            for (long n = b; n < e; ++n) {
-                                double ar = yi[n].real(), ai = yi[n].imag();
-                                double br = yj[n].real(), bi = yj[n].imag();
-                                re += ar * br + ai * bi;
-                                im += ai * br - ar * bi;
-                            }
-                            P[(size_t)i * m + j] += cd(re, im);
+    const int NG = (int)std::min<long>(16, nch);
+    std::vector<std::vector<cd>> part(NG, std::vector<cd>((size_t)m * m, cd(0)));
+    parallel_for(NG, [&](long gb, long ge) {
+        for (long g = gb; g < ge; ++g) {
+            std::vector<cd>& P = part[g];
+            const long c0 = g * nch / NG, c1 = (g + 1) * nch / NG;
+            for (long c = c0; c < c1; ++c) {
+                long b = c * CH, e = std::min(N, b + CH);
+                for (int i = 0; i < m; ++i) {
+                    const cd* yi = Y + (size_t)i * N;
+                    for (int j = i; j < m; ++j) {
+                        const cd* yj = Y + (size_t)j * N;
+                        double re = 0, im = 0;
+                        for (long n = b; n < e; ++n) {
+                            double ar = yi[n].real(), ai = yi[n].imag();
+                            double br = yj[n].real(), bi = yj[n].imag();
+                            re += ar * br + ai * bi;
+                            im += ai * br - ar * bi;
                         }
+                        P[(size_t)i * m + j] += cd(re, im);
                     }
                 }
-            });
-        for (auto& t : th) t.join();
-    }
+            }
+        }
+    });
     std::vector<cd> G((size_t)m * m);
     for (int i = 0; i < m; ++i)
         for (int j = i; j < m; ++j) {
             cd acc = 0;
-            for (int t = 0; t < nt; ++t) acc += part[t][(size_t)i * m + j];
+            for (int g = 0; g < NG; ++g) acc += part[g][(size_t)i * m + j];
             G[(size_t)i * m + j] = acc;
             G[(size_t)j * m + i] = std::conj(acc);
         }

@@ -159,3 +159,35 @@ def test_magnetic_and_jm_argument_errors():
     assert lib.vie_jm_workspace_bytes(None, None, 0) == 0
     assert lib.vie_solve_jm_workspace_bytes(None, None, 0, None) == 0
     assert lib.vie_solve_jm(None, None, 0, 1.0, 1.0, None, None, None, None, None, None, None, 0, None) == vie.VIE_E_ARG
+
+
+def test_host_hosvd_is_independent_of_the_thread_count():
+    # the Gram sums of the host SVD are grouped independently of the number
+    # of host threads, so the compression is bitwise the same on any machine
+    vie = _lib()
+    G = vi.green_tensor((64, 48, 40), 0.002, vi.wavenumber(298e6))
+    old = os.environ.get("VIE_NUM_THREADS")
+    results = []
+    try:
+        for nt in ("1", "3", "4", "16"):
+            os.environ["VIE_NUM_THREADS"] = nt
+            results.append([vie.debug_hosvd(G[c], 1e-8) for c in (0, 4)])
+    finally:
+        if old is None:
+            os.environ.pop("VIE_NUM_THREADS", None)
+        else:
+            os.environ["VIE_NUM_THREADS"] = old
+    for other in results[1:]:
+        for (r0, s0, rec0, t0), (r1, s1, rec1, t1) in zip(results[0], other):
+            assert r0 == r1 and t0 == t1
+            for a in range(3):
+                assert np.array_equal(s0[a], s1[a])
+            assert np.array_equal(rec0, rec1)
+
+
+def test_debug_pass_entry_points_reject_null_arguments():
+    vie = _lib()
+    lib = vie.load()
+    assert lib.vie_debug_pad(None, 0, None, None, 1, None) == vie.VIE_E_ARG
+    assert lib.vie_debug_crop(None, 0, None, None, 1, None) == vie.VIE_E_ARG
+    assert lib.vie_debug_pass(None, 0, 0, 0, 0, 0, None, None, None, None, 1, None) == vie.VIE_E_ARG
