@@ -410,6 +410,53 @@ vie_status vie_debug_nhat(const vie_op* op, int dtype, int recon, const int* idx
                           double* out);
 
 /*
+ * Single passes of the matvec (Sec. V-A: zero padding, circulant embedding
+ * and FFT of the currents, the Fourier-domain product, inverse FFT and
+ * cropping), for tests of the index maps and of each transform on its own.
+ * Buffers are DEVICE complex (dtype VIE_C64 or VIE_C128), caller-owned, in
+ * the layouts the five passes exchange, with L_a = 2 n_a (per right-hand
+ * side, index order slowest first):
+ *   vector  [3][n3][n2][n1]   (the layout of x and y of vie_matvec)
+ *   S1, S3  [3][n3][L1][n2]   (after X+, and after Y-)
+ *   S2      [3][L2][L1][n3]   (after Y+ and after the z pass; only the n3
+ *                               kept z positions of each (k1, k2) pencil)
+ * F_L is the unnormalised DFT sum_m a[m] exp(-2 pi i m k / L) and F_L^* its
+ * conjugate-kernel counterpart (also unnormalised: the 1/(8 n1 n2 n3) of the
+ * inverse transform is carried by the Fourier-domain tensor, see
+ * vie_debug_nhat).  All are asynchronous on `stream`; out must not overlap
+ * the inputs (except in == out for pass 2).  Errors: VIE_E_ARG (null or
+ * overlapping buffers, bad pass/kind/dtype), VIE_E_UNSUPPORTED, VIE_E_HIP.
+ *
+ * vie_debug_pad -- the index map of pass X+ with the identity in place of
+ *   its transform: S1[b][q][k][i][j] = x[b][q][k][j][i] for i < n1 and 0 for
+ *   n1 <= i < L1 (zero padding along x, transposed so that y is contiguous).
+ *   Same kernel as the matvec's pass (register-FFT kernel for L1 in 128,
+ *   192, 224, 256, 512, mixed-radix kernel otherwise).
+ * vie_debug_crop -- the index map of pass X- with the identity in place of
+ *   its transform and the bare (VIE_OP_N) epilogue:
+ *   y[b][q][k][j][i] = S3[b][q][k][i][j] for i < n1 (rows n1..L1-1 dropped).
+ *   vie_debug_crop(vie_debug_pad(x)) = x bit for bit.
+ * vie_debug_pass -- pass `pass` of the matvec of kind (VIE_OP_A or VIE_OP_N)
+ *   and adjoint flag, exactly as vie_matvec runs it:
+ *   0 (X+):  in unused; reads x (and eps_c for the A^H pre-scale x <- conj(chi) x);
+ *            out S1[b][q][k][.][j] = F_L1 of x[b][q][k][j][.] padded to L1
+ *   1 (Y+):  in S1, out S2[b][q][.][i][k] = F_L2 of S1[b][q][k][i][.] padded to L2
+ *   2 (Z*):  in S2, out S2 (in may equal out): per pencil (i, j) and output
+ *            component p, the first n3 values of
+ *            F_L3^* ( sum_q N^_pq(i, j, .) * F_L3(S2[b][q][j][i][.] padded to L3) )
+ *            with N^ reconstructed from the Tucker form (conj(N^) for the adjoint;
+ *            recon as in vie_matvec)
+ *   3 (Y-):  in S2, out S3[b][q][k][i][.] = first n2 values of F_L2^* of S2[b][q][.][i][k]
+ *   4 (X-):  in S3, reads x and eps_c for kind A; r = first n1 values of F_L1^* of
+ *            S3[b][q][k][.][j]; out y = r (N), eps_c x - chi r (A),
+ *            conj(eps_c) x - r (A^H), chi = eps_c - 1.
+ */
+vie_status vie_debug_pad(const vie_op* op, int dtype, const void* x, void* s1, int nrhs, void* stream);
+vie_status vie_debug_crop(const vie_op* op, int dtype, const void* s3, void* y, int nrhs, void* stream);
+vie_status vie_debug_pass(const vie_op* op, int pass, int kind, int adjoint, int dtype, int recon,
+                          const void* eps_c, const void* x, const void* in, void* out, int nrhs, void* stream);
+
+/*
  * vie_debug_hosvd: the host part of vie_compress for ONE defining tensor,
  * with no device work (for CPU tests of the compression logic).
  *   n       HOST int[3]; tensor HOST complex128 [n3][n2][n1].

@@ -32,8 +32,10 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <type_traits>
 
 #include "fft_device.h"
+
 #include "vie_internal.h"
 
 namespace vie {
@@ -595,16 +597,20 @@ static size_t z_lds_bytes(const OpView& v, int G)
     default: { constexpr int Wc = 1; __VA_ARGS__; } break;               \
     }
 
+// One pass of the matvec on explicit buffers (see launch_matvec for the
+// layouts): pass 0 reads x and writes S1 (out), 1 reads S1 (in) and writes
+// S2 (out), 2 transforms S2 in place (out), 3 reads S2 (in) and writes S3
+// (out), 4 reads S3 (in) and writes y (out).  ident (passes 0 and 4 only):
+// the transform is replaced by the identity, so only the pass's index maps
+// (padding, transposes, cropping; pass 4 with the bare epilogue) remain.
 template <typename TV, typename T>
-hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* eps, const c2<TV>* x,
-                         c2<TV>* y, int nrhs, c2<T>* ws, hipStream_t s, const int* rhs_map,
-                         std::string& err)
+hipError_t run_pass(const DeviceOp& op, int pass, int mode, int recon, const c2<TV>* eps, const c2<TV>* x,
+                    const void* in, void* out, int nrhs, hipStream_t s, const int* rhs_map, std::string& err,
+                    bool ident)
 {
     const OpView& v = op.view;
     const int n1 = v.n[0], n2 = v.n[1], n3 = v.n[2];
     const int L1 = v.L[0], L2 = v.L[1], L3 = v.L[2];
-    c2<T>* S2 = ws;
-    c2<T>* S1 = ws + (size_t)3 * L2 * L1 * n3 * nrhs;
     const c2<T>* tw[3];
     const c2<T>* core;
     const c2<T>* fac;
@@ -620,21 +626,25 @@ hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* 
         fac = op.d32.fac;
         dense = op.dense32;
     }
-    if (recon == 1 && (sizeof(T) != 4 || g_kernel_path != 0 || !bf16_recon_available(op))) {
-        err = "BF16 reconstruction needs complex64, the register-FFT z pass (2 n3 = 128, 256 or 512) "
-              "and z ranks <= 32";
-        return hipErrorInvalidValue;
-    }
     constexpr int MAXE_XY = 32;   // W * L <= MAXE * NT for W*L <= 8192
     constexpr int MAXE_Z = 24;    // 3 * G * L3 <= 6144
-
     const bool allow_fast = g_kernel_path == 0;
-    // ---- X+
-    {
-        PassTimer timer(0, s);
-        if (allow_fast && xy_pass_fast<TV, T>(0, L1, nullptr, S1, x, eps, tw[0], n1, n2, n3, L1, L2, mode, nrhs,
-                                              rhs_map, s)) {
-        } else {
+    // the identity "transform": a plan without stages leaves the LDS tile as loaded
+    FftPlan id0 = op.plan[0];
+    id0.nst = 0;
+    const FftPlan& px = ident ? id0 : op.plan[0];
+    PassTimer timer(pass, s);
+    if (pass == 0) {
+        c2<T>* S1 = reinterpret_cast<c2<T>*>(out);
+        if (ident) {
+            if constexpr (std::is_same<TV, T>::value) {
+                if (allow_fast && xy_ident_fast<T>(0, L1, nullptr, S1, x, tw[0], n1, n2, n3, L1, L2, nrhs, s))
+                    return hipGetLastError();
+            }
+        } else if (allow_fast && xy_pass_fast<TV, T>(0, L1, nullptr, S1, x, eps, tw[0], n1, n2, n3, L1, L2, mode,
+                                                     nrhs, rhs_map, s)) {
+            return hipGetLastError();
+        }
         int W = tile_width<T>(op.max_lds, L1);
         if ((size_t)W * L1 > (size_t)MAXE_XY * NT) { err = "x length too large"; return hipErrorInvalidValue; }
         size_t lds = (size_t)(W + 1) * L1 * sizeof(c2<T>) + (size_t)L1 * sizeof(c2<T>);
@@ -642,17 +652,15 @@ hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* 
         VIE_W_DISPATCH(W, {
             auto kern = k_xfwd<TV, T, Wc, MAXE_XY>;
             (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, x, eps, S1, op.plan[0], tw[0], n1, n2, n3, mode,
-                               rhs_map);
+            hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, x, eps, S1, px, tw[0], n1, n2, n3,
+                               ident ? (int)MODE_N : mode, rhs_map);
         });
-        }
-    }
-    // ---- Y+
-    {
-        PassTimer timer(1, s);
+    } else if (pass == 1) {
+        const c2<T>* S1 = reinterpret_cast<const c2<T>*>(in);
+        c2<T>* S2 = reinterpret_cast<c2<T>*>(out);
         if (allow_fast && xy_pass_fast<TV, T>(1, L2, S1, S2, x, eps, tw[1], n1, n2, n3, L1, L2, mode, nrhs,
-                                              rhs_map, s)) {
-        } else {
+                                              rhs_map, s))
+            return hipGetLastError();
         int W = tile_width<T>(op.max_lds, L2);
         if ((size_t)W * L2 > (size_t)MAXE_XY * NT) { err = "y length too large"; return hipErrorInvalidValue; }
         size_t lds = (size_t)(W + 1) * L2 * sizeof(c2<T>) + (size_t)L2 * sizeof(c2<T>);
@@ -662,20 +670,18 @@ hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* 
             (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S1, S2, op.plan[1], tw[1], L1, n2, n3);
         });
+    } else if (pass == 2) {
+        c2<T>* S2 = reinterpret_cast<c2<T>*>(out);
+        if (op.nhat_source == 1 && dense == nullptr) {
+            err = "dense spectrum not materialised";
+            return hipErrorInvalidValue;
         }
-    }
-    // ---- Z*
-    if (op.nhat_source == 1 && dense == nullptr) {
-        err = "dense spectrum not materialised";
-        return hipErrorInvalidValue;
-    }
-    {
-        PassTimer timer(2, s);
-        if (allow_fast && z_pass_fast<T>(op, mode, recon, nrhs, S2, tw[2], core, fac, dense, s)) {
-        } else if (recon == 1) {
+        if (allow_fast && z_pass_fast<T>(op, mode, recon, nrhs, S2, tw[2], core, fac, dense, s))
+            return hipGetLastError();
+        if (recon == 1) {
             err = "BF16 z pass could not be launched";
             return hipErrorInvalidValue;
-        } else {
+        }
         int G = 4;
         while (G > 1 && z_lds_bytes<T>(v, G) > op.max_lds) G /= 2;
         size_t lds = z_lds_bytes<T>(v, G);
@@ -686,49 +692,77 @@ hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* 
         za.G = G;
         za.conj = (mode == MODE_AH || mode == MODE_NH);
         za.dense = op.nhat_source == 1;
-        if (za.dense && dense == nullptr) { err = "dense spectrum not materialised"; return hipErrorInvalidValue; }
         int nblk = G == 4 ? (n1 + 1) * (n2 + 1) : (G == 2 ? (n1 + 1) * L2 : L1 * L2);
         dim3 grid(nblk, nrhs);
         auto kern = k_zmid<T, MAXE_Z>;
         (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S2, op.plan[2], tw[2], za, core, fac, dense);
-        }
-    }
-    // ---- Y-
-    {
-        PassTimer timer(3, s);
-        if (allow_fast && xy_pass_fast<TV, T>(2, L2, S2, S1, x, eps, tw[1], n1, n2, n3, L1, L2, mode, nrhs,
-                                              rhs_map, s)) {
-        } else {
+    } else if (pass == 3) {
+        const c2<T>* S2 = reinterpret_cast<const c2<T>*>(in);
+        c2<T>* S3 = reinterpret_cast<c2<T>*>(out);
+        if (allow_fast && xy_pass_fast<TV, T>(2, L2, S2, S3, x, eps, tw[1], n1, n2, n3, L1, L2, mode, nrhs,
+                                              rhs_map, s))
+            return hipGetLastError();
         int W = tile_width<T>(op.max_lds, L2);
         size_t lds = (size_t)(W + 1) * L2 * sizeof(c2<T>) + (size_t)L2 * sizeof(c2<T>);
         dim3 grid((n3 + W - 1) / W, L1, nrhs * 3);
         VIE_W_DISPATCH(W, {
             auto kern = k_yinv<T, Wc, MAXE_XY>;
             (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S2, S1, op.plan[1], tw[1], L1, n2, n3);
+            hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S2, S3, op.plan[1], tw[1], L1, n2, n3);
         });
+    } else {
+        const c2<T>* S3 = reinterpret_cast<const c2<T>*>(in);
+        c2<TV>* y = reinterpret_cast<c2<TV>*>(out);
+        if (ident) {
+            if constexpr (std::is_same<TV, T>::value) {
+                if (allow_fast && xy_ident_fast<T>(3, L1, S3, y, nullptr, tw[0], n1, n2, n3, L1, L2, nrhs, s))
+                    return hipGetLastError();
+            }
+        } else if (allow_fast && xy_pass_fast<TV, T>(3, L1, S3, y, x, eps, tw[0], n1, n2, n3, L1, L2, mode, nrhs,
+                                                     rhs_map, s)) {
+            return hipGetLastError();
         }
-    }
-    // ---- X-
-    {
-        PassTimer timer(4, s);
-        if (allow_fast && xy_pass_fast<TV, T>(3, L1, S1, y, x, eps, tw[0], n1, n2, n3, L1, L2, mode, nrhs,
-                                              rhs_map, s)) {
-        } else {
         int W = tile_width<T>(op.max_lds, L1);
         size_t lds = (size_t)(W + 1) * L1 * sizeof(c2<T>) + (size_t)L1 * sizeof(c2<T>);
         dim3 grid((n2 + W - 1) / W, n3, nrhs * 3);
         VIE_W_DISPATCH(W, {
             auto kern = k_xinv<TV, T, Wc, MAXE_XY>;
             (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S1, x, eps, y, op.plan[0], tw[0], n1, n2, n3, mode,
-                               rhs_map);
+            hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S3, x, eps, y, px, tw[0], n1, n2, n3,
+                               ident ? (int)MODE_N : mode, rhs_map);
         });
-        }
     }
     return hipGetLastError();
 }
+
+template <typename TV, typename T>
+hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* eps, const c2<TV>* x,
+                         c2<TV>* y, int nrhs, c2<T>* ws, hipStream_t s, const int* rhs_map,
+                         std::string& err)
+{
+    const OpView& v = op.view;
+    c2<T>* S2 = ws;
+    c2<T>* S1 = ws + (size_t)3 * v.L[1] * v.L[0] * v.n[2] * nrhs;
+    if (recon == 1 && (sizeof(T) != 4 || g_kernel_path != 0 || !bf16_recon_available(op))) {
+        err = "BF16 reconstruction needs complex64, the register-FFT z pass (2 n3 = 128, 256 or 512) "
+              "and z ranks <= 32";
+        return hipErrorInvalidValue;
+    }
+    // X+ : x -> S1, Y+ : S1 -> S2, Z* : S2 in place, Y- : S2 -> S1 (S3), X- : S1 -> y
+    void* const ins[5] = {nullptr, S1, S2, S2, S1};
+    void* const outs[5] = {S1, S2, S2, S1, y};
+    for (int p = 0; p < 5; ++p) {
+        hipError_t e = run_pass<TV, T>(op, p, mode, recon, eps, x, ins[p], outs[p], nrhs, s, rhs_map, err, false);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template hipError_t run_pass<float, float>(const DeviceOp&, int, int, int, const c2<float>*, const c2<float>*,
+                                           const void*, void*, int, hipStream_t, const int*, std::string&, bool);
+template hipError_t run_pass<double, double>(const DeviceOp&, int, int, int, const c2<double>*, const c2<double>*,
+                                             const void*, void*, int, hipStream_t, const int*, std::string&, bool);
 
 template hipError_t launch_matvec<float, float>(const DeviceOp&, int, int, const c2<float>*, const c2<float>*,
                                                 c2<float>*, int, c2<float>*, hipStream_t, const int*,

@@ -181,8 +181,11 @@ struct PL {
 // ---------------------------------------------------------------------------
 // X/Y passes.  KIND: 0 = X+, 1 = Y+, 2 = Y-, 3 = X-.
 // One workgroup of an X/Y pass: pencil tile tx, row, component q, compact
-// right-hand side bl (mapped through rhs_map).
-template <typename TV, typename T, int L, int E, int W, int KIND>
+// right-hand side bl (mapped through rhs_map).  IDENT replaces the transform
+// by the identity (every element stays at its position), leaving the pass's
+// index maps (padding, transposes, cropping, epilogue): the debug entry
+// points check those bit for bit.
+template <typename TV, typename T, int L, int E, int W, int KIND, bool IDENT = false>
 __device__ __forceinline__ void xy_body(const void* __restrict__ in_, void* __restrict__ out_,
                                         const c2<TV>* __restrict__ x, const c2<TV>* __restrict__ eps,
                                         const c2<T>* __restrict__ tw, const XYArgs& a,
@@ -241,8 +244,16 @@ __device__ __forceinline__ void xy_body(const void* __restrict__ in_, void* __re
                 v[u * R0 + r] = val;
             }
         __syncthreads();   // twiddle table complete (the FFT stages sync per wavefront only)
-        Plan::template fwd<T, TPP, 1, -1>(v, slice, 0, t, tws);
-        reg_store<L, TPP, Plan::RFL, L / Plan::RFL>(v, slice, t);
+        if constexpr (IDENT) {
+            constexpr int R0I = Plan::RF0;
+#pragma unroll
+            for (int u = 0; u < E / R0I; ++u)
+#pragma unroll
+                for (int r = 0; r < R0I; ++r) slice[lds_pad(t + TPP * u + r * (L / R0I))] = v[u * R0I + r];
+        } else {
+            Plan::template fwd<T, TPP, 1, -1>(v, slice, 0, t, tws);
+            reg_store<L, TPP, Plan::RFL, L / Plan::RFL>(v, slice, t);
+        }
         __syncthreads();
         // ---- transposed output [m][p0 + w], all L frequencies
         c2<T>* S = reinterpret_cast<c2<T>*>(out_);
@@ -304,9 +315,16 @@ __device__ __forceinline__ void xy_body(const void* __restrict__ in_, void* __re
             }
         }
         __syncthreads();
-        reg_load<L, TPP, Plan::RI0>(v, slice, t);
-        wave_sync();   // the slice is only rewritten by the lanes of this pencil's wavefront
-        Plan::template inv<T, TPP, 1, 1>(v, slice, 0, t, tws);
+        if constexpr (IDENT) {
+#pragma unroll
+            for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+                for (int r = 0; r < RL; ++r) v[u * RL + r] = slice[lds_pad(t + TPP * u + r * (L / RL))];
+        } else {
+            reg_load<L, TPP, Plan::RI0>(v, slice, t);
+            wave_sync();   // the slice is only rewritten by the lanes of this pencil's wavefront
+            Plan::template inv<T, TPP, 1, 1>(v, slice, 0, t, tws);
+        }
         // ---- cropped rows straight from the registers of the last stage
         if (pw < npen) {
 #pragma unroll
@@ -345,7 +363,7 @@ __device__ __forceinline__ void xy_body(const void* __restrict__ in_, void* __re
     }
 }
 
-template <typename TV, typename T, int L, int E, int W, int KIND>
+template <typename TV, typename T, int L, int E, int W, int KIND, bool IDENT = false>
 __global__ void __launch_bounds__(W*(L / E)) k_xy_fast(const void* __restrict__ in_, void* __restrict__ out_,
                                                        const c2<TV>* __restrict__ x, const c2<TV>* __restrict__ eps,
                                                        const c2<T>* __restrict__ tw, XYArgs a,
@@ -371,7 +389,7 @@ __global__ void __launch_bounds__(W*(L / E)) k_xy_fast(const void* __restrict__ 
         tx = blockIdx.x;
         row = blockIdx.y;
     }
-    xy_body<TV, T, L, E, W, KIND>(in_, out_, x, eps, tw, a, rhs_map, tx, row, q, bl);
+    xy_body<TV, T, L, E, W, KIND, IDENT>(in_, out_, x, eps, tw, a, rhs_map, tx, row, q, bl);
 }
 
 // Grouped launch over several instances with the same FFT length: workgroup
@@ -767,7 +785,7 @@ static constexpr int xy_W()
     else return 256 / (L / xy_E<T, L>());
 }
 
-template <typename TV, typename T, int L, int KIND>
+template <typename TV, typename T, int L, int KIND, bool IDENT = false>
 static void launch_xy(const void* in, void* out, const c2<TV>* x, const c2<TV>* eps, const c2<T>* tw,
                       const XYArgs& a, int grid_x, int grid_y, int nz, const int* rhs_map, hipStream_t s)
 {
@@ -775,7 +793,7 @@ static void launch_xy(const void* in, void* out, const c2<TV>* x, const c2<TV>* 
     constexpr int W = xy_W<T, L>();
     constexpr int NT = W * (L / E);
     size_t lds = sizeof(c2<T>) * ((size_t)W * PL<L>::value + RegPlan<L>::TW);
-    auto kern = k_xy_fast<TV, T, L, E, W, KIND>;
+    auto kern = k_xy_fast<TV, T, L, E, W, KIND, IDENT>;
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     dim3 grid((grid_x + W - 1) / W, grid_y, nz);
     if (KIND == 3) {
@@ -847,6 +865,39 @@ bool xy_pass_fast(int kind, int L, const void* in, void* out, const c2<TV>* x, c
     default: return dispatch_xy<TV, T, 3>(L, in, out, x, eps, tw, a, n2, n3, nz, rhs_map, s);
     }
 }
+
+// The X+ (kind 0) and X- (kind 3) index maps with the identity in place of
+// the transform (debug entry points; vector and compute types equal).
+template <typename T, int KIND>
+static bool dispatch_xy_ident(int L, const void* in, void* out, const c2<T>* x, const c2<T>* tw, const XYArgs& a,
+                              int gx, int gy, int nz, hipStream_t s)
+{
+    switch (L) {
+    case 512: launch_xy<T, T, 512, KIND, true>(in, out, x, nullptr, tw, a, gx, gy, nz, nullptr, s); return true;
+    case 256: launch_xy<T, T, 256, KIND, true>(in, out, x, nullptr, tw, a, gx, gy, nz, nullptr, s); return true;
+    case 128: launch_xy<T, T, 128, KIND, true>(in, out, x, nullptr, tw, a, gx, gy, nz, nullptr, s); return true;
+    case 192: launch_xy<T, T, 192, KIND, true>(in, out, x, nullptr, tw, a, gx, gy, nz, nullptr, s); return true;
+    case 224: launch_xy<T, T, 224, KIND, true>(in, out, x, nullptr, tw, a, gx, gy, nz, nullptr, s); return true;
+    default: return false;
+    }
+}
+
+template <typename T>
+bool xy_ident_fast(int kind, int L, const void* in, void* out, const c2<T>* x, const c2<T>* tw, int n1, int n2,
+                   int n3, int L1, int L2, int nrhs, hipStream_t s)
+{
+    const int nz = nrhs * 3;
+    if (kind == 0) {
+        XYArgs a{n1, n2, n3, L1, L2, MODE_N};
+        return dispatch_xy_ident<T, 0>(L, in, out, x, tw, a, n2, n3, nz, s);
+    }
+    XYArgs a{n1, n2, n3, L1, L2, MODE_N};
+    return dispatch_xy_ident<T, 3>(L, in, out, x, tw, a, n2, n3, nz, s);
+}
+template bool xy_ident_fast<float>(int, int, const void*, void*, const c2<float>*, const c2<float>*, int, int, int,
+                                   int, int, int, hipStream_t);
+template bool xy_ident_fast<double>(int, int, const void*, void*, const c2<double>*, const c2<double>*, int, int,
+                                    int, int, int, int, hipStream_t);
 
 bool bf16_recon_available(const DeviceOp& op)
 {

@@ -614,6 +614,99 @@ vie_status vie_matvec_jm(const vie_op* op_n, const vie_op* op_k, int dtype, doub
     return VIE_OK;
 }
 
+// Buffer sizes (complex elements per right-hand side) of the pass layouts.
+static size_t pass_elems(const OpView& v, int which)
+{
+    const size_t n1 = v.n[0], n2 = v.n[1], n3 = v.n[2], L1 = v.L[0], L2 = v.L[1];
+    switch (which) {
+    case 0: return 3 * n3 * n2 * n1;   // vector [3][n3][n2][n1]
+    case 1: return 3 * n3 * L1 * n2;   // S1 / S3 [3][n3][L1][n2]
+    default: return 3 * L2 * L1 * n3;  // S2 [3][L2][L1][n3]
+    }
+}
+
+static bool disjoint(const void* a, size_t na, const void* b, size_t nb)
+{
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    return pa + na <= pb || pb + nb <= pa;
+}
+
+static vie_status debug_pass_common(const char* who, const vie_op* op, int pass, int mode, int dtype, int recon,
+                                    const void* eps_c, const void* x, const void* in, void* out, int nrhs,
+                                    void* stream, bool ident)
+{
+    std::string w(who);
+    if (!op || !out || nrhs < 1) return fail(VIE_E_ARG, w + ": null argument or nrhs < 1");
+    if (dtype != VIE_C64 && dtype != VIE_C128) return fail(VIE_E_ARG, w + ": bad dtype");
+    if (pass < 0 || pass > 4) return fail(VIE_E_ARG, w + ": pass must be 0..4");
+    const OpView& v = op->d.view;
+    if (v.fam != 0 && (mode != MODE_N || recon == VIE_RECON_BF16))
+        return fail(VIE_E_UNSUPPORTED, w + ": a K operator has the bare forward product only");
+    const bool needs_eps = mode == MODE_A || mode == MODE_AH;
+    const bool needs_x = pass == 0 || (pass == 4 && needs_eps);
+    if (needs_x && !x) return fail(VIE_E_ARG, w + ": x is required by this pass and mode");
+    if (((pass == 0 && mode == MODE_AH) || (pass == 4 && needs_eps)) && !eps_c)
+        return fail(VIE_E_ARG, w + ": eps_c is required by this pass and mode");
+    if (pass != 0 && !in) return fail(VIE_E_ARG, w + ": in is required by passes 1..4");
+    if (recon < VIE_RECON_AUTO || recon > VIE_RECON_FP64) return fail(VIE_E_ARG, w + ": bad recon");
+    if ((dtype == VIE_C64 && recon == VIE_RECON_FP64) ||
+        (dtype == VIE_C128 && (recon == VIE_RECON_FP32 || recon == VIE_RECON_BF16)))
+        return fail(VIE_E_UNSUPPORTED, w + ": recon does not match dtype");
+    if (recon == VIE_RECON_BF16 && (g_kernel_path != 0 || !bf16_recon_available(op->d)))
+        return fail(VIE_E_UNSUPPORTED, w + ": BF16 reconstruction is not available for this operator");
+    const size_t el = dtype == VIE_C128 ? 16 : 8;
+    static const int in_layout[5] = {0, 1, 2, 2, 1};
+    static const int out_layout[5] = {1, 2, 2, 1, 0};
+    const size_t nin = pass_elems(v, in_layout[pass]) * nrhs * el;
+    const size_t nout = pass_elems(v, out_layout[pass]) * nrhs * el;
+    if (pass != 2) {
+        if (pass != 0 && !disjoint(in, nin, out, nout)) return fail(VIE_E_ARG, w + ": in and out overlap");
+        if (x && pass == 0 && !disjoint(x, nin, out, nout)) return fail(VIE_E_ARG, w + ": x and out overlap");
+        if (x && pass == 4 && !disjoint(x, nout, out, nout)) return fail(VIE_E_ARG, w + ": x and out overlap");
+    } else if (in != out && !disjoint(in, nin, out, nout)) {
+        return fail(VIE_E_ARG, w + ": in and out partly overlap");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (pass == 2 && in != out) e = hipMemcpyAsync(out, in, nin, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, w.c_str());
+    std::string err;
+    if (dtype == VIE_C128)
+        e = run_pass<double, double>(op->d, pass, mode, 0, (const c2<double>*)eps_c, (const c2<double>*)x, in, out,
+                                     nrhs, s, nullptr, err, ident);
+    else
+        e = run_pass<float, float>(op->d, pass, mode, recon == VIE_RECON_BF16 ? 1 : 0, (const c2<float>*)eps_c,
+                                   (const c2<float>*)x, in, out, nrhs, s, nullptr, err, ident);
+    if (e != hipSuccess) {
+        if (!err.empty()) return fail(VIE_E_UNSUPPORTED, w + ": " + err);
+        return hip_fail(e, w.c_str());
+    }
+    return VIE_OK;
+}
+
+vie_status vie_debug_pad(const vie_op* op, int dtype, const void* x, void* s1, int nrhs, void* stream)
+{
+    if (!x) return fail(VIE_E_ARG, "vie_debug_pad: null argument");
+    return debug_pass_common("vie_debug_pad", op, 0, MODE_N, dtype, VIE_RECON_AUTO, nullptr, x, nullptr, s1, nrhs,
+                             stream, true);
+}
+
+vie_status vie_debug_crop(const vie_op* op, int dtype, const void* s3, void* y, int nrhs, void* stream)
+{
+    if (!s3) return fail(VIE_E_ARG, "vie_debug_crop: null argument");
+    return debug_pass_common("vie_debug_crop", op, 4, MODE_N, dtype, VIE_RECON_AUTO, nullptr, nullptr, s3, y, nrhs,
+                             stream, true);
+}
+
+vie_status vie_debug_pass(const vie_op* op, int pass, int kind, int adjoint, int dtype, int recon,
+                          const void* eps_c, const void* x, const void* in, void* out, int nrhs, void* stream)
+{
+    if (kind != VIE_OP_A && kind != VIE_OP_N) return fail(VIE_E_ARG, "vie_debug_pass: bad kind");
+    const int mode = kind == VIE_OP_A ? (adjoint ? MODE_AH : MODE_A) : (adjoint ? MODE_NH : MODE_N);
+    return debug_pass_common("vie_debug_pass", op, pass, mode, dtype, recon, eps_c, x, in, out, nrhs, stream, false);
+}
+
 vie_status vie_debug_nhat(const vie_op* op, int dtype, int recon, const int* idx, int count, double* out)
 {
     if (!op || !idx || !out || count < 0) return fail(VIE_E_ARG, "vie_debug_nhat: bad argument");

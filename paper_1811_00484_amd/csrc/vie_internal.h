@@ -162,6 +162,14 @@ hipError_t launch_matvec(const DeviceOp& op, int mode, int recon, const c2<TV>* 
                          c2<TV>* y, int nrhs, c2<T>* ws, hipStream_t s, const int* rhs_map,
                          std::string& err);
 
+// One pass p of the matvec on explicit buffers: 0 x -> S1, 1 S1 -> S2, 2 S2 in
+// place (out), 3 S2 -> S3, 4 S3 -> y; ident (passes 0 and 4) replaces the
+// transform by the identity.
+template <typename TV, typename T>
+hipError_t run_pass(const DeviceOp& op, int pass, int mode, int recon, const c2<TV>* eps, const c2<TV>* x,
+                    const void* in, void* out, int nrhs, hipStream_t s, const int* rhs_map, std::string& err,
+                    bool ident);
+
 // Multi-instance matvec: one launch per pass over all instances (mixed-radix
 // LDS kernels).  tab_dev: device scratch for the instance table.
 template <typename TV, typename T>
@@ -193,6 +201,11 @@ struct ZGroup {
 template <typename TV, typename T>
 bool xy_pass_fast(int kind, int L, const void* in, void* out, const c2<TV>* x, const c2<TV>* eps, const c2<T>* tw,
                   int n1, int n2, int n3, int L1, int L2, int mode, int nrhs, const int* rhs_map, hipStream_t s);
+// the X+ (kind 0) or X- (kind 3, bare epilogue) register kernel with the
+// identity in place of the transform; false = no register kernel for L
+template <typename T>
+bool xy_ident_fast(int kind, int L, const void* in, void* out, const c2<T>* x, const c2<T>* tw, int n1, int n2,
+                   int n3, int L1, int L2, int nrhs, hipStream_t s);
 // recon 1: N^ tables from the BF16 z factors on MFMA (T = float only)
 template <typename T>
 bool z_pass_fast(const DeviceOp& op, int mode, int recon, int nrhs, c2<T>* S2, const c2<T>* tw, const c2<T>* core,
