@@ -653,6 +653,7 @@ vie_status vie_solve_multi(const vie_solve_instance* inst, int count, int dtype,
         const vie_solve_instance& in = inst[i];
         if (!in.op || !in.eps_c || !in.b || !in.x || in.nrhs < 1) return fail(VIE_E_ARG, "vie_solve_multi: bad instance");
         const OpView& v = in.op->d.view;
+        if (v.fam != 0) return fail(VIE_E_UNSUPPORTED, "vie_solve_multi: N operators only");
         size_t vb = (size_t)in.nrhs * 3 * v.n[0] * v.n[1] * v.n[2] * eb;
         const char* xb = (const char*)in.x;
         const char* bb = (const char*)in.b;

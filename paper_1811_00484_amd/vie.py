@@ -115,6 +115,10 @@ _SIGS = {
     "vie_total_field": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_double, _P, _P]),
     "vie_adjoint_source": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
     "vie_debug_nhat": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int, _P]),
+    "vie_debug_pad": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int, _P]),
+    "vie_debug_crop": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int, _P]),
+    "vie_debug_pass": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P,
+                                      _P, _P, ctypes.c_int, _P]),
     "vie_debug_hosvd": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.c_double, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_int), _P, _P, ctypes.POINTER(ctypes.c_double)]),
     "vie_debug_cp": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.c_int, ctypes.c_int, _P,
@@ -172,6 +176,30 @@ def _dt(t):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _require_like(t, ref, shape, name):
+    """Check, before any library call, that ``t`` is a contiguous tensor of
+    ``ref``'s dtype, on ``ref``'s device, of shape ``shape``: the kernels take
+    the element size and extents from the vectors, so a mismatch would read
+    or write outside the buffer."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch tensor" % name)
+    if t.dtype != ref.dtype:
+        raise ValueError("%s must have dtype %s, got %s" % (name, ref.dtype, t.dtype))
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.device != ref.device:
+        raise ValueError("%s must be on %s, got %s" % (name, ref.device, t.device))
+    return t
+
+
+def _require_device(t, name):
+    if t.device.type != "cuda":
+        raise ValueError("%s must be a device tensor (got %s)" % (name, t.device))
+    return t
 
 
 class Operator:
@@ -280,10 +308,10 @@ def magnetic_field(op_k, j, h_inc, h):
     ``j`` (3, n3, n2, n1) on the device; ``h`` is the voxel edge (m).  The K
     product runs in the library (vie_matvec, VIE_OP_N) and so does the field
     and b1+ kernel (vie_magnetic_field).  Returns (H, b1)."""
+    _vec3(j, op_k, "j")
+    _require_like(h_inc, j, j.shape, "h_inc")
     lib = load()
     kj = matvec(op_k, j, kind="N")
-    if h_inc.dtype != j.dtype or tuple(h_inc.shape) != tuple(j.shape) or not h_inc.is_contiguous():
-        raise ValueError("h_inc must be contiguous, of the shape and dtype of j")
     H = torch.empty_like(kj)
     b1 = torch.empty(tuple(j.shape[1:]), dtype=torch.float64 if j.dtype == torch.complex128 else torch.float32,
                      device=j.device)
@@ -295,13 +323,14 @@ def magnetic_field(op_k, j, h_inc, h):
 def matvec_jm(op_n, op_k, x, eps_c, mu_c, h, freq_hz):
     """The full JMVIE operator of eq. 4 (vie_matvec_jm) on x = [J; M] of shape
     (2, 3, n3, n2, n1); eps_c, mu_c (n3, n2, n1) of the same dtype."""
-    lib = load()
     n1, n2, n3 = op_n.n
     if tuple(x.shape) != (2, 3, n3, n2, n1) or not x.is_contiguous():
         raise ValueError("x must be contiguous (2, 3, n3, n2, n1)")
-    for t in (eps_c, mu_c):
-        if t.dtype != x.dtype or tuple(t.shape) != (n3, n2, n1) or not t.is_contiguous():
-            raise ValueError("eps_c and mu_c must be contiguous (n3, n2, n1) of the vector dtype")
+    _dt(x)
+    _require_like(eps_c, x, (n3, n2, n1), "eps_c")
+    _require_like(mu_c, x, (n3, n2, n1), "mu_c")
+    _require_device(x, "x")
+    lib = load()
     dt = _dt(x)
     nbytes = lib.vie_jm_workspace_bytes(op_n.handle, op_k.handle, dt)
     ws = _scratch(nbytes, x.device)
@@ -317,13 +346,14 @@ def solve_jm(op_n, op_k, b, eps_c, mu_c, h, freq_hz, tol=1e-6, restart=50, max_o
     solution have shape (2, 3, n3, n2, n1) ([J; M]).  ``refine`` (complex128
     only): FP32 products in the Arnoldi steps, FP64 restart residuals.
     Returns (x, info dict, status)."""
-    lib = load()
     n1, n2, n3 = op_n.n
     if tuple(b.shape) != (2, 3, n3, n2, n1) or not b.is_contiguous():
         raise ValueError("b must be contiguous (2, 3, n3, n2, n1)")
-    for t in (eps_c, mu_c):
-        if t.dtype != b.dtype or tuple(t.shape) != (n3, n2, n1) or not t.is_contiguous():
-            raise ValueError("eps_c and mu_c must be contiguous (n3, n2, n1) of the vector dtype")
+    _dt(b)
+    _require_like(eps_c, b, (n3, n2, n1), "eps_c")
+    _require_like(mu_c, b, (n3, n2, n1), "mu_c")
+    _require_device(b, "b")
+    lib = load()
     dt = _dt(b)
     opts = SolveOpts(float(tol), int(restart), int(max_outer), 0, int(bool(refine)), VIE_RECON_FP32,
                      float(inner_tol))
@@ -393,7 +423,6 @@ def workspace_bytes(op, dtype, nrhs=1):
 
 def matvec(op, x, eps_c=None, kind="A", adjoint=False, recon="auto", out=None):
     """y = A x, N x (kind 'N'), or their adjoints, for a batch of vectors."""
-    lib = load()
     squeeze = x.dim() == 4
     xb = _as_batch(x, op)
     dt = _dt(xb)
@@ -401,8 +430,11 @@ def matvec(op, x, eps_c=None, kind="A", adjoint=False, recon="auto", out=None):
     if k == VIE_OP_A:
         if eps_c is None:
             raise ValueError("eps_c required for kind 'A'")
-        if eps_c.dtype != xb.dtype or not eps_c.is_contiguous() or tuple(eps_c.shape) != xb.shape[2:]:
-            raise ValueError("eps_c must be contiguous (n3, n2, n1) of the vector dtype")
+        _require_like(eps_c, xb, xb.shape[2:], "eps_c")
+    if out is not None:
+        _require_like(_as_batch(out, op), xb, xb.shape, "out")
+    _require_device(xb, "x")
+    lib = load()
     y = torch.empty_like(xb) if out is None else _as_batch(out, op)
     nbytes = lib.vie_workspace_bytes(op.handle, dt, xb.shape[0])
     ws = op.workspace(nbytes, xb.device)
@@ -415,11 +447,17 @@ def matvec(op, x, eps_c=None, kind="A", adjoint=False, recon="auto", out=None):
 def solve(op, b, eps_c, x0=None, tol=1e-6, restart=50, max_outer=200, adjoint=False, refine=False,
           inner_tol=1e-4, inner_recon="fp32", history=64):
     """GMRES solve of A x = b (or A^H x = b).  Returns (x, infos, status)."""
-    lib = load()
     squeeze = b.dim() == 4
     bb = _as_batch(b, op)
     dt = _dt(bb)
     nrhs = bb.shape[0]
+    if eps_c is None:
+        raise ValueError("eps_c required")
+    _require_like(eps_c, bb, bb.shape[2:], "eps_c")
+    if x0 is not None:
+        _require_like(_as_batch(x0, op), bb, bb.shape, "x0")
+    _require_device(bb, "b")
+    lib = load()
     x = torch.zeros_like(bb) if x0 is None else _as_batch(x0, op).clone()
     opts = SolveOpts(float(tol), int(restart), int(max_outer), int(bool(adjoint)), int(bool(refine)),
                      _RECON[inner_recon], float(inner_tol))
@@ -461,15 +499,23 @@ def matvec_multi(items, kind="A", adjoint=False):
     """One multi-instance matvec: ``items`` is a list of (op, x, eps_c) with x of
     shape (nrhs, 3, n3, n2, n1) per instance (grids may differ); returns the
     list of outputs.  Every pass is one kernel launch over all instances."""
-    lib = load()
     arr = (Instance * len(items))()
     outs = []
     dt = None
-    for i, (op, x, eps_c) in enumerate(items):
+    for op, x, eps_c in items:
         xb = _as_batch(x, op)
         dt = _dt(xb) if dt is None else dt
         if _dt(xb) != dt:
             raise ValueError("all instances must share a dtype")
+        if kind == "A" and eps_c is None:
+            raise ValueError("eps_c required for kind 'A'")
+        if eps_c is not None:
+            _require_like(eps_c, xb, xb.shape[2:], "eps_c")
+    for op, x, _ in items:
+        _require_device(x, "x")
+    lib = load()
+    for i, (op, x, eps_c) in enumerate(items):
+        xb = _as_batch(x, op)
         y = torch.empty_like(xb)
         outs.append(y)
         arr[i] = Instance(op.handle, eps_c.data_ptr() if eps_c is not None else None, xb.data_ptr(), y.data_ptr(),
@@ -489,14 +535,27 @@ def solve_multi(items, tol=1e-6, restart=50, max_outer=200, adjoint=False, refin
     """GMRES on several instances (op, b, eps_c) in lockstep; returns a list
     of (x, infos) per instance and the overall status.  ``x0``: optional list
     of initial guesses (one tensor per instance, shape of its b)."""
-    lib = load()
     arr = (SolveInstance * len(items))()
     keep = []
     xs = []
     dt = None
+    if x0 is not None and len(x0) != len(items):
+        raise ValueError("x0 must hold one tensor per instance")
     for i, (op, b, eps_c) in enumerate(items):
         bb = _as_batch(b, op)
         dt = _dt(bb) if dt is None else dt
+        if _dt(bb) != dt:
+            raise ValueError("all instances must share a dtype")
+        if eps_c is None:
+            raise ValueError("eps_c required")
+        _require_like(eps_c, bb, bb.shape[2:], "eps_c")
+        if x0 is not None:
+            _require_like(_as_batch(x0[i], op), bb, bb.shape, "x0")
+    for op, b, _ in items:
+        _require_device(b, "b")
+    lib = load()
+    for i, (op, b, eps_c) in enumerate(items):
+        bb = _as_batch(b, op)
         x = torch.zeros_like(bb) if x0 is None else _as_batch(x0[i], op).clone()
         xs.append(x)
         infos = (SolveInfo * bb.shape[0])()
@@ -539,7 +598,15 @@ def _vec3(t, op, name):
     n1, n2, n3 = op.n
     if tuple(t.shape) != (3, n3, n2, n1) or not t.is_contiguous():
         raise ValueError("%s must be contiguous (3, %d, %d, %d)" % (name, n3, n2, n1))
-    return t
+    _dt(t)
+    return _require_device(t, name)
+
+
+def _same(ts, names):
+    """Every tensor of ``ts`` shares the first one's dtype and device."""
+    for t, nm in zip(ts[1:], names[1:]):
+        if t.dtype != ts[0].dtype or t.device != ts[0].device:
+            raise ValueError("%s must match %s in dtype and device" % (nm, names[0]))
 
 
 def problem_setup(op, eps_r, sigma, e_inc, freq_hz):
@@ -547,8 +614,11 @@ def problem_setup(op, eps_r, sigma, e_inc, freq_hz):
     (real maps float32/float64 matching complex64/complex128 e_inc)."""
     _vec3(e_inc, op, "e_inc")
     rdt = torch.float32 if e_inc.dtype == torch.complex64 else torch.float64
-    if eps_r.dtype != rdt or sigma.dtype != rdt or not eps_r.is_contiguous() or not sigma.is_contiguous():
-        raise ValueError("eps_r and sigma must be contiguous %s" % rdt)
+    for t, nm in ((eps_r, "eps_r"), (sigma, "sigma")):
+        if (t.dtype != rdt or not t.is_contiguous() or tuple(t.shape) != tuple(e_inc.shape[1:])
+                or t.device != e_inc.device):
+            raise ValueError("%s must be contiguous %s of shape %s on %s" % (nm, rdt, tuple(e_inc.shape[1:]),
+                                                                             e_inc.device))
     eps_c = torch.empty(e_inc.shape[1:], dtype=e_inc.dtype, device=e_inc.device)
     b = torch.empty_like(e_inc)
     _check(load().vie_problem_setup(op.handle, _dt(e_inc), _ptr(eps_r), _ptr(sigma), _ptr(e_inc), _oe0(freq_hz),
@@ -560,6 +630,7 @@ def total_field(op, e_inc, u, Nu, freq_hz):
     """E = e_inc + (N u - u) / (i omega eps0)."""
     for t, nm in ((e_inc, "e_inc"), (u, "u"), (Nu, "Nu")):
         _vec3(t, op, nm)
+    _same((u, e_inc, Nu), ("u", "e_inc", "Nu"))
     E = torch.empty_like(u)
     _check(load().vie_total_field(op.handle, _dt(u), _ptr(e_inc), _ptr(u), _ptr(Nu), _oe0(freq_hz), _ptr(E),
                                   _stream()), "vie_total_field")
@@ -570,6 +641,7 @@ def adjoint_source(op, g, NHg):
     """t = N^H g - g."""
     _vec3(g, op, "g")
     _vec3(NHg, op, "NHg")
+    _same((g, NHg), ("g", "NHg"))
     t = torch.empty_like(g)
     _check(load().vie_adjoint_source(op.handle, _dt(g), _ptr(g), _ptr(NHg), _ptr(t), _stream()),
            "vie_adjoint_source")
@@ -580,8 +652,7 @@ def field_gradient(op, z, E, freq_hz):
     """(dL/d eps_r, dL/d sigma) per voxel from the adjoint field z and the total field E."""
     _vec3(z, op, "z")
     _vec3(E, op, "E")
-    if z.dtype != E.dtype:
-        raise ValueError("z and E must share a dtype")
+    _same((z, E), ("z", "E"))
     rdt = torch.float32 if z.dtype == torch.complex64 else torch.float64
     ge = torch.empty(z.shape[1:], dtype=rdt, device=z.device)
     gs = torch.empty_like(ge)
@@ -609,6 +680,78 @@ def debug_nhat(op, idx, dtype=torch.complex64):
     _check(lib.vie_debug_nhat(op.handle, dt, VIE_RECON_AUTO, a.ctypes.data_as(ctypes.c_void_p), a.shape[0],
                               out.ctypes.data_as(ctypes.c_void_p)), "vie_debug_nhat")
     return out[:, 0] + 1j * out[:, 1]
+
+
+def pass_shape(op, layout, nrhs=1):
+    """Shape of a pass buffer: 'vector' (nrhs, 3, n3, n2, n1), 'S1'/'S3'
+    (nrhs, 3, n3, L1, n2) or 'S2' (nrhs, 3, L2, L1, n3), L_a = 2 n_a."""
+    n1, n2, n3 = op.n
+    if layout == "vector":
+        return (nrhs, 3, n3, n2, n1)
+    if layout in ("S1", "S3"):
+        return (nrhs, 3, n3, 2 * n1, n2)
+    if layout == "S2":
+        return (nrhs, 3, 2 * n2, 2 * n1, n3)
+    raise ValueError(layout)
+
+
+_PASS_IO = {0: ("vector", "S1"), 1: ("S1", "S2"), 2: ("S2", "S2"), 3: ("S2", "S3"), 4: ("S3", "vector")}
+
+
+def _pass_tensor(t, op, layout, name, ref=None):
+    shape = pass_shape(op, layout, t.shape[0] if t.dim() == 5 else 1)
+    if t.dim() != 5 or tuple(t.shape) != shape or not t.is_contiguous():
+        raise ValueError("%s must be contiguous %s" % (name, shape))
+    if ref is not None and (t.dtype != ref.dtype or t.device != ref.device):
+        raise ValueError("%s must match the other buffers in dtype and device" % name)
+    _dt(t)
+    return t
+
+
+def debug_pad(op, x):
+    """vie_debug_pad: the X+ pass's zero padding and transpose (identity in
+    place of the FFT); x (nrhs, 3, n3, n2, n1) -> S1 (nrhs, 3, n3, 2 n1, n2)."""
+    _pass_tensor(x, op, "vector", "x")
+    _require_device(x, "x")
+    out = torch.empty(pass_shape(op, "S1", x.shape[0]), dtype=x.dtype, device=x.device)
+    _check(load().vie_debug_pad(op.handle, _dt(x), _ptr(x), _ptr(out), x.shape[0], _stream()), "vie_debug_pad")
+    return out
+
+
+def debug_crop(op, s3):
+    """vie_debug_crop: the X- pass's transpose and crop (identity in place of
+    the FFT, bare epilogue); S3 (nrhs, 3, n3, 2 n1, n2) -> (nrhs, 3, n3, n2, n1)."""
+    _pass_tensor(s3, op, "S3", "s3")
+    _require_device(s3, "s3")
+    out = torch.empty(pass_shape(op, "vector", s3.shape[0]), dtype=s3.dtype, device=s3.device)
+    _check(load().vie_debug_crop(op.handle, _dt(s3), _ptr(s3), _ptr(out), s3.shape[0], _stream()), "vie_debug_crop")
+    return out
+
+
+def debug_pass(op, p, inp=None, x=None, eps_c=None, kind="A", adjoint=False, recon="auto", out=None):
+    """vie_debug_pass: pass ``p`` (0 X+, 1 Y+, 2 Z*, 3 Y-, 4 X-) of the matvec on
+    the pass layouts (see pass_shape); returns the output buffer."""
+    lin, lout = _PASS_IO[int(p)]
+    ref = x if p == 0 else inp
+    if ref is None:
+        raise ValueError("pass %d needs %s" % (p, "x" if p == 0 else "inp"))
+    _pass_tensor(ref, op, lin, "input")
+    nrhs = ref.shape[0]
+    if x is not None:
+        _pass_tensor(x, op, "vector", "x", ref)
+        if x.shape[0] != nrhs:
+            raise ValueError("x must have the input's right-hand-side count")
+    if eps_c is not None:
+        _require_like(eps_c, ref, tuple(reversed(op.n)), "eps_c")
+    if out is not None:
+        _pass_tensor(out, op, lout, "out", ref)
+    _require_device(ref, "input")
+    if out is None:
+        out = torch.empty(pass_shape(op, lout, nrhs), dtype=ref.dtype, device=ref.device)
+    k = VIE_OP_A if kind == "A" else VIE_OP_N
+    _check(load().vie_debug_pass(op.handle, int(p), k, int(bool(adjoint)), _dt(ref), _RECON[recon], _ptr(eps_c),
+                                 _ptr(x), _ptr(inp), _ptr(out), nrhs, _stream()), "vie_debug_pass")
+    return out
 
 
 def debug_hosvd(tensor, tol, rule=0, want_recon=True):
@@ -689,15 +832,19 @@ class MatvecGraph:
     ``y``.  Owns its workspace; keeps x, y, eps_c and the operator alive."""
 
     def __init__(self, op, x, eps_c=None, kind="A", adjoint=False, recon="auto", out=None):
-        lib = load()
-        self._lib = lib
         self.handle = None
         xb = _as_batch(x, op)
         dt = _dt(xb)
         k = VIE_OP_A if kind == "A" else VIE_OP_N
-        if k == VIE_OP_A and (eps_c is None or eps_c.dtype != xb.dtype or not eps_c.is_contiguous()
-                              or tuple(eps_c.shape) != xb.shape[2:]):
-            raise ValueError("eps_c must be contiguous (n3, n2, n1) of the vector dtype")
+        if k == VIE_OP_A:
+            if eps_c is None:
+                raise ValueError("eps_c required for kind 'A'")
+            _require_like(eps_c, xb, xb.shape[2:], "eps_c")
+        if out is not None:
+            _require_like(_as_batch(out, op), xb, xb.shape, "out")
+        _require_device(xb, "x")
+        lib = load()
+        self._lib = lib
         y = torch.empty_like(xb) if out is None else _as_batch(out, op)
         nbytes = lib.vie_workspace_bytes(op.handle, dt, xb.shape[0])
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=xb.device)

@@ -5,9 +5,16 @@ benchmark times (register-FFT kernels, complex64, one right-hand side):
   parity with the FP64 oracle and GMRES to 1e-6, the solution's residual
   checked with the oracle's operator;
 * the 256^3 head at 1 mm (512^3 embedding): whole-vector matvec parity with
-  the oracle's dense-spectrum FFT convolution (same Tucker tolerance, so the
-  difference is FP32 rounding plus the 1e-6 truncation of both sides'
-  HOSVD: the oracle's dense tensor is the uncompressed one)."""
+  the oracle's FFT convolution on the same Tucker operator (its own HOSVD
+  at the same tolerance and the same ranks, so the difference is the FP32
+  arithmetic alone), then with the oracle's dense-spectrum operator (the
+  uncompressed tensor: FP32 rounding plus the 1e-6 truncation).
+
+Plain complex64 GMRES (FP32 Arnoldi and FP32 residual) on the head
+workload stops at an FP64 residual near 1.3e-6: it does not reach 1e-6, which
+the FP64-refined solve does.  The test states that floor and asserts it."""
+import warnings
+
 import numpy as np
 import pytest
 import torch
@@ -49,18 +56,31 @@ def test_head_96x112x128_matvec_and_solve():
         say("   dipole %d: %d FP32 + %d FP64 matvecs, oracle residual %.3e"
             % (s, infos[s]["matvecs"], infos[s]["matvecs_fp64"], r))
         assert r <= 1.01e-6
-    # plain complex64 GMRES (FP32 Arnoldi and residual): reaches the FP32
-    # floor; its FP64 residual is stated, bounded at 1e-5
-    x32, i32, st32 = vie.solve(op, to_dev(b[:2], torch.complex64), e, tol=1e-6, restart=50, max_outer=10)
+    # plain complex64 GMRES (FP32 Arnoldi and residual) to 1e-6: it either
+    # converges (status 0, every FP32 residual <= 1e-6) or reports that it did
+    # not (status VIE_NOT_CONVERGED) at its FP32 floor; the floor, measured in
+    # FP64 with the oracle's operator, is stated and bounded at 1e-5
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        x32, i32, st32 = vie.solve(op, to_dev(b[:2], torch.complex64), e, tol=1e-6, restart=50, max_outer=10)
+    assert st32 in (vie.VIE_OK, vie.VIE_NOT_CONVERGED)
     x32 = x32.cpu().numpy().astype(np.complex128)
+    floor = 0.0
     for s in range(2):
         r = rel(opm.matvec(ref, epsc, x32[s], "A"), b[s])
-        say("   plain complex64 dipole %d: FP32 residual %.3e, FP64 residual %.3e"
-            % (s, i32[s]["rel_residual"], r))
-        assert r <= 1e-5
+        floor = max(floor, r)
+        assert i32[s]["converged"] == (i32[s]["rel_residual"] <= 1e-6)
+        say("   plain complex64 dipole %d: FP32 residual %.3e, FP64 residual %.3e, converged %s"
+            % (s, i32[s]["rel_residual"], r, i32[s]["converged"]))
+    if st32 == vie.VIE_NOT_CONVERGED:
+        say("   plain complex64 GMRES did not reach 1e-6; FP64 residual floor %.3e" % floor)
+    else:
+        assert all(i["converged"] for i in i32)
+    assert floor <= 1e-5
 
 
-def test_head_256_matvec_vs_dense_oracle():
+@pytest.mark.timeout(900)
+def test_head_256_matvec_vs_oracle():
     n = (256, 256, 256)
     h = 0.001
     G = vi.green_tensor(n, h, K0)
@@ -69,6 +89,15 @@ def test_head_256_matvec_vs_dense_oracle():
     b = vi.rhs_from_field(epsc, vi.plane_wave(n, h, F), F)
     op = vie.compress(G, tol=1e-6)
     y = vie.matvec(op, to_dev(b, torch.complex64), to_dev(epsc, torch.complex64)).cpu().numpy()
+    # the same Tucker operator: the oracle's HOSVD at the same tolerance
+    ref = opm.tucker_operator(G, 1e-6)
+    assert op.ranks == ref.ranks
+    yt = opm.matvec(ref, epsc, b, "A")
+    del ref
+    err_t = rel(y.astype(np.complex128), yt)
+    say("   256^3 matvec rel err vs the oracle's Tucker operator (FP32 only)", err_t)
+    assert err_t <= 1e-5
+    del yt
     dense = opm.dense_operator(G)
     yo = opm.matvec(dense, epsc, b, "A")
     del dense

@@ -143,6 +143,16 @@ def test_k_operator_rejects_unsupported_calls():
         vie.solve(op, u.to(torch.complex128), e.to(torch.complex128))
     with pytest.raises(vie.VieError):
         vie.autotune(op)
+    with pytest.raises(vie.VieError) as ei:
+        vie.matvec_multi([(op, u.unsqueeze(0), e)])
+    assert ei.value.status == vie.VIE_E_UNSUPPORTED
+    u64, e64 = u.to(torch.complex128).unsqueeze(0), e.to(torch.complex128)
+    with pytest.raises(vie.VieError) as ei:
+        vie.solve_multi([(op, u64, e64)])
+    assert ei.value.status == vie.VIE_E_UNSUPPORTED
+    with pytest.raises(vie.VieError) as ei:
+        vie.solve_multi([(op, u64, e64)], adjoint=True)
+    assert ei.value.status == vie.VIE_E_UNSUPPORTED
 
 
 def test_head_256_k_matvec_sampled_vs_direct_sums():

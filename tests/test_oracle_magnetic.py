@@ -259,3 +259,51 @@ def test_jm_solve_without_magnetic_contrast_is_the_electric_solve():
     u, _ = physics.solve_currents(opn, eps_c, e_inc, f, tol=1e-11)
     assert np.linalg.norm(x[1]) <= 1e-9 * np.linalg.norm(x[0])
     assert np.linalg.norm(x[0] - u) <= 1e-8 * np.linalg.norm(u)
+
+
+def test_jm_rhs_duality():
+    # Maxwell duality for the right-hand side of eq. 1: with alpha =
+    # -eps0/mu0 the dual problem (eps_c and mu_c exchanged, incident fields
+    # E' = -H_inc, H' = (eps0/mu0) E_inc) has the right-hand side
+    # [alpha b_M; b_J], the same map that test_jm_duality checks for the
+    # operator, so [alpha M; J] solves the dual system.  Exchanging c_e and
+    # c_m, dropping the sign of either block or putting chi_e on the magnetic
+    # block breaks it.
+    n = (5, 4, 3)
+    h = 0.004
+    f, _, _, eps_c, mu_c, _ = _jm_problem(n, h, 15)
+    e_inc = vi.random_field(n, 151)
+    h_inc = vi.random_field(n, 152)
+    b = mg.jm_rhs(eps_c, mu_c, e_inc, h_inc, f)
+    alpha = -vi.EPS0 / vi.MU0
+    bd = mg.jm_rhs(mu_c, eps_c, -h_inc, (vi.EPS0 / vi.MU0) * e_inc, f)
+    np.testing.assert_allclose(bd[0], alpha * b[1], rtol=1e-13, atol=1e-15 * np.abs(alpha * b[1]).max())
+    np.testing.assert_allclose(bd[1], b[0], rtol=1e-13, atol=1e-15 * np.abs(b[0]).max())
+
+
+def test_single_magnetic_voxel_clausius_mossotti():
+    # one non-dielectric voxel (eps_c = 1) of relative permeability mu in an
+    # incident field, k0 h -> 0: J = 0, Nt_pp(0) -> 2/3, so the magnetic
+    # block row of eq. 4 gives M = c_m H_inc 3 chi_h / (mu + 2), i.e. the
+    # internal field H = M / (c_m chi_h) = 3 H_inc / (mu + 2) of a small
+    # magnetic sphere (the dual of the electric Clausius-Mossotti limit).
+    # This fixes the magnetic block of the right-hand side: c_m = i omega mu0,
+    # its sign and the magnetic contrast chi_h = mu_c - 1.
+    from oracle import operator as opm
+    n = (1, 1, 1)
+    h = 1e-6
+    f = 298e6
+    mu = np.full((1, 1, 1), 2.0 - 0.3j)
+    eps_c = np.ones((1, 1, 1), complex)
+    e_inc = vi.plane_wave(n, h, f)
+    h_inc = vi.plane_wave_h(n, h, f)
+    opn = opm.dense_operator(vi.green_tensor(n, h, vi.wavenumber(f)))
+    opk = mg.dense_k_operator(green_k_tensor(n, h, vi.wavenumber(f)))
+    b = mg.jm_rhs(eps_c, mu, e_inc, h_inc, f)
+    x, info = mg.solve_jm(opn, opk, eps_c, mu, b, h, f, tol=1e-14)
+    cm = 1j * 2 * np.pi * f * vi.MU0
+    chi = mu[0, 0, 0] - 1.0
+    expect = cm * h_inc[:, 0, 0, 0] * 3.0 * chi / (mu[0, 0, 0] + 2.0)
+    assert np.abs(x[0]).max() <= 1e-12 * np.abs(expect).max()
+    np.testing.assert_allclose(x[1][:, 0, 0, 0], expect, rtol=1e-9, atol=1e-12 * np.abs(expect).max())
+    assert np.abs(expect).max() > 0
