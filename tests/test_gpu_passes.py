@@ -8,8 +8,8 @@
 * every pass on integer data with n_i in {1, 2} (FFT lengths 2 and 4: twiddles
   +-1, +-i, all arithmetic exact) equals the oracle's pass bit for bit, the
   z pass with an integer Tucker form, in all four modes;
-* every pass at register-FFT lengths against the oracle's pass (relative
-  1e-6 complex64, 1e-13 complex128);
+* every pass at register-FFT lengths against the oracle's pass on the same
+  (the oracle's) Tucker form (relative 1e-6 complex64, 1e-13 complex128);
 * the five debug passes in sequence equal vie_matvec bitwise."""
 import itertools
 
@@ -82,6 +82,23 @@ def _integer_op(n, seed):
     return vie.from_tucker(n, cores, factors), opm.FourierOperator(n, nhat)
 
 
+def _oracle_form_on_device(ref):
+    """The oracle's own HOSVD Tucker form uploaded with vie_op_from_tucker,
+    so that both sides apply the same operator (two HOSVD implementations
+    at tol 1e-6 give forms that differ far above the complex128 rounding);
+    the factor rows at offset 0 of odd axes, zero up to rounding, are set to
+    exact zeros as the upload requires."""
+    factors = []
+    for c in range(6):
+        signs = circulant.axis_signs(c)
+        Us = [U.copy() for U in ref.factors[c]]
+        for a in range(3):
+            if signs[a] < 0:
+                Us[a][0, :] = 0
+        factors.append(Us)
+    return vie.from_tucker(ref.n, ref.cores, factors)
+
+
 @pytest.mark.parametrize("n", list(itertools.product((1, 2), repeat=3)))
 @pytest.mark.parametrize("dt", DTYPES)
 def test_each_pass_is_bit_exact_on_integer_data(n, dt):
@@ -118,8 +135,8 @@ REG_GRIDS = [(64, 64, 64), (96, 112, 20), (112, 8, 128), (256, 6, 5), (12, 256, 
 def test_each_pass_matches_the_oracle_at_register_fft_lengths(n, dt):
     say("   passes", n, dt)
     G = vi.green_tensor(n, 0.004, K0)
-    op = vie.compress(G, tol=1e-6)
     ref = opm.tucker_operator(G, 1e-6)
+    op = _oracle_form_on_device(ref)
     n1, n2, n3 = n
     rng = np.random.default_rng(sum(n) + 1)
     x = rng.standard_normal((1, 3, n3, n2, n1)) + 1j * rng.standard_normal((1, 3, n3, n2, n1))
