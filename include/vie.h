@@ -225,6 +225,31 @@ vie_status vie_matvec_adjoint(const vie_op* op, int kind, int dtype, int recon, 
                               const void* x, void* y, int nrhs, void* ws, size_t ws_bytes,
                               void* stream);
 
+/*
+ * vie_matvec_noalloc -- the product of vie_matvec (adjoint = 0) or
+ * vie_matvec_adjoint (adjoint = 1) for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It allocates nothing and takes no workspace argument:
+ * the five passes run in a fixed scratch array of VIE_NOALLOC_SCRATCH_BYTES
+ * (256 MiB) that the library holds on each device it runs on until the
+ * process ends.  The caller still passes eps_c, x and y as for vie_matvec
+ * (same layouts, kinds, dtypes, recon values and results: the same kernels
+ * run).  The current device must be the operator's device.
+ * Limit: vie_workspace_bytes(op, dtype, nrhs) <= VIE_NOALLOC_SCRATCH_BYTES
+ * (e.g. a 96 x 112 x 128 grid with one complex64 right-hand side, 198 MB);
+ * larger requests return VIE_E_ARG before any launch.  No part of the
+ * scratch needs to start at zero: every pass writes all of what the next
+ * pass reads.  Every call on one device shares that device's array, so calls
+ * that overlap in time on one device (different streams or host threads)
+ * race and give undefined results; calls on one stream are ordered and safe.
+ * Not available while per-pass profiling is on (VIE_E_UNSUPPORTED).
+ * Asynchronous on `stream`.  Errors: VIE_E_ARG, VIE_E_UNSUPPORTED, VIE_E_HIP.
+ */
+#define VIE_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+size_t vie_noalloc_scratch_bytes(void);
+vie_status vie_matvec_noalloc(const vie_op* op, int kind, int adjoint, int dtype, int recon, const void* eps_c,
+                              const void* x, void* y, int nrhs, void* stream);
+
 typedef struct {
     double tol;        /* target relative residual ||b - A x|| / ||b|| (true residual) */
     int restart;       /* GMRES restart length m (inner iterations per cycle), 1..200 */

@@ -100,6 +100,9 @@ _SIGS = {
                                   ctypes.c_size_t, _P]),
     "vie_matvec_adjoint": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, ctypes.c_int,
                                           _P, ctypes.c_size_t, _P]),
+    "vie_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+    "vie_matvec_noalloc": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P,
+                                          ctypes.c_int, _P]),
     "vie_solve_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SolveOpts)]),
     "vie_solve": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int, ctypes.POINTER(SolveOpts),
                                  ctypes.POINTER(SolveInfo), _P, ctypes.c_size_t, _P]),
