@@ -72,6 +72,28 @@ def tucker_operator(green, tol, rule=0):
     return FourierOperator(n, nhat, ranks, factors, cores, svals)
 
 
+def cross_operator(n, entries_of, tol, rule=0, **kw):
+    """Tucker cross approximation (Sec. IV-A's cross-Tucker, ``cross.tucker_cross``)
+    of each defining tensor from its entries, then the Fourier-domain tensor
+    from the Tucker forms (Sec. V-A).  ``entries_of(c)`` returns the entries
+    callable (i, j, k) -> Nt_c of component c; the parity zeros of the odd
+    components are imposed.  ``op.cross_info`` holds each component's
+    counts."""
+    from .cross import green_entries, tucker_cross
+    nhat, ranks, factors, cores, infos = [], [], [], [], []
+    for c in range(6):
+        odd = [s < 0 for s in axis_signs(c)]
+        G, Us, info = tucker_cross(green_entries(entries_of(c), odd), n, tol, rule, **kw)
+        nhat.append(fourier_tensor_tucker(G, Us, axis_signs(c)))
+        ranks.append(tuple(U.shape[1] for U in Us))
+        factors.append(Us)
+        cores.append(G)
+        infos.append(info)
+    op = FourierOperator(n, nhat, ranks, factors, cores)
+    op.cross_info = infos
+    return op
+
+
 def tucker_cp_operator(green, tol, R=None, iters=1000, rule=0):
     """Tucker+CP of each defining tensor (Alg. 2: HOSVD at ``tol``, CP of the
     core with R terms by alternating least squares), then the Fourier-domain

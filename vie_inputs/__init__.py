@@ -18,12 +18,12 @@ from .grid import voxel_centres
 from .materials import complex_permittivity, TISSUES_298MHZ
 from .phantoms import sphere_phantom, head_phantom, head_semi_axes
 from .fields import plane_wave, plane_wave_h, dipole_field, dipole_ring, dipole_cylinder, rhs_from_field
-from .green import green_tensor, green_k_tensor
+from .green import GreenEntryCallback, green_entries, green_k_tensor, green_tensor
 from .random import random_field, random_complex
 
 __all__ = [
     "C0", "EPS0", "MU0", "COMPONENTS", "omega", "wavenumber", "voxel_centres",
     "complex_permittivity", "TISSUES_298MHZ", "sphere_phantom", "head_phantom",
     "head_semi_axes", "plane_wave", "plane_wave_h", "dipole_field", "dipole_ring", "dipole_cylinder",
-    "rhs_from_field", "green_tensor", "green_k_tensor", "random_field", "random_complex",
+    "rhs_from_field", "green_tensor", "green_k_tensor", "green_entries", "GreenEntryCallback", "random_field", "random_complex",
 ]

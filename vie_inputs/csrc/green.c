@@ -350,6 +350,59 @@ int vie_green_fill(int n1, int n2, int n3, double kappa, int near_q, int boost,
     return 0;
 }
 
+/* Entries of one component at arbitrary offsets: out[2 t], out[2 t + 1] =
+ * Nt_comp(D = idx[3 t .. 3 t + 2]) for t < count, computed exactly as
+ * vie_green_fill computes them (same per-offset quadrature), so the values
+ * equal the dense tensor's bit for bit.  Offsets must be non-negative.
+ * Used by fiber-sampling (cross) compressions, which never form the dense
+ * tensor. */
+int vie_green_entries(double kappa, int near_q, int boost, int comp, long count, const int *idx, double *out)
+{
+    gl_init();
+    if (near_q < 2 || near_q > QMAX || comp < 0 || comp > 5 || count < 0) return -1;
+    /* the 8 offsets with every D_i in {0, 1} (the singular shell) are
+     * evaluated once here and looked up below: fibers meet them often */
+    cplx nearv[8][6];
+#pragma omp parallel for schedule(static, 1)
+    for (int b = 0; b < 8; ++b) {
+        int D[3] = {b & 1, (b >> 1) & 1, (b >> 2) & 1};
+        near_entry(D, kappa, near_q, nearv[b]);
+    }
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(|: bad)
+    for (long t = 0; t < count; ++t) {
+        int D[3] = {idx[3 * t], idx[3 * t + 1], idx[3 * t + 2]};
+        if (D[0] < 0 || D[1] < 0 || D[2] < 0) {
+            bad = 1;
+            continue;
+        }
+        int d = D[0];
+        if (D[1] > d) d = D[1];
+        if (D[2] > d) d = D[2];
+        cplx e[6];
+        const cplx *src = e;
+        if (d <= 1) src = nearv[D[0] | (D[1] << 1) | (D[2] << 2)];
+        else far_entry(D, kappa, far_order(d, boost), e);
+        out[2 * t] = creal(src[comp]);
+        out[2 * t + 1] = cimag(src[comp]);
+    }
+    return bad ? -2 : 0;
+}
+
+/* The same as a callback of the shape the VIE library's cross compression
+ * takes: ctx points at {double kappa; int near_q; int boost;}. */
+typedef struct {
+    double kappa;
+    int near_q;
+    int boost;
+} vie_green_ctx;
+
+int vie_green_entry_cb(void *ctx, int comp, long count, const int *idx, double *out)
+{
+    const vie_green_ctx *g = (const vie_green_ctx *)ctx;
+    return vie_green_entries(g->kappa, g->near_q, g->boost, comp, count, idx, out);
+}
+
 /* ---------------- the K operator (curl of the single-layer potential) ----------------
  * Entries Kt_pq(D) = <P_D e_p, K P_0 e_q> / vol: observation voxel D, source
  * voxel 0, so that (K u)_p(m) = sum_m' Kt_pq(m - m') u_q(m') is a

@@ -5,6 +5,8 @@ the Galerkin entries used.  The result depends only on kappa = k0 h and the
 grid size: entries are normalised by the voxel volume, so that the identity
 part of the operator has unit diagonal.
 """
+import ctypes
+
 import numpy as np
 
 from . import _native
@@ -43,3 +45,38 @@ def green_k_tensor(n, h, k0, near_order=16, far_boost=0):
     if rc != 0:
         raise ValueError("vie_green_k_fill failed (%d)" % rc)
     return out[..., 0] + 1j * out[..., 1]
+
+
+def green_entries(idx, comp, h, k0, near_order=16, far_boost=0):
+    """Entries Nt_comp(D) of the defining tensor at the offsets ``idx``
+    (integer array (..., 3) of (i, j, k) >= 0), complex128 of shape
+    idx.shape[:-1]; bitwise equal to ``green_tensor(...)[comp, k, j, i]``."""
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int32))
+    if idx.shape[-1] != 3:
+        raise ValueError("idx must have shape (..., 3)")
+    flat = idx.reshape(-1, 3)
+    out = np.empty((flat.shape[0], 2), dtype=np.float64)
+    rc = _native.lib().vie_green_entries(float(k0) * float(h), int(near_order), int(far_boost), int(comp),
+                                         flat.shape[0], flat.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("vie_green_entries failed (%d)" % rc)
+    return (out[:, 0] + 1j * out[:, 1]).reshape(idx.shape[:-1])
+
+
+class GreenEntryCallback:
+    """C function pointer and context that evaluate defining-tensor entries
+    (``vie_green_entry_cb`` in csrc/green.c), in the form a fiber-sampling
+    compression takes: ``fn(ctx, comp, count, idx[count][3], out[count][2])``.
+    Keep this object alive while the pointer is in use."""
+
+    class _Ctx(ctypes.Structure):
+        _fields_ = [("kappa", ctypes.c_double), ("near_q", ctypes.c_int), ("boost", ctypes.c_int)]
+
+    def __init__(self, h, k0, near_order=16, far_boost=0):
+        self.ctx = self._Ctx(float(k0) * float(h), int(near_order), int(far_boost))
+        lib = _native.lib()
+        self.fn = ctypes.cast(lib.vie_green_entry_cb, ctypes.c_void_p)
+
+    @property
+    def ctx_ptr(self):
+        return ctypes.cast(ctypes.pointer(self.ctx), ctypes.c_void_p)
