@@ -12,7 +12,9 @@ tensor has G^(1) = V1 K1^T with K1 = khatri_rao(V2, V3); the least-squares
 update of V1 for fixed V2, V3 is G^(1) conj(K1) M1^{-1} with
 M1 = (V2^T conj V2) * (V3^T conj V3) (element-wise), and likewise for
 modes 2 and 3 in that order.  The start is deterministic: the leading R left
-singular vectors of each unfolding of the core (R <= min r_i).
+singular vectors of each unfolding of the core; a CP rank R above that
+mode's Tucker rank r (allowed: more terms fit the core better) adds columns
+of generic deterministic phases (``start_columns``).
 
 Parity pins (tests/test_oracle_cp.py): exact recovery of tensors built from
 known rank-R CP factors, rank-one exactness, a fit that never increases over
@@ -39,17 +41,33 @@ def cp_reconstruct(Vs, lam=None):
     return np.einsum("l,il,jl,kl->ijk", w, V1, V2, V3)
 
 
+GOLDEN = (np.sqrt(5.0) - 1.0) / 2.0
+
+
+def start_columns(U, R):
+    """CP start of one mode: the leading R left singular vectors of the
+    unfolding (its r columns); when R > r, columns j = r..R-1 are
+    exp(2 pi i frac(g (a + 1) (j + 1))) / sqrt(r) over the rows a, with g
+    the golden ratio conjugate (deterministic, generic phases)."""
+    r = U.shape[1]
+    if R <= r:
+        return U[:, :R].copy()
+    a = np.arange(U.shape[0], dtype=np.float64)[:, None] + 1.0
+    j = np.arange(r, R, dtype=np.float64)[None, :] + 1.0
+    ph = np.mod(GOLDEN * a * j, 1.0)
+    extra = np.exp(2j * np.pi * ph) / np.sqrt(r)
+    return np.concatenate([U, extra], axis=1)
+
+
 def cp_als(G, R, iters=1000, tol=0.0):
     """CP of G (r1 x r2 x r3) with R terms by alternating least squares.
     Returns ([V1, V2, V3], errors) with the relative Frobenius error after
     every sweep; stops early when a sweep improves it by less than ``tol``."""
     G = np.asarray(G, dtype=np.complex128)
-    if R > min(G.shape):
-        raise ValueError("CP rank must not exceed the smallest core dimension")
     Vs = []
     for mode in (1, 2, 3):
         U, _, _ = np.linalg.svd(unfold(G, mode), full_matrices=False)
-        Vs.append(U[:, :R].copy())
+        Vs.append(start_columns(U, R))
     norm = np.linalg.norm(G)
     errs = []
     for _ in range(iters):

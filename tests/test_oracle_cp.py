@@ -95,3 +95,27 @@ def test_tucker_cp_operator_exact_on_cp_tensors():
     y = opm.apply_N(op, u)
     yd = opm.apply_N(dense, u)
     assert np.linalg.norm(y - yd) <= 1e-8 * np.linalg.norm(yd)
+
+
+def test_cp_rank_above_the_core_size_recovers_a_unique_decomposition():
+    # a 5 x 6 x 7 tensor of CP rank 7 > 5: Kruskal's condition (k-ranks
+    # 5 + 6 + 7 >= 2 R + 2) makes the decomposition unique, and ALS from the
+    # padded start reaches it
+    rng = np.random.default_rng(4)
+    r, R = (5, 6, 7), 7
+    Vs = [rng.standard_normal((r[a], R)) + 1j * rng.standard_normal((r[a], R)) for a in range(3)]
+    G = cp.cp_reconstruct(Vs)
+    _, errs = cp.cp_als(G, R, 3000)
+    assert errs[-1] <= 1e-10
+
+
+def test_start_columns_beyond_the_singular_vectors():
+    U = np.linalg.qr(np.random.default_rng(1).standard_normal((4, 4)))[0]
+    S = cp.start_columns(U, 6)
+    assert np.array_equal(S[:, :4], U)
+    g = (np.sqrt(5) - 1) / 2
+    for a in range(4):
+        for j in (4, 5):
+            t = g * (a + 1) * (j + 1)
+            assert abs(S[a, j] - np.exp(2j * np.pi * (t - np.floor(t))) / 2.0) <= 1e-15
+    assert np.array_equal(cp.start_columns(U, 3), U[:, :3])
