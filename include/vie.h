@@ -17,7 +17,10 @@
  * (the "component decompression" of Sec. V-B, done per pencil, never into a
  * dense buffer).
  *
- * Beside it: the Tucker+CP form of Alg. 2 / eq. 17 (vie_compress_cp), the
+ * Beside it: the cross-Tucker compression named in Sec. IV-A, which reads
+ * only fibers of the defining tensors through an entry callback
+ * (vie_compress_cross, vie_tucker_cross), the Tucker+CP form of Alg. 2 /
+ * eq. 17 (vie_compress_cp), the
  * magnetic operator K of eq. 5 as a compressed operator of its own
  * (vie_compress_k) with the field and |b1+| of eq. 18
  * (vie_magnetic_field), and the full JMVIE system of eq. 4 with electric
@@ -122,13 +125,15 @@ vie_status vie_compress(const int n[3], const double* green, const vie_compress_
 /*
  * vie_compress_cp -- Tucker+CP compression (Alg. 2): the HOSVD of vie_compress
  * (same n, green, opts), then a CP decomposition of each core with cp_rank
- * terms (0 = the smallest of that core's Tucker ranks) by alternating least
- * squares, cp_iters sweeps (0 = 1000), started from the leading left singular
- * vectors of the core's unfoldings; the operator holds the Tucker+CP factors
- * W^i = U^i V^i (eq. 17) and the z pass builds each N^ pencil from them with
- * no core contraction.
+ * terms (0 = the smallest of that core's Tucker ranks; up to 64, also above
+ * the Tucker ranks, where more terms fit the core better) by alternating
+ * least squares, cp_iters sweeps (0 = 1000), started from the leading left
+ * singular vectors of the core's unfoldings (columns beyond a mode's Tucker
+ * rank r: exp(2 pi i frac(g (i + 1) (l + 1))) / sqrt(r), g = (sqrt 5 - 1) / 2);
+ * the operator holds the Tucker+CP factors W^i = U^i V^i (eq. 17) and the z
+ * pass builds each N^ pencil from them with no core contraction.
  *   cp_rel_err  HOST double[6] out (may be NULL): ||G_c - CP(G_c)||_F / ||G_c||_F.
- * Errors as vie_compress; VIE_E_ARG for a CP rank above a Tucker rank.
+ * Errors as vie_compress; VIE_E_UNSUPPORTED for a CP rank above 64.
  */
 vie_status vie_compress_cp(const int n[3], const double* green, const vie_compress_opts* opts, int cp_rank,
                            int cp_iters, vie_op** out, vie_compress_info* info, double cp_rel_err[6]);
@@ -174,6 +179,100 @@ vie_status vie_compress_k(const int n[3], const double* green_k, const vie_compr
  */
 vie_status vie_op_from_tucker(const int n[3], const int ranks[6][3], const double* cores, const double* factors,
                               vie_op** out, vie_compress_info* info);
+
+/*
+ * Entry callback of the cross compressions: write Nt_comp at `count` offsets
+ * idx[3 t], idx[3 t + 1], idx[3 t + 2] = (i, j, k), 0 <= i < n1, 0 <= j < n2,
+ * 0 <= k < n3 (the defining tensor of vie_compress), into out[2 t],
+ * out[2 t + 1] (complex128 interleaved).  Return 0, nonzero on failure.  The
+ * library calls it from one host thread at a time with whole batches of
+ * fibers (up to n_a times a few hundred entries); it may parallelise inside.
+ */
+typedef int (*vie_entry_fn)(void* ctx, int comp, long count, const int* idx, double* out);
+
+typedef struct {
+    double tol;          /* truncation tolerance, with trunc_rule and max_rank as in
+                            vie_compress_opts (applied to the fiber matrices and to the
+                            recompression of the cross core) */
+    int trunc_rule;
+    int max_rank;        /* 0 = no cap */
+    int oversample;      /* p: index-set size beyond the rank found (0 = 2) */
+    int max_sweeps;      /* sweep limit over the three modes (0 = 8) */
+    int n_sample;        /* extra random entries for an a-posteriori error estimate (0 = none) */
+    unsigned long long seed;   /* positions of those sample entries */
+} vie_cross_opts;
+
+typedef struct {
+    long evals[6];           /* entries read to build each component's Tucker form */
+    long evals_sample[6];    /* entries read for the error estimate */
+    int sweeps[6];           /* sweeps until the index sets stopped changing */
+    double sample_rel_err[6];/* estimate of ||A - A~||_F / ||A~||_F from the sample entries
+                                (V times their mean squared error) */
+    double seconds;          /* host time */
+} vie_cross_info;
+
+/*
+ * vie_compress_cross -- Tucker cross approximation (the cross-Tucker
+ * alternative to the HOSVD named in Sec. IV-A, cost linear in n) of each
+ * defining tensor from its entries, without the dense tensor: only mode
+ * fibers through index sets chosen by maxvol (alternating over the modes
+ * until the sets stop changing) and the entries at the sets' crossings are
+ * read through `fn`; the interpolation form is recompressed (QR of the
+ * factors, HOSVD of the small core at tol) to orthonormal factors and
+ * tolerance-based ranks, then embedded, transformed and uploaded as in
+ * vie_compress.  The parity zeros of xy, xz, yz (offset 0 along their odd
+ * axes) are taken as exact zeros whatever fn returns there.
+ *   n      HOST int[3], 1 <= n_i <= 256, 2 n_i a product of 2, 3, 5, 7.
+ *   fn, ctx  entry callback (see vie_entry_fn), components 0..5 = xx .. yz.
+ *   opts   HOST, may be NULL (tol 1e-6, rule 0, p 2, 8 sweeps, no sample).
+ *   out    receives the new operator; info (may be NULL) as vie_compress,
+ *          tail_bound and fro_norm of the recompressed core; xinfo (may be
+ *          NULL) the entry counts and the sampled error.
+ * Synchronous.  Errors: VIE_E_ARG (also a failing callback), VIE_E_NONFINITE,
+ * VIE_E_UNSUPPORTED, VIE_E_NOMEM, VIE_E_HIP.
+ */
+vie_status vie_compress_cross(const int n[3], vie_entry_fn fn, void* ctx, const vie_cross_opts* opts,
+                              vie_op** out, vie_compress_info* info, vie_cross_info* xinfo);
+
+/*
+ * vie_tucker_cross -- the same cross approximation of one component `comp`
+ * (0..5, with that component's parity zeros) on the host only, returned as
+ * a Tucker form: for grids of any size (1 <= n_i <= 65536; no FFT plan is
+ * needed) and for checking the compression by itself.
+ *   ranks    HOST int[3] out.
+ *   core     HOST complex128 out, [r1][r2][r3] (r3 fastest), core_cap complex
+ *            entries available (NULL: not returned).
+ *   factors  HOST complex128 out, U1 (n1 x r1), U2, U3 row-major one after
+ *            another, fac_cap complex entries available (NULL: not returned).
+ *   xinfo    HOST, may be NULL; the counts of this component sit at [comp].
+ * VIE_E_ARG if a given output is too small (ranks are still set).
+ */
+vie_status vie_tucker_cross(const int n[3], vie_entry_fn fn, void* ctx, int comp, const vie_cross_opts* opts,
+                            int ranks[3], double* core, size_t core_cap, double* factors, size_t fac_cap,
+                            vie_cross_info* xinfo);
+
+/*
+ * vie_tucker_hadamard -- one compressed component applied element-wise on
+ * its own grid: y = D .* x with D = G x1 U1 x2 U2 x3 U3 (Tucker, eq. 14) or
+ * D(i,j,k) = sum_l lambda_l U1(i,l) U2(j,l) U3(k,l) (Tucker+CP, eq. 17 with
+ * the CP weights folded into a diagonal core): the "decompression and
+ * element-wise product" of Sec. V-B that Table IV times (and, for CP, its
+ * 4-D loop), done in one pass with no buffer for D.  Building block and
+ * benchmark of the per-component step; the matvec itself reconstructs its
+ * Fourier-domain components inside the z pass.
+ *   n      HOST int[3] grid; r HOST int[3] ranks, 1 <= r_a <= 32 (cp: r1 = r2 = r3).
+ *   cp     0: core = G [r1][r2][r3] (r3 fastest); 1: core = lambda [r1].
+ *   dtype  VIE_C64 or VIE_C128 for every array.
+ *   core, u1, u2, u3  DEVICE; U_a is n_a x r_a row-major.
+ *   x, y   DEVICE [n3][n2][n1]; y may equal x (in place) but not partly overlap it.
+ *   ws     DEVICE workspace of vie_tucker_hadamard_ws_bytes (n3 r1 r2
+ *          complex for Tucker, none for CP; may be NULL then).
+ * Asynchronous on `stream`.  Errors: VIE_E_ARG, VIE_E_UNSUPPORTED, VIE_E_HIP.
+ */
+size_t vie_tucker_hadamard_ws_bytes(const int n[3], const int r[3], int cp, int dtype);
+vie_status vie_tucker_hadamard(const int n[3], const int r[3], int cp, int dtype, const void* core, const void* u1,
+                               const void* u2, const void* u3, const void* x, void* y, void* ws, size_t ws_bytes,
+                               void* stream);
 
 /* Release the operator's device memory.  NULL is accepted. */
 vie_status vie_op_destroy(vie_op* op);
@@ -499,7 +598,7 @@ vie_status vie_debug_hosvd(const int n[3], const double* tensor, double tol, int
  * vie_debug_cp: the CP step of vie_compress_cp (Alg. 2) for ONE core, with no
  * device work.
  *   r       HOST int[3], 1 <= r_i <= 64; core HOST complex128 [r1][r2][r3].
- *   R       CP rank, 1 <= R <= min r_i; iters: ALS sweeps (0 = start only).
+ *   R       CP rank, 1 <= R <= 64; iters: ALS sweeps (0 = start only).
  *   V       HOST complex128 out, V1 [r1][R] then V2 [r2][R] then V3 [r3][R],
  *           so that core ~ sum_l V1[:, l] (x) V2[:, l] (x) V3[:, l].
  *   rel_err HOST double out (may be NULL): ||core - CP||_F / ||core||_F.

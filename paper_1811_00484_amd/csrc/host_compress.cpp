@@ -475,9 +475,22 @@ double cp_als(const std::vector<cd>& G, const int r[3], int R, int iters, std::v
             U.assign((size_t)r[m] * r[m], 0);
             for (int i = 0; i < r[m]; ++i) U[(size_t)i * r[m] + i] = 1.0;
         }
+        // columns beyond the r_m singular vectors (a CP rank above this
+        // mode's Tucker rank): generic deterministic phases
+        // exp(2 pi i frac(g (i + 1) (l + 1))) / sqrt(r_m), g = (sqrt 5 - 1) / 2
+        const double g = (std::sqrt(5.0) - 1.0) / 2.0;
+        const double two_pi = 6.283185307179586476925286766559;
         V[m].assign((size_t)r[m] * R, 0);
         for (int i = 0; i < r[m]; ++i)
-            for (int l = 0; l < R; ++l) V[m][(size_t)i * R + l] = U[(size_t)i * r[m] + l];
+            for (int l = 0; l < R; ++l) {
+                if (l < r[m]) {
+                    V[m][(size_t)i * R + l] = U[(size_t)i * r[m] + l];
+                } else {
+                    const double t = g * (double)(i + 1) * (double)(l + 1);
+                    const double ph = t - std::floor(t);
+                    V[m][(size_t)i * R + l] = std::polar(1.0 / std::sqrt((double)r[m]), two_pi * ph);
+                }
+            }
     }
     auto fit_error = [&]() {
         double e = 0;

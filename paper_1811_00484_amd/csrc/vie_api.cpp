@@ -12,6 +12,7 @@
 
 #include "../../include/vie.h"
 #include "host_compress.h"
+#include "host_cross.h"
 #include "krylov.h"
 #include "vie_internal.h"
 
@@ -367,7 +368,7 @@ static vie_status compress_common(const int n[3], const double* green, const vie
             TuckerComponent& t = tc[c];
             const int rmin = std::min(t.r[0], std::min(t.r[1], t.r[2]));
             const int R = cp_rank == 0 ? rmin : cp_rank;
-            if (R > rmin) return fail(VIE_E_ARG, "vie_compress_cp: CP rank above the smallest Tucker rank");
+            if (R > 64) return fail(VIE_E_UNSUPPORTED, "vie_compress_cp: CP rank above 64");
             std::vector<cd> Vf[3];
             const double e = cp_als(t.G, t.r, R, cp_iters, Vf);
             if (cp_err) cp_err[c] = e;
@@ -391,6 +392,117 @@ static vie_status compress_common(const int n[3], const double* green, const vie
         }
     }
     return build_operator(n, plans, tc, out, info, t0);
+}
+
+static vie_status cross_params(const vie_cross_opts* opts, CrossParams& p, const char* who)
+{
+    if (opts) {
+        p.tol = opts->tol;
+        p.rule = opts->trunc_rule;
+        p.max_rank = opts->max_rank;
+        p.oversample = opts->oversample == 0 ? 2 : opts->oversample;
+        p.max_sweeps = opts->max_sweeps == 0 ? 8 : opts->max_sweeps;
+        p.n_sample = opts->n_sample;
+        p.seed = opts->seed;
+    }
+    if (!(p.tol > 0.0 && p.tol < 1.0) || (p.rule != 0 && p.rule != 1) || p.max_rank < 0 || p.max_rank > 64 ||
+        p.oversample < 0 || p.oversample > 16 || p.max_sweeps < 1 || p.max_sweeps > 100 || p.n_sample < 0 ||
+        p.n_sample > (1 << 24))
+        return fail(VIE_E_ARG, std::string(who) + ": bad options");
+    return VIE_OK;
+}
+
+static vie_status cross_status(int rc, const std::string& err, const char* who)
+{
+    if (rc == 0) return VIE_OK;
+    if (rc == -4) return fail(VIE_E_NONFINITE, std::string(who) + ": " + err);
+    if (rc == -1) return fail(VIE_E_ARG, std::string(who) + ": " + err);
+    return fail(VIE_E_UNSUPPORTED, std::string(who) + ": " + err);
+}
+
+vie_status vie_compress_cross(const int n[3], vie_entry_fn fn, void* ctx, const vie_cross_opts* opts,
+                              vie_op** out, vie_compress_info* info, vie_cross_info* xinfo)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!n || !fn || !out) return fail(VIE_E_ARG, "vie_compress_cross: null argument");
+    *out = nullptr;
+    for (int a = 0; a < 3; ++a)
+        if (n[a] < 1 || n[a] > 256) return fail(VIE_E_UNSUPPORTED, "vie_compress_cross: n_i must be in [1, 256]");
+    CrossParams p;
+    vie_status st = cross_params(opts, p, "vie_compress_cross");
+    if (st != VIE_OK) return st;
+    FftPlan plans[3];
+    for (int a = 0; a < 3; ++a)
+        if (!make_plan(2 * n[a], plans[a]))
+            return fail(VIE_E_UNSUPPORTED, "vie_compress_cross: 2 n_i must factor into 2, 3, 5, 7");
+    TuckerComponent tc[6];
+    vie_cross_info xi;
+    std::memset(&xi, 0, sizeof(xi));
+    for (int c = 0; c < 6; ++c) {
+        int odd[3];
+        for (int a = 0; a < 3; ++a) odd[a] = comp_odd(0, c, a);
+        CrossStats cs;
+        std::string err;
+        const int rc = tucker_cross(fn, ctx, c, odd, n, p, tc[c], cs, err);
+        if (rc != 0) return cross_status(rc, err, "vie_compress_cross");
+        xi.evals[c] = cs.evals;
+        xi.evals_sample[c] = cs.evals_sample;
+        xi.sweeps[c] = cs.sweeps;
+        xi.sample_rel_err[c] = cs.sample_rel_err;
+    }
+    xi.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    st = build_operator(n, plans, tc, out, info, t0);
+    if (st == VIE_OK && xinfo) *xinfo = xi;
+    return st;
+}
+
+vie_status vie_tucker_cross(const int n[3], vie_entry_fn fn, void* ctx, int comp, const vie_cross_opts* opts,
+                            int ranks[3], double* core, size_t core_cap, double* factors, size_t fac_cap,
+                            vie_cross_info* xinfo)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!n || !fn || !ranks) return fail(VIE_E_ARG, "vie_tucker_cross: null argument");
+    if (comp < 0 || comp > 5) return fail(VIE_E_ARG, "vie_tucker_cross: comp must be in [0, 5]");
+    for (int a = 0; a < 3; ++a)
+        if (n[a] < 1 || n[a] > 65536) return fail(VIE_E_ARG, "vie_tucker_cross: n_i must be in [1, 65536]");
+    CrossParams p;
+    vie_status st = cross_params(opts, p, "vie_tucker_cross");
+    if (st != VIE_OK) return st;
+    int odd[3];
+    for (int a = 0; a < 3; ++a) odd[a] = comp_odd(0, comp, a);
+    TuckerComponent tc;
+    CrossStats cs;
+    std::string err;
+    const int rc = tucker_cross(fn, ctx, comp, odd, n, p, tc, cs, err);
+    if (rc != 0) return cross_status(rc, err, "vie_tucker_cross");
+    for (int a = 0; a < 3; ++a) ranks[a] = tc.r[a];
+    if (xinfo) {
+        xinfo->evals[comp] = cs.evals;
+        xinfo->evals_sample[comp] = cs.evals_sample;
+        xinfo->sweeps[comp] = cs.sweeps;
+        xinfo->sample_rel_err[comp] = cs.sample_rel_err;
+        xinfo->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    const size_t ng = (size_t)tc.r[0] * tc.r[1] * tc.r[2];
+    const size_t nf = (size_t)n[0] * tc.r[0] + (size_t)n[1] * tc.r[1] + (size_t)n[2] * tc.r[2];
+    if ((core && core_cap < ng) || (factors && fac_cap < nf))
+        return fail(VIE_E_ARG, "vie_tucker_cross: output buffer too small for ranks (" + std::to_string(tc.r[0]) +
+                                   ", " + std::to_string(tc.r[1]) + ", " + std::to_string(tc.r[2]) + ")");
+    if (core)
+        for (size_t t = 0; t < ng; ++t) {
+            core[2 * t] = tc.G[t].real();
+            core[2 * t + 1] = tc.G[t].imag();
+        }
+    if (factors) {
+        size_t o = 0;
+        for (int a = 0; a < 3; ++a)
+            for (const auto& v : tc.U[a]) {
+                factors[2 * o] = v.real();
+                factors[2 * o + 1] = v.imag();
+                ++o;
+            }
+    }
+    return VIE_OK;
 }
 
 vie_status vie_op_from_tucker(const int n[3], const int ranks[6][3], const double* cores, const double* factors,
@@ -776,8 +888,7 @@ vie_status vie_debug_cp(const int r[3], const double* core, int R, int iters, do
     if (!r || !core || !V) return fail(VIE_E_ARG, "vie_debug_cp: null argument");
     for (int a = 0; a < 3; ++a)
         if (r[a] < 1 || r[a] > 64) return fail(VIE_E_ARG, "vie_debug_cp: bad core size");
-    if (R < 1 || R > std::min(r[0], std::min(r[1], r[2])) || iters < 0)
-        return fail(VIE_E_ARG, "vie_debug_cp: bad CP rank or iteration count");
+    if (R < 1 || R > 64 || iters < 0) return fail(VIE_E_ARG, "vie_debug_cp: bad CP rank or iteration count");
     using cd = std::complex<double>;
     const size_t nG = (size_t)r[0] * r[1] * r[2];
     std::vector<cd> G(nG);

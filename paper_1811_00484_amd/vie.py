@@ -50,6 +50,17 @@ class CompressInfo(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("cp", ctypes.c_int)]
 
 
+class CrossOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("trunc_rule", ctypes.c_int), ("max_rank", ctypes.c_int),
+                ("oversample", ctypes.c_int), ("max_sweeps", ctypes.c_int), ("n_sample", ctypes.c_int),
+                ("seed", ctypes.c_ulonglong)]
+
+
+class CrossInfo(ctypes.Structure):
+    _fields_ = [("evals", ctypes.c_long * 6), ("evals_sample", ctypes.c_long * 6), ("sweeps", ctypes.c_int * 6),
+                ("sample_rel_err", ctypes.c_double * 6), ("seconds", ctypes.c_double)]
+
+
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_outer", ctypes.c_int),
                 ("adjoint", ctypes.c_int), ("refine", ctypes.c_int), ("inner_recon", ctypes.c_int),
@@ -89,6 +100,15 @@ _SIGS = {
     "vie_solve_jm": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P,
                                     ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P, ctypes.c_size_t, _P]),
     "vie_magnetic_field": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
+    "vie_compress_cross": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, _P, ctypes.POINTER(CrossOpts),
+                                          ctypes.POINTER(_P), ctypes.POINTER(CompressInfo), ctypes.POINTER(CrossInfo)]),
+    "vie_tucker_cross": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, _P, ctypes.c_int, ctypes.POINTER(CrossOpts),
+                                        ctypes.POINTER(ctypes.c_int), _P, ctypes.c_size_t, _P, ctypes.c_size_t,
+                                        ctypes.POINTER(CrossInfo)]),
+    "vie_tucker_hadamard_ws_bytes": (ctypes.c_size_t, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                                       ctypes.c_int, ctypes.c_int]),
+    "vie_tucker_hadamard": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                           ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "vie_op_from_tucker": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _P, _P,
                                           ctypes.POINTER(_P), ctypes.POINTER(CompressInfo)]),
     "vie_op_destroy": (ctypes.c_int, [_P]),
@@ -377,6 +397,94 @@ def solve_jm(op_n, op_k, b, eps_c, mu_c, h, freq_hz, tol=1e-6, restart=50, max_o
          "refine_steps": info.refine_steps, "converged": bool(info.converged),
          "rel_residual": info.rel_residual, "history": hist[:info.hist_len].tolist()}
     return x, d, st
+
+
+def _cross_opts(tol, trunc_rule, max_rank, oversample, max_sweeps, n_sample, seed):
+    return CrossOpts(float(tol), int(trunc_rule), int(max_rank), int(oversample), int(max_sweeps), int(n_sample),
+                     int(seed))
+
+
+def _cross_info_dict(xi, comps):
+    return {"evals": [int(xi.evals[c]) for c in comps], "evals_sample": [int(xi.evals_sample[c]) for c in comps],
+            "sweeps": [int(xi.sweeps[c]) for c in comps],
+            "sample_rel_err": [float(xi.sample_rel_err[c]) for c in comps], "seconds": float(xi.seconds)}
+
+
+def compress_cross(n, entry_fn, ctx, tol=1e-6, trunc_rule=0, max_rank=0, oversample=0, max_sweeps=0, n_sample=0,
+                   seed=0):
+    """Cross-Tucker compression (vie_compress_cross) from an entry callback:
+    ``entry_fn`` a C function pointer (ctypes.c_void_p) of the vie_entry_fn
+    shape and ``ctx`` its context pointer.  Returns (Operator, info dict)."""
+    lib = load()
+    nn = (ctypes.c_int * 3)(*[int(v) for v in n])
+    opts = _cross_opts(tol, trunc_rule, max_rank, oversample, max_sweeps, n_sample, seed)
+    info = CompressInfo()
+    xi = CrossInfo()
+    h = ctypes.c_void_p()
+    _check(lib.vie_compress_cross(nn, entry_fn, ctx, ctypes.byref(opts), ctypes.byref(h), ctypes.byref(info),
+                                  ctypes.byref(xi)), "vie_compress_cross")
+    return Operator(h, tuple(int(v) for v in n), info), _cross_info_dict(xi, range(6))
+
+
+def tucker_cross(n, entry_fn, ctx, comp, tol=1e-6, trunc_rule=0, max_rank=0, oversample=0, max_sweeps=0,
+                 n_sample=0, seed=0):
+    """Host-only cross-Tucker form of one component (vie_tucker_cross).
+    Returns (core (r1, r2, r3), [U1, U2, U3], info dict), complex128."""
+    lib = load()
+    nn = (ctypes.c_int * 3)(*[int(v) for v in n])
+    opts = _cross_opts(tol, trunc_rule, max_rank, oversample, max_sweeps, n_sample, seed)
+    ranks = (ctypes.c_int * 3)()
+    rcap = 64 + 16
+    core = np.empty(2 * rcap ** 3, dtype=np.float64)
+    fac = np.empty(2 * rcap * sum(int(v) for v in n), dtype=np.float64)
+    xi = CrossInfo()
+    _check(lib.vie_tucker_cross(nn, entry_fn, ctx, int(comp), ctypes.byref(opts), ranks,
+                                core.ctypes.data_as(ctypes.c_void_p), rcap ** 3,
+                                fac.ctypes.data_as(ctypes.c_void_p), rcap * sum(int(v) for v in n),
+                                ctypes.byref(xi)), "vie_tucker_cross")
+    r = [int(ranks[a]) for a in range(3)]
+    cz = core[:2 * r[0] * r[1] * r[2]].view(np.complex128).reshape(r)
+    fz = fac.view(np.complex128)
+    Us, o = [], 0
+    for a in range(3):
+        Us.append(fz[o:o + int(n[a]) * r[a]].reshape(int(n[a]), r[a]).copy())
+        o += int(n[a]) * r[a]
+    return cz.copy(), Us, _cross_info_dict(xi, [int(comp)])
+
+
+def tucker_hadamard(core, factors, x, cp=False, out=None):
+    """y = D .* x for one component D = core x1 U1 x2 U2 x3 U3 (or, with
+    ``cp``, the CP form with weights ``core`` of length R) on the grid of x
+    (vie_tucker_hadamard).  ``core``, ``factors`` (U_a of shape (n_a, r_a))
+    and ``x`` (shape (n3, n2, n1)) are device tensors of one complex dtype."""
+    dt = _dt(x)
+    n3, n2, n1 = x.shape
+    _require_device(x, "x")
+    for name, t in [("core", core)] + [("U%d" % (a + 1), f) for a, f in enumerate(factors)]:
+        if t.dtype != x.dtype or t.device != x.device or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s tensor on %s" % (name, x.dtype, x.device))
+    r = [int(f.shape[1]) for f in factors]
+    if [int(f.shape[0]) for f in factors] != [n1, n2, n3]:
+        raise ValueError("factor rows must be (n1, n2, n3) = %s" % ((n1, n2, n3),))
+    if cp:
+        if tuple(core.shape) != (r[0],) or len(set(r)) != 1:
+            raise ValueError("a CP form takes weights of shape (R,) and factors of R columns")
+    elif tuple(core.shape) != tuple(r):
+        raise ValueError("core shape must equal the factor ranks %s" % (tuple(r),))
+    if not x.is_contiguous():
+        raise ValueError("x must be contiguous")
+    y = torch.empty_like(x) if out is None else out
+    if out is not None:
+        _require_like(out, x, x.shape, "out")
+    lib = load()
+    nn = (ctypes.c_int * 3)(n1, n2, n3)
+    rr = (ctypes.c_int * 3)(*r)
+    nbytes = lib.vie_tucker_hadamard_ws_bytes(nn, rr, int(bool(cp)), dt)
+    ws = torch.empty(max(1, int(nbytes)), dtype=torch.uint8, device=x.device)
+    _check(lib.vie_tucker_hadamard(nn, rr, int(bool(cp)), dt, _ptr(core), _ptr(factors[0]), _ptr(factors[1]),
+                                   _ptr(factors[2]), _ptr(x), _ptr(y), _ptr(ws), nbytes, _stream()),
+           "vie_tucker_hadamard")
+    return y
 
 
 def from_tucker(n, cores, factors):

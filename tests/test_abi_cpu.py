@@ -128,6 +128,28 @@ def test_host_cp_als_matches_oracle(c, iters):
     assert np.linalg.norm(rl - ro) <= (1e-10 if tight else 2e-6) * np.linalg.norm(ro)
 
 
+@pytest.mark.parametrize("iters", [0, 1, 30])
+def test_host_cp_above_the_tucker_rank_matches_oracle(iters):
+    # a CP rank above the core's smallest dimension: the extra start columns
+    # follow the same definition on both sides, so the sweeps agree
+    from oracle import cp
+    vie = _lib()
+    n = (14, 12, 10)
+    G = vi.green_tensor(n, 0.004, vi.wavenumber(298e6))
+    Gc, _, _ = tucker.hosvd(tucker.from_storage(G[0]), 1e-6)
+    R = int(1.5 * min(Gc.shape))
+    Vl, el = vie.debug_cp(Gc, R, iters)
+    Vo, eo = cp.cp_als(Gc, R, max(iters, 0))
+    if iters == 0:
+        for a in range(3):
+            assert np.allclose(np.abs(Vl[a]), np.abs(cp.start_columns(np.linalg.svd(tucker.unfold(Gc, a + 1),
+                                                                                       full_matrices=False)[0], R)),
+                               atol=1e-12)
+        return
+    rl, ro = cp.cp_reconstruct(Vl), cp.cp_reconstruct(Vo)
+    assert np.linalg.norm(rl - ro) <= (1e-9 if iters == 1 else 1e-5) * np.linalg.norm(ro)
+
+
 def test_host_cp_argument_errors():
     import ctypes
     vie = _lib()
@@ -136,7 +158,7 @@ def test_host_cp_argument_errors():
     r = (ctypes.c_int * 3)(3, 3, 2)
     V = np.empty(64, dtype=np.complex128)
     p = G.ctypes.data_as(ctypes.c_void_p)
-    assert lib.vie_debug_cp(r, p, 3, 5, V.ctypes.data_as(ctypes.c_void_p), None) == vie.VIE_E_ARG   # R > min r
+    assert lib.vie_debug_cp(r, p, 65, 5, V.ctypes.data_as(ctypes.c_void_p), None) == vie.VIE_E_ARG   # R > 64
     assert lib.vie_debug_cp(r, p, 0, 5, V.ctypes.data_as(ctypes.c_void_p), None) == vie.VIE_E_ARG
     assert lib.vie_debug_cp(r, None, 2, 5, V.ctypes.data_as(ctypes.c_void_p), None) == vie.VIE_E_ARG
     n = (ctypes.c_int * 3)(4, 4, 4)

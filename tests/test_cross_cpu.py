@@ -1,0 +1,103 @@
+"""The library's cross-Tucker compression on the host (vie_tucker_cross,
+through the C ABI; no device needed) against the oracle's cross scheme on
+the same entries: the same ranks and the same Tucker tensor to rounding,
+both within the tolerance of the dense tensor; argument and callback
+errors."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import vie_inputs as vi
+from oracle import circulant, cross, tucker
+
+K0 = vi.wavenumber(298e6)
+
+
+def _vie():
+    from paper_1811_00484_amd import vie
+    if not __import__("os").path.exists(vie.LIB_PATH):
+        from paper_1811_00484_amd import build
+        build.build()
+    return vie
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("n,h", [((32, 32, 32), 0.005), ((48, 40, 36), 0.004), ((9, 70, 5), 0.004)])
+@pytest.mark.parametrize("tol", [1e-6, 1e-8])
+@pytest.mark.parametrize("c", [0, 2, 3, 4])
+def test_library_cross_equals_the_oracle_cross(n, h, tol, c):
+    vie = _vie()
+    cb = vi.GreenEntryCallback(h, K0)
+    G, Us, info = vie.tucker_cross(n, cb.fn, cb.ctx_ptr, c, tol=tol)
+    odd = [s < 0 for s in circulant.axis_signs(c)]
+    fn = cross.green_entries(lambda i, j, k: vi.green_entries(np.stack([i, j, k], -1), c, h, K0), odd)
+    Go, Uo, io = cross.tucker_cross(fn, n, tol)
+    assert G.shape == Go.shape
+    B, Bo = tucker.tucker_reconstruct(G, *Us), tucker.tucker_reconstruct(Go, *Uo)
+    assert _rel(B, Bo) <= 1e-12
+    A = tucker.from_storage(vi.green_tensor(n, h, K0)[c])
+    for ax in range(3):
+        if odd[ax]:
+            sl = [slice(None)] * 3
+            sl[ax] = 0
+            A[tuple(sl)] = 0
+            assert np.abs(Us[ax][0]).max() == 0.0   # exact parity zeros in the library's factors
+    assert _rel(B, A) <= tol
+    assert info["evals"][0] > 0 and info["sweeps"][0] >= 2
+
+
+def test_sampled_error_estimate_tracks_the_true_error():
+    vie = _vie()
+    n, h = (48, 48, 48), 0.004
+    cb = vi.GreenEntryCallback(h, K0)
+    G, Us, info = vie.tucker_cross(n, cb.fn, cb.ctx_ptr, 0, tol=1e-6, n_sample=20000, seed=7)
+    A = tucker.from_storage(vi.green_tensor(n, h, K0)[0])
+    err = _rel(tucker.tucker_reconstruct(G, *Us), A)
+    est = info["sample_rel_err"][0]
+    assert info["evals_sample"][0] == 20000
+    assert err / 10 <= est <= err * 10
+
+
+def test_cross_argument_and_callback_errors():
+    vie = _vie()
+    lib = vie.load()
+    cb = vi.GreenEntryCallback(0.005, K0)
+    n = (ctypes.c_int * 3)(8, 8, 8)
+    ranks = (ctypes.c_int * 3)()
+    opts = vie.CrossOpts(1e-6, 0, 0, 0, 0, 0, 0)
+    assert lib.vie_tucker_cross(n, None, cb.ctx_ptr, 0, ctypes.byref(opts), ranks, None, 0, None, 0,
+                                None) == vie.VIE_E_ARG
+    assert lib.vie_tucker_cross(n, cb.fn, cb.ctx_ptr, 6, ctypes.byref(opts), ranks, None, 0, None, 0,
+                                None) == vie.VIE_E_ARG
+    bad = vie.CrossOpts(0.0, 0, 0, 0, 0, 0, 0)
+    assert lib.vie_tucker_cross(n, cb.fn, cb.ctx_ptr, 0, ctypes.byref(bad), ranks, None, 0, None, 0,
+                                None) == vie.VIE_E_ARG
+    # a core buffer too small for the ranks found: VIE_E_ARG, ranks still set
+    core = (ctypes.c_double * 2)()
+    assert lib.vie_tucker_cross(n, cb.fn, cb.ctx_ptr, 0, ctypes.byref(opts), ranks, core, 1, None, 0,
+                                None) == vie.VIE_E_ARG
+    assert min(ranks) >= 1
+    FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.POINTER(ctypes.c_int),
+                          ctypes.POINTER(ctypes.c_double))
+
+    def failing(ctx, comp, count, idx, out):
+        return 3
+
+    def nan_values(ctx, comp, count, idx, out):
+        for t in range(2 * count):
+            out[t] = float("nan")
+        return 0
+
+    for f, status in ((failing, vie.VIE_E_ARG), (nan_values, vie.VIE_E_NONFINITE)):
+        cf = FN(f)
+        assert lib.vie_tucker_cross(n, ctypes.cast(cf, ctypes.c_void_p), None, 0, ctypes.byref(opts), ranks, None,
+                                    0, None, 0, None) == status
+    # the device form checks its grid before reading any entry
+    h = ctypes.c_void_p()
+    big = (ctypes.c_int * 3)(300, 8, 8)
+    assert lib.vie_compress_cross(big, cb.fn, cb.ctx_ptr, ctypes.byref(opts), ctypes.byref(h), None,
+                                  None) == vie.VIE_E_UNSUPPORTED
