@@ -14,7 +14,11 @@ references, written out plainly:
    n_m x (|J_a| |J_b|); its SVD gives the rank r_m by the truncation rule of
    the HOSVD (relative to the fibers' own Frobenius norm), and J_m becomes
    the maxvol rows of the leading min(r_m + p, rank) left singular vectors
-   (p extra columns let the sets grow while the rank is still rising).
+   (p = 8 extra columns let the sets grow while the rank is still rising,
+   and give the interpolation enough fibers through the smooth far field:
+   with p = 2 the 256^3 Green's tensor at tol 1e-6 came out 7x the tolerance
+   in Frobenius norm and 8e-3 off in its sum, with p = 8 as accurate as the
+   HOSVD in both).
 3. Stop when a sweep leaves every index set unchanged (or after a sweep
    limit).
 4. Interpolation form: A ~= A(J1, J2, J3) x1 B1 x2 B2 x3 B3 with
@@ -94,7 +98,7 @@ def _fibers(entries, n, m, Ja, Jb):
     return np.asarray(entries(*np.broadcast_arrays(*idx)), dtype=np.complex128)
 
 
-def tucker_cross(entries, n, tol, rule=0, oversample=2, start=2, max_sweeps=8):
+def tucker_cross(entries, n, tol, rule=0, oversample=8, start=2, max_sweeps=8):
     """Tucker form (G, [U1, U2, U3]) of the n1 x n2 x n3 tensor whose entries
     ``entries(i, j, k)`` returns for integer index arrays of equal shape.
     Returns (G, Us, info) with info = dict(evals, sweeps, index_sets,

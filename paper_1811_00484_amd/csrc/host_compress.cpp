@@ -58,6 +58,11 @@ static void parallel_for(long n, F f, long min_chunk = 1)
     for (auto& t : th) t.join();
 }
 
+void parallel_rows(long n, const std::function<void(long, long)>& f)
+{
+    parallel_for(n, [&](long b, long e) { f(b, e); });
+}
+
 // Jacobi rotation parameters diagonalising [[a, c], [conj(c), b]] (a, b
 // real): returns cs, sn and the phase e^{i phi} of c.  The transform is
 // J = [[cs, sn], [-ph* sn, ph* cs]], J^H M J diagonal.

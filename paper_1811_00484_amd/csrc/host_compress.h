@@ -1,6 +1,7 @@
 // Host-side HOSVD compression (FP64) of the Green's defining tensors.
 #pragma once
 #include <complex>
+#include <functional>
 #include <vector>
 
 namespace vie {
@@ -15,6 +16,11 @@ struct TuckerComponent {
 };
 
 int host_threads();
+
+// f(begin, end) over [0, n) in contiguous chunks on the host threads; each
+// index is handled by exactly one call, so results written per index do not
+// depend on the thread count.
+void parallel_rows(long n, const std::function<void(long, long)>& f);
 
 // Left singular vectors (U, m x m row-major, columns by descending singular
 // value) and singular values of a row-major m x N matrix, m <= N.  With

@@ -8,9 +8,14 @@
 //  * index sets J1, J2, J3 start as s evenly spaced indices floor((t+1/2) n/s);
 //  * a sweep visits the modes m = 1, 2, 3: the mode-m fibers through every
 //    pair of the other two sets form C_m (n_m x |J_a||J_b|); its SVD gives
-//    the rank r_m by the HOSVD's truncation rule (relative to ||C_m||_F),
+//    the rank r_m by the HOSVD's truncation rule (relative to ||C_m||_F;
+//    above 96 columns and rows only the 96 leading singular triplets are
+//    computed, by randomized subspace iteration, with the norm of the rest
+//    formed explicitly),
 //    and J_m becomes the maxvol rows of its leading min(r_m + p, numerical
-//    rank) left singular vectors U_m;
+//    rank) left singular vectors U_m (p = 8 by default: enough fibers through
+//    the smooth far field for the interpolation to match the HOSVD's
+//    accuracy there);
 //  * sweeps stop when one leaves every set unchanged;
 //  * interpolation form A ~= A(J1, J2, J3) x_m U_m U_m[J_m]^{-1};
 //  * recompression: QR of each B_m = U_m U_m[J_m]^{-1}, the small core
@@ -189,6 +194,89 @@ void left_svd(const std::vector<cd>& C, int n, int K, std::vector<cd>& U, int& q
     matmul(Q, Ur, n, K, K, U);
 }
 
+// C (n x K) times M (K x m), or C^H (K x n) times M (n x m) with `herm`;
+// rows of the product on the host threads.
+void mat_apply(const std::vector<cd>& C, int n, int K, const std::vector<cd>& M, int m, bool herm,
+               std::vector<cd>& out)
+{
+    const int rows = herm ? K : n;
+    out.assign((size_t)rows * m, cd(0));
+    parallel_rows(rows, [&](long b, long e) {
+        for (long r = b; r < e; ++r) {
+            cd* o = &out[(size_t)r * m];
+            if (!herm) {
+                for (int t = 0; t < K; ++t) {
+                    const cd a = C[(size_t)r * K + t];
+                    const cd* mm = &M[(size_t)t * m];
+                    for (int c = 0; c < m; ++c) o[c] += a * mm[c];
+                }
+            } else {
+                for (int t = 0; t < n; ++t) {
+                    const cd a = std::conj(C[(size_t)t * K + r]);
+                    const cd* mm = &M[(size_t)t * m];
+                    for (int c = 0; c < m; ++c) o[c] += a * mm[c];
+                }
+            }
+        }
+    });
+}
+
+uint64_t splitmix(uint64_t& x);
+
+// The m leading left singular vectors (n x m) and values of C (n x K) and
+// the squared Frobenius norm resid2 of what they leave out, by randomized
+// subspace iteration (Halko, Martinsson, Tropp): a K x m test matrix of
+// unit-modulus entries with splitmix64 phases (fixed seed), two power steps,
+// orthonormalised after every product, then the exact SVD of the m x K
+// projection Q^H C and resid2 = ||C - Q Q^H C||_F^2 formed explicitly (no
+// cancellation).  When min(n, K) <= m every singular value is computed
+// exactly instead and resid2 = 0.
+void leading_svd(const std::vector<cd>& C, int n, int K, int m, std::vector<cd>& U, int& q, std::vector<double>& s,
+                 double& resid2)
+{
+    resid2 = 0;
+    if (std::min(n, K) <= m) {
+        left_svd(C, n, K, U, q, s);
+        return;
+    }
+    std::vector<cd> Om((size_t)K * m);
+    uint64_t st = 0x2545F4914F6CDD1Dull;
+    const double two_pi = 6.283185307179586476925286766559;
+    for (auto& v : Om) v = std::polar(1.0, two_pi * (double)(splitmix(st) >> 11) * (1.0 / 9007199254740992.0));
+    std::vector<cd> Y, Q, R, Z, Qz;
+    mat_apply(C, n, K, Om, m, false, Y);
+    householder_qr(Y, n, m, Q, R);
+    for (int it = 0; it < 2; ++it) {
+        mat_apply(C, n, K, Q, m, true, Z);
+        householder_qr(Z, K, m, Qz, R);
+        mat_apply(C, n, K, Qz, m, false, Y);
+        householder_qr(Y, n, m, Q, R);
+    }
+    // B = Q^H C (m x K) as (C^H Q)^H
+    mat_apply(C, n, K, Q, m, true, Z);
+    std::vector<cd> B((size_t)m * K);
+    for (int k = 0; k < K; ++k)
+        for (int c = 0; c < m; ++c) B[(size_t)c * K + k] = std::conj(Z[(size_t)k * m + c]);
+    std::vector<cd> Ub;
+    svd_left(B.data(), m, K, Ub, s, true);
+    matmul(Q, Ub, n, m, m, U);
+    q = m;
+    // resid2 = ||C - Q B||_F^2
+    std::vector<double> part(n, 0.0);
+    parallel_rows(n, [&](long b, long e) {
+        for (long i = b; i < e; ++i) {
+            double acc = 0;
+            for (int k = 0; k < K; ++k) {
+                cd v = C[(size_t)i * K + k];
+                for (int c = 0; c < m; ++c) v -= Q[(size_t)i * m + c] * B[(size_t)c * K + k];
+                acc += std::norm(v);
+            }
+            part[i] = acc;
+        }
+    });
+    for (int i = 0; i < n; ++i) resid2 += part[i];
+}
+
 // Greedy row pivots of U (n x r): r times the row of largest residual norm
 // (first on ties), then its direction removed from every row.
 std::vector<int> greedy_rows(const std::vector<cd>& U, int n, int r)
@@ -248,6 +336,30 @@ std::vector<int> maxvol(const std::vector<cd>& U, int n, int r)
     }
     std::sort(rows.begin(), rows.end());
     return rows;
+}
+
+// Leading singular triplets computed per fiber matrix (above every rank the
+// device takes, 64, plus the oversampling)
+constexpr int kLead = 96;
+
+// Truncation rank from the leading singular values s and the squared norm
+// resid2 of everything beyond them: rule 0, the smallest r whose tail
+// resid2 + sum_{k >= r} s_k^2 is at most (tol / sqrt 3)^2 ||C||_F^2; rule 1,
+// the count of s_k >= tol / sqrt(3) s_0.
+int cross_rank(const std::vector<double>& s, double resid2, double tol, int rule, double fro)
+{
+    if (rule == 1 || resid2 == 0.0) return truncation_rank(s, tol, rule, fro);
+    const int m = (int)s.size();
+    double thr2 = tol / std::sqrt(3.0) * fro;
+    thr2 *= thr2;
+    double tail = resid2;
+    std::vector<double> tails(m + 1);
+    tails[m] = resid2;
+    for (int k = m - 1; k >= 0; --k) tails[k] = tails[k + 1] + s[k] * s[k];
+    (void)tail;
+    for (int r = 1; r <= m; ++r)
+        if (tails[r] <= thr2) return r;
+    return m;
 }
 
 std::vector<int> start_indices(int n, int s)
@@ -343,11 +455,12 @@ int tucker_cross(vie_entry_fn fn, void* ctx, int comp, const int odd[3], const i
             std::vector<cd> Uc;
             std::vector<double> s;
             int q = 0;
-            left_svd(C, n[m], K, Uc, q, s);
+            double resid2 = 0;
+            leading_svd(C, n[m], K, kLead, Uc, q, s, resid2);
             double fro = 0;
             for (const cd& v : C) fro += std::norm(v);
             fro = std::sqrt(fro);
-            const int r = fro > 0 ? truncation_rank(s, p.tol, p.rule, fro) : 1;
+            const int r = fro > 0 ? cross_rank(s, resid2, p.tol, p.rule, fro) : 1;
             int numerical = 0;
             for (int t = 0; t < q; ++t)
                 if (s[0] > 0 && s[t] > s[0] * 1e-14) ++numerical;

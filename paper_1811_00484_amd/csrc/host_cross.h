@@ -12,7 +12,7 @@ struct CrossParams {
     double tol = 1e-6;
     int rule = 0;
     int max_rank = 0;
-    int oversample = 2;
+    int oversample = 8;
     int start = 2;
     int max_sweeps = 8;
     int n_sample = 0;
