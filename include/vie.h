@@ -196,7 +196,7 @@ typedef struct {
                             recompression of the cross core) */
     int trunc_rule;
     int max_rank;        /* 0 = no cap */
-    int oversample;      /* p: index-set size beyond the rank found (0 = 2) */
+    int oversample;      /* p: index-set size beyond the rank found (0 = 8) */
     int max_sweeps;      /* sweep limit over the three modes (0 = 8) */
     int n_sample;        /* extra random entries for an a-posteriori error estimate (0 = none) */
     unsigned long long seed;   /* positions of those sample entries */
@@ -224,7 +224,7 @@ typedef struct {
  * axes) are taken as exact zeros whatever fn returns there.
  *   n      HOST int[3], 1 <= n_i <= 256, 2 n_i a product of 2, 3, 5, 7.
  *   fn, ctx  entry callback (see vie_entry_fn), components 0..5 = xx .. yz.
- *   opts   HOST, may be NULL (tol 1e-6, rule 0, p 2, 8 sweeps, no sample).
+ *   opts   HOST, may be NULL (tol 1e-6, rule 0, p 8, 8 sweeps, no sample).
  *   out    receives the new operator; info (may be NULL) as vie_compress,
  *          tail_bound and fro_norm of the recompressed core; xinfo (may be
  *          NULL) the entry counts and the sampled error.
@@ -265,8 +265,9 @@ vie_status vie_tucker_cross(const int n[3], vie_entry_fn fn, void* ctx, int comp
  *   dtype  VIE_C64 or VIE_C128 for every array.
  *   core, u1, u2, u3  DEVICE; U_a is n_a x r_a row-major.
  *   x, y   DEVICE [n3][n2][n1]; y may equal x (in place) but not partly overlap it.
- *   ws     DEVICE workspace of vie_tucker_hadamard_ws_bytes (n3 r1 r2
- *          complex for Tucker, none for CP; may be NULL then).
+ *   ws     DEVICE workspace of vie_tucker_hadamard_ws_bytes: U1 transposed
+ *          (n1 r1 complex), V (n3 n2 r1 complex) and, for Tucker, W (n3 r1 r2
+ *          complex).
  * Asynchronous on `stream`.  Errors: VIE_E_ARG, VIE_E_UNSUPPORTED, VIE_E_HIP.
  */
 size_t vie_tucker_hadamard_ws_bytes(const int n[3], const int r[3], int cp, int dtype);

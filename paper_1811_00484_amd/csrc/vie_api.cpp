@@ -400,7 +400,7 @@ static vie_status cross_params(const vie_cross_opts* opts, CrossParams& p, const
         p.tol = opts->tol;
         p.rule = opts->trunc_rule;
         p.max_rank = opts->max_rank;
-        p.oversample = opts->oversample == 0 ? 2 : opts->oversample;
+        p.oversample = opts->oversample == 0 ? 8 : opts->oversample;
         p.max_sweeps = opts->max_sweeps == 0 ? 8 : opts->max_sweeps;
         p.n_sample = opts->n_sample;
         p.seed = opts->seed;
