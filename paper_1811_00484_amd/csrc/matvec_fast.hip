@@ -21,6 +21,13 @@
 #include "reg_fft.h"
 #include "vie_internal.h"
 
+// Extra complex elements at the end of every per-pencil LDS slice: the
+// slice stride sets the bank offset between the pencils of a transposed
+// row access.
+#ifndef VIE_SLICE_EXTRA
+#define VIE_SLICE_EXTRA 1
+#endif
+
 namespace vie {
 
 // ---------------------------------------------------------------------------
@@ -175,7 +182,7 @@ struct RegPlan<224> {
 
 template <int L>
 struct PL {
-    static constexpr int value = L + L / 8 + 1;
+    static constexpr int value = L + L / 8 + VIE_SLICE_EXTRA;
 };
 
 // ---------------------------------------------------------------------------
@@ -543,6 +550,72 @@ __device__ __forceinline__ void z_tables_mfma(const OpView& v, const unsigned sh
     }
 }
 
+typedef __attribute__((ext_vector_type(4))) float f32x4m;
+
+// N^ tables of a quad pair in FP32 on MFMA (v_mfma_f32_4x4x1f32: 16 blocks
+// of 4 x 4 per instruction, FP32 accumulate).  Per component the pair's
+// tables are the real product
+//   [Re T_A; Im T_A; Re T_B; Im T_B] (4 rows x k3) = A (4 x 2 r3) B (2 r3 x k3),
+// B's rows the real and imaginary parts of U3(k3, g), A's columns
+// (Re V_A, Im V_A, Re V_B, Im V_B) against Re U3 and
+// (-Im V_A, Re V_A, -Im V_B, Re V_B) against Im U3.  The z length fixes
+// N3 / 64 = the number of wavefronts: wavefront w takes the 64 rows
+// k3 = 64 w + lane of every component (block b of an instruction = rows
+// 64 w + 4 b + 0..3; lane l supplies A row l mod 4 and B column l mod 4 of
+// block l / 4 and receives the four rows of that column); the last row
+// k3 = N3 is done on the vector ALUs by 12 threads.  Eight z-factor rows are
+// loaded before their products, and four accumulators (Re / Im U3 halves,
+// even / odd g) keep consecutive MFMAs independent.
+template <int L3>
+__device__ __forceinline__ void z_tables_mfma32(const OpView& v, const c2<float>* __restrict__ fac,
+                                                const c2<float>* Vc, c2<float>* tabA, c2<float>* tabB, int tid)
+{
+    constexpr int N3 = L3 / 2;
+    const int rmax = v.rmax;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int k3 = 64 * wv + lane;
+    const int qrow = lane & 3;
+    const int qd = qrow >> 1, im = qrow & 1;
+#pragma unroll 1
+    for (int c = 0; c < 6; ++c) {
+        const int r3 = v.r[c][2];
+        const c2<float>* U3 = fac + v.fac3t_off[c] + k3;
+        const c2<float>* vq = Vc + qd * 6 * rmax + c * rmax;
+        f32x4m acc[4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+        for (int g0 = 0; g0 < r3; g0 += 8) {
+            // eight z-factor rows in flight, then their 16 products
+            c2<float> uv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) uv[q] = g0 + q < r3 ? U3[(long)(g0 + q) * (N3 + 1)] : mk<float>(0, 0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (g0 + q < r3) {
+                    const c2<float> w = vq[g0 + q];
+                    const float a0 = im ? w.y : w.x;     // coefficient of Re U3
+                    const float a1 = im ? w.x : -w.y;    // coefficient of Im U3
+                    acc[2 * (q & 1)] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0, uv[q].x, acc[2 * (q & 1)], 0, 0, 0);
+                    acc[2 * (q & 1) + 1] =
+                        __builtin_amdgcn_mfma_f32_4x4x1f32(a1, uv[q].y, acc[2 * (q & 1) + 1], 0, 0, 0);
+                }
+            }
+        }
+        const int o = c * (N3 + 1) + k3;
+        tabA[o] = mk<float>((acc[0][0] + acc[1][0]) + (acc[2][0] + acc[3][0]),
+                            (acc[0][1] + acc[1][1]) + (acc[2][1] + acc[3][1]));
+        tabB[o] = mk<float>((acc[0][2] + acc[1][2]) + (acc[2][2] + acc[3][2]),
+                            (acc[0][3] + acc[1][3]) + (acc[2][3] + acc[3][3]));
+    }
+    if (tid < 12) {
+        const int c = tid >> 1, q = tid & 1;
+        const int r3 = v.r[c][2];
+        const c2<float>* U3 = fac + v.fac3t_off[c] + N3;
+        const c2<float>* vq = Vc + q * 6 * rmax + c * rmax;
+        c2<float> acc = mk<float>(0, 0);
+        for (int g = 0; g < r3; ++g) fma_c(acc, vq[g], U3[(long)g * (N3 + 1)]);
+        (q ? tabB : tabA)[c * (N3 + 1) + N3] = acc;
+    }
+}
+
 // REC: 0 = N^ tables in T on the vector ALUs, 1 = BF16 z factors on MFMA
 // (T = float), 2 = a K operator (antisymmetric product, K parities; tables
 // on the vector ALUs).
@@ -673,6 +746,10 @@ __device__ __forceinline__ void z_body(c2<T>* __restrict__ S2, const c2<T>* __re
         //      and used for the two quads
         if (!a.dense && REC == 1) {
             if constexpr (REC == 1) z_tables_mfma<L3>(v, f3m, Vc, X, NTB, tid, NT);
+#ifndef VIE_Z_TABLES_VALU
+        } else if (!a.dense && sizeof(T) == 4) {
+            if constexpr (sizeof(T) == 4) z_tables_mfma32<L3>(v, fac, Vc, X, NTB, tid);
+#endif
         } else if (!a.dense) {
             for (int e = tid; e < NTS; e += NT) {
                 const int c = e / (N3 + 1), kk = e - c * (N3 + 1);
