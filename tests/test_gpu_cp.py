@@ -19,7 +19,7 @@ oracle's Tucker+CP.
   host test of the CP step), but the two HOSVD cores differ at the 1e-9
   level and 200 sweeps turn that into fits whose errors differ by up to
   ~50%.  So the end-to-end checks are properties: the library's fit error
-  is within a factor 3 of the oracle's, its Fourier-domain tensor obeys the
+  is within a factor 2 of the oracle's, its Fourier-domain tensor obeys the
   Tucker+CP error bound against the dense (uncompressed) spectrum, and its
   matvec differs from the oracle's Tucker+CP matvec by no more than the two
   fit errors together.
@@ -111,10 +111,11 @@ def test_compress_cp_end_to_end(n):
         assert op.ranks[c] == (R, R, R)
         say("   component %d: R %d, CP fit error library %.6e oracle %.6e"
             % (c, R, op.cp_rel_err[c], ref.cp_rel_err[c]))
-        # the same quality of fit: within a factor 3 (the host HOSVD sums its
-        # Gram matrix over as many threads as the machine has, so the core,
-        # and after 200 sweeps the fit, moves with the thread count)
-        assert ref.cp_rel_err[c] / 3.0 <= op.cp_rel_err[c] <= 3.0 * ref.cp_rel_err[c]
+        # the same quality of fit: within a factor 2 (the library's HOSVD is
+        # bitwise independent of the thread count, but its core differs from
+        # numpy's at the 1e-9 level, which 200 near-degenerate ALS sweeps
+        # amplify in the fit)
+        assert ref.cp_rel_err[c] / 2.0 <= op.cp_rel_err[c] <= 2.0 * ref.cp_rel_err[c]
     bound = max(op.cp_rel_err) + max(ref.cp_rel_err)
     u = vi.random_field(n, 32)
     for dt in (torch.complex128, torch.complex64):
