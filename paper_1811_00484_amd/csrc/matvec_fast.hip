@@ -647,8 +647,9 @@ __device__ __forceinline__ void z_body(c2<T>* __restrict__ S2, const c2<T>* __re
     // quad's table has a region of its own
     c2<T>* X = reinterpret_cast<c2<T>*>(smem_raw);
     c2<T>* NTB = X + 4 * P;                                     // [6][N3+1]
-    c2<T>* Wc = NTB + NTS;                                      // [6][rmax*rmax]
-    c2<T>* Vc = Wc + 6 * rmax * rmax;                           // [2][6][rmax]
+    c2<T>* Wc = NTB + NTS;                                      // [6][wst]
+    const int wst = v.cp ? rmax : rmax * rmax;                  // W_c stride per component
+    c2<T>* Vc = Wc + 6 * wst;                                   // [2][6][rmax]
     c2<T>* tws = Vc + 12 * rmax;                                // [Plan::TW]
     Plan::fill_tw(tws, tw, tid, NT);
 
@@ -667,7 +668,7 @@ __device__ __forceinline__ void z_body(c2<T>* __restrict__ S2, const c2<T>* __re
             const int c = e / rmax, l = e - c * rmax;
             const int R = v.r[c][0];
             if (l < R)
-                Wc[c * rmax * rmax + l] = core[v.core_off[c] + (long)l * (R * R + R + 1)] *
+                Wc[c * wst + l] = core[v.core_off[c] + (long)l * (R * R + R + 1)] *
                                                fac[v.fac_off[c][1] + (long)k2 * R + l];
         }
     } else if (!a.dense) {
@@ -690,7 +691,7 @@ __device__ __forceinline__ void z_body(c2<T>* __restrict__ S2, const c2<T>* __re
 #pragma unroll
                     for (int q = 0; q < 8; ++q) fma_c(acc, gv[q], uv[q]);
                 }
-                Wc[c * rmax * rmax + e] = acc;
+                Wc[c * wst + e] = acc;
             }
         }
     }
@@ -713,7 +714,7 @@ __device__ __forceinline__ void z_body(c2<T>* __restrict__ S2, const c2<T>* __re
                 const int c = rem / rmax, l = rem - c * rmax;
                 const int R = v.r[c][0];
                 if (l < R && (qd == 0 || hasB))
-                    Vc[e] = fac[v.fac_off[c][0] + (long)(qd ? kB : kA) * R + l] * Wc[c * rmax * rmax + l];
+                    Vc[e] = fac[v.fac_off[c][0] + (long)(qd ? kB : kA) * R + l] * Wc[c * wst + l];
             }
         } else if (!a.dense) {
             for (int e = tid; e < 12 * rmax; e += NT) {
@@ -723,7 +724,7 @@ __device__ __forceinline__ void z_body(c2<T>* __restrict__ S2, const c2<T>* __re
                 const int k1 = qd ? kB : kA;
                 if (ga < r3 && (qd == 0 || hasB)) {
                     const c2<T>* U1 = fac + v.fac_off[c][0] + (long)k1 * r1;
-                    const c2<T>* w = Wc + c * rmax * rmax + ga;
+                    const c2<T>* w = Wc + c * wst + ga;
                     c2<T> acc = mk<T>(0, 0);
                     for (int a0 = 0; a0 < r1; a0 += 8) {
                         c2<T> uv[8];
@@ -899,8 +900,11 @@ template <typename T, int L3>
 static size_t zfast_lds(const OpView& v)
 {
     static_assert(6 * (L3 / 2 + 1) <= 4 * PL<L3>::value, "N^ table must fit in the FFT slices");
-    return sizeof(c2<T>) * ((size_t)4 * PL<L3>::value + 6 * (L3 / 2 + 1) + 6 * (size_t)v.rmax * v.rmax +
-                            12 * v.rmax + RegPlan<L3>::TW);
+    // W_c holds r1 x r3 per component, or the R diagonal weights of a
+    // superdiagonal (Tucker+CP) core
+    const size_t wst = v.cp ? (size_t)v.rmax : (size_t)v.rmax * v.rmax;
+    return sizeof(c2<T>) * ((size_t)4 * PL<L3>::value + 6 * (L3 / 2 + 1) + 6 * wst + 12 * v.rmax +
+                            RegPlan<L3>::TW);
 }
 
 template <typename T, int L3>
