@@ -505,3 +505,304 @@ void vie_dyadic_points(long npts, const double *x, double kappa, double *out)
         }
     }
 }
+
+/* ================= piecewise-linear basis (eq. 7b) =================
+ *
+ * Per voxel four scalar functions: the pulse and the pulse times
+ * (x_a - x_a,m)/h for a = x, y, z.  Per axis the test function of voxel 0 is
+ * phi_al(t) and the basis function of voxel D is phi_be(t - D), with
+ * phi_0 = pulse on [-1/2, 1/2] and phi_1 = t * pulse.  As for pulses, the
+ * 6-D Galerkin integral of eq. 8a becomes a 3-D integral of g^ against the
+ * product over the axes of the correlations
+ *   c_{al be}(s) = int phi_al(t) phi_be(t + s) dt,   s = x - D,
+ * which are (type = al + 2 be)
+ *   type 0 (pulse test, pulse basis)    1 - |s|
+ *   type 1 (linear test, pulse basis)  -s (1 - |s|) / 2
+ *   type 2 (pulse test, linear basis)   s (1 - |s|) / 2
+ *   type 3 (linear test, linear basis)  1/12 - |s|/4 + |s|^3 / 6
+ * on |s| <= 1, zero outside.  With W_D(x) = prod_a c_{type_a}(x_a - D_a):
+ *   Nt^{pl,ql'}(D) = d_pq d_ll' m_l d_D0 + kappa^2 d_pq int g^ W_D
+ *                    + int g^ d_p d_q W_D                     (distributional)
+ * with the self products m = (1, 1/12, 1/12, 1/12).  d_p d_q W (p != q) has
+ * bounded first derivatives only; d_p^2 W has a regular part on the open
+ * cells plus point masses of c'' at s_p = -1, 0, 1 (pwl_jump), which turn
+ * into plane integrals.  Far from the singularity the smooth dyadic form
+ * int Gd_pq W_D is used, as for pulses.
+ *
+ * The ten pairs l <= l' are stored; the others follow from
+ * Nt^{(l',l)} = sigma Nt^{(l,l')}, sigma = -1 when exactly one of l, l' is
+ * the pulse (c_{type 2} = -c_{type 1}).
+ */
+static const int pwl_pairs[10][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 1}, {1, 2}, {1, 3}, {2, 2}, {2, 3}, {3, 3}};
+/* coefficients of the point masses of c'' at s = -1, 0, 1 per type */
+static const double pwl_jump[4][3] = {{1.0, -2.0, 1.0}, {0.5, 0.0, -0.5}, {-0.5, 0.0, 0.5}, {-0.25, -0.5, -0.25}};
+
+static inline int pwl_type(int P, int a)
+{
+    return (pwl_pairs[P][0] == a + 1) + 2 * (pwl_pairs[P][1] == a + 1);
+}
+
+/* values, first derivatives and regular second derivatives of the four
+ * correlation types at s (|s| < 1 and s != 0 on every quadrature point) */
+static inline void pwl_axis(double s, double v[4], double d1[4], double d2[4])
+{
+    double a = fabs(s);
+    if (a >= 1.0) {
+        for (int t = 0; t < 4; ++t) v[t] = d1[t] = d2[t] = 0.0;
+        return;
+    }
+    double sg = s > 0 ? 1.0 : (s < 0 ? -1.0 : 0.0);
+    v[0] = 1.0 - a;
+    d1[0] = -sg;
+    d2[0] = 0.0;
+    v[1] = -0.5 * s * (1.0 - a);
+    d1[1] = a - 0.5;
+    d2[1] = sg;
+    v[2] = -v[1];
+    d1[2] = -d1[1];
+    d2[2] = -sg;
+    v[3] = 1.0 / 12.0 - 0.25 * a + a * a * a / 6.0;
+    d1[3] = sg * (0.5 * s * s - 0.25);
+    d2[3] = a;
+}
+
+static int pwl_ty[10][3];
+static int pwl_ty_ready = 0;
+static void pwl_init(void)
+{
+    gl_init();
+    if (pwl_ty_ready) return;
+    for (int P = 0; P < 10; ++P)
+        for (int a = 0; a < 3; ++a) pwl_ty[P][a] = pwl_type(P, a);
+    pwl_ty_ready = 1;
+}
+
+/* far field: int Gd_pq(x) W_D(x) dx over the 8 unit cells around D */
+static void pwl_far_entry(const int D[3], double kappa, int q, cplx out[60])
+{
+    cplx acc[60];
+    for (int m = 0; m < 60; ++m) acc[m] = 0;
+    const double *gx = gl_x[q], *gw = gl_w[q];
+    for (int cell = 0; cell < 8; ++cell) {
+        double lo[3];
+        for (int a = 0; a < 3; ++a) lo[a] = ((cell >> a) & 1) ? 0.0 : -1.0;
+        for (int ia = 0; ia < q; ++ia)
+            for (int ib = 0; ib < q; ++ib)
+                for (int ic = 0; ic < q; ++ic) {
+                    double t[3] = {lo[0] + gx[ia], lo[1] + gx[ib], lo[2] + gx[ic]};
+                    double w = gw[ia] * gw[ib] * gw[ic];
+                    double x0 = D[0] + t[0], x1 = D[1] + t[1], x2 = D[2] + t[2];
+                    double r2 = x0 * x0 + x1 * x1 + x2 * x2;
+                    double r = sqrt(r2);
+                    cplx g = ghat(r, kappa);
+                    cplx ikr = I * kappa * r;
+                    cplx diag = g * (kappa * kappa - (1.0 + ikr) / r2);
+                    cplx radial = g * (3.0 + 3.0 * ikr - kappa * kappa * r2) / (r2 * r2);
+                    double xs[3] = {x0, x1, x2};
+                    cplx Gd[6];
+                    for (int c = 0; c < 6; ++c) {
+                        Gd[c] = radial * xs[comp_p[c]] * xs[comp_q[c]];
+                        if (comp_p[c] == comp_q[c]) Gd[c] += diag;
+                    }
+                    double v[3][4], d1[4], d2[4];
+                    for (int a = 0; a < 3; ++a) pwl_axis(t[a], v[a], d1, d2);
+                    for (int P = 0; P < 10; ++P) {
+                        double wt = w * v[0][pwl_ty[P][0]] * v[1][pwl_ty[P][1]] * v[2][pwl_ty[P][2]];
+                        for (int c = 0; c < 6; ++c) acc[P * 6 + c] += wt * Gd[c];
+                    }
+                }
+    }
+    for (int m = 0; m < 60; ++m) out[m] = acc[m];
+}
+
+/* volume weights at x (s = x - D) for all pairs: per pair
+ * [0] W, [1..3] d_p W d_q for xy, xz, yz, [4..6] regular d_p^2 W */
+static inline void pwl_vol_point(const double x[3], const int D[3], cplx g, cplx acc[70])
+{
+    double v[3][4], d1[3][4], d2[3][4];
+    for (int a = 0; a < 3; ++a) pwl_axis(x[a] - D[a], v[a], d1[a], d2[a]);
+    for (int P = 0; P < 10; ++P) {
+        const int t0 = pwl_ty[P][0], t1 = pwl_ty[P][1], t2 = pwl_ty[P][2];
+        cplx *o = acc + 7 * P;
+        o[0] += g * (v[0][t0] * v[1][t1] * v[2][t2]);
+        o[1] += g * (d1[0][t0] * d1[1][t1] * v[2][t2]);
+        o[2] += g * (d1[0][t0] * v[1][t1] * d1[2][t2]);
+        o[3] += g * (v[0][t0] * d1[1][t1] * d1[2][t2]);
+        o[4] += g * (d2[0][t0] * v[1][t1] * v[2][t2]);
+        o[5] += g * (v[0][t0] * d2[1][t1] * v[2][t2]);
+        o[6] += g * (v[0][t0] * v[1][t1] * d2[2][t2]);
+    }
+}
+
+static void pwl_near_volume(const int D[3], double kappa, int q, cplx acc[70])
+{
+    const double *gx = gl_x[q], *gw = gl_w[q];
+    for (int cell = 0; cell < 8; ++cell) {
+        double lo[3], sigma[3];
+        int corner = 1;
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = D[a] + (((cell >> a) & 1) ? 0.0 : -1.0);
+            if (lo[a] == 0.0) sigma[a] = 1.0;
+            else if (lo[a] == -1.0) sigma[a] = -1.0;
+            else corner = 0;
+        }
+        if (!corner) {
+            for (int ia = 0; ia < q; ++ia)
+                for (int ib = 0; ib < q; ++ib)
+                    for (int ic = 0; ic < q; ++ic) {
+                        double x[3] = {lo[0] + gx[ia], lo[1] + gx[ib], lo[2] + gx[ic]};
+                        double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+                        pwl_vol_point(x, D, ghat(r, kappa) * (gw[ia] * gw[ib] * gw[ic]), acc);
+                    }
+        } else {
+            /* Duffy: three pyramids with apex at the origin, Jacobian s^2 */
+            for (int face = 0; face < 3; ++face) {
+                int a1 = (face + 1) % 3, a2 = (face + 2) % 3;
+                for (int is = 0; is < q; ++is) {
+                    double s = gx[is];
+                    for (int ib = 0; ib < q; ++ib)
+                        for (int ic = 0; ic < q; ++ic) {
+                            double y[3];
+                            y[face] = s;
+                            y[a1] = s * gx[ib];
+                            y[a2] = s * gx[ic];
+                            double x[3] = {sigma[0] * y[0], sigma[1] * y[1], sigma[2] * y[2]};
+                            double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+                            pwl_vol_point(x, D, ghat(r, kappa) * (gw[is] * gw[ib] * gw[ic] * s * s), acc);
+                        }
+                }
+            }
+        }
+    }
+}
+
+/* plane integrals over x_p = c (the unit squares of the support in the
+ * other two axes) of g^ * c_{type_a}(x_a - D_a) c_{type_b}(x_b - D_b), all
+ * pairs: acc[P] */
+static void pwl_plane(int p, double c, const int D[3], double kappa, int q, cplx acc[10])
+{
+    const double *gx = gl_x[q], *gw = gl_w[q];
+    int a = (p + 1) % 3, b = (p + 2) % 3;
+    for (int cell = 0; cell < 4; ++cell) {
+        double lo2[2] = {D[a] + ((cell & 1) ? 0.0 : -1.0), D[b] + ((cell & 2) ? 0.0 : -1.0)};
+        int corner = (c == 0.0);
+        double sig2[2];
+        for (int m = 0; m < 2; ++m) {
+            if (lo2[m] == 0.0) sig2[m] = 1.0;
+            else if (lo2[m] == -1.0) sig2[m] = -1.0;
+            else corner = 0;
+        }
+        int npts = corner ? 2 * q * q : q * q;
+        for (int e = 0; e < npts; ++e) {
+            double xa, xb, r, w;
+            if (!corner) {
+                int i = e / q, j = e % q;
+                xa = lo2[0] + gx[i];
+                xb = lo2[1] + gx[j];
+                r = sqrt(c * c + xa * xa + xb * xb);
+                w = gw[i] * gw[j];
+            } else {
+                /* origin at a corner of the square in the plane through it:
+                 * two triangles with apex at the origin, Jacobian s */
+                int tri = e / (q * q), i = (e / q) % q, j = e % q;
+                double s = gx[i];
+                double ya = tri == 0 ? s : s * gx[j];
+                double yb = tri == 0 ? s * gx[j] : s;
+                xa = sig2[0] * ya;
+                xb = sig2[1] * yb;
+                r = sqrt(ya * ya + yb * yb);
+                w = gw[i] * gw[j] * s;
+            }
+            cplx g = ghat(r, kappa) * w;
+            double va[4], vb[4], d1[4], d2[4];
+            pwl_axis(xa - D[a], va, d1, d2);
+            pwl_axis(xb - D[b], vb, d1, d2);
+            for (int P = 0; P < 10; ++P) acc[P] += g * (va[pwl_ty[P][a]] * vb[pwl_ty[P][b]]);
+        }
+    }
+}
+
+/* distributional form, valid at every offset (the Duffy maps take care of
+ * cells and squares that have the origin at a corner) */
+static void pwl_near_entry(const int D[3], double kappa, int q, cplx out[60])
+{
+    cplx vol[70];
+    for (int m = 0; m < 70; ++m) vol[m] = 0;
+    pwl_near_volume(D, kappa, q, vol);
+    cplx diag[10][3];
+    for (int P = 0; P < 10; ++P)
+        for (int p = 0; p < 3; ++p) diag[P][p] = 0;
+    for (int p = 0; p < 3; ++p)
+        for (int sft = -1; sft <= 1; ++sft) {
+            cplx pl[10];
+            for (int P = 0; P < 10; ++P) pl[P] = 0;
+            pwl_plane(p, (double)(D[p] + sft), D, kappa, q, pl);
+            for (int P = 0; P < 10; ++P) diag[P][p] += pwl_jump[pwl_ty[P][p]][sft + 1] * pl[P];
+        }
+    const int self = (D[0] == 0 && D[1] == 0 && D[2] == 0);
+    for (int P = 0; P < 10; ++P) {
+        const int l = pwl_pairs[P][0], lp = pwl_pairs[P][1];
+        const double mass = (self && l == lp) ? (l == 0 ? 1.0 : 1.0 / 12.0) : 0.0;
+        const cplx *v = vol + 7 * P;
+        for (int p = 0; p < 3; ++p) out[P * 6 + p] = mass + kappa * kappa * v[0] + v[4 + p] + diag[P][p];
+        out[P * 6 + 3] = v[1];
+        out[P * 6 + 4] = v[2];
+        out[P * 6 + 5] = v[3];
+    }
+}
+
+/* Dense PWL defining tensors: out[(((P * 6 + c) * n3 + k) * n2 + j) * n1 + i]
+ * (complex128 interleaved) = Nt^{(l,l')}_c(D = (i, j, k)) for the pairs
+ * P = (0,0), (0,1), (0,2), (0,3), (1,1), (1,2), (1,3), (2,2), (2,3), (3,3)
+ * (test index l, basis index l'; 0 = pulse, 1..3 = linear in x, y, z) and
+ * c = xx, yy, zz, xy, xz, yz.  Offsets with every D_i <= 1 use the
+ * distributional form at Gauss order near_q, the others the smooth dyadic
+ * form at the pulse orders plus one (the weights are cubic per axis).
+ * Entries with linear offset index in [lo_lin, hi_lin) only. */
+int vie_green_pwl_fill(int n1, int n2, int n3, double kappa, int near_q, int boost, double *out, long lo_lin,
+                       long hi_lin)
+{
+    pwl_init();
+    if (near_q < 2 || near_q > QMAX) return -1;
+    long V = (long)n1 * n2 * n3;
+    if (hi_lin > V) hi_lin = V;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long lin = lo_lin; lin < hi_lin; ++lin) {
+        int D[3] = {(int)(lin % n1), (int)((lin / n1) % n2), (int)(lin / ((long)n1 * n2))};
+        int d = D[0];
+        if (D[1] > d) d = D[1];
+        if (D[2] > d) d = D[2];
+        cplx e[60];
+        if (d <= 1) pwl_near_entry(D, kappa, near_q, e);
+        else {
+            int q = far_order(d, boost) + 1;
+            pwl_far_entry(D, kappa, q > QMAX ? QMAX : q, e);
+        }
+        for (int m = 0; m < 60; ++m) {
+            out[2 * (m * V + lin)] = creal(e[m]);
+            out[2 * (m * V + lin) + 1] = cimag(e[m]);
+        }
+    }
+    return 0;
+}
+
+/* All 60 entries at one offset D (any signs allowed) by one method at Gauss
+ * order q: method 0 = distributional form (any D), 1 = smooth dyadic form
+ * (needs max |D_i| >= 2).  out: 60 complex interleaved, index P * 6 + c. */
+int vie_green_pwl_entry(const int D[3], double kappa, int q, int method, double *out)
+{
+    pwl_init();
+    if (q < 2 || q > QMAX || (method != 0 && method != 1)) return -1;
+    int d = abs(D[0]);
+    if (abs(D[1]) > d) d = abs(D[1]);
+    if (abs(D[2]) > d) d = abs(D[2]);
+    if (method == 1 && d < 2) return -1;
+    cplx e[60];
+    if (method == 0) pwl_near_entry(D, kappa, q, e);
+    else pwl_far_entry(D, kappa, q, e);
+    for (int m = 0; m < 60; ++m) {
+        out[2 * m] = creal(e[m]);
+        out[2 * m + 1] = cimag(e[m]);
+    }
+    return 0;
+}

@@ -1,4 +1,5 @@
-"""Galerkin Green's tensors of the volume operators N and K (PWC basis).
+"""Galerkin Green's tensors of the volume operators N and K (PWC basis) and
+of N for the piecewise-linear basis (eq. 7b).
 
 Thin wrapper over ``csrc/green.c``; see the header there for the reading of
 the Galerkin entries used.  The result depends only on kappa = k0 h and the
@@ -80,3 +81,46 @@ class GreenEntryCallback:
     @property
     def ctx_ptr(self):
         return ctypes.cast(ctypes.pointer(self.ctx), ctypes.c_void_p)
+
+
+#: basis-function pairs (test l, basis l') of the stored PWL tensors;
+#: 0 = pulse, 1..3 = pulse times (x - x_m)/h, (y - y_m)/h, (z - z_m)/h
+PWL_PAIRS = ((0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (1, 3), (2, 2), (2, 3), (3, 3))
+
+
+def pwl_pair_index(l, lp):
+    """Index of the stored pair holding (l, l') and the sign that turns it
+    into (l, l'): Nt^(l',l) = sigma Nt^(l,l'), sigma = -1 when exactly one
+    of the two is the pulse."""
+    a, b = (l, lp) if l <= lp else (lp, l)
+    sign = 1.0 if (l <= lp or (a != 0) == (b != 0)) else -1.0
+    return PWL_PAIRS.index((a, b)), sign
+
+
+def green_pwl_tensor(n, h, k0, near_order=16, far_boost=0):
+    """Dense PWL defining tensors, shape (10, 6, n3, n2, n1) complex128:
+    entry [P, c, k, j, i] = Nt^{(l,l')}_c(offset (i, j, k)) for the pair
+    P = PWL_PAIRS.index((l, l')) (test function l in voxel 0, basis
+    function l' in the voxel at the offset) and c = xx, yy, zz, xy, xz, yz.
+    The self products of the basis are (1, 1/12, 1/12, 1/12)."""
+    n1, n2, n3 = (int(v) for v in n)
+    V = n1 * n2 * n3
+    out = np.empty((10, 6, n3, n2, n1, 2), dtype=np.float64)
+    rc = _native.lib().vie_green_pwl_fill(n1, n2, n3, float(k0) * float(h), int(near_order),
+                                          int(far_boost), out.ctypes.data, 0, V)
+    if rc != 0:
+        raise ValueError("vie_green_pwl_fill failed (%d)" % rc)
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def green_pwl_entry(D, kappa, order, method=0):
+    """All 60 PWL entries at one offset D (any signs), shape (10, 6):
+    method 0 = the distributional form (any offset), 1 = the smooth dyadic
+    form (max |D_i| >= 2), each at Gauss order ``order``; kappa = k0 h."""
+    Dc = np.ascontiguousarray(np.asarray(D, dtype=np.int32).reshape(3))
+    out = np.empty((60, 2), dtype=np.float64)
+    rc = _native.lib().vie_green_pwl_entry(Dc.ctypes.data, float(kappa), int(order), int(method),
+                                           out.ctypes.data)
+    if rc != 0:
+        raise ValueError("vie_green_pwl_entry failed (%d)" % rc)
+    return (out[:, 0] + 1j * out[:, 1]).reshape(10, 6)
