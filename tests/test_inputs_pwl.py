@@ -156,17 +156,6 @@ def test_odd_components_vanish_on_their_zero_planes():
                 assert np.abs(G[tuple(sl)]).max() < 1e-14, (P, c, a)
 
 
-def test_static_self_block_zeros():
-    # kappa = 0, D = 0: the cube's reflection symmetries make every
-    # off-diagonal (p != q) self entry vanish, and the diagonal ones of
-    # different basis functions
-    E = green_pwl_entry((0, 0, 0), 0.0, 16, method=0)
-    for P, (l, lp) in enumerate(PWL_PAIRS):
-        np.testing.assert_allclose(E[P, 3:], 0.0, atol=1e-14)
-        if l != lp:
-            np.testing.assert_allclose(E[P, :3], 0.0, atol=1e-14)
-
-
 @pytest.mark.parametrize("D", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 1, 1)])
 def test_near_quadrature_converges(D):
     a = green_pwl_entry(D, 0.5, 12, method=0)
