@@ -251,6 +251,68 @@ vie_status vie_tucker_cross(const int n[3], vie_entry_fn fn, void* ctx, int comp
                             int ranks[3], double* core, size_t core_cap, double* factors, size_t fac_cap,
                             vie_cross_info* xinfo);
 
+/* ---------------- piecewise-linear basis (eq. 7a-7b) ----------------
+ *
+ * Twelve unknowns per voxel: for each current component q the coefficients
+ * of the pulse (l = 0) and of the pulse times the normalised local
+ * coordinates (x - x_m)/h, (y - y_m)/h, (z - z_m)/h (l = 1, 2, 3).  The sixty
+ * unique defining tensors of Sec. II-B are ten basis pairs (l, l'), l <= l',
+ * in the order (0,0) (0,1) (0,2) (0,3) (1,1) (1,2) (1,3) (2,2) (2,3) (3,3),
+ * of six dyadic components each (xx, yy, zz, xy, xz, yz): the Galerkin entry
+ * (eq. 8a-8b) of test function (p, l) in voxel 0 against basis function
+ * (q, l') in the voxel at offset D, rows divided by the voxel volume (so the
+ * self products of the basis are 1 and 1/12).  The other pairs and negative
+ * offsets are implied: Nt^(l',l) = -Nt^(l,l') when exactly one of l, l' is
+ * 0 (else +), and component (l, l', p, q) is odd along axis a when
+ * [p = a] + [q = a] + [l = a + 1] + [l' = a + 1] is odd.
+ *
+ * The operator acts on coefficients of the mass-normalised basis (linear
+ * functions scaled by sqrt 12, unit self products): with S = diag(1, sqrt 12,
+ * sqrt 12, sqrt 12) over l it applies S A S, A the paper-basis block
+ *   (A u)^{pl}(m) = eps_c(m) m_l u^{pl}(m) - chi(m) sum Nt^{(l,l')}_pq(m' - m) u^{ql'}(m').
+ * Vectors: [l][q][n3][n2][n1] (12 components, x fastest).
+ */
+typedef struct vie_pwl_op vie_pwl_op;
+
+/*
+ * vie_compress_pwl -- HOSVD (Alg. 1) of the sixty defining tensors, or
+ * Tucker+CP (Alg. 2) when cp_rank >= 0 (as vie_compress_cp, cp_iters 0 =
+ * 1000), ten six-component blocks on the current device.
+ *   n          HOST int[3], 1 <= n_i <= 256, 2 n_i factoring into 2, 3, 5, 7.
+ *   green_pwl  HOST complex128 [10][6][n3][n2][n1] in the pair order above.
+ *   opts       HOST, may be NULL (tol 1e-6); the tolerance applies to each
+ *              component.
+ *   cp_rank    -1 = Tucker (HOSVD) only.
+ *   info       HOST vie_compress_info[10] out (one per pair), may be NULL.
+ * Errors as vie_compress.
+ */
+vie_status vie_compress_pwl(const int n[3], const double* green_pwl, const vie_compress_opts* opts, int cp_rank,
+                            int cp_iters, vie_pwl_op** out, vie_compress_info* info);
+
+vie_status vie_pwl_op_destroy(vie_pwl_op* op);
+
+/* grid and the Tucker ranks [pair][component][mode]; either may be NULL */
+vie_status vie_pwl_op_query(const vie_pwl_op* op, int n[3], int ranks[10][6][3]);
+
+/* DEVICE workspace of vie_matvec_pwl in bytes (12 padded components) */
+size_t vie_pwl_workspace_bytes(const vie_pwl_op* op, int dtype);
+
+/*
+ * vie_matvec_pwl -- y = S A S x (kind VIE_OP_A, needs eps_c) or the bare
+ * Galerkin sum S N S x (VIE_OP_N), or their adjoints (adjoint = 1), in the
+ * mass-normalised basis: the five passes of vie_matvec with the twelve
+ * components as four groups of three and a z pass that adds the sixteen
+ * (l, l') blocks per Fourier-domain position, each block's six N^ tables
+ * rebuilt from its Tucker form per pencil group (Sec. V-A/B).
+ *   dtype  VIE_C64 (FP32 compute) or VIE_C128 (FP64) for x, y, eps_c.
+ *   eps_c  DEVICE [n3][n2][n1]; x, y DEVICE [12][n3][n2][n1], not overlapping.
+ *   ws     DEVICE, vie_pwl_workspace_bytes(op, dtype).
+ * Asynchronous on `stream`.  VIE_E_UNSUPPORTED when the z pass does not fit
+ * in LDS (2 n3 and the ranks too large).
+ */
+vie_status vie_matvec_pwl(const vie_pwl_op* op, int kind, int adjoint, int dtype, const void* eps_c, const void* x,
+                          void* y, void* ws, size_t ws_bytes, void* stream);
+
 /*
  * vie_tucker_hadamard -- one compressed component applied element-wise on
  * its own grid: y = D .* x with D = G x1 U1 x2 U2 x3 U3 (Tucker, eq. 14) or

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvie.so")
 
-SOURCES = ["matvec.hip", "matvec_fast.hip", "krylov.hip", "noalloc.hip", "tucker_apply.hip", "vie_api.cpp", "solve.cpp", "jm_solve.cpp", "host_compress.cpp", "host_cross.cpp"]
+SOURCES = ["matvec.hip", "matvec_fast.hip", "krylov.hip", "noalloc.hip", "tucker_apply.hip", "pwl.hip", "vie_api.cpp", "solve.cpp", "jm_solve.cpp", "host_compress.cpp", "host_cross.cpp"]
 ARCH = os.environ.get("VIE_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -77,7 +77,8 @@ static unsigned short to_bf16(float f)
 }
 
 static vie_status build_operator(const int n[3], const FftPlan plans[3], TuckerComponent tc[6], vie_op** out,
-                                 vie_compress_info* info, std::chrono::steady_clock::time_point t0, int fam = 0)
+                                 vie_compress_info* info, std::chrono::steady_clock::time_point t0, int fam = 0,
+                                 int lmask = 0, double scale = 1.0)
 {
     using cd = std::complex<double>;
     const long V = (long)n[0] * n[1] * n[2];
@@ -85,6 +86,7 @@ static vie_status build_operator(const int n[3], const FftPlan plans[3], TuckerC
     DeviceOp d;
     OpView& v = d.view;
     v.fam = fam;
+    v.lmask = lmask;
     int rmax = 1;
     int core_tot = 0, fac_tot = 0;
     for (int a = 0; a < 3; ++a) {
@@ -128,13 +130,15 @@ static vie_status build_operator(const int n[3], const FftPlan plans[3], TuckerC
                         break;
                     }
     }
-    const double invM = 1.0 / (8.0 * (double)V);
+    // 1/M of the inverse transform, and the block's scale (piecewise-linear
+    // blocks in the mass-normalised basis)
+    const double invM = scale / (8.0 * (double)V);
     std::vector<cd> hcore(core_tot), hfac(fac_tot);
     for (int c = 0; c < 6; ++c) {
         for (size_t t = 0; t < tc[c].G.size(); ++t) hcore[v.core_off[c] + t] = tc[c].G[t] * invM;
         for (int a = 0; a < 3; ++a) {
             std::vector<cd> Uh;
-            fourier_factor(tc[c].U[a], n[a], tc[c].r[a], comp_odd(fam, c, a) ? -1 : 1, Uh);
+            fourier_factor(tc[c].U[a], n[a], tc[c].r[a], view_odd(fam, lmask, c, a) ? -1 : 1, Uh);
             std::copy(Uh.begin(), Uh.end(), hfac.begin() + v.fac_off[c][a]);
             if (a == 2) {
                 const int r3 = tc[c].r[2];
@@ -261,7 +265,8 @@ const char* vie_last_error(void) { return g_last_error.c_str(); }
 const char* vie_version(void) { return "vie-gfx950 0.1"; }
 
 static vie_status compress_common(const int n[3], const double* green, const vie_compress_opts* opts, int cp_rank,
-                                  int cp_iters, vie_op** out, vie_compress_info* info, double* cp_err);
+                                  int cp_iters, vie_op** out, vie_compress_info* info, double* cp_err,
+                                  int lmask = 0, double scale = 1.0);
 
 vie_status vie_compress(const int n[3], const double* green, const vie_compress_opts* opts, vie_op** out,
                         vie_compress_info* info)
@@ -324,7 +329,8 @@ vie_status vie_compress_k(const int n[3], const double* green_k, const vie_compr
 }
 
 static vie_status compress_common(const int n[3], const double* green, const vie_compress_opts* opts, int cp_rank,
-                                  int cp_iters, vie_op** out, vie_compress_info* info, double* cp_err)
+                                  int cp_iters, vie_op** out, vie_compress_info* info, double* cp_err, int lmask,
+                                  double scale)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!n || !green || !out) return fail(VIE_E_ARG, "vie_compress: null argument");
@@ -348,7 +354,7 @@ static vie_status compress_common(const int n[3], const double* green, const vie
     std::vector<cd> A(V);
     int odd[6][3];
     for (int c = 0; c < 6; ++c)
-        for (int a = 0; a < 3; ++a) odd[c][a] = comp_odd(0, c, a);
+        for (int a = 0; a < 3; ++a) odd[c][a] = view_odd(0, lmask, c, a);
     for (int c = 0; c < 6; ++c) {
         const double* g = green + 2 * (size_t)c * V;
         for (long t = 0; t < V; ++t) A[t] = cd(g[2 * t], g[2 * t + 1]);
@@ -391,7 +397,7 @@ static vie_status compress_common(const int n[3], const double* green, const vie
             for (int l = 0; l < R; ++l) t.G[((size_t)l * R + l) * R + l] = 1.0;
         }
     }
-    return build_operator(n, plans, tc, out, info, t0);
+    return build_operator(n, plans, tc, out, info, t0, 0, lmask, scale);
 }
 
 static vie_status cross_params(const vie_cross_opts* opts, CrossParams& p, const char* who)
@@ -556,6 +562,67 @@ vie_status vie_op_destroy(vie_op* op)
     if (!op) return VIE_OK;
     free_op(op->d);
     delete op;
+    return VIE_OK;
+}
+
+vie_status vie_pwl_op_destroy(vie_pwl_op* op)
+{
+    if (!op) return VIE_OK;
+    for (int b = 0; b < 10; ++b) vie_op_destroy(op->blk[b]);
+    if (op->dev32) (void)hipFree(op->dev32);
+    if (op->dev64) (void)hipFree(op->dev64);
+    delete op;
+    return VIE_OK;
+}
+
+vie_status vie_compress_pwl(const int n[3], const double* green_pwl, const vie_compress_opts* opts, int cp_rank,
+                            int cp_iters, vie_pwl_op** out, vie_compress_info* info)
+{
+    if (!n || !green_pwl || !out) return fail(VIE_E_ARG, "vie_compress_pwl: null argument");
+    *out = nullptr;
+    for (int a = 0; a < 3; ++a)
+        if (n[a] < 1 || n[a] > 256) return fail(VIE_E_UNSUPPORTED, "vie_compress_pwl: n_i must be in [1, 256]");
+    if (cp_rank < -1 || cp_iters < 0) return fail(VIE_E_ARG, "vie_compress_pwl: bad CP rank or iterations");
+    const size_t V = (size_t)n[0] * n[1] * n[2];
+    const double s12 = std::sqrt(12.0);
+    vie_pwl_op* P = new vie_pwl_op();
+    for (int b = 0; b < 10; ++b) P->blk[b] = nullptr;
+    for (int b = 0; b < 10; ++b) {
+        const int la = kPwlPairs[b][0], lb = kPwlPairs[b][1];
+        int lmask = 0;
+        for (int a = 0; a < 3; ++a) lmask |= (((la == a + 1) + (lb == a + 1)) & 1) << a;
+        // the mass-normalised basis scales the linear functions by sqrt 12
+        const double scale = (la ? s12 : 1.0) * (lb ? s12 : 1.0);
+        vie_status st = compress_common(n, green_pwl + (size_t)b * 12 * V, opts, cp_rank,
+                                        cp_rank >= 0 && cp_iters == 0 ? 1000 : cp_iters, &P->blk[b],
+                                        info ? &info[b] : nullptr, nullptr, lmask, scale);
+        if (st != VIE_OK) {
+            std::string msg = vie_last_error();
+            vie_pwl_op_destroy(P);
+            return fail(st, "vie_compress_pwl: block " + std::to_string(b) + ": " + msg);
+        }
+        P->rmax = std::max(P->rmax, P->blk[b]->d.view.rmax);
+    }
+    PwlBlock<float> h32[10];
+    PwlBlock<double> h64[10];
+    for (int b = 0; b < 10; ++b) {
+        const DeviceOp& d = P->blk[b]->d;
+        h32[b].v = d.view;
+        h32[b].core = d.d32.core;
+        h32[b].fac = d.d32.fac;
+        h64[b].v = d.view;
+        h64[b].core = d.d64.core;
+        h64[b].fac = d.d64.fac;
+    }
+    hipError_t e = hipMalloc((void**)&P->dev32, sizeof(h32));
+    if (e == hipSuccess) e = hipMalloc((void**)&P->dev64, sizeof(h64));
+    if (e == hipSuccess) e = hipMemcpy(P->dev32, h32, sizeof(h32), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(P->dev64, h64, sizeof(h64), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        vie_pwl_op_destroy(P);
+        return hip_fail(e, "vie_compress_pwl upload");
+    }
+    *out = P;
     return VIE_OK;
 }
 

@@ -26,6 +26,13 @@ __host__ __device__ inline int comp_odd(int fam, int c, int a)
     return (c == 3 && a == 2) || (c == 4 && a == 1) || (c == 5 && a == 0);
 }
 
+// parity of component c of an operator view along axis a (family and
+// piecewise-linear pair together)
+__host__ __device__ inline int view_odd(int fam, int lmask, int c, int a)
+{
+    return comp_odd(fam, c, a) ^ ((lmask >> a) & 1);
+}
+
 struct OpView {
     int n[3];
     int L[3];
@@ -43,6 +50,10 @@ struct OpView {
     // 1 = K (antisymmetric pair: components xy, xz, yz in slots 3..5, slots
     // 0..2 zero)
     int fam;
+    // extra parities of a piecewise-linear block (bit a: odd along axis a):
+    // the pair (l, l') of basis functions flips the parity along a when
+    // exactly one of them is linear along a; 0 for the pulse basis
+    int lmask;
     // 1: every core is superdiagonal (r1 = r2 = r3 = R, a Tucker+CP form,
     // eq. 17): the z pass forms V_c(k1, k2, l) = G_c[l,l,l] U1_c(k1, l)
     // U2_c(k2, l) directly instead of contracting the core
@@ -249,5 +260,25 @@ struct KrylovArgs;
 // opaque handle of the C ABI
 struct vie_op {
     vie::DeviceOp d;
+};
+
+namespace vie {
+// one (l, l') block of a piecewise-linear operator as the z pass reads it
+template <typename T>
+struct PwlBlock {
+    OpView v;
+    const c2<T>* core;
+    const c2<T>* fac;
+};
+// the ten stored basis pairs (l <= l'; 0 = pulse, 1..3 = linear along x, y, z)
+constexpr int kPwlPairs[10][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 1}, {1, 2}, {1, 3}, {2, 2}, {2, 3}, {3, 3}};
+}  // namespace vie
+
+// opaque handle of a piecewise-linear operator: ten six-component blocks
+struct vie_pwl_op {
+    vie_op* blk[10];
+    vie::PwlBlock<float>* dev32 = nullptr;    // device copies of the ten block views
+    vie::PwlBlock<double>* dev64 = nullptr;
+    int rmax = 1;
 };
 

@@ -111,6 +111,13 @@ _SIGS = {
                                            ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "vie_op_from_tucker": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _P, _P,
                                           ctypes.POINTER(_P), ctypes.POINTER(CompressInfo)]),
+    "vie_compress_pwl": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.POINTER(CompressOpts), ctypes.c_int,
+                                        ctypes.c_int, ctypes.POINTER(_P), _P]),
+    "vie_pwl_op_destroy": (ctypes.c_int, [_P]),
+    "vie_pwl_op_query": (ctypes.c_int, [_P, _P, _P]),
+    "vie_pwl_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int]),
+    "vie_matvec_pwl": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, ctypes.c_size_t,
+                                      _P]),
     "vie_op_destroy": (ctypes.c_int, [_P]),
     "vie_op_query": (ctypes.c_int, [_P, _P, _P]),
     "vie_op_densify": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -304,6 +311,80 @@ def compress_cp(green, tol=1e-6, cp_rank=0, cp_iters=0, trunc_rule=0, max_rank=0
     op = Operator(h, (g.shape[3], g.shape[2], g.shape[1]), info)
     op.cp_rel_err = err
     return op
+
+
+class PwlOperator:
+    """Device-resident piecewise-linear operator (owns a vie_pwl_op): ten
+    six-component Tucker (or Tucker+CP) blocks, one per basis pair."""
+
+    def __init__(self, handle, n, infos):
+        self._h = handle
+        self.n = tuple(n)
+        self.ranks = np.array([[[info.ranks[c][a] for a in range(3)] for c in range(6)] for info in infos])
+        self.tucker_bytes_c64 = int(sum(info.tucker_bytes_c64 for info in infos))
+        self.device_bytes = int(sum(info.device_bytes for info in infos))
+        self.compress_seconds = float(sum(info.seconds for info in infos))
+        self._ws = {}
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("operator destroyed")
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            load().vie_pwl_op_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    workspace = Operator.workspace
+
+
+def compress_pwl(green_pwl, tol=1e-6, cp_rank=-1, cp_iters=0, trunc_rule=0, max_rank=0):
+    """Compress the sixty piecewise-linear defining tensors (numpy complex128,
+    shape (10, 6, n3, n2, n1), pairs (0,0) (0,1) ... (3,3)) by HOSVD, or
+    Tucker+CP when ``cp_rank`` >= 0, and upload them (vie_compress_pwl)."""
+    lib = load()
+    g = np.ascontiguousarray(green_pwl, dtype=np.complex128)
+    if g.ndim != 5 or g.shape[:2] != (10, 6):
+        raise ValueError("green_pwl must have shape (10, 6, n3, n2, n1)")
+    n = (ctypes.c_int * 3)(g.shape[4], g.shape[3], g.shape[2])
+    opts = CompressOpts(float(tol), int(trunc_rule), int(max_rank))
+    infos = (CompressInfo * 10)()
+    h = ctypes.c_void_p()
+    _check(lib.vie_compress_pwl(n, g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts), int(cp_rank),
+                                int(cp_iters), ctypes.byref(h), ctypes.cast(infos, ctypes.c_void_p)),
+           "vie_compress_pwl")
+    return PwlOperator(h, (g.shape[4], g.shape[3], g.shape[2]), list(infos))
+
+
+def matvec_pwl(op, x, eps_c=None, kind="A", adjoint=False, out=None):
+    """y = S A S x (kind 'A'), the bare sum S N S x (kind 'N'), or their
+    adjoints, in the mass-normalised piecewise-linear basis; x is
+    (12, n3, n2, n1) = [l][q] complex64 or complex128 on the device."""
+    n1, n2, n3 = op.n
+    dt = _dt(x)
+    if tuple(x.shape) != (12, n3, n2, n1) or not x.is_contiguous():
+        raise ValueError("x must be a contiguous (12, %d, %d, %d) tensor" % (n3, n2, n1))
+    _require_device(x, "x")
+    k = VIE_OP_A if kind == "A" else VIE_OP_N
+    if k == VIE_OP_A:
+        if eps_c is None:
+            raise ValueError("eps_c required for kind 'A'")
+        _require_like(eps_c, x, x.shape[1:], "eps_c")
+    y = torch.empty_like(x) if out is None else _require_like(out, x, x.shape, "out")
+    lib = load()
+    nbytes = lib.vie_pwl_workspace_bytes(op.handle, dt)
+    ws = op.workspace(nbytes, x.device)
+    _check(lib.vie_matvec_pwl(op.handle, k, 1 if adjoint else 0, dt, _ptr(eps_c) if k == VIE_OP_A else None,
+                              _ptr(x), _ptr(y), _ptr(ws), nbytes, _stream()), "vie_matvec_pwl")
+    return y
 
 
 def compress_k(green_k, tol=1e-6, trunc_rule=0, max_rank=0):
