@@ -16,12 +16,13 @@ matvec, solve, accuracy and the observables of eq. 18 against the HOSVD
 solution), the magnetic operator K with |b1+| and the coupled JMVIE operator
 and solves, the batching workload (6 phantoms x 16 dipole fields), the
 differentiation workload (128^3 adjoint gradient against central
-differences), and the FP64 oracle timed on the host (cpu_baseline).
+differences), the piecewise-linear basis on the sphere refinement series of
+Fig. 9, and the FP64 oracle timed on the host (cpu_baseline).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--grid 256]
                     [--no-dense] [--no-solve] [--no-cpu-baseline] [--no-cp]
                     [--no-magnetic] [--no-cross] [--no-table4] [--no-fig7] [--no-batch]
-                    [--no-grad] [--copy-calibration]
+                    [--no-grad] [--no-pwl] [--pwl-grids 30,60,90,120] [--copy-calibration]
 """
 import argparse
 import glob
@@ -130,10 +131,21 @@ def recorded_traffic(kernel, grid):
     return None
 
 
-def cpu_baseline(G, epsc, u, budget_s=60.0):
+def cpu_baseline(G, epsc, u, budget_s=60.0, pwl_check=None):
     """The FP64 oracle's matvec (dense Fourier-domain tensor, FFT
-    convolution) timed on this host at the same workload, one application."""
+    convolution) timed on this host at the same workload, one application.
+    ``pwl_check`` = (tensors, eps_c, u, device result, tol) of the smallest
+    piecewise-linear grid: returns also the device result's relative error
+    against the oracle's PWL matvec on the same HOSVD tensors, in the
+    mass-normalised basis (None without it)."""
     from oracle import operator as opm
+    from oracle import pwl as opwl
+    pwl_err = None
+    if pwl_check is not None:
+        G0, eps0, u0, y0, tol0 = pwl_check
+        kh0, _ = opwl.tucker_kernels(G0, tol0)
+        yr = opwl.to_normalised(lambda w: opwl.matvec(kh0, eps0, w, "A"), u0)
+        pwl_err = float(np.linalg.norm(y0 - yr) / np.linalg.norm(yr))
     cores = len(os.sched_getaffinity(0))
     t0 = time.time()
     op = opm.dense_operator(G)
@@ -145,7 +157,7 @@ def cpu_baseline(G, epsc, u, budget_s=60.0):
     del op
     return {"value": 1.0 / t, "unit": "matvecs/s", "cores": cores, "kind": "oracle",
             "sample": "one FP64 oracle application of A (dense Fourier-domain tensor precomputed, "
-                      "scipy.fft with %d workers) on the full workload; %.2f s" % (cores, t)}, y
+                      "scipy.fft with %d workers) on the full workload; %.2f s" % (cores, t)}, y, pwl_err
 
 
 def main():
@@ -171,6 +183,10 @@ def main():
                     help="skip the p_abs / |b1+| error sweep over SVD tolerances (64^3 head, HOSVD and Tucker+CP)")
     ap.add_argument("--no-cross", action="store_true",
                     help="skip the cross-Tucker compression leg (256^3 and the 270 x 141 x 902 body domain)")
+    ap.add_argument("--no-pwl", action="store_true", help="skip the piecewise-linear basis leg")
+    ap.add_argument("--pwl-grids", default="30,60,90,120",
+                    help="edges of the piecewise-linear refinement series (0.3 m cube)")
+    ap.add_argument("--pwl-tol", type=float, default=1e-8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 1 GiB (untimed) so that counter runs can "
                          "calibrate FETCH_SIZE / WRITE_SIZE")
@@ -380,6 +396,13 @@ def main():
             log("table4 leg failed: %r" % (exc,))
             extra["table4"] = {"error": repr(exc)}
 
+    if not args.no_pwl:
+        try:
+            extra["pwl"] = pwl_leg(args, vie, torch, dev)
+        except Exception as exc:   # the headline line is printed regardless
+            log("pwl leg failed: %r" % (exc,))
+            extra["pwl"] = {"error": repr(exc)}
+
     x_sol = None
     opk = None
     if not args.no_solve:
@@ -455,7 +478,7 @@ def main():
     if not args.no_cpu_baseline:
         u = b
         log("cpu baseline: timing the FP64 oracle matvec ...")
-        cb, y_ref = cpu_baseline(G, epsc, u)
+        cb, y_ref, pwl_err = cpu_baseline(G, epsc, u, pwl_check=result.get("pwl", {}).get("_check"))
         result["cpu_baseline"] = cb
         for key, yy in (("matvec_rel_err_vs_oracle_dense", y32), ("bf16_matvec_rel_err_vs_oracle_dense", y16)):
             yg = yy.cpu().numpy().astype(np.complex128)
@@ -468,6 +491,10 @@ def main():
             yg = ycr.cpu().numpy().astype(np.complex128)
             result["cross"]["matvec_rel_err_vs_oracle_dense"] = float(np.linalg.norm(yg - y_ref) /
                                                                       np.linalg.norm(y_ref))
+        if pwl_err is not None:
+            result["pwl"]["rel_err_vs_oracle_smallest_grid"] = pwl_err
+    if isinstance(result.get("pwl"), dict):
+        result["pwl"].pop("_check", None)
     if isinstance(result.get("cross"), dict):
         result["cross"].pop("_y", None)
         if y_cp is not None:
@@ -475,6 +502,90 @@ def main():
             result["tucker_cp"]["matvec_rel_err_vs_oracle_dense"] = float(np.linalg.norm(yg - y_ref) /
                                                                           np.linalg.norm(y_ref))
     print(json.dumps(result), flush=True)
+
+
+def pwl_z_flops(n, ranks):
+    """Algorithmic FP32 flops of the piecewise-linear z pass: forward and
+    inverse length-2n3 FFTs of 12 components, the 16 blocks of 3x3 complex
+    products (144 complex MACs) at every Fourier point, and the Tucker
+    reconstruction of the sixty components' half spectra (as z_pass_flops)."""
+    n1, n2, n3 = n
+    L1, L2, L3 = 2 * n1, 2 * n2, 2 * n3
+    fft = 2 * 12 * L1 * L2 * 5 * L3 * np.log2(L3)
+    prod = 8.0 * 144 * L1 * L2 * L3
+    rec = 0.0
+    for r1, r2, r3 in np.asarray(ranks).reshape(-1, 3):
+        rec += 8.0 * (n1 + 1) * (n2 + 1) * (n3 + 1) * r3
+        rec += 8.0 * ((n1 + 1) * (n2 + 1) * r1 * r3 + (n2 + 1) * r1 * r2 * r3)
+    return float(fft + prod + rec)
+
+
+# algorithmic complex elements per pass of the piecewise-linear matvec, units
+# of V: twelve components through the five passes, the contrast read once
+PWL_PASS_ELEMS_V = [12 + 24, 24 + 48, 48 + 48, 48 + 24, 24 + 12 + 1 + 12]
+
+
+def pwl_leg(args, vie, torch, dev):
+    """Piecewise-linear basis (eq. 7a-7b, twelve unknowns per voxel) on the
+    refinement series of Sec. VI-C (Fig. 9): a homogeneous sphere of radius
+    0.15 m, eps_r = 65, sigma = 0.6 S/m, centred in a 0.3 m cube, 298 MHz,
+    edges 30, 60, 90, 120 (and 150) voxels = 10, 5, 3.3, 2.5 (2) mm, i.e.
+    0.3, 2.6, 8.7, 20.7 (40.5) million unknowns; HOSVD of the sixty tensors
+    at tol 1e-8 (the figure's), complex64 matvec A (mass-normalised basis) on
+    a seeded random vector, timed over the step count; the memory of the
+    compressed and of the dense circulant tensors (complex128, as Sec. VI
+    quotes it)."""
+    import vie_inputs as vi
+    out = {}
+    f = 298e6
+    k0 = vi.wavenumber(f)
+    st = torch.cuda.current_stream()
+    grids = [int(g) for g in args.pwl_grids.split(",") if g.strip()]
+    for idx, N in enumerate(grids):
+        n = (N, N, N)
+        h = 0.3 / N
+        V = N ** 3
+        t0 = time.perf_counter()
+        G = vi.green_pwl_tensor(n, h, k0)
+        t_gen = time.perf_counter() - t0
+        er, sg, _ = vi.sphere_phantom(n, h, 0.15, 65.0, 0.6)
+        epsc = vi.complex_permittivity(er, sg, f)
+        t0 = time.perf_counter()
+        op = vie.compress_pwl(G, tol=args.pwl_tol)
+        t_cmp = time.perf_counter() - t0
+        rng = np.random.default_rng(300 + N)
+        u = rng.standard_normal((4, 3, N, N, N)) + 1j * rng.standard_normal((4, 3, N, N, N))
+        x = torch.from_numpy(u.reshape(12, N, N, N)).to(dev, torch.complex64)
+        e = torch.from_numpy(epsc).to(dev, torch.complex64)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            vie.matvec_pwl(op, x, e, out=y)
+        steps = max(1, min(args.steps, 20))
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        c0.record(st)
+        for _ in range(steps):
+            vie.matvec_pwl(op, x, e, out=y)
+        c1.record(st)
+        torch.cuda.synchronize()
+        ms = c0.elapsed_time(c1) / steps
+        alg = 8.0 * V * sum(PWL_PASS_ELEMS_V)
+        row = {"grid": list(n), "h_mm": h * 1e3, "unknowns": 12 * V, "ms_per_matvec": ms,
+               "matvecs_per_s": 1000.0 / ms, "Munknowns_per_s": 12 * V / (ms * 1e-3) / 1e6,
+               "alg_bytes_per_matvec": alg, "alg_GBps": alg / (ms * 1e-3) / 1e9,
+               "z_alg_flops": pwl_z_flops(n, op.ranks), "z_alg_bytes": 8.0 * V * PWL_PASS_ELEMS_V[2],
+               "max_rank": int(op.ranks.max()), "tucker_bytes_c64": op.tucker_bytes_c64,
+               "dense_circulant_bytes_c128": 60 * 8 * V * 16,
+               "green_seconds": t_gen, "compress_seconds": t_cmp}
+        out["n%d" % N] = row
+        log("pwl %d^3: %.3f ms/matvec (%.1f Munknowns/s), ranks <= %d, compress %.1f s, green %.1f s"
+            % (N, ms, row["Munknowns_per_s"], row["max_rank"], t_cmp, t_gen))
+        if idx == 0:
+            out["_check"] = (G, epsc, u, y.cpu().numpy().astype(np.complex128).reshape(u.shape), args.pwl_tol)
+        op.close()
+        del x, e, y, G
+    return out
 
 
 def cross_leg(G, op_t, x, e, y_t, n, h, k0, args, vie, torch, dev):

@@ -294,7 +294,9 @@ vie_status vie_pwl_op_destroy(vie_pwl_op* op);
 /* grid and the Tucker ranks [pair][component][mode]; either may be NULL */
 vie_status vie_pwl_op_query(const vie_pwl_op* op, int n[3], int ranks[10][6][3]);
 
-/* DEVICE workspace of vie_matvec_pwl in bytes (12 padded components) */
+/* DEVICE workspace of vie_matvec_pwl in bytes: the 12 padded components of
+ * the five passes and the core products W_c(k2) = G_c x2 U2_c(k2, :) of the
+ * sixty components for k2 in [0, n2] */
 size_t vie_pwl_workspace_bytes(const vie_pwl_op* op, int dtype);
 
 /*

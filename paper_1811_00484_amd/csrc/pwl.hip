@@ -26,13 +26,16 @@
 // block is the 3 x 3 product of the pulse basis.
 //
 // Kernel layout: one workgroup per mirror group of pencils (as the generic z
-// pass), the twelve pencils of each in LDS; every thread owns up to EPT
+// pass, 512 threads), the twelve pencils of each in LDS; every thread owns up to EPT
 // Fourier-domain positions and keeps their twelve output components in
 // registers while the ten pairs go by, each pair's six tables rebuilt from
-// the Tucker form into LDS (W = G x3 U3 contracted with the y row, then the
-// x row, then the z factor per k3).
+// the Tucker form into LDS: W_c(k2) = G_c x2 U2_c(k2, :) comes from a small
+// kernel that runs first (once per canonical k2, not per pencil group),
+// V_c = U1_c(k1, :) W_c(k2), then the z factor per k3.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdlib>
 #include <string>
 
 #include "fft_device.h"
@@ -49,7 +52,8 @@ namespace {
 
 using namespace vie;
 
-constexpr int kNT = 256;
+constexpr int kNT = 256;    // threads of the W kernel
+constexpr int kNTZ = 512;   // threads of the z kernel
 
 struct PwlZArgs {
     int n[3];
@@ -57,6 +61,7 @@ struct PwlZArgs {
     int G;       // pencils per workgroup (mirror group size: 1, 2 or 4)
     int conj;    // adjoint
     int rmax;    // largest Tucker rank over the ten blocks
+    int pb;      // pairs whose tables are built and applied together (1..10)
 };
 
 template <typename T>
@@ -67,9 +72,32 @@ __device__ __forceinline__ void sym3(const c2<T> (&N)[6], const c2<T> (&x)[3], c
     y[2] = N[4] * x[0] + N[5] * x[1] + N[2] * x[2];
 }
 
+// W_c(k2) = G_c x2 U2_c(k2, :) (r1 x r3) for every component of the ten
+// blocks and every canonical k2 in [0, n2], once per matvec:
+// Wg[((k2 * 60) + 6 b + c) * rmax^2 + al * r3 + ga].  The z pass then only
+// contracts the x row and the z factor per pencil group.
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_pwl_w(const PwlBlock<T>* __restrict__ blk, int rmax, c2<T>* __restrict__ Wg)
+{
+    const int k2 = blockIdx.x, bc = blockIdx.y;
+    const int b = bc / 6, c = bc - 6 * b;
+    const OpView& v = blk[b].v;
+    const int r1 = v.r[c][0], r2 = v.r[c][1], r3 = v.r[c][2];
+    const c2<T>* Gc = blk[b].core + v.core_off[c];
+    const c2<T>* U2 = blk[b].fac + v.fac_off[c][1] + (long)k2 * r2;
+    c2<T>* out = Wg + ((size_t)k2 * 60 + bc) * rmax * rmax;
+    for (int e = threadIdx.x; e < r1 * r3; e += kNT) {
+        const int al = e / r3, ga = e - al * r3;
+        c2<T> s = mk<T>(0, 0);
+        for (int be = 0; be < r2; ++be) fma_c(s, Gc[((long)al * r2 + be) * r3 + ga], U2[be]);
+        out[e] = s;
+    }
+}
+
 template <typename T, int MAXE, int EPT>
-__global__ void __launch_bounds__(kNT) k_pwl_z(c2<T>* __restrict__ S2, FftPlan pl, const c2<T>* __restrict__ tw,
-                                               PwlZArgs a, const PwlBlock<T>* __restrict__ blk)
+__global__ void __launch_bounds__(kNTZ) k_pwl_z(c2<T>* __restrict__ S2, FftPlan pl, const c2<T>* __restrict__ tw,
+                                               PwlZArgs a, const PwlBlock<T>* __restrict__ blk,
+                                               const c2<T>* __restrict__ Wg)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int n1 = a.n[0], n2 = a.n[1], n3 = a.n[2];
@@ -112,15 +140,14 @@ __global__ void __launch_bounds__(kNT) k_pwl_z(c2<T>* __restrict__ S2, FftPlan p
     }
 
     // ---- LDS: pencils [12 * G][L3] (sequence (3 l + q) * P + pencil), the
-    // six N^ tables of the current pair, W, V, twiddles
+    // N^ tables and V of a batch of pairs, twiddles
     c2<T>* X = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* NT6 = X + (size_t)12 * a.G * L3;        // [6][n3 + 1]
-    c2<T>* Wc = NT6 + (size_t)6 * (n3 + 1);        // [rmax * rmax]
-    c2<T>* Vc = Wc + (size_t)rmax * rmax;          // [6][rmax]
-    c2<T>* tws = Vc + (size_t)6 * rmax;            // [L3]
-    for (int m = tid; m < L3; m += kNT) tws[m] = tw[m];
+    c2<T>* NTT = X + (size_t)12 * a.G * L3;        // [pb][6][n3 + 1]
+    c2<T>* Vc = NTT + (size_t)a.pb * 6 * (n3 + 1); // [pb][6][rmax]
+    c2<T>* tws = Vc + (size_t)a.pb * 6 * rmax;     // [L3]
+    for (int m = tid; m < L3; m += kNTZ) tws[m] = tw[m];
 
-    for (int e = tid; e < 12 * P * L3; e += kNT) {
+    for (int e = tid; e < 12 * P * L3; e += kNTZ) {
         const int s = e / L3, m = e - s * L3;
         const int comp = s / P, pe = s - comp * P;
         c2<T> val = mk<T>(0, 0);
@@ -128,7 +155,7 @@ __global__ void __launch_bounds__(kNT) k_pwl_z(c2<T>* __restrict__ S2, FftPlan p
         X[s * L3 + m] = val;
     }
     __syncthreads();
-    fft_lds<-1, false, MAXE>(X, 12 * P, L3, 1, pl, tws, tid, kNT);
+    fft_lds<-1, false, MAXE>(X, 12 * P, L3, 1, pl, tws, tid, kNTZ);
 
     c2<T> acc[12][EPT];
 #pragma unroll
@@ -136,83 +163,112 @@ __global__ void __launch_bounds__(kNT) k_pwl_z(c2<T>* __restrict__ S2, FftPlan p
 #pragma unroll
         for (int j = 0; j < EPT; ++j) acc[c][j] = mk<T>(0, 0);
 
+    // ---- the ten pairs in batches of a.pb whose tables fit in LDS together:
+    // per batch V_c = U1_c(k1, :) W_c(k2) of every component, then the
+    // N^_c(k1, k2, k3) tables for k3 in [0, n3], then the (a, b) and (b, a)
+    // blocks of every pair on every owned position
 #pragma unroll 1
-    for (int b = 0; b < 10; ++b) {
-        const OpView& v = blk[b].v;
-        const c2<T>* core = blk[b].core;
-        const c2<T>* fac = blk[b].fac;
-        // ---- N^_c(k1, k2, k3) of this pair for k3 in [0, n3]
-        for (int c = 0; c < 6; ++c) {
-            const int r1 = v.r[c][0], r2 = v.r[c][1], r3 = v.r[c][2];
-            const c2<T>* Gc = core + v.core_off[c];
-            const c2<T>* U1 = fac + v.fac_off[c][0] + (long)k1 * r1;
-            const c2<T>* U2 = fac + v.fac_off[c][1] + (long)k2 * r2;
-            for (int e = tid; e < r1 * r3; e += kNT) {
-                const int al = e / r3, ga = e - al * r3;
-                c2<T> s = mk<T>(0, 0);
-                for (int be = 0; be < r2; ++be) fma_c(s, Gc[((long)al * r2 + be) * r3 + ga], U2[be]);
-                Wc[e] = s;
+    for (int b0 = 0; b0 < 10; b0 += a.pb) {
+        const int nb = min(a.pb, 10 - b0);
+        for (int e = tid; e < nb * 6 * rmax; e += kNTZ) {
+            const int bc = e / rmax, ga = e - bc * rmax;
+            const int b = b0 + bc / 6, c = bc % 6;
+            const OpView& v = blk[b].v;
+            const int r1 = v.r[c][0], r3 = v.r[c][2];
+            if (ga < r3) {
+                const c2<T>* U1 = blk[b].fac + v.fac_off[c][0] + (long)k1 * r1;
+                const c2<T>* W = Wg + ((size_t)k2 * 60 + 6 * b + c) * rmax * rmax + ga;
+                c2<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
+                int al = 0;
+                for (; al + 4 <= r1; al += 4) {
+                    const c2<T> w0 = W[al * r3], w1 = W[(al + 1) * r3], w2 = W[(al + 2) * r3], w3 = W[(al + 3) * r3];
+                    fma_c(s0, U1[al], w0);
+                    fma_c(s1, U1[al + 1], w1);
+                    fma_c(s0, U1[al + 2], w2);
+                    fma_c(s1, U1[al + 3], w3);
+                }
+                for (; al < r1; ++al) fma_c(s0, U1[al], W[al * r3]);
+                Vc[e] = s0 + s1;
             }
-            __syncthreads();
-            for (int ga = tid; ga < r3; ga += kNT) {
-                c2<T> s = mk<T>(0, 0);
-                for (int al = 0; al < r1; ++al) fma_c(s, U1[al], Wc[al * r3 + ga]);
-                Vc[c * rmax + ga] = s;
-            }
-            __syncthreads();
         }
-        for (int e = tid; e < 6 * (n3 + 1); e += kNT) {
-            const int c = e / (n3 + 1), kk = e - c * (n3 + 1);
+        __syncthreads();
+        for (int e = tid; e < nb * 6 * (n3 + 1); e += kNTZ) {
+            // z factor read column-major ([g][k3]): consecutive threads take
+            // consecutive k3; four rows in flight
+            const int bc = e / (n3 + 1), kk = e - bc * (n3 + 1);
+            const int b = b0 + bc / 6, c = bc % 6;
+            const OpView& v = blk[b].v;
             const int r3 = v.r[c][2];
-            const c2<T>* U3 = fac + v.fac_off[c][2] + (long)kk * r3;
-            c2<T> s = mk<T>(0, 0);
-            for (int ga = 0; ga < r3; ++ga) fma_c(s, Vc[c * rmax + ga], U3[ga]);
-            NT6[e] = s;
+            const long st = n3 + 1;
+            const c2<T>* U3 = blk[b].fac + v.fac3t_off[c] + kk;
+            const c2<T>* vc = Vc + bc * rmax;
+            c2<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
+            int ga = 0;
+            for (; ga + 4 <= r3; ga += 4) {
+                const c2<T> u0 = U3[ga * st], u1 = U3[(ga + 1) * st], u2 = U3[(ga + 2) * st], u3 = U3[(ga + 3) * st];
+                fma_c(s0, vc[ga], u0);
+                fma_c(s1, vc[ga + 1], u1);
+                fma_c(s0, vc[ga + 2], u2);
+                fma_c(s1, vc[ga + 3], u3);
+            }
+            for (; ga < r3; ++ga) fma_c(s0, vc[ga], U3[ga * st]);
+            NTT[e] = s0 + s1;
         }
         __syncthreads();
 
-        // ---- the (a, b) and (b, a) blocks on every owned position
-        const int la = kPwlPairs[b][0], lb = kPwlPairs[b][1];
-        const T sig = ((la == 0) != (lb == 0)) ? (T)-1 : (T)1;
-        const T sab = a.conj ? (T)1 : sig;     // factor of the (a, b) block
-        const T sba = a.conj ? sig : (T)1;     // factor of the (b, a) block
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-            const int e = tid + j * kNT;
+            const int e = tid + j * kNTZ;
             if (e < P * L3) {
                 const int pe = e / L3, m = e - pe * L3;
                 const int f3 = m > n3;
                 const int kk = f3 ? L3 - m : m;
-                c2<T> Nc[6];
+                c2<T> x[12];
 #pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    c2<T> t = NT6[c * (n3 + 1) + kk];
-                    const int neg = (view_odd(0, v.lmask, c, 0) & pf1[pe]) ^ (view_odd(0, v.lmask, c, 1) & pf2[pe]) ^
-                                    (view_odd(0, v.lmask, c, 2) & f3);
-                    if (neg) t = mk<T>(-t.x, -t.y);
-                    Nc[c] = a.conj ? vie::conj(t) : t;
-                }
-                c2<T> xa[3], xb[3], y[3];
+                for (int c = 0; c < 12; ++c) x[c] = X[(c * P + pe) * L3 + m];
+#pragma unroll 1
+                for (int bi = 0; bi < nb; ++bi) {
+                    const int b = b0 + bi;
+                    const int lmask = blk[b].v.lmask;
+                    const int la = kPwlPairs[b][0], lb = kPwlPairs[b][1];
+                    const T sig = ((la == 0) != (lb == 0)) ? (T)-1 : (T)1;
+                    const T sab = a.conj ? (T)1 : sig;     // factor of the (a, b) block
+                    const T sba = a.conj ? sig : (T)1;     // factor of the (b, a) block
+                    c2<T> Nc[6];
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    xa[q] = X[((3 * la + q) * P + pe) * L3 + m];
-                    xb[q] = X[((3 * lb + q) * P + pe) * L3 + m];
-                }
-                sym3(Nc, xb, y);
+                    for (int c = 0; c < 6; ++c) {
+                        c2<T> t = NTT[(bi * 6 + c) * (n3 + 1) + kk];
+                        const int neg = (view_odd(0, lmask, c, 0) & pf1[pe]) ^ (view_odd(0, lmask, c, 1) & pf2[pe]) ^
+                                        (view_odd(0, lmask, c, 2) & f3);
+                        if (neg) t = mk<T>(-t.x, -t.y);
+                        Nc[c] = a.conj ? vie::conj(t) : t;
+                    }
+                    // register arrays need compile-time indices: select the rows
+                    c2<T> xa[3], xb[3], y[3];
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    // register arrays need compile-time indices: select the row
+                    for (int q = 0; q < 3; ++q) {
+                        xa[q] = mk<T>(0, 0);
+                        xb[q] = mk<T>(0, 0);
 #pragma unroll
-                    for (int l = 0; l < 4; ++l)
-                        if (l == la) acc[3 * l + q][j] = acc[3 * l + q][j] + sab * y[q];
-                }
-                if (la != lb) {
-                    sym3(Nc, xa, y);
+                        for (int l = 0; l < 4; ++l) {
+                            if (l == la) xa[q] = x[3 * l + q];
+                            if (l == lb) xb[q] = x[3 * l + q];
+                        }
+                    }
+                    sym3(Nc, xb, y);
 #pragma unroll
                     for (int q = 0; q < 3; ++q)
 #pragma unroll
                         for (int l = 0; l < 4; ++l)
-                            if (l == lb) acc[3 * l + q][j] = acc[3 * l + q][j] + sba * y[q];
+                            if (l == la) acc[3 * l + q][j] = acc[3 * l + q][j] + sab * y[q];
+                    if (la != lb) {
+                        sym3(Nc, xa, y);
+#pragma unroll
+                        for (int q = 0; q < 3; ++q)
+#pragma unroll
+                            for (int l = 0; l < 4; ++l)
+                                if (l == lb) acc[3 * l + q][j] = acc[3 * l + q][j] + sba * y[q];
+                    }
                 }
             }
         }
@@ -222,7 +278,7 @@ __global__ void __launch_bounds__(kNT) k_pwl_z(c2<T>* __restrict__ S2, FftPlan p
     // ---- outputs back into the pencils, inverse FFT, cropped store
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-        const int e = tid + j * kNT;
+        const int e = tid + j * kNTZ;
         if (e < P * L3) {
             const int pe = e / L3, m = e - pe * L3;
 #pragma unroll
@@ -230,8 +286,8 @@ __global__ void __launch_bounds__(kNT) k_pwl_z(c2<T>* __restrict__ S2, FftPlan p
         }
     }
     __syncthreads();
-    fft_lds<1, false, MAXE>(X, 12 * P, L3, 1, pl, tws, tid, kNT);
-    for (int e = tid; e < 12 * P * n3; e += kNT) {
+    fft_lds<1, false, MAXE>(X, 12 * P, L3, 1, pl, tws, tid, kNTZ);
+    for (int e = tid; e < 12 * P * n3; e += kNTZ) {
         const int s = e / n3, m = e - s * n3;
         const int comp = s / P, pe = s - comp * P;
         S2[(((long)comp * L2 + pk2[pe]) * L1 + pk1[pe]) * n3 + m] = X[s * L3 + m];
@@ -241,32 +297,46 @@ __global__ void __launch_bounds__(kNT) k_pwl_z(c2<T>* __restrict__ S2, FftPlan p
 template <typename T>
 constexpr int pwl_ept()
 {
-    return 2;   // owned positions per thread: G * L3 <= EPT * 256
+    return 1;   // owned positions per thread: G * L3 <= EPT * 512
 }
 
 template <typename T>
-size_t pwl_z_lds(const OpView& v, int rmax, int G)
+size_t pwl_z_lds(const OpView& v, int rmax, int G, int pb)
 {
-    return sizeof(c2<T>) * ((size_t)12 * G * v.L[2] + 6 * (size_t)(v.n[2] + 1) + (size_t)rmax * rmax +
-                            6 * (size_t)rmax + v.L[2]);
+    return sizeof(c2<T>) * ((size_t)12 * G * v.L[2] + (size_t)pb * 6 * ((v.n[2] + 1) + rmax) + v.L[2]);
 }
 
-// pencils per workgroup for the z pass; 0 = does not fit
+// pencils per workgroup for the z pass (the largest mirror group whose
+// pencils fit the threads) and the pairs per table batch (as many as the LDS
+// then holds); G = 0: does not fit
 template <typename T>
-int pwl_z_group(const DeviceOp& op, int rmax)
+void pwl_z_shape(const DeviceOp& op, int rmax, int& G, int& pb)
 {
-    for (int G = 4; G >= 1; G /= 2)
-        if ((size_t)G * op.view.L[2] <= (size_t)pwl_ept<T>() * kNT && pwl_z_lds<T>(op.view, rmax, G) <= op.max_lds)
-            return G;
-    return 0;
+    for (G = 4; G >= 1; G /= 2)
+        if ((size_t)G * op.view.L[2] <= (size_t)pwl_ept<T>() * kNTZ && pwl_z_lds<T>(op.view, rmax, G, 1) <= op.max_lds)
+            break;
+    if (G < 1) {
+        G = 0;
+        return;
+    }
+    for (pb = 10; pb > 1; --pb)
+        if (pwl_z_lds<T>(op.view, rmax, G, pb) <= op.max_lds) break;
+}
+
+// complex elements of the W buffer (every k2 of every block component)
+size_t pwl_w_elems(const vie_pwl_op& P)
+{
+    return (size_t)(P.blk[0]->d.view.n[1] + 1) * 60 * P.rmax * P.rmax;
 }
 
 template <typename T>
-hipError_t launch_pwl_z(const vie_pwl_op& P, int conj, c2<T>* S2, hipStream_t s, std::string& err)
+hipError_t launch_pwl_z(const vie_pwl_op& P, int conj, c2<T>* S2, c2<T>* Wg, hipStream_t s, std::string& err)
 {
     const DeviceOp& op = P.blk[0]->d;
     const OpView& v = op.view;
-    const int G = pwl_z_group<T>(op, P.rmax);
+    int G = 0, pb = 1;
+    pwl_z_shape<T>(op, P.rmax, G, pb);
+    if (const char* e = getenv("VIE_PWL_PAIRS_PER_BATCH")) pb = std::max(1, std::min(pb, atoi(e)));
     if (G == 0) {
         err = "the piecewise-linear z pass does not fit in LDS (z length or ranks too large)";
         return hipErrorInvalidValue;
@@ -279,9 +349,10 @@ hipError_t launch_pwl_z(const vie_pwl_op& P, int conj, c2<T>* S2, hipStream_t s,
     za.G = G;
     za.conj = conj;
     za.rmax = P.rmax;
+    za.pb = pb;
     const int n1 = v.n[0], n2 = v.n[1];
     const int nblk = G == 4 ? (n1 + 1) * (n2 + 1) : (G == 2 ? (n1 + 1) * v.L[1] : v.L[0] * v.L[1]);
-    const size_t lds = pwl_z_lds<T>(v, P.rmax, G);
+    const size_t lds = pwl_z_lds<T>(v, P.rmax, G, pb);
     const c2<T>* tw;
     const PwlBlock<T>* blk;
     if constexpr (sizeof(T) == 8) {
@@ -293,9 +364,10 @@ hipError_t launch_pwl_z(const vie_pwl_op& P, int conj, c2<T>* S2, hipStream_t s,
     }
     constexpr int EPT = pwl_ept<T>();
     constexpr int MAXE = 12 * EPT;
+    hipLaunchKernelGGL((k_pwl_w<T>), dim3(n2 + 1, 60), dim3(kNT), 0, s, blk, P.rmax, Wg);
     auto kern = k_pwl_z<T, MAXE, EPT>;
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, dim3(nblk), dim3(kNT), lds, s, S2, op.plan[2], tw, za, blk);
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(kNTZ), lds, s, S2, op.plan[2], tw, za, blk, (const c2<T>*)Wg);
     return hipGetLastError();
 }
 
@@ -307,11 +379,12 @@ hipError_t pwl_matvec(const vie_pwl_op& P, int mode, const c2<T>* eps, const c2<
     const OpView& v = op.view;
     c2<T>* S2 = ws;
     c2<T>* S1 = ws + (size_t)3 * v.L[1] * v.L[0] * v.n[2] * 4;
+    c2<T>* Wg = ws + matvec_ws_elems(op, 4);
     const bool conj = (mode == MODE_AH || mode == MODE_NH);
     // X+ : x -> S1, Y+ : S1 -> S2, Z : S2 in place, Y- : S2 -> S1, X- : S1 -> y
     hipError_t e = run_pass<T, T>(op, 0, mode, 0, eps, x, nullptr, S1, 4, s, nullptr, err, false);
     if (e == hipSuccess) e = run_pass<T, T>(op, 1, mode, 0, eps, x, S1, S2, 4, s, nullptr, err, false);
-    if (e == hipSuccess) e = launch_pwl_z<T>(P, conj ? 1 : 0, S2, s, err);
+    if (e == hipSuccess) e = launch_pwl_z<T>(P, conj ? 1 : 0, S2, Wg, s, err);
     if (e == hipSuccess) e = run_pass<T, T>(op, 3, mode, 0, eps, x, S2, S1, 4, s, nullptr, err, false);
     if (e == hipSuccess) e = run_pass<T, T>(op, 4, mode, 0, eps, x, S1, y, 4, s, nullptr, err, false);
     return e;
@@ -325,7 +398,7 @@ size_t vie_pwl_workspace_bytes(const vie_pwl_op* op, int dtype)
 {
     if (!op || !op->blk[0]) return 0;
     const size_t el = dtype == VIE_C128 ? sizeof(c2<double>) : sizeof(c2<float>);
-    return matvec_ws_elems(op->blk[0]->d, 4) * el;
+    return (matvec_ws_elems(op->blk[0]->d, 4) + pwl_w_elems(*op)) * el;
 }
 
 vie_status vie_pwl_op_query(const vie_pwl_op* op, int n[3], int ranks[10][6][3])
