@@ -464,6 +464,23 @@ vie_status vie_solve(const vie_op* op, int dtype, const void* eps_c, const void*
                      size_t ws_bytes, void* stream);
 
 /*
+ * vie_solve_pwl -- GMRES(m) solve of S A S x = b (or its adjoint, opts
+ * adjoint = 1) for the piecewise-linear operator, one system, x starting at
+ * zero: the device Krylov basis and classical Gram-Schmidt of vie_solve_jm
+ * (two passes, FP64 dots), restart on the true residual.  With opts refine
+ * (VIE_C128 vectors only) the Arnoldi steps apply the operator with FP32
+ * products on the FP64 vectors and each restart takes the FP64 residual
+ * (inner_tol per cycle).  b, x DEVICE [12][n3][n2][n1] (not overlapping),
+ * eps_c DEVICE [n3][n2][n1]; ws DEVICE, vie_solve_pwl_workspace_bytes.
+ * Returns VIE_NOT_CONVERGED (x holds the last iterate) when max_outer
+ * restarts do not reach tol.  Synchronous on `stream`.
+ */
+size_t vie_solve_pwl_workspace_bytes(const vie_pwl_op* op, int dtype, const vie_solve_opts* opts);
+vie_status vie_solve_pwl(const vie_pwl_op* op, int dtype, const void* eps_c, const void* b, void* x,
+                         const vie_solve_opts* opts, vie_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+
+
+/*
  * Batches of several grids (instances) of uneven size: every pass of the
  * matvec runs as ONE launch over all instances' tiles (the work of each
  * block is looked up in a device table of instances).  Each instance has its

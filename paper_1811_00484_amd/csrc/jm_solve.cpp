@@ -1,6 +1,8 @@
-// GMRES(m) for the full JMVIE system of eq. 4: one system, unknown x = [J; M]
-// (2 x 3 x n3 x n2 x n1 complex), operator vie_matvec_jm (the N and K
-// products of J and M combined with the electric and magnetic contrasts).
+// GMRES(m) for one system of a single operator: the full JMVIE system of
+// eq. 4, unknown x = [J; M] (2 x 3 x n3 x n2 x n1 complex), operator
+// vie_matvec_jm (the N and K products of J and M combined with the electric
+// and magnetic contrasts); and the electric block in the piecewise-linear
+// basis (12 x n3 x n2 x n1, operator vie_matvec_pwl).
 // The Krylov basis stays on the device; classical Gram-Schmidt with a second
 // pass on every step, dots accumulated in FP64 (krylov.hip); the Hessenberg
 // column and Givens rotations on the host; restart on the true residual.
@@ -19,6 +21,8 @@
 namespace vie {
 vie_status fail(vie_status st, const std::string& msg);
 vie_status hip_fail(hipError_t e, const char* where);
+vie_status pwl_apply_mixed(const vie_pwl_op* op, int mode, const void* eps, const void* x, void* y, void* ws,
+                           hipStream_t s);
 
 namespace {
 
@@ -26,23 +30,23 @@ using cd = std::complex<double>;
 
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-struct JmLayout {
-    size_t V, R, jm, partial, h1, h2, coef, nrm, map, total;
+// Device buffers of one GMRES(m) solve of n unknowns whose operator needs
+// `opws` bytes of workspace.
+struct KLayout {
+    size_t V, R, op, partial, h1, h2, coef, nrm, map, total;
 };
 
-JmLayout jm_layout(const vie_op* op_n, const vie_op* op_k, int dtype, int m)
+KLayout k_layout(long n, size_t opws, int dtype, int m)
 {
-    const OpView& v = op_n->d.view;
-    const long n = 6L * v.n[0] * v.n[1] * v.n[2];
     const size_t ek = dtype == VIE_C128 ? 16 : 8;
-    JmLayout L;
+    KLayout L;
     size_t off = 0;
     L.V = off;
     off += al256((size_t)(m + 1) * n * ek);
     L.R = off;
     off += al256((size_t)n * ek);
-    L.jm = off;
-    off += al256(vie_jm_workspace_bytes(op_n, op_k, dtype));
+    L.op = off;
+    off += al256(opws);
     L.partial = off;
     off += al256((size_t)(m + 2) * krylov_nblk(n) * 16);
     L.h1 = off;
@@ -59,19 +63,23 @@ JmLayout jm_layout(const vie_op* op_n, const vie_op* op_k, int dtype, int m)
     return L;
 }
 
-template <typename TK>
-vie_status run_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, double omega, const void* eps_c,
-                  const void* mu_c, const c2<TK>* b, c2<TK>* x, const vie_solve_opts& o, vie_solve_info* info,
-                  char* ws, hipStream_t st)
+KLayout jm_layout(const vie_op* op_n, const vie_op* op_k, int dtype, int m)
 {
     const OpView& v = op_n->d.view;
-    const long n = 6L * v.n[0] * v.n[1] * v.n[2];
+    return k_layout(6L * v.n[0] * v.n[1] * v.n[2], vie_jm_workspace_bytes(op_n, op_k, dtype), dtype, m);
+}
+
+// GMRES(m) on n unknowns: apply(in, out) is the operator (the restart
+// residual), apply_inner(in, out) the one of the Arnoldi steps (the same, or
+// FP32 products on FP64 vectors when refining); `who` names the entry point
+// in errors.
+template <typename TK, typename FA, typename FI>
+vie_status gmres_run(long n, const KLayout& L, FA apply, FI apply_inner, bool refine, const c2<TK>* b, c2<TK>* x,
+                     const vie_solve_opts& o, vie_solve_info* info, char* ws, hipStream_t st, const char* who)
+{
     const int m = o.restart;
-    const JmLayout L = jm_layout(op_n, op_k, dtype, m);
     c2<TK>* V = (c2<TK>*)(ws + L.V);
     c2<TK>* R = (c2<TK>*)(ws + L.R);
-    void* jw = ws + L.jm;
-    const size_t jwb = vie_jm_workspace_bytes(op_n, op_k, dtype);
     c2<double>* partial = (c2<double>*)(ws + L.partial);
     c2<double>* dh1 = (c2<double>*)(ws + L.h1);
     c2<double>* dh2 = (c2<double>*)(ws + L.h2);
@@ -83,21 +91,10 @@ vie_status run_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, d
         hipError_t er = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st);
         return er == hipSuccess ? hipStreamSynchronize(st) : er;
     };
-    // refinement (o.refine, complex128 vectors): the Arnoldi steps use the
-    // operator with FP32 products, the restart residual the FP64 one
-    const bool refine = o.refine && sizeof(TK) == 8;
-    auto apply_prec = [&](const c2<TK>* in, c2<TK>* out, bool mixed) {
-        jm_mixed_products = mixed;
-        vie_status r = vie_matvec_jm(op_n, op_k, dtype, h, omega, eps_c, mu_c, in, out, jw, jwb, st);
-        jm_mixed_products = false;
-        return r;
-    };
-    auto apply = [&](const c2<TK>* in, c2<TK>* out) { return apply_prec(in, out, false); };
-    auto apply_inner = [&](const c2<TK>* in, c2<TK>* out) { return apply_prec(in, out, refine); };
     const int zero = 0;
     if ((e = hipMemcpyAsync(dmap, &zero, sizeof(int), hipMemcpyHostToDevice, st)) != hipSuccess)
-        return hip_fail(e, "vie_solve_jm map");
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "vie_solve_jm map");
+        return hip_fail(e, who);
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, who);
     vie_solve_info inf{};
     if (info) {
         inf.history = info->history;
@@ -107,8 +104,8 @@ vie_status run_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, d
     if ((e = kr_norm2<TK>(b, 0, n, n, dmap, 1, partial, dnrm, st)) != hipSuccess) return hip_fail(e, "norm");
     if ((e = sync_copy(&hn, dnrm, sizeof(hn))) != hipSuccess) return hip_fail(e, "norm copy");
     const double bnorm = std::sqrt(hn.x);
-    if (!std::isfinite(bnorm)) return fail(VIE_E_NONFINITE, "vie_solve_jm: non-finite right-hand side");
-    if ((e = hipMemsetAsync(x, 0, sizeof(c2<TK>) * n, st)) != hipSuccess) return hip_fail(e, "vie_solve_jm init");
+    if (!std::isfinite(bnorm)) return fail(VIE_E_NONFINITE, std::string(who) + ": non-finite right-hand side");
+    if ((e = hipMemsetAsync(x, 0, sizeof(c2<TK>) * n, st)) != hipSuccess) return hip_fail(e, who);
     vie_status status = VIE_NOT_CONVERGED;
     if (bnorm == 0.0) {
         inf.converged = 1;
@@ -127,7 +124,7 @@ vie_status run_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, d
         if ((e = kr_norm2<TK>(R, 0, n, n, dmap, 1, partial, dnrm, st)) != hipSuccess) return hip_fail(e, "norm");
         if ((e = sync_copy(&hn, dnrm, sizeof(hn))) != hipSuccess) return hip_fail(e, "norm copy");
         const double beta = std::sqrt(hn.x);
-        if (!std::isfinite(beta)) return fail(VIE_E_NONFINITE, "vie_solve_jm: non-finite residual");
+        if (!std::isfinite(beta)) return fail(VIE_E_NONFINITE, std::string(who) + ": non-finite residual");
         inf.rel_residual = beta / bnorm;
         if (inf.history && inf.hist_len < inf.hist_cap) inf.history[inf.hist_len++] = inf.rel_residual;
         if (inf.rel_residual <= o.tol) {
@@ -154,7 +151,7 @@ vie_status run_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, d
             if (e == hipSuccess) e = hipMemcpyAsync(h1.data(), dh1, sizeof(c2<double>) * (j + 2), hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipMemcpyAsync(h2.data(), dh2, sizeof(c2<double>) * (j + 1), hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = sync_copy(&hn, dnrm, sizeof(hn));
-            if (e != hipSuccess) return hip_fail(e, "vie_solve_jm arnoldi");
+            if (e != hipSuccess) return hip_fail(e, who);
             cd* Hc = &H[(size_t)j * (m + 1)];
             for (int i = 0; i <= j; ++i) Hc[i] = cd(h1[i].x + h2[i].x, h1[i].y + h2[i].y);
             const double hj1 = std::sqrt(std::max(hn.x, 0.0));
@@ -216,6 +213,57 @@ vie_status run_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, d
     return status;
 }
 
+template <typename TK>
+vie_status run_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, double omega, const void* eps_c,
+                  const void* mu_c, const c2<TK>* b, c2<TK>* x, const vie_solve_opts& o, vie_solve_info* info,
+                  char* ws, hipStream_t st)
+{
+    const OpView& v = op_n->d.view;
+    const long n = 6L * v.n[0] * v.n[1] * v.n[2];
+    const KLayout L = jm_layout(op_n, op_k, dtype, o.restart);
+    void* jw = ws + L.op;
+    const size_t jwb = vie_jm_workspace_bytes(op_n, op_k, dtype);
+    // refinement (o.refine, complex128 vectors): the Arnoldi steps use the
+    // operator with FP32 products, the restart residual the FP64 one
+    const bool refine = o.refine && sizeof(TK) == 8;
+    auto apply_prec = [&](const c2<TK>* in, c2<TK>* out, bool mixed) {
+        jm_mixed_products = mixed;
+        vie_status r = vie_matvec_jm(op_n, op_k, dtype, h, omega, eps_c, mu_c, in, out, jw, jwb, st);
+        jm_mixed_products = false;
+        return r;
+    };
+    auto apply = [&](const c2<TK>* in, c2<TK>* out) { return apply_prec(in, out, false); };
+    auto apply_inner = [&](const c2<TK>* in, c2<TK>* out) { return apply_prec(in, out, refine); };
+    return gmres_run<TK>(n, L, apply, apply_inner, refine, b, x, o, info, ws, st, "vie_solve_jm");
+}
+
+KLayout pwl_layout(const vie_pwl_op* op, int dtype, int m)
+{
+    const OpView& v = op->blk[0]->d.view;
+    return k_layout(12L * v.n[0] * v.n[1] * v.n[2], vie_pwl_workspace_bytes(op, dtype), dtype, m);
+}
+
+template <typename TK>
+vie_status run_pwl(const vie_pwl_op* op, int dtype, const void* eps_c, const c2<TK>* b, c2<TK>* x,
+                   const vie_solve_opts& o, vie_solve_info* info, char* ws, hipStream_t st)
+{
+    const OpView& v = op->blk[0]->d.view;
+    const long n = 12L * v.n[0] * v.n[1] * v.n[2];
+    const KLayout L = pwl_layout(op, dtype, o.restart);
+    void* pw = ws + L.op;
+    const size_t pwb = vie_pwl_workspace_bytes(op, dtype);
+    const int mode = o.adjoint ? MODE_AH : MODE_A;
+    const bool refine = o.refine && sizeof(TK) == 8;
+    auto apply = [&](const c2<TK>* in, c2<TK>* out) {
+        return vie_matvec_pwl(op, VIE_OP_A, o.adjoint, dtype, eps_c, in, out, pw, pwb, (void*)st);
+    };
+    auto apply_inner = [&](const c2<TK>* in, c2<TK>* out) {
+        if (refine) return pwl_apply_mixed(op, mode, eps_c, in, out, pw, st);
+        return vie_matvec_pwl(op, VIE_OP_A, o.adjoint, dtype, eps_c, in, out, pw, pwb, (void*)st);
+    };
+    return gmres_run<TK>(n, L, apply, apply_inner, refine, b, x, o, info, ws, st, "vie_solve_pwl");
+}
+
 }  // namespace
 }  // namespace vie
 
@@ -263,6 +311,49 @@ vie_status vie_solve_jm(const vie_op* op_n, const vie_op* op_k, int dtype, doubl
                               (char*)ws, st);
     return run_jm<float>(op_n, op_k, dtype, h, omega, eps_c, mu_c, (const c2<float>*)b, (c2<float>*)x, o, info,
                          (char*)ws, st);
+}
+
+size_t vie_solve_pwl_workspace_bytes(const vie_pwl_op* op, int dtype, const vie_solve_opts* opts)
+{
+    if (!op || !op->blk[0] || (dtype != VIE_C64 && dtype != VIE_C128)) return 0;
+    const int m = opts ? opts->restart : 50;
+    if (m < 1 || m > 200) return 0;
+    return pwl_layout(op, dtype, m).total;
+}
+
+vie_status vie_solve_pwl(const vie_pwl_op* op, int dtype, const void* eps_c, const void* b, void* x,
+                         const vie_solve_opts* opts, vie_solve_info* info, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!op || !op->blk[0] || !eps_c || !b || !x || !ws) return fail(VIE_E_ARG, "vie_solve_pwl: null argument");
+    vie_solve_opts o;
+    o.tol = 1e-6;
+    o.restart = 50;
+    o.max_outer = 200;
+    o.adjoint = 0;
+    o.refine = 0;
+    o.inner_recon = VIE_RECON_FP32;
+    o.inner_tol = 1e-4;
+    if (opts) o = *opts;
+    if (!(o.tol > 0) || o.restart < 1 || o.restart > 200 || o.max_outer < 0 || (o.adjoint != 0 && o.adjoint != 1) ||
+        (o.refine != 0 && o.refine != 1))
+        return fail(VIE_E_ARG, "vie_solve_pwl: bad options");
+    if (dtype != VIE_C64 && dtype != VIE_C128) return fail(VIE_E_ARG, "vie_solve_pwl: bad dtype");
+    if (o.refine && (dtype != VIE_C128 || !(o.inner_tol > 0 && o.inner_tol < 1)))
+        return fail(VIE_E_ARG, "vie_solve_pwl: refinement needs VIE_C128 vectors and inner_tol in (0, 1)");
+    if (o.refine && o.inner_recon != VIE_RECON_FP32)
+        return fail(VIE_E_UNSUPPORTED, "vie_solve_pwl: refinement takes FP32 inner products only");
+    if (ws_bytes < vie_solve_pwl_workspace_bytes(op, dtype, &o))
+        return fail(VIE_E_ARG, "vie_solve_pwl: workspace too small");
+    if (info && info->history && info->hist_cap < 0) return fail(VIE_E_ARG, "vie_solve_pwl: bad history capacity");
+    const OpView& v = op->blk[0]->d.view;
+    const size_t vbytes = (size_t)12 * v.n[0] * v.n[1] * v.n[2] * (dtype == VIE_C128 ? 16 : 8);
+    const char* xb = (const char*)x;
+    const char* bb = (const char*)b;
+    if (!(xb + vbytes <= bb || bb + vbytes <= xb)) return fail(VIE_E_ARG, "vie_solve_pwl: x and b overlap");
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == VIE_C128)
+        return run_pwl<double>(op, dtype, eps_c, (const c2<double>*)b, (c2<double>*)x, o, info, (char*)ws, st);
+    return run_pwl<float>(op, dtype, eps_c, (const c2<float>*)b, (c2<float>*)x, o, info, (char*)ws, st);
 }
 
 }  // extern "C"

@@ -763,6 +763,8 @@ template hipError_t run_pass<float, float>(const DeviceOp&, int, int, int, const
                                            const void*, void*, int, hipStream_t, const int*, std::string&, bool);
 template hipError_t run_pass<double, double>(const DeviceOp&, int, int, int, const c2<double>*, const c2<double>*,
                                              const void*, void*, int, hipStream_t, const int*, std::string&, bool);
+template hipError_t run_pass<double, float>(const DeviceOp&, int, int, int, const c2<double>*, const c2<double>*,
+                                            const void*, void*, int, hipStream_t, const int*, std::string&, bool);
 
 template hipError_t launch_matvec<float, float>(const DeviceOp&, int, int, const c2<float>*, const c2<float>*,
                                                 c2<float>*, int, c2<float>*, hipStream_t, const int*,

@@ -371,8 +371,10 @@ hipError_t launch_pwl_z(const vie_pwl_op& P, int conj, c2<T>* S2, c2<T>* Wg, hip
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t pwl_matvec(const vie_pwl_op& P, int mode, const c2<T>* eps, const c2<T>* x, c2<T>* y, c2<T>* ws,
+// TV: vector element type, T: compute type (T = float with TV = double: the
+// FP32 products on FP64 vectors of a refined solve)
+template <typename TV, typename T>
+hipError_t pwl_matvec(const vie_pwl_op& P, int mode, const c2<TV>* eps, const c2<TV>* x, c2<TV>* y, c2<T>* ws,
                       hipStream_t s, std::string& err)
 {
     const DeviceOp& op = P.blk[0]->d;
@@ -382,15 +384,31 @@ hipError_t pwl_matvec(const vie_pwl_op& P, int mode, const c2<T>* eps, const c2<
     c2<T>* Wg = ws + matvec_ws_elems(op, 4);
     const bool conj = (mode == MODE_AH || mode == MODE_NH);
     // X+ : x -> S1, Y+ : S1 -> S2, Z : S2 in place, Y- : S2 -> S1, X- : S1 -> y
-    hipError_t e = run_pass<T, T>(op, 0, mode, 0, eps, x, nullptr, S1, 4, s, nullptr, err, false);
-    if (e == hipSuccess) e = run_pass<T, T>(op, 1, mode, 0, eps, x, S1, S2, 4, s, nullptr, err, false);
+    hipError_t e = run_pass<TV, T>(op, 0, mode, 0, eps, x, nullptr, S1, 4, s, nullptr, err, false);
+    if (e == hipSuccess) e = run_pass<TV, T>(op, 1, mode, 0, eps, x, S1, S2, 4, s, nullptr, err, false);
     if (e == hipSuccess) e = launch_pwl_z<T>(P, conj ? 1 : 0, S2, Wg, s, err);
-    if (e == hipSuccess) e = run_pass<T, T>(op, 3, mode, 0, eps, x, S2, S1, 4, s, nullptr, err, false);
-    if (e == hipSuccess) e = run_pass<T, T>(op, 4, mode, 0, eps, x, S1, y, 4, s, nullptr, err, false);
+    if (e == hipSuccess) e = run_pass<TV, T>(op, 3, mode, 0, eps, x, S2, S1, 4, s, nullptr, err, false);
+    if (e == hipSuccess) e = run_pass<TV, T>(op, 4, mode, 0, eps, x, S1, y, 4, s, nullptr, err, false);
     return e;
 }
 
 }  // namespace
+
+namespace vie {
+// FP32 products on complex128 vectors (refined solves); ws as for VIE_C128
+vie_status pwl_apply_mixed(const vie_pwl_op* op, int mode, const void* eps, const void* x, void* y, void* ws,
+                           hipStream_t s)
+{
+    std::string err;
+    hipError_t e = pwl_matvec<double, float>(*op, mode, (const c2<double>*)eps, (const c2<double>*)x, (c2<double>*)y,
+                                             (c2<float>*)ws, s, err);
+    if (e != hipSuccess) {
+        if (!err.empty()) return fail(VIE_E_UNSUPPORTED, "vie_solve_pwl: " + err);
+        return hip_fail(e, "vie_solve_pwl launch");
+    }
+    return VIE_OK;
+}
+}  // namespace vie
 
 extern "C" {
 
@@ -432,10 +450,10 @@ vie_status vie_matvec_pwl(const vie_pwl_op* op, int kind, int adjoint, int dtype
     hipStream_t s = (hipStream_t)stream;
     std::string err;
     hipError_t e = dtype == VIE_C128
-                       ? pwl_matvec<double>(*op, mode, (const c2<double>*)eps_c, (const c2<double>*)x, (c2<double>*)y,
-                                            (c2<double>*)ws, s, err)
-                       : pwl_matvec<float>(*op, mode, (const c2<float>*)eps_c, (const c2<float>*)x, (c2<float>*)y,
-                                           (c2<float>*)ws, s, err);
+                       ? pwl_matvec<double, double>(*op, mode, (const c2<double>*)eps_c, (const c2<double>*)x,
+                                                    (c2<double>*)y, (c2<double>*)ws, s, err)
+                       : pwl_matvec<float, float>(*op, mode, (const c2<float>*)eps_c, (const c2<float>*)x,
+                                                  (c2<float>*)y, (c2<float>*)ws, s, err);
     if (e != hipSuccess) {
         if (!err.empty()) return fail(VIE_E_UNSUPPORTED, "vie_matvec_pwl: " + err);
         return hip_fail(e, "vie_matvec_pwl launch");

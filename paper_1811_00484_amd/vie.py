@@ -118,6 +118,9 @@ _SIGS = {
     "vie_pwl_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int]),
     "vie_matvec_pwl": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, ctypes.c_size_t,
                                       _P]),
+    "vie_solve_pwl_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int, ctypes.POINTER(SolveOpts)]),
+    "vie_solve_pwl": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.POINTER(SolveOpts),
+                                     ctypes.POINTER(SolveInfo), _P, ctypes.c_size_t, _P]),
     "vie_op_destroy": (ctypes.c_int, [_P]),
     "vie_op_query": (ctypes.c_int, [_P, _P, _P]),
     "vie_op_densify": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -385,6 +388,39 @@ def matvec_pwl(op, x, eps_c=None, kind="A", adjoint=False, out=None):
     _check(lib.vie_matvec_pwl(op.handle, k, 1 if adjoint else 0, dt, _ptr(eps_c) if k == VIE_OP_A else None,
                               _ptr(x), _ptr(y), _ptr(ws), nbytes, _stream()), "vie_matvec_pwl")
     return y
+
+
+def solve_pwl(op, b, eps_c, tol=1e-6, restart=50, max_outer=200, adjoint=False, refine=False, inner_tol=1e-4,
+              history=64):
+    """GMRES for the piecewise-linear operator (vie_solve_pwl): b and the
+    solution are (12, n3, n2, n1) in the mass-normalised basis.  ``refine``
+    (complex128 only): FP32 products in the Arnoldi steps, FP64 restart
+    residuals.  Returns (x, info dict, status)."""
+    n1, n2, n3 = op.n
+    if tuple(b.shape) != (12, n3, n2, n1) or not b.is_contiguous():
+        raise ValueError("b must be contiguous (12, n3, n2, n1)")
+    dt = _dt(b)
+    _require_like(eps_c, b, (n3, n2, n1), "eps_c")
+    _require_device(b, "b")
+    lib = load()
+    opts = SolveOpts(float(tol), int(restart), int(max_outer), int(bool(adjoint)), int(bool(refine)),
+                     VIE_RECON_FP32, float(inner_tol))
+    nbytes = lib.vie_solve_pwl_workspace_bytes(op.handle, dt, ctypes.byref(opts))
+    if nbytes == 0:
+        raise VieError(VIE_E_ARG, "vie_solve_pwl_workspace_bytes rejected the options")
+    ws = _scratch(nbytes, b.device)
+    x = torch.empty_like(b)
+    hist = np.zeros(max(1, int(history)))
+    info = SolveInfo()
+    info.history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    info.hist_cap = int(history)
+    st = lib.vie_solve_pwl(op.handle, dt, _ptr(eps_c), _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(info),
+                           _ptr(ws), nbytes, _stream())
+    _check(st, "vie_solve_pwl")
+    d = {"matvecs": info.matvecs, "matvecs_fp64": info.matvecs_fp64, "restarts": info.restarts,
+         "refine_steps": info.refine_steps, "converged": bool(info.converged),
+         "rel_residual": info.rel_residual, "history": hist[:info.hist_len].tolist()}
+    return x, d, st
 
 
 def compress_k(green_k, tol=1e-6, trunc_rule=0, max_rank=0):

@@ -119,3 +119,25 @@ def test_pwl_rejects_bad_arguments():
         vie.matvec_pwl(op, x[:11])
     with pytest.raises(ValueError):
         vie.matvec_pwl(op, x, None, kind="A")
+
+
+@pytest.mark.parametrize("dtype,refine,tol", [(torch.complex64, False, 1e-5), (torch.complex128, True, 1e-8)])
+def test_pwl_solve_residual_by_the_oracle(dtype, refine, tol):
+    # GMRES on the PWL operator (plane-wave moments as the right-hand side);
+    # the residual of the device solution measured by the FP64 oracle on the
+    # same HOSVD tensors
+    n = (10, 9, 8)
+    say("pwl solve", n, dtype, refine)
+    G, epsc, kh, _ = pwl_problem(n)
+    op = vie.compress_pwl(G, tol=1e-6)
+    b = vi.rhs_from_field(epsc, vi.plane_wave_pwl(n, 0.005, F), F)
+    bn = pwl.SCALE[:, None, None, None, None] * b
+    x, info, st = vie.solve_pwl(op, to_dev(bn.reshape(12, n[2], n[1], n[0]), dtype), to_dev(epsc, dtype), tol=tol,
+                                restart=30, max_outer=100, refine=refine)
+    say("   ", {k: v for k, v in info.items() if k != "history"})
+    assert st == 0 and info["converged"]
+    xs = x.cpu().numpy().astype(np.complex128).reshape(bn.shape)
+    r = _reference(kh, epsc, xs, "A") - bn
+    rel_res = np.linalg.norm(r) / np.linalg.norm(bn)
+    say("   oracle residual", rel_res)
+    assert rel_res <= (3e-5 if dtype == torch.complex64 else 2 * tol)

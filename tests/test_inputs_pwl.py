@@ -161,3 +161,20 @@ def test_near_quadrature_converges(D):
     a = green_pwl_entry(D, 0.5, 12, method=0)
     b = green_pwl_entry(D, 0.5, 24, method=0)
     np.testing.assert_allclose(a, b, rtol=0, atol=1e-10)
+
+
+def test_plane_wave_moments_match_closed_forms():
+    # x-polarised exp(-i k0 z): pulse moment = sinc(a/2) exp(-i k0 z_m),
+    # z-linear moment = i (a cos(a/2) - 2 sin(a/2)) / a^2 exp(-i k0 z_m),
+    # a = k0 h; the x- and y-linear moments and the other components vanish
+    import vie_inputs as vi
+    n, h, f = (4, 3, 5), 0.01, 3e9
+    m = vi.plane_wave_pwl(n, h, f)
+    k0 = vi.wavenumber(f)
+    a = k0 * h
+    _, _, z = vi.voxel_centres(n, h)
+    ez = np.exp(-1j * k0 * z)
+    np.testing.assert_allclose(m[0, 0], np.sin(a / 2) / (a / 2) * ez, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(m[3, 0], 1j * (a * np.cos(a / 2) - 2 * np.sin(a / 2)) / a ** 2 * ez, rtol=0,
+                               atol=1e-14)
+    assert np.abs(m[1:3]).max() < 1e-15 and np.abs(m[:, 1:]).max() == 0.0

@@ -18,7 +18,8 @@ from .constants import C0, EPS0, MU0, COMPONENTS, omega, wavenumber
 from .grid import voxel_centres
 from .materials import complex_permittivity, TISSUES_298MHZ
 from .phantoms import sphere_phantom, head_phantom, head_semi_axes
-from .fields import plane_wave, plane_wave_h, dipole_field, dipole_ring, dipole_cylinder, rhs_from_field
+from .fields import plane_wave, plane_wave_h, plane_wave_pwl, pwl_moments, dipole_field, dipole_ring, \
+    dipole_cylinder, rhs_from_field
 from .green import GreenEntryCallback, PWL_PAIRS, green_entries, green_k_tensor, green_pwl_entry, \
     green_pwl_tensor, green_tensor, pwl_pair_index
 from .random import random_field, random_complex
@@ -26,7 +27,7 @@ from .random import random_field, random_complex
 __all__ = [
     "C0", "EPS0", "MU0", "COMPONENTS", "omega", "wavenumber", "voxel_centres",
     "complex_permittivity", "TISSUES_298MHZ", "sphere_phantom", "head_phantom",
-    "head_semi_axes", "plane_wave", "plane_wave_h", "dipole_field", "dipole_ring", "dipole_cylinder",
+    "head_semi_axes", "plane_wave", "plane_wave_h", "plane_wave_pwl", "pwl_moments", "dipole_field", "dipole_ring", "dipole_cylinder",
     "rhs_from_field", "green_tensor", "green_pwl_tensor", "green_pwl_entry", "PWL_PAIRS",
     "pwl_pair_index", "green_k_tensor", "green_entries", "GreenEntryCallback", "random_field", "random_complex",
 ]

@@ -81,3 +81,38 @@ def rhs_from_field(eps_c, e_inc, freq_hz):
     ce = 1j * omega(freq_hz) * EPS0
     chi = np.asarray(eps_c) - 1.0
     return ce * chi[None] * e_inc
+
+
+def pwl_moments(n, h, field, order=6):
+    """Voxel moments of a vector field against the piecewise-linear basis
+    (eq. 7b): out[l, p, k, j, i] = (1/h^3) int_voxel C^l(r) E_p(r) dr with
+    C^0 = 1 and C^l = (r_a - r_a,m)/h (a = l - 1) inside the voxel, by a
+    tensor Gauss-Legendre rule of ``order`` points per axis.  ``field(x, y,
+    z)`` returns the (3, ...) complex field at points of the broadcast
+    shape.  Shape (4, 3, n3, n2, n1) complex128."""
+    x, y, z = voxel_centres(n, h)
+    t, w = np.polynomial.legendre.leggauss(order)
+    t, w = 0.5 * t, 0.5 * w
+    out = np.zeros((4, 3) + z.shape, dtype=np.complex128)
+    for a, ta in enumerate(t):
+        for b, tb in enumerate(t):
+            for c, tc in enumerate(t):
+                e = np.asarray(field(x + h * ta, y + h * tb, z + h * tc))
+                wt = w[a] * w[b] * w[c]
+                out[0] += wt * e
+                out[1] += (wt * ta) * e
+                out[2] += (wt * tb) * e
+                out[3] += (wt * tc) * e
+    return out
+
+
+def plane_wave_pwl(n, h, freq_hz, pol=0, amplitude=1.0):
+    """``plane_wave`` as piecewise-linear voxel moments (``pwl_moments``),
+    shape (4, 3, n3, n2, n1)."""
+    k0 = wavenumber(freq_hz)
+
+    def field(x, y, z):
+        e = np.zeros((3,) + np.broadcast(x, y, z).shape, dtype=np.complex128)
+        e[pol] = amplitude * np.exp(-1j * k0 * z)
+        return e
+    return pwl_moments(n, h, field)
