@@ -229,3 +229,28 @@ def to_normalised(op, u):
     mass-normalised basis: S op(S u)."""
     S = SCALE[:, None, None, None, None]
     return S * op(S * u)
+
+
+def sampled_outputs(green, eps_c, u, samples):
+    """(A u)^{pl}(m) at the sampled (l, p, k, j, i) one by one, each as the
+    Galerkin sum written out over every basis function of the grid (the
+    offsets D = m' - m of all m', with the parities and the pair swap of the
+    stored tensors): for grids too large for ``dense_kernels``."""
+    n3, n2, n1 = u.shape[2:]
+    out = []
+    for (l, p, k, j, i) in samples:
+        acc = 0j
+        for lp in range(4):
+            for q in range(3):
+                a, b = (l, lp) if l <= lp else (lp, l)
+                sign0 = swap_sign(l, lp) if l > lp else 1.0
+                odd = odd_axes(l, lp, p, q)
+                T = green[PAIRS.index((a, b)), comp_index(p, q)]
+                D = [np.arange(n1) - i, np.arange(n2) - j, np.arange(n3) - k]
+                sg = [np.where((d < 0) & o, -1.0, 1.0) for d, o in zip(D, odd)]
+                vals = T[np.ix_(np.abs(D[2]), np.abs(D[1]), np.abs(D[0]))]
+                vals = vals * (sign0 * sg[2][:, None, None] * sg[1][None, :, None] * sg[0][None, None, :])
+                acc += np.sum(vals * u[lp, q])
+        e = eps_c[k, j, i]
+        out.append(e * MASS[l] * u[l, p, k, j, i] - (e - 1.0) * acc)
+    return np.array(out)

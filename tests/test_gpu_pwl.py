@@ -141,3 +141,33 @@ def test_pwl_solve_residual_by_the_oracle(dtype, refine, tol):
     rel_res = np.linalg.norm(r) / np.linalg.norm(bn)
     say("   oracle residual", rel_res)
     assert rel_res <= (3e-5 if dtype == torch.complex64 else 2 * tol)
+
+
+@pytest.mark.parametrize("N", [120, 128])
+def test_pwl_fullsize_sampled_outputs(N):
+    # the refinement series' 2.5 mm grid (the bench's launch configuration,
+    # mixed-radix passes) and 128^3 (register-FFT X/Y passes): sampled
+    # outputs of the device matvec against the Galerkin sums written out over
+    # the oracle's HOSVD tensors at the same tolerance
+    n = (N, N, N)
+    h = 0.3 / N
+    say("pwl full size", n)
+    G = vi.green_pwl_tensor(n, h, K0)
+    er, sg, _ = vi.sphere_phantom(n, h, 0.15, 65.0, 0.6)
+    epsc = vi.complex_permittivity(er, sg, F)
+    op = vie.compress_pwl(G, tol=1e-6)
+    Gt, ranks = pwl.tucker_tensors(G, 1e-6)
+    assert np.array_equal(op.ranks, ranks)
+    del G
+    rng = np.random.default_rng(210)
+    u = rng.standard_normal((4, 3, N, N, N)) + 1j * rng.standard_normal((4, 3, N, N, N))
+    y = _device(op, epsc, u, "A", torch.complex64)
+    S = pwl.SCALE
+    samples = [(int(rng.integers(4)), int(rng.integers(3)), int(rng.integers(N)), int(rng.integers(N)),
+                int(rng.integers(N))) for _ in range(12)] + [(3, 2, N - 1, N - 1, N - 1), (0, 0, 0, 0, 0)]
+    ref = pwl.sampled_outputs(Gt, epsc, S[:, None, None, None, None] * u, samples)
+    ref = np.array([S[s[0]] * r for s, r in zip(samples, ref)])
+    got = np.array([y[s] for s in samples])
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say("   max sampled error / max |y|", err)
+    assert err <= 1e-5

@@ -112,3 +112,14 @@ def test_tucker_kernels_approach_the_dense_ones():
     kt6, ranks6 = pwl.tucker_kernels(g, 1e-4)
     assert ranks6.sum() < ranks.sum()
     assert np.linalg.norm(pwl.apply(kt6, u) - yd) < 1e-3 * np.linalg.norm(yd)
+
+
+def test_sampled_outputs_equal_the_fft_matvec():
+    n = (5, 4, 3)
+    g = green_pwl_tensor(n, 1.0, 0.45)
+    eps = 1.0 + _vec((n[2], n[1], n[0]), 21)
+    u = _vec((4, 3, n[2], n[1], n[0]), 22)
+    y = pwl.matvec(pwl.dense_kernels(g), eps, u, "A")
+    samples = [(0, 0, 0, 0, 0), (3, 2, 2, 3, 4), (1, 1, 1, 2, 0), (2, 0, 0, 1, 3), (1, 2, 2, 0, 2)]
+    ys = pwl.sampled_outputs(g, eps, u, samples)
+    np.testing.assert_allclose(ys, [y[s] for s in samples], rtol=0, atol=1e-13)
