@@ -37,6 +37,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <string>
+#include <utility>
 
 #include "fft_device.h"
 
@@ -55,6 +56,14 @@ using namespace vie;
 constexpr int kNT = 256;    // threads of the W kernel
 constexpr int kNTZ = 512;   // threads of the z kernel
 
+template <typename T>
+__device__ __forceinline__ void sym3(const c2<T> (&N)[6], const c2<T> (&x)[3], c2<T> (&y)[3])
+{
+    y[0] = N[0] * x[0] + N[3] * x[1] + N[4] * x[2];
+    y[1] = N[3] * x[0] + N[1] * x[1] + N[5] * x[2];
+    y[2] = N[4] * x[0] + N[5] * x[1] + N[2] * x[2];
+}
+
 struct PwlZArgs {
     int n[3];
     int L[3];
@@ -62,14 +71,79 @@ struct PwlZArgs {
     int conj;    // adjoint
     int rmax;    // largest Tucker rank over the ten blocks
     int pb;      // pairs whose tables are built and applied together (1..10)
+    // parity mask of component c of pair b (bit a: odd along axis a)
+    unsigned char om[60];
 };
 
-template <typename T>
-__device__ __forceinline__ void sym3(const c2<T> (&N)[6], const c2<T> (&x)[3], c2<T> (&y)[3])
+// the sign of a table entry at a mirrored position: f = f1 | f2 << 1 | f3 << 2
+// (mirror flags), odd along each flagged axis of the mask
+__device__ __forceinline__ bool pwl_neg(unsigned om, unsigned f)
 {
-    y[0] = N[0] * x[0] + N[3] * x[1] + N[4] * x[2];
-    y[1] = N[3] * x[0] + N[1] * x[1] + N[5] * x[2];
-    y[2] = N[4] * x[0] + N[5] * x[1] + N[2] * x[2];
+    return __popc(om & f) & 1;
+}
+
+// the (a, b) and (b, a) blocks of stored pair B on one Fourier position,
+// pair indices known at compile time (no runtime selection of registers)
+template <int B, typename T>
+__device__ __forceinline__ void pwl_pair(c2<T> (&acc)[12], const c2<T> (&x)[12], const c2<T>* NTT, int n3p1, int kk,
+                                         unsigned f, const unsigned char* om, bool conj)
+{
+    constexpr int la = kPwlPairs[B][0], lb = kPwlPairs[B][1];
+    constexpr bool sig = (la == 0) != (lb == 0);
+    c2<T> N[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        c2<T> t = NTT[(B * 6 + c) * n3p1 + kk];
+        if (pwl_neg(om[B * 6 + c], f)) t = mk<T>(-t.x, -t.y);
+        N[c] = conj ? vie::conj(t) : t;
+    }
+    const T sab = (sig && !conj) ? (T)-1 : (T)1;
+    const T sba = (sig && conj) ? (T)-1 : (T)1;
+    c2<T> y[3];
+    const c2<T> xb[3] = {x[3 * lb], x[3 * lb + 1], x[3 * lb + 2]};
+    sym3(N, xb, y);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[3 * la + q] = acc[3 * la + q] + sab * y[q];
+    if constexpr (la != lb) {
+        const c2<T> xa[3] = {x[3 * la], x[3 * la + 1], x[3 * la + 2]};
+        sym3(N, xa, y);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[3 * lb + q] = acc[3 * lb + q] + sba * y[q];
+    }
+}
+
+template <typename T, int... B>
+__device__ __forceinline__ void pwl_all_pairs(c2<T> (&acc)[12], const c2<T> (&x)[12], const c2<T>* NTT, int n3p1,
+                                              int kk, unsigned f, const unsigned char* om, bool conj,
+                                              std::integer_sequence<int, B...>)
+{
+    (pwl_pair<B, T>(acc, x, NTT, n3p1, kk, f, om, conj), ...);
+}
+
+// mixed-radix LDS transform of the 12 P pencils; LC > 0: the length is
+// known at compile time (radix-8 stages, then 4 or 2), so the stage index
+// arithmetic divides by constants
+template <int DIR, int MAXE, int LC, typename T>
+__device__ __forceinline__ void pwl_fft(c2<T>* X, int nseq, int L3, const FftPlan& pl, const c2<T>* tws, int tid)
+{
+    if constexpr (LC == 512) {
+        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
+        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 8, tws, tid, kNTZ);
+        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 64, tws, tid, kNTZ);
+    } else if constexpr (LC == 256) {
+        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
+        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 8, tws, tid, kNTZ);
+        stage_r<4, DIR, false, MAXE>(X, nseq, LC, 1, LC, 64, tws, tid, kNTZ);
+    } else if constexpr (LC == 128) {
+        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
+        stage_r<4, DIR, false, MAXE>(X, nseq, LC, 1, LC, 8, tws, tid, kNTZ);
+        stage_r<4, DIR, false, MAXE>(X, nseq, LC, 1, LC, 32, tws, tid, kNTZ);
+    } else if constexpr (LC == 64) {
+        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
+        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 8, tws, tid, kNTZ);
+    } else {
+        fft_lds<DIR, false, MAXE>(X, nseq, L3, 1, pl, tws, tid, kNTZ);
+    }
 }
 
 // W_c(k2) = G_c x2 U2_c(k2, :) (r1 x r3) for every component of the ten
@@ -94,14 +168,15 @@ __global__ void __launch_bounds__(kNT) k_pwl_w(const PwlBlock<T>* __restrict__ b
     }
 }
 
-template <typename T, int MAXE, int EPT>
+template <typename T, int MAXE, int EPT, int LC>
 __global__ void __launch_bounds__(kNTZ) k_pwl_z(c2<T>* __restrict__ S2, FftPlan pl, const c2<T>* __restrict__ tw,
                                                PwlZArgs a, const PwlBlock<T>* __restrict__ blk,
                                                const c2<T>* __restrict__ Wg)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int n1 = a.n[0], n2 = a.n[1], n3 = a.n[2];
-    const int L1 = a.L[0], L2 = a.L[1], L3 = a.L[2];
+    const int n1 = a.n[0], n2 = a.n[1];
+    const int n3 = LC ? LC / 2 : a.n[2];
+    const int L1 = a.L[0], L2 = a.L[1], L3 = LC ? LC : a.L[2];
     const int rmax = a.rmax;
     const int tid = threadIdx.x;
 
@@ -155,7 +230,7 @@ __global__ void __launch_bounds__(kNTZ) k_pwl_z(c2<T>* __restrict__ S2, FftPlan 
         X[s * L3 + m] = val;
     }
     __syncthreads();
-    fft_lds<-1, false, MAXE>(X, 12 * P, L3, 1, pl, tws, tid, kNTZ);
+    pwl_fft<-1, MAXE, LC>(X, 12 * P, L3, pl, tws, tid);
 
     c2<T> acc[12][EPT];
 #pragma unroll
@@ -226,10 +301,20 @@ __global__ void __launch_bounds__(kNTZ) k_pwl_z(c2<T>* __restrict__ S2, FftPlan 
                 c2<T> x[12];
 #pragma unroll
                 for (int c = 0; c < 12; ++c) x[c] = X[(c * P + pe) * L3 + m];
+                const unsigned fb = (unsigned)pf1[pe] | ((unsigned)pf2[pe] << 1) | ((unsigned)f3 << 2);
+                if (nb == 10) {
+                    c2<T> ac[12];
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) ac[c] = acc[c][j];
+                    pwl_all_pairs<T>(ac, x, NTT, n3 + 1, kk, fb, a.om, a.conj != 0,
+                                     std::make_integer_sequence<int, 10>{});
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) acc[c][j] = ac[c];
+                    continue;
+                }
 #pragma unroll 1
                 for (int bi = 0; bi < nb; ++bi) {
                     const int b = b0 + bi;
-                    const int lmask = blk[b].v.lmask;
                     const int la = kPwlPairs[b][0], lb = kPwlPairs[b][1];
                     const T sig = ((la == 0) != (lb == 0)) ? (T)-1 : (T)1;
                     const T sab = a.conj ? (T)1 : sig;     // factor of the (a, b) block
@@ -238,9 +323,7 @@ __global__ void __launch_bounds__(kNTZ) k_pwl_z(c2<T>* __restrict__ S2, FftPlan 
 #pragma unroll
                     for (int c = 0; c < 6; ++c) {
                         c2<T> t = NTT[(bi * 6 + c) * (n3 + 1) + kk];
-                        const int neg = (view_odd(0, lmask, c, 0) & pf1[pe]) ^ (view_odd(0, lmask, c, 1) & pf2[pe]) ^
-                                        (view_odd(0, lmask, c, 2) & f3);
-                        if (neg) t = mk<T>(-t.x, -t.y);
+                        if (pwl_neg(a.om[b * 6 + c], fb)) t = mk<T>(-t.x, -t.y);
                         Nc[c] = a.conj ? vie::conj(t) : t;
                     }
                     // register arrays need compile-time indices: select the rows
@@ -286,7 +369,7 @@ __global__ void __launch_bounds__(kNTZ) k_pwl_z(c2<T>* __restrict__ S2, FftPlan 
         }
     }
     __syncthreads();
-    fft_lds<1, false, MAXE>(X, 12 * P, L3, 1, pl, tws, tid, kNTZ);
+    pwl_fft<1, MAXE, LC>(X, 12 * P, L3, pl, tws, tid);
     for (int e = tid; e < 12 * P * n3; e += kNTZ) {
         const int s = e / n3, m = e - s * n3;
         const int comp = s / P, pe = s - comp * P;
@@ -350,6 +433,12 @@ hipError_t launch_pwl_z(const vie_pwl_op& P, int conj, c2<T>* S2, c2<T>* Wg, hip
     za.conj = conj;
     za.rmax = P.rmax;
     za.pb = pb;
+    for (int b = 0; b < 10; ++b)
+        for (int c = 0; c < 6; ++c) {
+            const int lm = P.blk[b]->d.view.lmask;
+            za.om[b * 6 + c] = (unsigned char)(view_odd(0, lm, c, 0) | (view_odd(0, lm, c, 1) << 1) |
+                                               (view_odd(0, lm, c, 2) << 2));
+        }
     const int n1 = v.n[0], n2 = v.n[1];
     const int nblk = G == 4 ? (n1 + 1) * (n2 + 1) : (G == 2 ? (n1 + 1) * v.L[1] : v.L[0] * v.L[1]);
     const size_t lds = pwl_z_lds<T>(v, P.rmax, G, pb);
@@ -365,7 +454,12 @@ hipError_t launch_pwl_z(const vie_pwl_op& P, int conj, c2<T>* S2, c2<T>* Wg, hip
     constexpr int EPT = pwl_ept<T>();
     constexpr int MAXE = 12 * EPT;
     hipLaunchKernelGGL((k_pwl_w<T>), dim3(n2 + 1, 60), dim3(kNT), 0, s, blk, P.rmax, Wg);
-    auto kern = k_pwl_z<T, MAXE, EPT>;
+    const int L3 = v.L[2];
+    auto kern = L3 == 512 ? k_pwl_z<T, MAXE, EPT, 512>
+                : L3 == 256 ? k_pwl_z<T, MAXE, EPT, 256>
+                : L3 == 128 ? k_pwl_z<T, MAXE, EPT, 128>
+                : L3 == 64 ? k_pwl_z<T, MAXE, EPT, 64>
+                : k_pwl_z<T, MAXE, EPT, 0>;
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(kNTZ), lds, s, S2, op.plan[2], tw, za, blk, (const c2<T>*)Wg);
     return hipGetLastError();
