@@ -121,7 +121,7 @@ __device__ __forceinline__ void pwl_all_pairs(c2<T> (&acc)[12], const c2<T> (&x)
 }
 
 // mixed-radix LDS transform of the 12 P pencils; LC > 0: the length is
-// known at compile time (radix-8 stages, then 4 or 2), so the stage index
+// known at compile time (a fixed radix sequence), so the stage index
 // arithmetic divides by constants
 template <int DIR, int MAXE, int LC, typename T>
 __device__ __forceinline__ void pwl_fft(c2<T>* X, int nseq, int L3, const FftPlan& pl, const c2<T>* tws, int tid)
@@ -141,6 +141,29 @@ __device__ __forceinline__ void pwl_fft(c2<T>* X, int nseq, int L3, const FftPla
     } else if constexpr (LC == 64) {
         stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
         stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 8, tws, tid, kNTZ);
+    } else if constexpr (LC == 300) {   // the refinement series' edges 150, 120, 90, 60, 30
+        stage_r<5, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
+        stage_r<5, DIR, false, MAXE>(X, nseq, LC, 1, LC, 5, tws, tid, kNTZ);
+        stage_r<4, DIR, false, MAXE>(X, nseq, LC, 1, LC, 25, tws, tid, kNTZ);
+        stage_r<3, DIR, false, MAXE>(X, nseq, LC, 1, LC, 100, tws, tid, kNTZ);
+    } else if constexpr (LC == 240) {
+        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
+        stage_r<5, DIR, false, MAXE>(X, nseq, LC, 1, LC, 8, tws, tid, kNTZ);
+        stage_r<3, DIR, false, MAXE>(X, nseq, LC, 1, LC, 40, tws, tid, kNTZ);
+        stage_r<2, DIR, false, MAXE>(X, nseq, LC, 1, LC, 120, tws, tid, kNTZ);
+    } else if constexpr (LC == 180) {
+        stage_r<5, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
+        stage_r<4, DIR, false, MAXE>(X, nseq, LC, 1, LC, 5, tws, tid, kNTZ);
+        stage_r<3, DIR, false, MAXE>(X, nseq, LC, 1, LC, 20, tws, tid, kNTZ);
+        stage_r<3, DIR, false, MAXE>(X, nseq, LC, 1, LC, 60, tws, tid, kNTZ);
+    } else if constexpr (LC == 120) {
+        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
+        stage_r<5, DIR, false, MAXE>(X, nseq, LC, 1, LC, 8, tws, tid, kNTZ);
+        stage_r<3, DIR, false, MAXE>(X, nseq, LC, 1, LC, 40, tws, tid, kNTZ);
+    } else if constexpr (LC == 60) {
+        stage_r<5, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
+        stage_r<4, DIR, false, MAXE>(X, nseq, LC, 1, LC, 5, tws, tid, kNTZ);
+        stage_r<3, DIR, false, MAXE>(X, nseq, LC, 1, LC, 20, tws, tid, kNTZ);
     } else {
         fft_lds<DIR, false, MAXE>(X, nseq, L3, 1, pl, tws, tid, kNTZ);
     }
@@ -377,10 +400,16 @@ __global__ void __launch_bounds__(kNTZ) k_pwl_z(c2<T>* __restrict__ S2, FftPlan 
     }
 }
 
+// Fourier positions per thread of the z kernel in complex64 (G L3 <= EPT 512):
+// 2 lets four mirror pencils share each table at z lengths up to 256
+#ifndef VIE_PWL_EPT32
+#define VIE_PWL_EPT32 1
+#endif
+
 template <typename T>
 constexpr int pwl_ept()
 {
-    return 1;   // owned positions per thread: G * L3 <= EPT * 512
+    return sizeof(T) == 4 ? VIE_PWL_EPT32 : 1;
 }
 
 template <typename T>
@@ -459,6 +488,11 @@ hipError_t launch_pwl_z(const vie_pwl_op& P, int conj, c2<T>* S2, c2<T>* Wg, hip
                 : L3 == 256 ? k_pwl_z<T, MAXE, EPT, 256>
                 : L3 == 128 ? k_pwl_z<T, MAXE, EPT, 128>
                 : L3 == 64 ? k_pwl_z<T, MAXE, EPT, 64>
+                : L3 == 300 ? k_pwl_z<T, MAXE, EPT, 300>
+                : L3 == 240 ? k_pwl_z<T, MAXE, EPT, 240>
+                : L3 == 180 ? k_pwl_z<T, MAXE, EPT, 180>
+                : L3 == 120 ? k_pwl_z<T, MAXE, EPT, 120>
+                : L3 == 60 ? k_pwl_z<T, MAXE, EPT, 60>
                 : k_pwl_z<T, MAXE, EPT, 0>;
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(kNTZ), lds, s, S2, op.plan[2], tw, za, blk, (const c2<T>*)Wg);
