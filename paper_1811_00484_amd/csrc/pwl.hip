@@ -403,7 +403,7 @@ __global__ void __launch_bounds__(kNTZ) k_pwl_z(c2<T>* __restrict__ S2, FftPlan 
 // Fourier positions per thread of the z kernel in complex64 (G L3 <= EPT 512):
 // 2 lets four mirror pencils share each table at z lengths up to 256
 #ifndef VIE_PWL_EPT32
-#define VIE_PWL_EPT32 1
+#define VIE_PWL_EPT32 2
 #endif
 
 template <typename T>
