@@ -316,6 +316,18 @@ vie_status vie_matvec_pwl(const vie_pwl_op* op, int kind, int adjoint, int dtype
                           void* y, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * vie_tucker_cross_pwl -- vie_tucker_cross for one of the sixty
+ * piecewise-linear components, comp = 6 P + c (pair P in the order of
+ * vie_compress_pwl, dyadic component c): the callback receives that comp;
+ * the parity zeros follow the component's parities (see the PWL section);
+ * the counts go to slot c of xinfo.  Host only, grids up to 65536 per axis
+ * (the paper's 270 x 141 x 902 body domain, Table III).
+ */
+vie_status vie_tucker_cross_pwl(const int n[3], vie_entry_fn fn, void* ctx, int comp, const vie_cross_opts* opts,
+                                int ranks[3], double* core, size_t core_cap, double* factors, size_t fac_cap,
+                                vie_cross_info* xinfo);
+
+/*
  * vie_tucker_hadamard -- one compressed component applied element-wise on
  * its own grid: y = D .* x with D = G x1 U1 x2 U2 x3 U3 (Tucker, eq. 14) or
  * D(i,j,k) = sum_l lambda_l U1(i,l) U2(j,l) U3(k,l) (Tucker+CP, eq. 17 with

@@ -462,37 +462,35 @@ vie_status vie_compress_cross(const int n[3], vie_entry_fn fn, void* ctx, const 
     return st;
 }
 
-vie_status vie_tucker_cross(const int n[3], vie_entry_fn fn, void* ctx, int comp, const vie_cross_opts* opts,
-                            int ranks[3], double* core, size_t core_cap, double* factors, size_t fac_cap,
-                            vie_cross_info* xinfo)
+// host-only cross of one component whose parity zeros are odd[3]; the
+// counts go to slot `slot` of xinfo
+static vie_status tucker_cross_host(const char* who, const int n[3], vie_entry_fn fn, void* ctx, int comp,
+                                    const int odd[3], int slot, const vie_cross_opts* opts, int ranks[3], double* core,
+                                    size_t core_cap, double* factors, size_t fac_cap, vie_cross_info* xinfo)
 {
     auto t0 = std::chrono::steady_clock::now();
-    if (!n || !fn || !ranks) return fail(VIE_E_ARG, "vie_tucker_cross: null argument");
-    if (comp < 0 || comp > 5) return fail(VIE_E_ARG, "vie_tucker_cross: comp must be in [0, 5]");
     for (int a = 0; a < 3; ++a)
-        if (n[a] < 1 || n[a] > 65536) return fail(VIE_E_ARG, "vie_tucker_cross: n_i must be in [1, 65536]");
+        if (n[a] < 1 || n[a] > 65536) return fail(VIE_E_ARG, std::string(who) + ": n_i must be in [1, 65536]");
     CrossParams p;
-    vie_status st = cross_params(opts, p, "vie_tucker_cross");
+    vie_status st = cross_params(opts, p, who);
     if (st != VIE_OK) return st;
-    int odd[3];
-    for (int a = 0; a < 3; ++a) odd[a] = comp_odd(0, comp, a);
     TuckerComponent tc;
     CrossStats cs;
     std::string err;
     const int rc = tucker_cross(fn, ctx, comp, odd, n, p, tc, cs, err);
-    if (rc != 0) return cross_status(rc, err, "vie_tucker_cross");
+    if (rc != 0) return cross_status(rc, err, who);
     for (int a = 0; a < 3; ++a) ranks[a] = tc.r[a];
     if (xinfo) {
-        xinfo->evals[comp] = cs.evals;
-        xinfo->evals_sample[comp] = cs.evals_sample;
-        xinfo->sweeps[comp] = cs.sweeps;
-        xinfo->sample_rel_err[comp] = cs.sample_rel_err;
+        xinfo->evals[slot] = cs.evals;
+        xinfo->evals_sample[slot] = cs.evals_sample;
+        xinfo->sweeps[slot] = cs.sweeps;
+        xinfo->sample_rel_err[slot] = cs.sample_rel_err;
         xinfo->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     const size_t ng = (size_t)tc.r[0] * tc.r[1] * tc.r[2];
     const size_t nf = (size_t)n[0] * tc.r[0] + (size_t)n[1] * tc.r[1] + (size_t)n[2] * tc.r[2];
     if ((core && core_cap < ng) || (factors && fac_cap < nf))
-        return fail(VIE_E_ARG, "vie_tucker_cross: output buffer too small for ranks (" + std::to_string(tc.r[0]) +
+        return fail(VIE_E_ARG, std::string(who) + ": output buffer too small for ranks (" + std::to_string(tc.r[0]) +
                                    ", " + std::to_string(tc.r[1]) + ", " + std::to_string(tc.r[2]) + ")");
     if (core)
         for (size_t t = 0; t < ng; ++t) {
@@ -509,6 +507,33 @@ vie_status vie_tucker_cross(const int n[3], vie_entry_fn fn, void* ctx, int comp
             }
     }
     return VIE_OK;
+}
+
+vie_status vie_tucker_cross(const int n[3], vie_entry_fn fn, void* ctx, int comp, const vie_cross_opts* opts,
+                            int ranks[3], double* core, size_t core_cap, double* factors, size_t fac_cap,
+                            vie_cross_info* xinfo)
+{
+    if (!n || !fn || !ranks) return fail(VIE_E_ARG, "vie_tucker_cross: null argument");
+    if (comp < 0 || comp > 5) return fail(VIE_E_ARG, "vie_tucker_cross: comp must be in [0, 5]");
+    int odd[3];
+    for (int a = 0; a < 3; ++a) odd[a] = comp_odd(0, comp, a);
+    return tucker_cross_host("vie_tucker_cross", n, fn, ctx, comp, odd, comp, opts, ranks, core, core_cap, factors,
+                             fac_cap, xinfo);
+}
+
+vie_status vie_tucker_cross_pwl(const int n[3], vie_entry_fn fn, void* ctx, int comp, const vie_cross_opts* opts,
+                                int ranks[3], double* core, size_t core_cap, double* factors, size_t fac_cap,
+                                vie_cross_info* xinfo)
+{
+    if (!n || !fn || !ranks) return fail(VIE_E_ARG, "vie_tucker_cross_pwl: null argument");
+    if (comp < 0 || comp > 59) return fail(VIE_E_ARG, "vie_tucker_cross_pwl: comp must be in [0, 59]");
+    const int la = kPwlPairs[comp / 6][0], lb = kPwlPairs[comp / 6][1];
+    int lmask = 0;
+    for (int a = 0; a < 3; ++a) lmask |= (((la == a + 1) + (lb == a + 1)) & 1) << a;
+    int odd[3];
+    for (int a = 0; a < 3; ++a) odd[a] = view_odd(0, lmask, comp % 6, a);
+    return tucker_cross_host("vie_tucker_cross_pwl", n, fn, ctx, comp, odd, comp % 6, opts, ranks, core, core_cap,
+                             factors, fac_cap, xinfo);
 }
 
 vie_status vie_op_from_tucker(const int n[3], const int ranks[6][3], const double* cores, const double* factors,

@@ -105,6 +105,9 @@ _SIGS = {
     "vie_tucker_cross": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, _P, ctypes.c_int, ctypes.POINTER(CrossOpts),
                                         ctypes.POINTER(ctypes.c_int), _P, ctypes.c_size_t, _P, ctypes.c_size_t,
                                         ctypes.POINTER(CrossInfo)]),
+    "vie_tucker_cross_pwl": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, _P, ctypes.c_int,
+                                            ctypes.POINTER(CrossOpts), ctypes.POINTER(ctypes.c_int), _P, ctypes.c_size_t,
+                                            _P, ctypes.c_size_t, ctypes.POINTER(CrossInfo)]),
     "vie_tucker_hadamard_ws_bytes": (ctypes.c_size_t, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                                        ctypes.c_int, ctypes.c_int]),
     "vie_tucker_hadamard": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.c_int,
@@ -544,9 +547,11 @@ def compress_cross(n, entry_fn, ctx, tol=1e-6, trunc_rule=0, max_rank=0, oversam
 
 
 def tucker_cross(n, entry_fn, ctx, comp, tol=1e-6, trunc_rule=0, max_rank=0, oversample=0, max_sweeps=0,
-                 n_sample=0, seed=0):
-    """Host-only cross-Tucker form of one component (vie_tucker_cross).
-    Returns (core (r1, r2, r3), [U1, U2, U3], info dict), complex128."""
+                 n_sample=0, seed=0, pwl=False):
+    """Host-only cross-Tucker form of one component (vie_tucker_cross; with
+    ``pwl`` one of the sixty piecewise-linear components, comp = 6 P + c,
+    vie_tucker_cross_pwl).  Returns (core (r1, r2, r3), [U1, U2, U3], info
+    dict), complex128."""
     lib = load()
     nn = (ctypes.c_int * 3)(*[int(v) for v in n])
     opts = _cross_opts(tol, trunc_rule, max_rank, oversample, max_sweeps, n_sample, seed)
@@ -555,10 +560,10 @@ def tucker_cross(n, entry_fn, ctx, comp, tol=1e-6, trunc_rule=0, max_rank=0, ove
     core = np.empty(2 * rcap ** 3, dtype=np.float64)
     fac = np.empty(2 * rcap * sum(int(v) for v in n), dtype=np.float64)
     xi = CrossInfo()
-    _check(lib.vie_tucker_cross(nn, entry_fn, ctx, int(comp), ctypes.byref(opts), ranks,
-                                core.ctypes.data_as(ctypes.c_void_p), rcap ** 3,
-                                fac.ctypes.data_as(ctypes.c_void_p), rcap * sum(int(v) for v in n),
-                                ctypes.byref(xi)), "vie_tucker_cross")
+    fn = lib.vie_tucker_cross_pwl if pwl else lib.vie_tucker_cross
+    _check(fn(nn, entry_fn, ctx, int(comp), ctypes.byref(opts), ranks, core.ctypes.data_as(ctypes.c_void_p),
+              rcap ** 3, fac.ctypes.data_as(ctypes.c_void_p), rcap * sum(int(v) for v in n), ctypes.byref(xi)),
+           "vie_tucker_cross_pwl" if pwl else "vie_tucker_cross")
     r = [int(ranks[a]) for a in range(3)]
     cz = core[:2 * r[0] * r[1] * r[2]].view(np.complex128).reshape(r)
     fz = fac.view(np.complex128)
@@ -566,7 +571,7 @@ def tucker_cross(n, entry_fn, ctx, comp, tol=1e-6, trunc_rule=0, max_rank=0, ove
     for a in range(3):
         Us.append(fz[o:o + int(n[a]) * r[a]].reshape(int(n[a]), r[a]).copy())
         o += int(n[a]) * r[a]
-    return cz.copy(), Us, _cross_info_dict(xi, [int(comp)])
+    return cz.copy(), Us, _cross_info_dict(xi, [int(comp) % 6])
 
 
 def tucker_hadamard(core, factors, x, cp=False, out=None):

@@ -103,3 +103,31 @@ def test_cross_argument_and_callback_errors():
     big = (ctypes.c_int * 3)(300, 8, 8)
     assert lib.vie_compress_cross(big, cb.fn, cb.ctx_ptr, ctypes.byref(opts), ctypes.byref(h), None,
                                   None) == vie.VIE_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("comp", [0, 9, 13, 26, 59])
+def test_library_cross_of_pwl_components_is_within_tolerance(comp):
+    # the sixty PWL components (vie_tucker_cross_pwl) from their entry
+    # callback: within the tolerance of the dense tensor, exact parity zeros
+    # on the component's odd axes, the same ranks as the oracle's cross
+    from oracle import pwl
+    vie = _vie()
+    n, h, tol = (30, 26, 22), 0.005, 1e-6
+    cb = vi.GreenPwlEntryCallback(h, K0)
+    G, Us, info = vie.tucker_cross(n, cb.fn, cb.ctx_ptr, comp, tol=tol, pwl=True)
+    P, c = divmod(comp, 6)
+    l, lp = pwl.PAIRS[P]
+    p, q = pwl.COMPONENTS[c]
+    odd = pwl.odd_axes(l, lp, p, q)
+    A = tucker.from_storage(vi.green_pwl_tensor(n, h, K0)[P, c])
+    for ax in range(3):
+        if odd[ax]:
+            sl = [slice(None)] * 3
+            sl[ax] = 0
+            A[tuple(sl)] = 0
+            assert np.abs(Us[ax][0]).max() == 0.0
+    B = tucker.tucker_reconstruct(G, *Us)
+    assert _rel(B, A) <= 2 * tol
+    fn = cross.green_entries(lambda i, j, k: vi.green_pwl_entries(np.stack([i, j, k], -1), comp, h, K0), odd)
+    Go, Uo, io = cross.tucker_cross(fn, n, tol)
+    assert G.shape == Go.shape

@@ -806,3 +806,84 @@ int vie_green_pwl_entry(const int D[3], double kappa, int q, int method, double 
     }
     return 0;
 }
+
+/* One PWL component (pair P, dyadic c) at an offset with max |D_i| >= 2 by
+ * the smooth dyadic form: the terms of pwl_far_entry for that component
+ * only, in the same order. */
+static cplx pwl_far_one(const int D[3], double kappa, int q, int P, int c)
+{
+    cplx acc = 0;
+    const double *gx = gl_x[q], *gw = gl_w[q];
+    const int t0 = pwl_ty[P][0], t1 = pwl_ty[P][1], t2 = pwl_ty[P][2];
+    const int p = comp_p[c], qq = comp_q[c];
+    for (int cell = 0; cell < 8; ++cell) {
+        double lo[3];
+        for (int a = 0; a < 3; ++a) lo[a] = ((cell >> a) & 1) ? 0.0 : -1.0;
+        for (int ia = 0; ia < q; ++ia)
+            for (int ib = 0; ib < q; ++ib)
+                for (int ic = 0; ic < q; ++ic) {
+                    double t[3] = {lo[0] + gx[ia], lo[1] + gx[ib], lo[2] + gx[ic]};
+                    double w = gw[ia] * gw[ib] * gw[ic];
+                    double x0 = D[0] + t[0], x1 = D[1] + t[1], x2 = D[2] + t[2];
+                    double r2 = x0 * x0 + x1 * x1 + x2 * x2;
+                    double r = sqrt(r2);
+                    cplx g = ghat(r, kappa);
+                    cplx ikr = I * kappa * r;
+                    double xs[3] = {x0, x1, x2};
+                    cplx Gd = g * (3.0 + 3.0 * ikr - kappa * kappa * r2) / (r2 * r2) * xs[p] * xs[qq];
+                    if (p == qq) Gd += g * (kappa * kappa - (1.0 + ikr) / r2);
+                    double v[3][4], d1[4], d2[4];
+                    for (int a = 0; a < 3; ++a) pwl_axis(t[a], v[a], d1, d2);
+                    acc += (w * v[0][t0] * v[1][t1] * v[2][t2]) * Gd;
+                }
+    }
+    return acc;
+}
+
+/* Entries of one PWL component comp = 6 P + c (0..59) at offsets idx[3 t ..
+ * 3 t + 2] >= 0, as vie_green_pwl_fill computes them up to rounding order:
+ * the 8 offsets with every D_i in {0, 1} by the distributional form (all
+ * sixty at once, evaluated once here), the others by the dyadic form of
+ * that component alone.  For fiber-sampling (cross) compressions. */
+int vie_green_pwl_entries(double kappa, int near_q, int boost, int comp, long count, const int *idx, double *out)
+{
+    pwl_init();
+    if (near_q < 2 || near_q > QMAX || comp < 0 || comp > 59 || count < 0) return -1;
+    const int P = comp / 6, c = comp % 6;
+    cplx nearv[8];
+#pragma omp parallel for schedule(static, 1)
+    for (int b = 0; b < 8; ++b) {
+        int D[3] = {b & 1, (b >> 1) & 1, (b >> 2) & 1};
+        cplx e[60];
+        pwl_near_entry(D, kappa, near_q, e);
+        nearv[b] = e[comp];
+    }
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(|: bad)
+    for (long t = 0; t < count; ++t) {
+        int D[3] = {idx[3 * t], idx[3 * t + 1], idx[3 * t + 2]};
+        if (D[0] < 0 || D[1] < 0 || D[2] < 0) {
+            bad = 1;
+            continue;
+        }
+        int d = D[0];
+        if (D[1] > d) d = D[1];
+        if (D[2] > d) d = D[2];
+        cplx e;
+        if (d <= 1) e = nearv[D[0] | (D[1] << 1) | (D[2] << 2)];
+        else {
+            int q = far_order(d, boost) + 1;
+            e = pwl_far_one(D, kappa, q > QMAX ? QMAX : q, P, c);
+        }
+        out[2 * t] = creal(e);
+        out[2 * t + 1] = cimag(e);
+    }
+    return bad ? -2 : 0;
+}
+
+/* The same as an entry callback (ctx as vie_green_entry_cb's) */
+int vie_green_pwl_entry_cb(void *ctx, int comp, long count, const int *idx, double *out)
+{
+    const vie_green_ctx *g = (const vie_green_ctx *)ctx;
+    return vie_green_pwl_entries(g->kappa, g->near_q, g->boost, comp, count, idx, out);
+}

@@ -124,3 +124,28 @@ def green_pwl_entry(D, kappa, order, method=0):
     if rc != 0:
         raise ValueError("vie_green_pwl_entry failed (%d)" % rc)
     return (out[:, 0] + 1j * out[:, 1]).reshape(10, 6)
+
+
+def green_pwl_entries(idx, comp, h, k0, near_order=16, far_boost=0):
+    """Entries of the PWL component comp = 6 P + c (pair P of PWL_PAIRS,
+    dyadic component c) at the offsets ``idx`` (integer array (..., 3) >= 0),
+    complex128 of shape idx.shape[:-1]; equal to
+    ``green_pwl_tensor(...)[P, c, k, j, i]`` up to rounding order."""
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int32))
+    if idx.shape[-1] != 3:
+        raise ValueError("idx must have shape (..., 3)")
+    flat = idx.reshape(-1, 3)
+    out = np.empty((flat.shape[0], 2), dtype=np.float64)
+    rc = _native.lib().vie_green_pwl_entries(float(k0) * float(h), int(near_order), int(far_boost), int(comp),
+                                             flat.shape[0], flat.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("vie_green_pwl_entries failed (%d)" % rc)
+    return (out[:, 0] + 1j * out[:, 1]).reshape(idx.shape[:-1])
+
+
+class GreenPwlEntryCallback(GreenEntryCallback):
+    """``GreenEntryCallback`` for the sixty PWL components (comp = 6 P + c)."""
+
+    def __init__(self, h, k0, near_order=16, far_boost=0):
+        super().__init__(h, k0, near_order, far_boost)
+        self.fn = ctypes.cast(_native.lib().vie_green_pwl_entry_cb, ctypes.c_void_p)
