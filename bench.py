@@ -189,6 +189,9 @@ def main():
     ap.add_argument("--pwl-tol", type=float, default=1e-6)
     ap.add_argument("--pwl-solve-grids", default="60,120",
                     help="grids of the series on which the plane-wave problem is solved")
+    ap.add_argument("--table3", default="",
+                    help="comma-separated HOSVD tolerances: compress the sixty PWL components of the 270 x 141 x "
+                         "902 body domain by cross-Tucker on the host (Table III; minutes per tolerance)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 1 GiB (untimed) so that counter runs can "
                          "calibrate FETCH_SIZE / WRITE_SIZE")
@@ -398,6 +401,12 @@ def main():
             log("table4 leg failed: %r" % (exc,))
             extra["table4"] = {"error": repr(exc)}
 
+    if args.table3:
+        try:
+            extra["table3"] = table3_leg(args, vie)
+        except Exception as exc:   # the headline line is printed regardless
+            log("table3 leg failed: %r" % (exc,))
+            extra["table3"] = {"error": repr(exc)}
     if not args.no_pwl:
         try:
             extra["pwl"] = pwl_leg(args, vie, torch, dev)
@@ -605,6 +614,45 @@ def pwl_leg(args, vie, torch, dev):
             out["_check"] = (G, epsc, u, y.cpu().numpy().astype(np.complex128).reshape(u.shape), args.pwl_tol)
         op.close()
         del x, e, y, G
+    return out
+
+
+# Table III of the paper: memory (MB) of the HOSVD-compressed sixty PWL N
+# components of the 270 x 141 x 902 body domain at 2 mm, 298 MHz
+PAPER_TABLE3_N_MB = {1e-4: 18.04, 1e-5: 24.16, 1e-6: 32.10, 1e-7: 40.94, 1e-8: 50.82, 1e-9: 60.90, 1e-10: 71.71}
+
+
+def table3_leg(args, vie):
+    """Table III analogue: the sixty piecewise-linear components of N on the
+    paper's body domain (270 x 141 x 902 voxels at 2 mm, 298 MHz) compressed
+    one by one by the host cross-Tucker (vie_tucker_cross_pwl, entries from
+    vie_inputs.GreenPwlEntryCallback; the dense tensors, 33 GB as complex128,
+    are never formed) at each tolerance of --table3; memory of the Tucker
+    forms in complex128, core + n_i x r_i factors and core + 2 n_i x r_i
+    factors (the circulant forms' multilinear ranks are the same), against
+    the dense circulant forms (245.6 GB) and the paper's Table III."""
+    import vie_inputs as vi
+    n = (270, 141, 902)
+    h, f = 0.002, 298e6
+    cb = vi.GreenPwlEntryCallback(h, vi.wavenumber(f))
+    out = {"grid": list(n), "dense_circulant_GB_c128": 60 * 8 * n[0] * n[1] * n[2] * 16 / 2 ** 30}
+    for tol in [float(t) for t in args.table3.split(",") if t.strip()]:
+        t0 = time.perf_counter()
+        tot, tot2, rmax, evals, ranks = 0, 0, 0, 0, []
+        for comp in range(60):
+            G, Us, info = vie.tucker_cross(n, cb.fn, cb.ctx_ptr, comp, tol=tol, pwl=True)
+            r = G.shape
+            ranks.append(list(r))
+            tot += (r[0] * r[1] * r[2] + sum(n[a] * r[a] for a in range(3))) * 16
+            tot2 += (r[0] * r[1] * r[2] + sum(2 * n[a] * r[a] for a in range(3))) * 16
+            rmax = max(rmax, max(r))
+            evals += info["evals"][0]
+        sec = time.perf_counter() - t0
+        row = {"MB_c128": tot / 1e6, "MB_c128_circulant_factors": tot2 / 1e6, "max_rank": rmax,
+               "entries_read": evals, "seconds": sec, "paper_MB": PAPER_TABLE3_N_MB.get(tol), "ranks": ranks}
+        out["tol%g" % tol] = row
+        log("table3 tol %g: %.2f MB (%.2f MB with factors of the 2n_i circulant forms; paper %s), ranks <= %d, %.0f s"
+            % (tol, row["MB_c128"], row["MB_c128_circulant_factors"], row["paper_MB"], rmax, sec))
     return out
 
 

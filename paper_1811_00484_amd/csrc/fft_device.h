@@ -229,4 +229,55 @@ __device__ void fft_lds(c2<T>* buf, int nseq, int ss, int es, const FftPlan& pl,
     }
 }
 
+
+// fft_lds with the radix sequence fixed at compile time for the lengths
+// below (the stage index arithmetic then divides by constants); any other
+// LC (0) takes the plan at run time.
+template <int DIR, bool SEQFAST, int MAXE, int LC, typename T>
+__device__ __forceinline__ void fft_lds_len(c2<T>* buf, int nseq, int ss, int es, const FftPlan& pl, const c2<T>* tw,
+                                            int tid, int nthr)
+{
+    if constexpr (LC == 512) {
+        stage_r<8, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 1, tw, tid, nthr);
+        stage_r<8, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 8, tw, tid, nthr);
+        stage_r<8, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 64, tw, tid, nthr);
+    } else if constexpr (LC == 256) {
+        stage_r<8, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 1, tw, tid, nthr);
+        stage_r<8, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 8, tw, tid, nthr);
+        stage_r<4, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 64, tw, tid, nthr);
+    } else if constexpr (LC == 128) {
+        stage_r<8, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 1, tw, tid, nthr);
+        stage_r<4, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 8, tw, tid, nthr);
+        stage_r<4, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 32, tw, tid, nthr);
+    } else if constexpr (LC == 64) {
+        stage_r<8, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 1, tw, tid, nthr);
+        stage_r<8, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 8, tw, tid, nthr);
+    } else if constexpr (LC == 300) {
+        stage_r<5, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 1, tw, tid, nthr);
+        stage_r<5, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 5, tw, tid, nthr);
+        stage_r<4, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 25, tw, tid, nthr);
+        stage_r<3, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 100, tw, tid, nthr);
+    } else if constexpr (LC == 240) {
+        stage_r<8, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 1, tw, tid, nthr);
+        stage_r<5, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 8, tw, tid, nthr);
+        stage_r<3, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 40, tw, tid, nthr);
+        stage_r<2, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 120, tw, tid, nthr);
+    } else if constexpr (LC == 180) {
+        stage_r<5, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 1, tw, tid, nthr);
+        stage_r<4, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 5, tw, tid, nthr);
+        stage_r<3, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 20, tw, tid, nthr);
+        stage_r<3, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 60, tw, tid, nthr);
+    } else if constexpr (LC == 120) {
+        stage_r<8, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 1, tw, tid, nthr);
+        stage_r<5, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 8, tw, tid, nthr);
+        stage_r<3, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 40, tw, tid, nthr);
+    } else if constexpr (LC == 60) {
+        stage_r<5, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 1, tw, tid, nthr);
+        stage_r<4, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 5, tw, tid, nthr);
+        stage_r<3, DIR, SEQFAST, MAXE>(buf, nseq, ss, es, LC, 20, tw, tid, nthr);
+    } else {
+        fft_lds<DIR, SEQFAST, MAXE>(buf, nseq, ss, es, pl, tw, tid, nthr);
+    }
+}
+
 }  // namespace vie

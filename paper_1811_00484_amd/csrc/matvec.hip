@@ -60,14 +60,14 @@ __device__ __forceinline__ void load_tw(c2<T>* dst, const c2<T>* src, int L, int
 }
 
 // ------------------------------- pass X+ --------------------------------
-template <typename TV, typename T, int W, int MAXE>
+template <typename TV, typename T, int W, int MAXE, int LC = 0>
 __device__ __forceinline__ void xfwd_body(const c2<TV>* __restrict__ x, const c2<TV>* __restrict__ eps,
                                              c2<T>* __restrict__ S1, FftPlan pl, const c2<T>* __restrict__ tw,
                                              int n1, int n2, int n3, int mode, const int* __restrict__ rhs_map, int bx, int by, int bz)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T>* buf = reinterpret_cast<c2<T>*>(smem_raw);
-    const int L1 = pl.L;
+    const int L1 = LC ? LC : pl.L;
     c2<T>* tws = buf + (size_t)L1 * (W + 1);
     const int tid = threadIdx.x;
     const int j0 = bx * W, k = by;
@@ -99,7 +99,7 @@ __device__ __forceinline__ void xfwd_body(const c2<TV>* __restrict__ x, const c2
         buf[i * (W + 1) + w] = mk<T>(0, 0);
     }
     __syncthreads();
-    fft_lds<-1, true, MAXE>(buf, W, 1, W + 1, pl, tws, tid, NT);
+    fft_lds_len<-1, true, MAXE, LC>(buf, W, 1, W + 1, pl, tws, tid, NT);
     for (int e = tid; e < W * L1; e += NT) {
         int w = e % W, i = e / W;
         int j = j0 + w;
@@ -108,13 +108,13 @@ __device__ __forceinline__ void xfwd_body(const c2<TV>* __restrict__ x, const c2
 }
 
 // ------------------------------- pass Y+ --------------------------------
-template <typename T, int W, int MAXE>
+template <typename T, int W, int MAXE, int LC = 0>
 __device__ __forceinline__ void yfwd_body(const c2<T>* __restrict__ S1, c2<T>* __restrict__ S2, FftPlan pl,
                                              const c2<T>* __restrict__ tw, int L1, int n2, int n3, int bx, int by, int bz)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T>* buf = reinterpret_cast<c2<T>*>(smem_raw);
-    const int L2 = pl.L;
+    const int L2 = LC ? LC : pl.L;
     c2<T>* tws = buf + (size_t)L2 * (W + 1);
     const int tid = threadIdx.x;
     const int k0 = bx * W, i = by;
@@ -132,7 +132,7 @@ __device__ __forceinline__ void yfwd_body(const c2<T>* __restrict__ S1, c2<T>* _
         buf[j * (W + 1) + w] = mk<T>(0, 0);
     }
     __syncthreads();
-    fft_lds<-1, true, MAXE>(buf, W, 1, W + 1, pl, tws, tid, NT);
+    fft_lds_len<-1, true, MAXE, LC>(buf, W, 1, W + 1, pl, tws, tid, NT);
     for (int e = tid; e < W * L2; e += NT) {
         int w = e % W, j = e / W;
         int k = k0 + w;
@@ -141,13 +141,13 @@ __device__ __forceinline__ void yfwd_body(const c2<T>* __restrict__ S1, c2<T>* _
 }
 
 // ------------------------------- pass Y- --------------------------------
-template <typename T, int W, int MAXE>
+template <typename T, int W, int MAXE, int LC = 0>
 __device__ __forceinline__ void yinv_body(const c2<T>* __restrict__ S2, c2<T>* __restrict__ S3, FftPlan pl,
                                              const c2<T>* __restrict__ tw, int L1, int n2, int n3, int bx, int by, int bz)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T>* buf = reinterpret_cast<c2<T>*>(smem_raw);
-    const int L2 = pl.L;
+    const int L2 = LC ? LC : pl.L;
     c2<T>* tws = buf + (size_t)L2 * (W + 1);
     const int tid = threadIdx.x;
     const int k0 = bx * W, i = by;
@@ -161,7 +161,7 @@ __device__ __forceinline__ void yinv_body(const c2<T>* __restrict__ S2, c2<T>* _
         buf[j * (W + 1) + w] = v;
     }
     __syncthreads();
-    fft_lds<1, true, MAXE>(buf, W, 1, W + 1, pl, tws, tid, NT);
+    fft_lds_len<1, true, MAXE, LC>(buf, W, 1, W + 1, pl, tws, tid, NT);
     for (int e = tid; e < W * n2; e += NT) {
         int w = e / n2, j = e - w * n2;
         int k = k0 + w;
@@ -170,7 +170,7 @@ __device__ __forceinline__ void yinv_body(const c2<T>* __restrict__ S2, c2<T>* _
 }
 
 // ------------------------------- pass X- --------------------------------
-template <typename TV, typename T, int W, int MAXE>
+template <typename TV, typename T, int W, int MAXE, int LC = 0>
 __device__ __forceinline__ void xinv_body(const c2<T>* __restrict__ S3, const c2<TV>* __restrict__ x,
                                              const c2<TV>* __restrict__ eps, c2<TV>* __restrict__ y, FftPlan pl,
                                              const c2<T>* __restrict__ tw, int n1, int n2, int n3, int mode,
@@ -178,7 +178,7 @@ __device__ __forceinline__ void xinv_body(const c2<T>* __restrict__ S3, const c2
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T>* buf = reinterpret_cast<c2<T>*>(smem_raw);
-    const int L1 = pl.L;
+    const int L1 = LC ? LC : pl.L;
     c2<T>* tws = buf + (size_t)L1 * (W + 1);
     const int tid = threadIdx.x;
     const int j0 = bx * W, k = by;
@@ -196,7 +196,7 @@ __device__ __forceinline__ void xinv_body(const c2<T>* __restrict__ S3, const c2
         buf[i * (W + 1) + w] = v;
     }
     __syncthreads();
-    fft_lds<1, true, MAXE>(buf, W, 1, W + 1, pl, tws, tid, NT);
+    fft_lds_len<1, true, MAXE, LC>(buf, W, 1, W + 1, pl, tws, tid, NT);
     for (int e = tid; e < W * n1; e += NT) {
         int w = e / n1, i = e - w * n1;
         int j = j0 + w;
@@ -377,35 +377,35 @@ __device__ __forceinline__ void zmid_body(c2<T>* __restrict__ S2, FftPlan pl, co
 }
 
 // ----------------------- single-instance kernels --------------------------
-template <typename TV, typename T, int W, int MAXE>
+template <typename TV, typename T, int W, int MAXE, int LC = 0>
 __global__ void __launch_bounds__(NT) k_xfwd(const c2<TV>* __restrict__ x, const c2<TV>* __restrict__ eps,
                                              c2<T>* __restrict__ S1, FftPlan pl, const c2<T>* __restrict__ tw,
                                              int n1, int n2, int n3, int mode, const int* __restrict__ rhs_map)
 {
-    xfwd_body<TV, T, W, MAXE>(x, eps, S1, pl, tw, n1, n2, n3, mode, rhs_map, blockIdx.x, blockIdx.y, blockIdx.z);
+    xfwd_body<TV, T, W, MAXE, LC>(x, eps, S1, pl, tw, n1, n2, n3, mode, rhs_map, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
-template <typename T, int W, int MAXE>
+template <typename T, int W, int MAXE, int LC = 0>
 __global__ void __launch_bounds__(NT) k_yfwd(const c2<T>* __restrict__ S1, c2<T>* __restrict__ S2, FftPlan pl,
                                              const c2<T>* __restrict__ tw, int L1, int n2, int n3)
 {
-    yfwd_body<T, W, MAXE>(S1, S2, pl, tw, L1, n2, n3, blockIdx.x, blockIdx.y, blockIdx.z);
+    yfwd_body<T, W, MAXE, LC>(S1, S2, pl, tw, L1, n2, n3, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
-template <typename T, int W, int MAXE>
+template <typename T, int W, int MAXE, int LC = 0>
 __global__ void __launch_bounds__(NT) k_yinv(const c2<T>* __restrict__ S2, c2<T>* __restrict__ S3, FftPlan pl,
                                              const c2<T>* __restrict__ tw, int L1, int n2, int n3)
 {
-    yinv_body<T, W, MAXE>(S2, S3, pl, tw, L1, n2, n3, blockIdx.x, blockIdx.y, blockIdx.z);
+    yinv_body<T, W, MAXE, LC>(S2, S3, pl, tw, L1, n2, n3, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
-template <typename TV, typename T, int W, int MAXE>
+template <typename TV, typename T, int W, int MAXE, int LC = 0>
 __global__ void __launch_bounds__(NT) k_xinv(const c2<T>* __restrict__ S3, const c2<TV>* __restrict__ x,
                                              const c2<TV>* __restrict__ eps, c2<TV>* __restrict__ y, FftPlan pl,
                                              const c2<T>* __restrict__ tw, int n1, int n2, int n3, int mode,
                                              const int* __restrict__ rhs_map)
 {
-    xinv_body<TV, T, W, MAXE>(S3, x, eps, y, pl, tw, n1, n2, n3, mode, rhs_map, blockIdx.x, blockIdx.y, blockIdx.z);
+    xinv_body<TV, T, W, MAXE, LC>(S3, x, eps, y, pl, tw, n1, n2, n3, mode, rhs_map, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 template <typename T, int MAXE>
@@ -597,6 +597,25 @@ static size_t z_lds_bytes(const OpView& v, int G)
     default: { constexpr int Wc = 1; __VA_ARGS__; } break;               \
     }
 
+// Default tile width of the mixed-radix X/Y kernels, and the lengths whose
+// radix sequence those kernels take at compile time (the sphere series'
+// 2n = 60 ... 300; the register-FFT lengths have kernels of their own)
+template <typename T>
+constexpr int kWDefault = sizeof(T) == 4 ? 16 : 8;
+
+template <class F>
+static void with_lc(int L, F&& f)
+{
+    switch (L) {
+    case 60: f(std::integral_constant<int, 60>{}); break;
+    case 120: f(std::integral_constant<int, 120>{}); break;
+    case 180: f(std::integral_constant<int, 180>{}); break;
+    case 240: f(std::integral_constant<int, 240>{}); break;
+    case 300: f(std::integral_constant<int, 300>{}); break;
+    default: f(std::integral_constant<int, 0>{}); break;
+    }
+}
+
 // One pass of the matvec on explicit buffers (see launch_matvec for the
 // layouts): pass 0 reads x and writes S1 (out), 1 reads S1 (in) and writes
 // S2 (out), 2 transforms S2 in place (out), 3 reads S2 (in) and writes S3
@@ -650,10 +669,14 @@ hipError_t run_pass(const DeviceOp& op, int pass, int mode, int recon, const c2<
         size_t lds = (size_t)(W + 1) * L1 * sizeof(c2<T>) + (size_t)L1 * sizeof(c2<T>);
         dim3 grid((n2 + W - 1) / W, n3, nrhs * 3);
         VIE_W_DISPATCH(W, {
-            auto kern = k_xfwd<TV, T, Wc, MAXE_XY>;
-            (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, x, eps, S1, px, tw[0], n1, n2, n3,
-                               ident ? (int)MODE_N : mode, rhs_map);
+            auto launch = [&](auto lc) {
+                auto kern = k_xfwd<TV, T, Wc, MAXE_XY, decltype(lc)::value>;
+                (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, x, eps, S1, px, tw[0], n1, n2, n3,
+                                   ident ? (int)MODE_N : mode, rhs_map);
+            };
+            if constexpr (Wc == kWDefault<T>) with_lc(ident ? 0 : L1, launch);
+            else launch(std::integral_constant<int, 0>{});
         });
     } else if (pass == 1) {
         const c2<T>* S1 = reinterpret_cast<const c2<T>*>(in);
@@ -666,9 +689,13 @@ hipError_t run_pass(const DeviceOp& op, int pass, int mode, int recon, const c2<
         size_t lds = (size_t)(W + 1) * L2 * sizeof(c2<T>) + (size_t)L2 * sizeof(c2<T>);
         dim3 grid((n3 + W - 1) / W, L1, nrhs * 3);
         VIE_W_DISPATCH(W, {
-            auto kern = k_yfwd<T, Wc, MAXE_XY>;
-            (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S1, S2, op.plan[1], tw[1], L1, n2, n3);
+            auto launch = [&](auto lc) {
+                auto kern = k_yfwd<T, Wc, MAXE_XY, decltype(lc)::value>;
+                (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S1, S2, op.plan[1], tw[1], L1, n2, n3);
+            };
+            if constexpr (Wc == kWDefault<T>) with_lc(L2, launch);
+            else launch(std::integral_constant<int, 0>{});
         });
     } else if (pass == 2) {
         c2<T>* S2 = reinterpret_cast<c2<T>*>(out);
@@ -707,9 +734,13 @@ hipError_t run_pass(const DeviceOp& op, int pass, int mode, int recon, const c2<
         size_t lds = (size_t)(W + 1) * L2 * sizeof(c2<T>) + (size_t)L2 * sizeof(c2<T>);
         dim3 grid((n3 + W - 1) / W, L1, nrhs * 3);
         VIE_W_DISPATCH(W, {
-            auto kern = k_yinv<T, Wc, MAXE_XY>;
-            (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S2, S3, op.plan[1], tw[1], L1, n2, n3);
+            auto launch = [&](auto lc) {
+                auto kern = k_yinv<T, Wc, MAXE_XY, decltype(lc)::value>;
+                (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S2, S3, op.plan[1], tw[1], L1, n2, n3);
+            };
+            if constexpr (Wc == kWDefault<T>) with_lc(L2, launch);
+            else launch(std::integral_constant<int, 0>{});
         });
     } else {
         const c2<T>* S3 = reinterpret_cast<const c2<T>*>(in);
@@ -727,10 +758,14 @@ hipError_t run_pass(const DeviceOp& op, int pass, int mode, int recon, const c2<
         size_t lds = (size_t)(W + 1) * L1 * sizeof(c2<T>) + (size_t)L1 * sizeof(c2<T>);
         dim3 grid((n2 + W - 1) / W, n3, nrhs * 3);
         VIE_W_DISPATCH(W, {
-            auto kern = k_xinv<TV, T, Wc, MAXE_XY>;
-            (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S3, x, eps, y, px, tw[0], n1, n2, n3,
-                               ident ? (int)MODE_N : mode, rhs_map);
+            auto launch = [&](auto lc) {
+                auto kern = k_xinv<TV, T, Wc, MAXE_XY, decltype(lc)::value>;
+                (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, S3, x, eps, y, px, tw[0], n1, n2, n3,
+                                   ident ? (int)MODE_N : mode, rhs_map);
+            };
+            if constexpr (Wc == kWDefault<T>) with_lc(ident ? 0 : L1, launch);
+            else launch(std::integral_constant<int, 0>{});
         });
     }
     return hipGetLastError();

@@ -120,53 +120,12 @@ __device__ __forceinline__ void pwl_all_pairs(c2<T> (&acc)[12], const c2<T> (&x)
     (pwl_pair<B, T>(acc, x, NTT, n3p1, kk, f, om, conj), ...);
 }
 
-// mixed-radix LDS transform of the 12 P pencils; LC > 0: the length is
-// known at compile time (a fixed radix sequence), so the stage index
-// arithmetic divides by constants
+// mixed-radix LDS transform of the 12 P pencils (sequence-major); LC > 0:
+// the length is known at compile time
 template <int DIR, int MAXE, int LC, typename T>
 __device__ __forceinline__ void pwl_fft(c2<T>* X, int nseq, int L3, const FftPlan& pl, const c2<T>* tws, int tid)
 {
-    if constexpr (LC == 512) {
-        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
-        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 8, tws, tid, kNTZ);
-        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 64, tws, tid, kNTZ);
-    } else if constexpr (LC == 256) {
-        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
-        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 8, tws, tid, kNTZ);
-        stage_r<4, DIR, false, MAXE>(X, nseq, LC, 1, LC, 64, tws, tid, kNTZ);
-    } else if constexpr (LC == 128) {
-        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
-        stage_r<4, DIR, false, MAXE>(X, nseq, LC, 1, LC, 8, tws, tid, kNTZ);
-        stage_r<4, DIR, false, MAXE>(X, nseq, LC, 1, LC, 32, tws, tid, kNTZ);
-    } else if constexpr (LC == 64) {
-        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
-        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 8, tws, tid, kNTZ);
-    } else if constexpr (LC == 300) {   // the refinement series' edges 150, 120, 90, 60, 30
-        stage_r<5, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
-        stage_r<5, DIR, false, MAXE>(X, nseq, LC, 1, LC, 5, tws, tid, kNTZ);
-        stage_r<4, DIR, false, MAXE>(X, nseq, LC, 1, LC, 25, tws, tid, kNTZ);
-        stage_r<3, DIR, false, MAXE>(X, nseq, LC, 1, LC, 100, tws, tid, kNTZ);
-    } else if constexpr (LC == 240) {
-        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
-        stage_r<5, DIR, false, MAXE>(X, nseq, LC, 1, LC, 8, tws, tid, kNTZ);
-        stage_r<3, DIR, false, MAXE>(X, nseq, LC, 1, LC, 40, tws, tid, kNTZ);
-        stage_r<2, DIR, false, MAXE>(X, nseq, LC, 1, LC, 120, tws, tid, kNTZ);
-    } else if constexpr (LC == 180) {
-        stage_r<5, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
-        stage_r<4, DIR, false, MAXE>(X, nseq, LC, 1, LC, 5, tws, tid, kNTZ);
-        stage_r<3, DIR, false, MAXE>(X, nseq, LC, 1, LC, 20, tws, tid, kNTZ);
-        stage_r<3, DIR, false, MAXE>(X, nseq, LC, 1, LC, 60, tws, tid, kNTZ);
-    } else if constexpr (LC == 120) {
-        stage_r<8, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
-        stage_r<5, DIR, false, MAXE>(X, nseq, LC, 1, LC, 8, tws, tid, kNTZ);
-        stage_r<3, DIR, false, MAXE>(X, nseq, LC, 1, LC, 40, tws, tid, kNTZ);
-    } else if constexpr (LC == 60) {
-        stage_r<5, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
-        stage_r<4, DIR, false, MAXE>(X, nseq, LC, 1, LC, 5, tws, tid, kNTZ);
-        stage_r<3, DIR, false, MAXE>(X, nseq, LC, 1, LC, 20, tws, tid, kNTZ);
-    } else {
-        fft_lds<DIR, false, MAXE>(X, nseq, L3, 1, pl, tws, tid, kNTZ);
-    }
+    fft_lds_len<DIR, false, MAXE, LC>(X, nseq, L3, 1, pl, tws, tid, kNTZ);
 }
 
 // W_c(k2) = G_c x2 U2_c(k2, :) (r1 x r3) for every component of the ten

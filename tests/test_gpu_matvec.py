@@ -25,6 +25,8 @@ SIZES = [
     (5, 3, 2),         # tiny odd
     (1, 1, 1),         # single voxel
     (35, 4, 6),        # pencil counts not multiples of the tile width (L1 = 70 = 2*5*7)
+    (30, 60, 90),      # X/Y lengths 60 and 120 with compile-time radix sequences, z length 180
+    (150, 30, 120),    # X/Y lengths 300 and 60 (compile-time), z length 240
 ]
 
 
