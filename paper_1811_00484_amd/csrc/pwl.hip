@@ -125,7 +125,14 @@ __device__ __forceinline__ void pwl_all_pairs(c2<T> (&acc)[12], const c2<T> (&x)
 template <int DIR, int MAXE, int LC, typename T>
 __device__ __forceinline__ void pwl_fft(c2<T>* X, int nseq, int L3, const FftPlan& pl, const c2<T>* tws, int tid)
 {
-    fft_lds_len<DIR, false, MAXE, LC>(X, nseq, L3, 1, pl, tws, tid, kNTZ);
+    if constexpr (LC == 252) {   // the head grid's z length (126 voxels)
+        stage_r<7, DIR, false, MAXE>(X, nseq, LC, 1, LC, 1, tws, tid, kNTZ);
+        stage_r<4, DIR, false, MAXE>(X, nseq, LC, 1, LC, 7, tws, tid, kNTZ);
+        stage_r<3, DIR, false, MAXE>(X, nseq, LC, 1, LC, 28, tws, tid, kNTZ);
+        stage_r<3, DIR, false, MAXE>(X, nseq, LC, 1, LC, 84, tws, tid, kNTZ);
+    } else {
+        fft_lds_len<DIR, false, MAXE, LC>(X, nseq, L3, 1, pl, tws, tid, kNTZ);
+    }
 }
 
 // W_c(k2) = G_c x2 U2_c(k2, :) (r1 x r3) for every component of the ten
@@ -448,6 +455,7 @@ hipError_t launch_pwl_z(const vie_pwl_op& P, int conj, c2<T>* S2, c2<T>* Wg, hip
                 : L3 == 128 ? k_pwl_z<T, MAXE, EPT, 128>
                 : L3 == 64 ? k_pwl_z<T, MAXE, EPT, 64>
                 : L3 == 300 ? k_pwl_z<T, MAXE, EPT, 300>
+                : L3 == 252 ? k_pwl_z<T, MAXE, EPT, 252>
                 : L3 == 240 ? k_pwl_z<T, MAXE, EPT, 240>
                 : L3 == 180 ? k_pwl_z<T, MAXE, EPT, 180>
                 : L3 == 120 ? k_pwl_z<T, MAXE, EPT, 120>
