@@ -48,7 +48,8 @@ def _device(op, epsc, u, mode, dtype):
     return y.cpu().numpy().astype(np.complex128).reshape(u.shape)
 
 
-SIZES = [(12, 10, 9), (8, 8, 8), (5, 3, 2), (1, 1, 1), (20, 15, 18), (16, 14, 7)]
+SIZES = [(12, 10, 9), (8, 8, 8), (5, 3, 2), (1, 1, 1), (20, 15, 18), (16, 14, 7),
+         (6, 5, 126), (7, 4, 120), (5, 6, 90)]   # z lengths 252, 240, 180 with compile-time radix stages
 
 
 @pytest.mark.parametrize("n", SIZES)
