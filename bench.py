@@ -194,6 +194,7 @@ def main():
     ap.add_argument("--table3", default="",
                     help="comma-separated HOSVD tolerances: compress the sixty PWL components of the 270 x 141 x "
                          "902 body domain by cross-Tucker on the host (Table III; minutes per tolerance)")
+    ap.add_argument("--table3-ops", default="NK", help="operators of the Table III leg (N, K or NK)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 1 GiB (untimed) so that counter runs can "
                          "calibrate FETCH_SIZE / WRITE_SIZE")
@@ -662,12 +663,14 @@ def pwl_head_solve(args, vie, torch, dev):
 # Table III of the paper: memory (MB) of the HOSVD-compressed sixty PWL N
 # components of the 270 x 141 x 902 body domain at 2 mm, 298 MHz
 PAPER_TABLE3_N_MB = {1e-4: 18.04, 1e-5: 24.16, 1e-6: 32.10, 1e-7: 40.94, 1e-8: 50.82, 1e-9: 60.90, 1e-10: 71.71}
+PAPER_TABLE3_K_MB = {1e-4: 12.06, 1e-5: 16.26, 1e-6: 21.24, 1e-7: 26.15, 1e-8: 31.03, 1e-9: 35.69, 1e-10: 40.96}
 
 
 def table3_leg(args, vie):
-    """Table III analogue: the sixty piecewise-linear components of N on the
-    paper's body domain (270 x 141 x 902 voxels at 2 mm, 298 MHz) compressed
-    one by one by the host cross-Tucker (vie_tucker_cross_pwl, entries from
+    """Table III analogue: the sixty piecewise-linear components of N and the
+    thirty of K on the paper's body domain (270 x 141 x 902 voxels at 2 mm,
+    298 MHz) compressed one by one by the host cross-Tucker
+    (vie_tucker_cross_pwl, entries from
     vie_inputs.GreenPwlEntryCallback; the dense tensors, 33 GB as complex128,
     are never formed) at each tolerance of --table3; memory of the Tucker
     forms in complex128, core + n_i x r_i factors and core + 2 n_i x r_i
@@ -679,22 +682,26 @@ def table3_leg(args, vie):
     cb = vi.GreenPwlEntryCallback(h, vi.wavenumber(f))
     out = {"grid": list(n), "dense_circulant_GB_c128": 60 * 8 * n[0] * n[1] * n[2] * 16 / 2 ** 30}
     for tol in [float(t) for t in args.table3.split(",") if t.strip()]:
-        t0 = time.perf_counter()
-        tot, tot2, rmax, evals, ranks = 0, 0, 0, 0, []
-        for comp in range(60):
-            G, Us, info = vie.tucker_cross(n, cb.fn, cb.ctx_ptr, comp, tol=tol, pwl=True)
-            r = G.shape
-            ranks.append(list(r))
-            tot += (r[0] * r[1] * r[2] + sum(n[a] * r[a] for a in range(3))) * 16
-            tot2 += (r[0] * r[1] * r[2] + sum(2 * n[a] * r[a] for a in range(3))) * 16
-            rmax = max(rmax, max(r))
-            evals += info["evals"][0]
-        sec = time.perf_counter() - t0
-        row = {"MB_c128": tot / 1e6, "MB_c128_circulant_factors": tot2 / 1e6, "max_rank": rmax,
-               "entries_read": evals, "seconds": sec, "paper_MB": PAPER_TABLE3_N_MB.get(tol), "ranks": ranks}
-        out["tol%g" % tol] = row
-        log("table3 tol %g: %.2f MB (%.2f MB with factors of the 2n_i circulant forms; paper %s), ranks <= %d, %.0f s"
-            % (tol, row["MB_c128"], row["MB_c128_circulant_factors"], row["paper_MB"], rmax, sec))
+        for op_name, comps, paper in (("N", range(60), PAPER_TABLE3_N_MB), ("K", range(60, 90), PAPER_TABLE3_K_MB)):
+            if op_name not in args.table3_ops:
+                continue
+            t0 = time.perf_counter()
+            tot, tot2, rmax, evals, ranks = 0, 0, 0, 0, []
+            for comp in comps:
+                G, Us, info = vie.tucker_cross(n, cb.fn, cb.ctx_ptr, comp, tol=tol, pwl=True)
+                r = G.shape
+                ranks.append(list(r))
+                tot += (r[0] * r[1] * r[2] + sum(n[a] * r[a] for a in range(3))) * 16
+                tot2 += (r[0] * r[1] * r[2] + sum(2 * n[a] * r[a] for a in range(3))) * 16
+                rmax = max(rmax, max(r))
+                evals += sum(info["evals"])
+            sec = time.perf_counter() - t0
+            row = {"MB_c128": tot / 1e6, "MB_c128_circulant_factors": tot2 / 1e6, "max_rank": rmax,
+                   "entries_read": evals, "seconds": sec, "paper_MB": paper.get(tol), "ranks": ranks}
+            out["%s_tol%g" % (op_name, tol)] = row
+            log("table3 %s tol %g: %.2f MB (%.2f MB with factors of the 2n_i circulant forms; paper %s), "
+                "ranks <= %d, %.0f s" % (op_name, tol, row["MB_c128"], row["MB_c128_circulant_factors"],
+                                        row["paper_MB"], rmax, sec))
     return out
 
 

@@ -316,12 +316,15 @@ vie_status vie_matvec_pwl(const vie_pwl_op* op, int kind, int adjoint, int dtype
                           void* y, void* ws, size_t ws_bytes, void* stream);
 
 /*
- * vie_tucker_cross_pwl -- vie_tucker_cross for one of the sixty
- * piecewise-linear components, comp = 6 P + c (pair P in the order of
- * vie_compress_pwl, dyadic component c): the callback receives that comp;
- * the parity zeros follow the component's parities (see the PWL section);
- * the counts go to slot c of xinfo.  Host only, grids up to 65536 per axis
- * (the paper's 270 x 141 x 902 body domain, Table III).
+ * vie_tucker_cross_pwl -- vie_tucker_cross for one piecewise-linear
+ * component: comp 0..59 the N components 6 P + c (pair P in the order of
+ * vie_compress_pwl, dyadic component c), comp 60..89 the thirty K components
+ * 60 + 3 P + c (c = xy, xz, yz of the magnetic operator, test function in
+ * the observation voxel; each odd along the axis of K's pulse component,
+ * flipped by the pair as for N).  The callback receives comp unchanged; the
+ * parity zeros follow the component's parities; the counts go to slot c of
+ * xinfo (K: slot 3 + c).  Host only, grids up to 65536 per axis (the paper's
+ * 270 x 141 x 902 body domain, Table III).
  */
 vie_status vie_tucker_cross_pwl(const int n[3], vie_entry_fn fn, void* ctx, int comp, const vie_cross_opts* opts,
                                 int ranks[3], double* core, size_t core_cap, double* factors, size_t fac_cap,

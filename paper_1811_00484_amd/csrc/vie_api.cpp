@@ -526,14 +526,19 @@ vie_status vie_tucker_cross_pwl(const int n[3], vie_entry_fn fn, void* ctx, int 
                                 vie_cross_info* xinfo)
 {
     if (!n || !fn || !ranks) return fail(VIE_E_ARG, "vie_tucker_cross_pwl: null argument");
-    if (comp < 0 || comp > 59) return fail(VIE_E_ARG, "vie_tucker_cross_pwl: comp must be in [0, 59]");
-    const int la = kPwlPairs[comp / 6][0], lb = kPwlPairs[comp / 6][1];
+    if (comp < 0 || comp > 89) return fail(VIE_E_ARG, "vie_tucker_cross_pwl: comp must be in [0, 89]");
+    // 0..59: N, pair comp / 6, dyadic component comp % 6; 60..89: K, pair
+    // (comp - 60) / 3, component xy, xz, yz = (comp - 60) % 3 (K's slots 3..5)
+    const bool isk = comp >= 60;
+    const int pair = isk ? (comp - 60) / 3 : comp / 6;
+    const int c = isk ? 3 + (comp - 60) % 3 : comp % 6;
+    const int la = kPwlPairs[pair][0], lb = kPwlPairs[pair][1];
     int lmask = 0;
     for (int a = 0; a < 3; ++a) lmask |= (((la == a + 1) + (lb == a + 1)) & 1) << a;
     int odd[3];
-    for (int a = 0; a < 3; ++a) odd[a] = view_odd(0, lmask, comp % 6, a);
-    return tucker_cross_host("vie_tucker_cross_pwl", n, fn, ctx, comp, odd, comp % 6, opts, ranks, core, core_cap,
-                             factors, fac_cap, xinfo);
+    for (int a = 0; a < 3; ++a) odd[a] = view_odd(isk ? 1 : 0, lmask, c, a);
+    return tucker_cross_host("vie_tucker_cross_pwl", n, fn, ctx, comp, odd, c, opts, ranks, core, core_cap, factors,
+                             fac_cap, xinfo);
 }
 
 vie_status vie_op_from_tucker(const int n[3], const int ranks[6][3], const double* cores, const double* factors,

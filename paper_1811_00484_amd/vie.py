@@ -549,8 +549,8 @@ def compress_cross(n, entry_fn, ctx, tol=1e-6, trunc_rule=0, max_rank=0, oversam
 def tucker_cross(n, entry_fn, ctx, comp, tol=1e-6, trunc_rule=0, max_rank=0, oversample=0, max_sweeps=0,
                  n_sample=0, seed=0, pwl=False):
     """Host-only cross-Tucker form of one component (vie_tucker_cross; with
-    ``pwl`` one of the sixty piecewise-linear components, comp = 6 P + c,
-    vie_tucker_cross_pwl).  Returns (core (r1, r2, r3), [U1, U2, U3], info
+    ``pwl`` a piecewise-linear component, vie_tucker_cross_pwl: comp 0..59
+    the N components 6 P + c, 60..89 the K components 60 + 3 P + c).  Returns (core (r1, r2, r3), [U1, U2, U3], info
     dict), complex128."""
     lib = load()
     nn = (ctypes.c_int * 3)(*[int(v) for v in n])
@@ -571,7 +571,8 @@ def tucker_cross(n, entry_fn, ctx, comp, tol=1e-6, trunc_rule=0, max_rank=0, ove
     for a in range(3):
         Us.append(fz[o:o + int(n[a]) * r[a]].reshape(int(n[a]), r[a]).copy())
         o += int(n[a]) * r[a]
-    return cz.copy(), Us, _cross_info_dict(xi, [int(comp) % 6])
+    slot = int(comp) if not pwl else (int(comp) % 6 if comp < 60 else 3 + (int(comp) - 60) % 3)
+    return cz.copy(), Us, _cross_info_dict(xi, [slot])
 
 
 def tucker_hadamard(core, factors, x, cp=False, out=None):

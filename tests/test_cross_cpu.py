@@ -131,3 +131,24 @@ def test_library_cross_of_pwl_components_is_within_tolerance(comp):
     fn = cross.green_entries(lambda i, j, k: vi.green_pwl_entries(np.stack([i, j, k], -1), comp, h, K0), odd)
     Go, Uo, io = cross.tucker_cross(fn, n, tol)
     assert G.shape == Go.shape
+
+
+@pytest.mark.parametrize("comp", [60, 65, 74, 89])
+def test_library_cross_of_pwl_k_components_is_within_tolerance(comp):
+    # the thirty PWL K components (comp 60 + 3 P + c) from the same callback
+    vie = _vie()
+    n, h, tol = (30, 26, 22), 0.005, 1e-6
+    cb = vi.GreenPwlEntryCallback(h, K0)
+    G, Us, info = vie.tucker_cross(n, cb.fn, cb.ctx_ptr, comp, tol=tol, pwl=True)
+    P, c = divmod(comp - 60, 3)
+    A = tucker.from_storage(vi.green_pwl_k_tensor(n, h, K0)[P, c])
+    from vie_inputs.green import PWL_PAIRS
+    l, lp = PWL_PAIRS[P]
+    s = 2 - c
+    for ax in range(3):
+        if ((s == ax) + (l == ax + 1) + (lp == ax + 1)) % 2:
+            sl = [slice(None)] * 3
+            sl[ax] = 0
+            assert np.abs(A[tuple(sl)]).max() == 0.0
+            assert np.abs(Us[ax][0]).max() == 0.0
+    assert _rel(tucker.tucker_reconstruct(G, *Us), A) <= 2 * tol

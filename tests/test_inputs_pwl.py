@@ -178,3 +178,111 @@ def test_plane_wave_moments_match_closed_forms():
     np.testing.assert_allclose(m[3, 0], 1j * (a * np.cos(a / 2) - 2 * np.sin(a / 2)) / a ** 2 * ez, rtol=0,
                                atol=1e-14)
     assert np.abs(m[1:3]).max() < 1e-15 and np.abs(m[:, 1:]).max() == 0.0
+
+
+# ---------------- the magnetic operator K in the PWL basis ----------------
+
+def _dg(R, kappa):
+    """grad g^ at displacements R (..., 3)."""
+    r2 = np.sum(R * R, axis=-1)
+    r = np.sqrt(r2)
+    f = -_ghat(r, kappa) * (1 + 1j * kappa * r) / r2
+    return f[..., None] * R
+
+
+def test_grad_helper_by_finite_differences():
+    kappa, x0, h = 0.6, np.array([1.7, 0.4, -2.2]), 1e-5
+    g = _dg(x0[None, :], kappa)[0]
+    for s in range(3):
+        e = np.eye(3)[s] * h
+        fd = (_ghat(np.linalg.norm(x0 + e), kappa) - _ghat(np.linalg.norm(x0 - e), kappa)) / (2 * h)
+        assert abs(fd - g[s]) < 1e-8 * abs(g[s])
+
+
+def _brute6_k(D, kappa, q=8):
+    """<C^l_D e_p, K C^l'_0 e_q> for the stored components xy, xz, yz of all
+    16 (l, l'): test function in the observation voxel D, basis function in
+    the source voxel 0, (curl g e_q)_p = eps_psq d_s g, 6-D Gauss rule."""
+    x, w = np.polynomial.legendre.leggauss(q)
+    x, w = 0.5 * x, 0.5 * w
+    T = np.stack(np.meshgrid(x, x, x, indexing="ij"), axis=-1).reshape(-1, 3)
+    W = np.einsum("i,j,k->ijk", w, w, w).reshape(-1)
+    R = (np.asarray(D, float)[None, None, :] + T[:, None, :]) - T[None, :, :]   # r_obs - r_src
+    G = _dg(R, kappa)                                                          # (obs, src, 3)
+    comp = np.stack([-G[..., 2], G[..., 1], -G[..., 0]], axis=-1)              # xy, xz, yz
+    phi = np.concatenate([np.ones((T.shape[0], 1)), T], axis=1)
+    out = np.empty((4, 4, 3), complex)
+    for l in range(4):
+        for lp in range(4):
+            wt = (W * phi[:, l])[:, None] * (W * phi[:, lp])[None, :]
+            out[l, lp] = np.einsum("ab,abc->c", wt, comp)
+    return out
+
+
+def test_pwl_k_pulse_pair_equals_the_pulse_k():
+    from vie_inputs import green_k_tensor, green_pwl_k_tensor
+    K = green_pwl_k_tensor((6, 5, 4), 1.0, 0.3)
+    np.testing.assert_allclose(K[0], green_k_tensor((6, 5, 4), 1.0, 0.3), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("D", [(3, 0, 0), (3, 2, 1), (0, 4, 2), (-3, 2, 4)])
+def test_pwl_k_far_entries_match_six_dim_integral(D):
+    from vie_inputs import green_pwl_k_entry
+    kappa = 0.45
+    B = _brute6_k(D, kappa)
+    E = green_pwl_k_entry(D, kappa, 12, method=1)
+    for l in range(4):
+        for lp in range(4):
+            P, sign = pwl_pair_index(l, lp)
+            scale = np.abs(B[l, lp]).max()
+            np.testing.assert_allclose(sign * E[P], B[l, lp], rtol=0, atol=2e-9 * scale + 1e-15,
+                                       err_msg="pair (%d,%d)" % (l, lp))
+
+
+@pytest.mark.parametrize("D", [(2, 0, 0), (2, 1, 1), (3, -2, 0), (1, 2, -3)])
+def test_pwl_k_volume_form_equals_smooth_form(D):
+    from vie_inputs import green_pwl_k_entry
+    a = green_pwl_k_entry(D, 0.35, 16, method=0)
+    b = green_pwl_k_entry(D, 0.35, 16, method=1)
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-13 * np.abs(b).max())
+
+
+def _odd_k(P, c, a):
+    l, lp = PWL_PAIRS[P]
+    s = 2 - c                      # xy <- F_z, xz <- F_y, yz <- F_x
+    return ((s == a) + (l == a + 1) + (lp == a + 1)) % 2
+
+
+def test_pwl_k_zero_planes_parities_and_entries():
+    from vie_inputs import green_pwl_k_entries, green_pwl_k_entry, green_pwl_k_tensor
+    kappa, n = 0.5, (5, 4, 3)
+    K = green_pwl_k_tensor(n, 1.0, kappa)
+    for P in range(10):
+        for c in range(3):
+            for a in range(3):
+                if _odd_k(P, c, a):
+                    sl = [P, c, slice(None), slice(None), slice(None)]
+                    sl[4 - a] = 0
+                    assert np.abs(K[tuple(sl)]).max() == 0.0, (P, c, a)
+    for D in [(1, 0, 1), (2, 1, 0), (3, 1, 2)]:
+        E = green_pwl_k_entry(D, kappa, 14, method=0)
+        for a in range(3):
+            Dm = list(D)
+            Dm[a] = -Dm[a]
+            Em = green_pwl_k_entry(Dm, kappa, 14, method=0)
+            for P in range(10):
+                for c in range(3):
+                    s = -1.0 if _odd_k(P, c, a) else 1.0
+                    assert abs(Em[P, c] - s * E[P, c]) < 1e-13, (D, a, P, c)
+    idx = np.array([[i, j, k] for k in range(n[2]) for j in range(n[1]) for i in range(n[0])])
+    for comp in (0, 7, 17, 29):
+        e = green_pwl_k_entries(idx, comp, 1.0, kappa)
+        np.testing.assert_allclose(e, K[comp // 3, comp % 3].reshape(-1), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("D", [(0, 0, 1), (1, 0, 0), (1, 1, 0), (1, 1, 1)])
+def test_pwl_k_near_quadrature_converges(D):
+    from vie_inputs import green_pwl_k_entry
+    a = green_pwl_k_entry(D, 0.5, 12, method=0)
+    b = green_pwl_k_entry(D, 0.5, 24, method=0)
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-10)

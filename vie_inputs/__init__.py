@@ -21,7 +21,7 @@ from .phantoms import sphere_phantom, head_phantom, head_semi_axes
 from .fields import plane_wave, plane_wave_h, plane_wave_pwl, pwl_moments, dipole_field, dipole_ring, \
     dipole_cylinder, rhs_from_field
 from .green import GreenEntryCallback, GreenPwlEntryCallback, PWL_PAIRS, green_entries, green_pwl_entries, green_k_tensor, green_pwl_entry, \
-    green_pwl_tensor, green_tensor, pwl_pair_index
+    green_pwl_k_entries, green_pwl_k_entry, green_pwl_k_tensor, green_pwl_tensor, green_tensor, pwl_pair_index
 from .random import random_field, random_complex
 
 __all__ = [
@@ -29,5 +29,5 @@ __all__ = [
     "complex_permittivity", "TISSUES_298MHZ", "sphere_phantom", "head_phantom",
     "head_semi_axes", "plane_wave", "plane_wave_h", "plane_wave_pwl", "pwl_moments", "dipole_field", "dipole_ring", "dipole_cylinder",
     "rhs_from_field", "green_tensor", "green_pwl_tensor", "green_pwl_entry", "PWL_PAIRS",
-    "pwl_pair_index", "green_pwl_entries", "GreenPwlEntryCallback", "green_k_tensor", "green_entries", "GreenEntryCallback", "random_field", "random_complex",
+    "pwl_pair_index", "green_pwl_entries", "green_pwl_k_tensor", "green_pwl_k_entry", "green_pwl_k_entries", "GreenPwlEntryCallback", "green_k_tensor", "green_entries", "GreenEntryCallback", "random_field", "random_complex",
 ]

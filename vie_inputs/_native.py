@@ -50,6 +50,16 @@ def lib():
         L.vie_green_pwl_entries.restype = ctypes.c_int
         L.vie_green_pwl_entries.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                             ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p]
+        L.vie_green_pwl_k_fill.restype = ctypes.c_int
+        L.vie_green_pwl_k_fill.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                           ctypes.c_long, ctypes.c_long]
+        L.vie_green_pwl_k_entry.restype = ctypes.c_int
+        L.vie_green_pwl_k_entry.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_void_p]
+        L.vie_green_pwl_k_entries.restype = ctypes.c_int
+        L.vie_green_pwl_k_entries.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p]
         L.vie_dyadic_points.restype = None
         L.vie_dyadic_points.argtypes = [ctypes.c_long, ctypes.c_void_p, ctypes.c_double,
                                         ctypes.c_void_p]

@@ -881,9 +881,263 @@ int vie_green_pwl_entries(double kappa, int near_q, int boost, int comp, long co
     return bad ? -2 : 0;
 }
 
-/* The same as an entry callback (ctx as vie_green_entry_cb's) */
+int vie_green_pwl_k_entries(double kappa, int near_q, int boost, int comp, long count, const int *idx,
+                            double *out);
+
+/* The same as an entry callback (ctx as vie_green_entry_cb's): comp 0..59
+ * the N components 6 P + c, 60..89 the K components 60 + 3 P + c */
 int vie_green_pwl_entry_cb(void *ctx, int comp, long count, const int *idx, double *out)
 {
     const vie_green_ctx *g = (const vie_green_ctx *)ctx;
+    if (comp >= 60) return vie_green_pwl_k_entries(g->kappa, g->near_q, g->boost, comp - 60, count, idx, out);
     return vie_green_pwl_entries(g->kappa, g->near_q, g->boost, comp, count, idx, out);
+}
+
+/* ============ the K operator in the piecewise-linear basis ============
+ * Kt^{(l,l')}_pq(D) = <C^l_D e_p, K C^l'_0 e_q> / vol: test function l in
+ * the observation voxel D, basis function l' in the source voxel 0, as for
+ * the pulse K above.  The offset x = r - r' then carries the weight
+ * W^K_D(x) = prod_a c_{type}(x_a - D_a) with the roles of test and basis
+ * exchanged against N (type = [l' = a + 1] + 2 [l = a + 1]), and
+ *   Kt_pq = eps_psq F_s,  F_s(D) = int d_s g^ W^K_D = -int g^ d_s W^K_D,
+ * the first form on the far shells, the second (bounded first derivatives of
+ * the correlations, no point masses) on the near ones.  Stored as the pulse K:
+ * xy = -F_z, xz = F_y, yz = -F_x, for the ten pairs l <= l' (the others:
+ * Kt^(l',l) = sigma Kt^(l,l') with the sigma of N).  A component vanishes on
+ * D_a = 0 when it is odd along a: [s = a] + [type_a odd] odd. */
+static int pwlk_ty[10][3];
+static int pwlk_ready = 0;
+static void pwlk_init(void)
+{
+    pwl_init();
+    if (pwlk_ready) return;
+    for (int P = 0; P < 10; ++P)
+        for (int a = 0; a < 3; ++a)
+            pwlk_ty[P][a] = (pwl_pairs[P][1] == a + 1) + 2 * (pwl_pairs[P][0] == a + 1);
+    pwlk_ready = 1;
+}
+
+static void pwlk_far(const int D[3], double kappa, int q, cplx F[30])
+{
+    for (int m = 0; m < 30; ++m) F[m] = 0;
+    const double *gx = gl_x[q], *gw = gl_w[q];
+    for (int cell = 0; cell < 8; ++cell) {
+        double lo[3];
+        for (int a = 0; a < 3; ++a) lo[a] = ((cell >> a) & 1) ? 0.0 : -1.0;
+        for (int ia = 0; ia < q; ++ia)
+            for (int ib = 0; ib < q; ++ib)
+                for (int ic = 0; ic < q; ++ic) {
+                    double t[3] = {lo[0] + gx[ia], lo[1] + gx[ib], lo[2] + gx[ic]};
+                    double w = gw[ia] * gw[ib] * gw[ic];
+                    double xs[3] = {D[0] + t[0], D[1] + t[1], D[2] + t[2]};
+                    double r2 = xs[0] * xs[0] + xs[1] * xs[1] + xs[2] * xs[2];
+                    double r = sqrt(r2);
+                    cplx dg = -ghat(r, kappa) * (1.0 + I * kappa * r) / r2;
+                    double v[3][4], d1[4], d2[4];
+                    for (int a = 0; a < 3; ++a) pwl_axis(t[a], v[a], d1, d2);
+                    for (int P = 0; P < 10; ++P) {
+                        cplx wd = (w * v[0][pwlk_ty[P][0]] * v[1][pwlk_ty[P][1]] * v[2][pwlk_ty[P][2]]) * dg;
+                        for (int s = 0; s < 3; ++s) F[P * 3 + s] += wd * xs[s];
+                    }
+                }
+    }
+}
+
+static inline void pwlk_vol_point(const double x[3], const int D[3], cplx g, cplx acc[30])
+{
+    double v[3][4], d1[3][4], d2[3][4];
+    for (int a = 0; a < 3; ++a) pwl_axis(x[a] - D[a], v[a], d1[a], d2[a]);
+    for (int P = 0; P < 10; ++P) {
+        const int t0 = pwlk_ty[P][0], t1 = pwlk_ty[P][1], t2 = pwlk_ty[P][2];
+        cplx *o = acc + 3 * P;
+        o[0] -= g * (d1[0][t0] * v[1][t1] * v[2][t2]);
+        o[1] -= g * (v[0][t0] * d1[1][t1] * v[2][t2]);
+        o[2] -= g * (v[0][t0] * v[1][t1] * d1[2][t2]);
+    }
+}
+
+/* -int g^ d_s W^K_D over the 8 unit cells (Duffy on cells with the origin
+ * at a corner): F for all pairs, valid at every offset */
+static void pwlk_near(const int D[3], double kappa, int q, cplx F[30])
+{
+    for (int m = 0; m < 30; ++m) F[m] = 0;
+    const double *gx = gl_x[q], *gw = gl_w[q];
+    for (int cell = 0; cell < 8; ++cell) {
+        double lo[3], sigma[3];
+        int corner = 1;
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = D[a] + (((cell >> a) & 1) ? 0.0 : -1.0);
+            if (lo[a] == 0.0) sigma[a] = 1.0;
+            else if (lo[a] == -1.0) sigma[a] = -1.0;
+            else corner = 0;
+        }
+        if (!corner) {
+            for (int ia = 0; ia < q; ++ia)
+                for (int ib = 0; ib < q; ++ib)
+                    for (int ic = 0; ic < q; ++ic) {
+                        double x[3] = {lo[0] + gx[ia], lo[1] + gx[ib], lo[2] + gx[ic]};
+                        double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+                        pwlk_vol_point(x, D, ghat(r, kappa) * (gw[ia] * gw[ib] * gw[ic]), F);
+                    }
+        } else {
+            for (int face = 0; face < 3; ++face) {
+                int a1 = (face + 1) % 3, a2 = (face + 2) % 3;
+                for (int is = 0; is < q; ++is) {
+                    double s = gx[is];
+                    for (int ib = 0; ib < q; ++ib)
+                        for (int ic = 0; ic < q; ++ic) {
+                            double y[3];
+                            y[face] = s;
+                            y[a1] = s * gx[ib];
+                            y[a2] = s * gx[ic];
+                            double x[3] = {sigma[0] * y[0], sigma[1] * y[1], sigma[2] * y[2]};
+                            double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+                            pwlk_vol_point(x, D, ghat(r, kappa) * (gw[is] * gw[ib] * gw[ic] * s * s), F);
+                        }
+                }
+            }
+        }
+    }
+}
+
+/* F (pairs x s) into the stored components (pairs x {xy, xz, yz}), with the
+ * exact zero planes of the odd components */
+static void pwlk_store(const int D[3], const cplx F[30], cplx e[30])
+{
+    for (int P = 0; P < 10; ++P) {
+        cplx f[3];
+        for (int s = 0; s < 3; ++s) {
+            int zero = 0;
+            for (int a = 0; a < 3; ++a)
+                if (D[a] == 0 && (((s == a) + (pwlk_ty[P][a] == 1 || pwlk_ty[P][a] == 2)) & 1)) zero = 1;
+            f[s] = zero ? 0 : F[P * 3 + s];
+        }
+        e[P * 3 + 0] = -f[2];
+        e[P * 3 + 1] = f[1];
+        e[P * 3 + 2] = -f[0];
+    }
+}
+
+/* Dense PWL K tensors: out[(((P * 3 + c) * n3 + k) * n2 + j) * n1 + i]
+ * (complex128 interleaved), pairs as vie_green_pwl_fill, c = xy, xz, yz;
+ * near form at order near_q on the shell max D_i <= 1, far form at the
+ * pulse orders plus one elsewhere.  Dimensionless (the physical entries are
+ * h times these). */
+int vie_green_pwl_k_fill(int n1, int n2, int n3, double kappa, int near_q, int boost, double *out, long lo_lin,
+                         long hi_lin)
+{
+    pwlk_init();
+    if (near_q < 2 || near_q > QMAX) return -1;
+    long V = (long)n1 * n2 * n3;
+    if (hi_lin > V) hi_lin = V;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long lin = lo_lin; lin < hi_lin; ++lin) {
+        int D[3] = {(int)(lin % n1), (int)((lin / n1) % n2), (int)(lin / ((long)n1 * n2))};
+        int d = D[0];
+        if (D[1] > d) d = D[1];
+        if (D[2] > d) d = D[2];
+        cplx F[30], e[30];
+        if (d <= 1) pwlk_near(D, kappa, near_q, F);
+        else {
+            int q = far_order(d, boost) + 1;
+            pwlk_far(D, kappa, q > QMAX ? QMAX : q, F);
+        }
+        pwlk_store(D, F, e);
+        for (int m = 0; m < 30; ++m) {
+            out[2 * (m * V + lin)] = creal(e[m]);
+            out[2 * (m * V + lin) + 1] = cimag(e[m]);
+        }
+    }
+    return 0;
+}
+
+/* All 30 PWL K entries at one offset D (any signs), method 0 = near form
+ * (any D), 1 = far form (max |D_i| >= 2), Gauss order q; no zero planes
+ * imposed.  out: 30 complex, index P * 3 + c. */
+int vie_green_pwl_k_entry(const int D[3], double kappa, int q, int method, double *out)
+{
+    pwlk_init();
+    if (q < 2 || q > QMAX || (method != 0 && method != 1)) return -1;
+    int d = abs(D[0]);
+    if (abs(D[1]) > d) d = abs(D[1]);
+    if (abs(D[2]) > d) d = abs(D[2]);
+    if (method == 1 && d < 2) return -1;
+    cplx F[30];
+    if (method == 0) pwlk_near(D, kappa, q, F);
+    else pwlk_far(D, kappa, q, F);
+    for (int P = 0; P < 10; ++P) {
+        cplx e[3] = {-F[P * 3 + 2], F[P * 3 + 1], -F[P * 3 + 0]};
+        for (int c = 0; c < 3; ++c) {
+            out[2 * (P * 3 + c)] = creal(e[c]);
+            out[2 * (P * 3 + c) + 1] = cimag(e[c]);
+        }
+    }
+    return 0;
+}
+
+/* Entries of one PWL K component comp = 3 P + c (0..29) at offsets >= 0, as
+ * vie_green_pwl_k_fill computes them up to rounding order */
+int vie_green_pwl_k_entries(double kappa, int near_q, int boost, int comp, long count, const int *idx, double *out)
+{
+    pwlk_init();
+    if (near_q < 2 || near_q > QMAX || comp < 0 || comp > 29 || count < 0) return -1;
+    const int P = comp / 3, c = comp % 3;
+    const int s = 2 - c;                       /* xy <- F_z, xz <- F_y, yz <- F_x */
+    const double sg = (c == 1) ? 1.0 : -1.0;
+    cplx nearv[8];
+#pragma omp parallel for schedule(static, 1)
+    for (int b = 0; b < 8; ++b) {
+        int D[3] = {b & 1, (b >> 1) & 1, (b >> 2) & 1};
+        cplx F[30], e[30];
+        pwlk_near(D, kappa, near_q, F);
+        pwlk_store(D, F, e);
+        nearv[b] = e[comp];
+    }
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(|: bad)
+    for (long t = 0; t < count; ++t) {
+        int D[3] = {idx[3 * t], idx[3 * t + 1], idx[3 * t + 2]};
+        if (D[0] < 0 || D[1] < 0 || D[2] < 0) {
+            bad = 1;
+            continue;
+        }
+        int d = D[0];
+        if (D[1] > d) d = D[1];
+        if (D[2] > d) d = D[2];
+        cplx e = 0;
+        if (d <= 1) e = nearv[D[0] | (D[1] << 1) | (D[2] << 2)];
+        else {
+            int zero = 0;
+            for (int a = 0; a < 3; ++a)
+                if (D[a] == 0 && (((s == a) + (pwlk_ty[P][a] == 1 || pwlk_ty[P][a] == 2)) & 1)) zero = 1;
+            if (!zero) {
+                int q = far_order(d, boost) + 1;
+                if (q > QMAX) q = QMAX;
+                const double *gx = gl_x[q], *gw = gl_w[q];
+                const int t0 = pwlk_ty[P][0], t1 = pwlk_ty[P][1], t2 = pwlk_ty[P][2];
+                cplx acc = 0;
+                for (int cell = 0; cell < 8; ++cell) {
+                    double lo[3];
+                    for (int a = 0; a < 3; ++a) lo[a] = ((cell >> a) & 1) ? 0.0 : -1.0;
+                    for (int ia = 0; ia < q; ++ia)
+                        for (int ib = 0; ib < q; ++ib)
+                            for (int ic = 0; ic < q; ++ic) {
+                                double tt[3] = {lo[0] + gx[ia], lo[1] + gx[ib], lo[2] + gx[ic]};
+                                double w = gw[ia] * gw[ib] * gw[ic];
+                                double xs[3] = {D[0] + tt[0], D[1] + tt[1], D[2] + tt[2]};
+                                double r2 = xs[0] * xs[0] + xs[1] * xs[1] + xs[2] * xs[2];
+                                double r = sqrt(r2);
+                                cplx dg = -ghat(r, kappa) * (1.0 + I * kappa * r) / r2;
+                                double v[3][4], d1[4], d2[4];
+                                for (int a = 0; a < 3; ++a) pwl_axis(tt[a], v[a], d1, d2);
+                                acc += ((w * v[0][t0] * v[1][t1] * v[2][t2]) * dg) * xs[s];
+                            }
+                }
+                e = sg * acc;
+            }
+        }
+        out[2 * t] = creal(e);
+        out[2 * t + 1] = cimag(e);
+    }
+    return bad ? -2 : 0;
 }

@@ -143,8 +143,51 @@ def green_pwl_entries(idx, comp, h, k0, near_order=16, far_boost=0):
     return (out[:, 0] + 1j * out[:, 1]).reshape(idx.shape[:-1])
 
 
+def green_pwl_k_tensor(n, h, k0, near_order=16, far_boost=0):
+    """Dense PWL tensors of the magnetic operator K, shape (10, 3, n3, n2,
+    n1) complex128: entry [P, c, k, j, i] = Kt^{(l,l')}_c(offset (i, j, k))
+    for the pair P = PWL_PAIRS.index((l, l')) with the test function l in the
+    observation voxel at the offset and the basis function l' in the source
+    voxel 0 (the pulse K's convention), c = xy, xz, yz; Kt^(l',l) =
+    sigma Kt^(l,l') as for N.  Dimensionless (physical: h times)."""
+    n1, n2, n3 = (int(v) for v in n)
+    V = n1 * n2 * n3
+    out = np.empty((10, 3, n3, n2, n1, 2), dtype=np.float64)
+    rc = _native.lib().vie_green_pwl_k_fill(n1, n2, n3, float(k0) * float(h), int(near_order),
+                                            int(far_boost), out.ctypes.data, 0, V)
+    if rc != 0:
+        raise ValueError("vie_green_pwl_k_fill failed (%d)" % rc)
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def green_pwl_k_entry(D, kappa, order, method=0):
+    """All 30 PWL K entries at one offset D (any signs), shape (10, 3):
+    method 0 = the volume form -int g^ d_s W (any offset), 1 = the smooth
+    form int d_s g^ W (max |D_i| >= 2); no zero planes imposed."""
+    Dc = np.ascontiguousarray(np.asarray(D, dtype=np.int32).reshape(3))
+    out = np.empty((30, 2), dtype=np.float64)
+    rc = _native.lib().vie_green_pwl_k_entry(Dc.ctypes.data, float(kappa), int(order), int(method),
+                                             out.ctypes.data)
+    if rc != 0:
+        raise ValueError("vie_green_pwl_k_entry failed (%d)" % rc)
+    return (out[:, 0] + 1j * out[:, 1]).reshape(10, 3)
+
+
+def green_pwl_k_entries(idx, comp, h, k0, near_order=16, far_boost=0):
+    """Entries of the PWL K component comp = 3 P + c at offsets ``idx`` >= 0."""
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int32))
+    flat = idx.reshape(-1, 3)
+    out = np.empty((flat.shape[0], 2), dtype=np.float64)
+    rc = _native.lib().vie_green_pwl_k_entries(float(k0) * float(h), int(near_order), int(far_boost), int(comp),
+                                               flat.shape[0], flat.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("vie_green_pwl_k_entries failed (%d)" % rc)
+    return (out[:, 0] + 1j * out[:, 1]).reshape(idx.shape[:-1])
+
+
 class GreenPwlEntryCallback(GreenEntryCallback):
-    """``GreenEntryCallback`` for the sixty PWL components (comp = 6 P + c)."""
+    """``GreenEntryCallback`` for the PWL components: comp 0..59 the N
+    components 6 P + c, 60..89 the K components 60 + 3 P + c."""
 
     def __init__(self, h, k0, near_order=16, far_boost=0):
         super().__init__(h, k0, near_order, far_boost)
