@@ -25,13 +25,14 @@
 // the (b, a) block.  T is symmetric over the dyadic pair (p, q), so each
 // block is the 3 x 3 product of the pulse basis.
 //
-// Kernel layout: one workgroup per mirror group of pencils (as the generic z
-// pass, 512 threads), the twelve pencils of each in LDS; every thread owns up to EPT
-// Fourier-domain positions and keeps their twelve output components in
-// registers while the ten pairs go by, each pair's six tables rebuilt from
-// the Tucker form into LDS: W_c(k2) = G_c x2 U2_c(k2, :) comes from a small
-// kernel that runs first (once per canonical k2, not per pencil group),
-// V_c = U1_c(k1, :) W_c(k2), then the z factor per k3.
+// Kernel layout: one 512-thread workgroup per mirror group of pencils (as
+// the generic z pass), the twelve pencils of each in LDS; every thread owns
+// up to EPT Fourier-domain positions and keeps their twelve output
+// components in registers while the ten pairs go by, in batches whose
+// tables fit the LDS together, each table rebuilt from the Tucker form:
+// W_c(k2) = G_c x2 U2_c(k2, :) comes from a small kernel that runs first
+// (once per canonical k2, not per pencil group), V_c = U1_c(k1, :) W_c(k2),
+// then the z factor per k3.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -414,6 +415,7 @@ hipError_t launch_pwl_z(const vie_pwl_op& P, int conj, c2<T>* S2, c2<T>* Wg, hip
     const OpView& v = op.view;
     int G = 0, pb = 1;
     pwl_z_shape<T>(op, P.rmax, G, pb);
+    // tuning override: at most this many pairs per table batch (same results)
     if (const char* e = getenv("VIE_PWL_PAIRS_PER_BATCH")) pb = std::max(1, std::min(pb, atoi(e)));
     if (G == 0) {
         err = "the piecewise-linear z pass does not fit in LDS (z length or ranks too large)";
