@@ -187,6 +187,12 @@ def main():
     ap.add_argument("--pwl-grids", default="30,60,90,120",
                     help="edges of the piecewise-linear refinement series (0.3 m cube)")
     ap.add_argument("--pwl-tol", type=float, default=1e-6)
+    ap.add_argument("--pwl-jm-grids", default="",
+                    help="PWL grids on which the coupled JM system (magnetic sphere) is timed and solved")
+    ap.add_argument("--pwl-k-grids", default="120",
+                    help="PWL grids on which the magnetic operator K is compressed and timed too")
+    ap.add_argument("--pwl-rhs", type=int, default=4,
+                    help="vectors per call in the multi-RHS timing on the last PWL grid")
     ap.add_argument("--pwl-head", type=int, default=1,
                     help="1: also solve the plane wave on the 96 x 120 x 126 PWL head (Table V analogue)")
     ap.add_argument("--pwl-solve-grids", default="60,120",
@@ -539,6 +545,49 @@ def pwl_z_flops(n, ranks):
 PWL_PASS_ELEMS_V = [12 + 24, 24 + 48, 48 + 48, 48 + 24, 24 + 12 + 1 + 12]
 
 
+def pwl_jm_solve(vie, vi, torch, dev, op, opk, n, h, f, epsc):
+    """The JMVIE system of eq. 4 in the piecewise-linear basis on the sphere
+    of the refinement series made magnetic (synthetic mu_r = 1.5, loss 0.1
+    inside), x-polarised plane wave (its voxel moments; H = z x E / eta0),
+    mass-normalised basis: one coupled product timed, then GMRES(50) to 1e-5
+    in complex64."""
+    N1, N2, N3 = n
+    inside = np.abs(epsc - 1.0) > 0
+    mu = np.where(inside, 1.5 - 0.1j, 1.0 + 0j)
+    S = np.array([1.0, np.sqrt(12.0), np.sqrt(12.0), np.sqrt(12.0)])[:, None, None, None, None]
+    Em = vi.plane_wave_pwl(n, h, f)
+    Hm = np.zeros_like(Em)
+    eta0 = np.sqrt(vi.MU0 / vi.EPS0)
+    Hm[:, 0] = -Em[:, 1] / eta0
+    Hm[:, 1] = Em[:, 0] / eta0
+    w = 2 * np.pi * f
+    b = np.stack([S * (1j * w * vi.EPS0) * (epsc - 1.0)[None, None] * Em,
+                  S * (1j * w * vi.MU0) * (mu - 1.0)[None, None] * Hm])
+    bd = torch.from_numpy(b.reshape(2, 12, N3, N2, N1)).to(dev, torch.complex64)
+    e = torch.from_numpy(epsc).to(dev, torch.complex64)
+    m = torch.from_numpy(mu).to(dev, torch.complex64)
+    vie.matvec_jm_pwl(op, opk, bd, e, m, h, f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        yd = vie.matvec_jm_pwl(op, opk, bd, e, m, h, f)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / 5 * 1e3
+    del yd
+    t0 = time.perf_counter()
+    xs, info, st_ = vie.solve_jm_pwl(op, opk, bd, e, m, h, f, tol=1e-5, restart=50, max_outer=200)
+    torch.cuda.synchronize()
+    t_sol = time.perf_counter() - t0
+    out = {"ms_per_jm_matvec": ms, "solve_c64_tol1e-5": {"seconds": t_sol, "matvecs": info["matvecs"],
+                                                         "converged": info["converged"],
+                                                         "rel_residual": info["rel_residual"]},
+           "unknowns": 24 * N1 * N2 * N3}
+    log("pwl %d^3 JM: %.3f ms per coupled product, plane-wave solve %.2f s, %d matvecs, residual %.2e"
+        % (N1, ms, t_sol, info["matvecs"], info["rel_residual"]))
+    del xs, bd
+    return out
+
+
 def pwl_leg(args, vie, torch, dev):
     """Piecewise-linear basis (eq. 7a-7b, twelve unknowns per voxel) on the
     refinement series of Sec. VI-C (Fig. 9): a homogeneous sphere of radius
@@ -551,7 +600,10 @@ def pwl_leg(args, vie, torch, dev):
     count; the memory of the compressed and of the dense circulant tensors
     (complex128, as Sec. VI quotes it); on --pwl-solve-grids the x-polarised
     plane wave (its voxel moments against the basis) solved by GMRES(50) to
-    1e-5 in complex64 (Sec. VI-C's solver settings)."""
+    1e-5 in complex64 (Sec. VI-C's solver settings); on --pwl-k-grids the
+    magnetic operator K of eq. 5 in the same basis (thirty tensors) compressed
+    at the same tolerance and its product timed; on the last grid --pwl-rhs
+    vectors in one call."""
     import vie_inputs as vi
     out = {}
     f = 298e6
@@ -559,6 +611,8 @@ def pwl_leg(args, vie, torch, dev):
     st = torch.cuda.current_stream()
     grids = [int(g) for g in args.pwl_grids.split(",") if g.strip()]
     solve_grids = {int(g) for g in args.pwl_solve_grids.split(",") if g.strip()}
+    jm_grids = {int(g) for g in args.pwl_jm_grids.split(",") if g.strip()}
+    k_grids = {int(g) for g in args.pwl_k_grids.split(",") if g.strip()} | jm_grids
     for idx, N in enumerate(grids):
         n = (N, N, N)
         h = 0.3 / N
@@ -599,6 +653,50 @@ def pwl_leg(args, vie, torch, dev):
         out["n%d" % N] = row
         log("pwl %d^3: %.3f ms/matvec (%.1f Munknowns/s), ranks <= %d, compress %.1f s, green %.1f s"
             % (N, ms, row["Munknowns_per_s"], row["max_rank"], t_cmp, t_gen))
+        if idx == len(grids) - 1 and args.pwl_rhs > 1:
+            # several excitations of the same phantom in one call
+            R = args.pwl_rhs
+            xr = x.unsqueeze(0).repeat(R, 1, 1, 1, 1)
+            yr = torch.empty_like(xr)
+            vie.matvec_pwl(op, xr, e, out=yr)
+            torch.cuda.synchronize()
+            c0.record(st)
+            for _ in range(steps):
+                vie.matvec_pwl(op, xr, e, out=yr)
+            c1.record(st)
+            torch.cuda.synchronize()
+            msr = c0.elapsed_time(c1) / steps
+            row["multi_rhs"] = {"nrhs": R, "ms_per_call": msr, "ms_per_vector": msr / R,
+                                "Munknowns_per_s": R * 12 * V / (msr * 1e-3) / 1e6}
+            log("pwl %d^3 x %d rhs: %.3f ms per vector" % (N, R, msr / R))
+            del xr, yr
+        if N in k_grids:
+            # the magnetic operator K in the same basis (thirty components)
+            t0 = time.perf_counter()
+            Kt = vi.green_pwl_k_tensor(n, h, k0)
+            t_kgen = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            opk = vie.compress_pwl_k(Kt, tol=args.pwl_tol)
+            t_kcmp = time.perf_counter() - t0
+            del Kt
+            for _ in range(2):
+                vie.matvec_pwl(opk, x, kind="N", out=y)
+            torch.cuda.synchronize()
+            c0.record(st)
+            for _ in range(steps):
+                vie.matvec_pwl(opk, x, kind="N", out=y)
+            c1.record(st)
+            torch.cuda.synchronize()
+            msk = c0.elapsed_time(c1) / steps
+            row["k_operator"] = {"ms_per_matvec": msk, "Munknowns_per_s": 12 * V / (msk * 1e-3) / 1e6,
+                                 "max_rank": int(opk.ranks[:, 3:].max()), "tucker_bytes_c64": opk.tucker_bytes_c64,
+                                 "dense_circulant_bytes_c128": 30 * 8 * V * 16,
+                                 "green_seconds": t_kgen, "compress_seconds": t_kcmp}
+            log("pwl %d^3 K: %.3f ms/matvec, ranks <= %d, compress %.1f s, green %.1f s"
+                % (N, msk, row["k_operator"]["max_rank"], t_kcmp, t_kgen))
+            if N in jm_grids:
+                row["jm"] = pwl_jm_solve(vie, vi, torch, dev, op, opk, n, h, f, epsc)
+            opk.close()
         if N in solve_grids:
             S = np.array([1.0, np.sqrt(12.0), np.sqrt(12.0), np.sqrt(12.0)])[:, None, None, None, None]
             bn = S * vi.rhs_from_field(epsc, vi.plane_wave_pwl(n, h, f), f)

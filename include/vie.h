@@ -291,13 +291,39 @@ vie_status vie_compress_pwl(const int n[3], const double* green_pwl, const vie_c
 
 vie_status vie_pwl_op_destroy(vie_pwl_op* op);
 
-/* grid and the Tucker ranks [pair][component][mode]; either may be NULL */
+/*
+ * vie_compress_pwl_k -- the magnetic operator K of eq. 5 (curl of the
+ * single-layer potential) in the piecewise-linear basis: HOSVD (Alg. 1) of
+ * its thirty defining tensors, ten pairs (l, l') in the order above times the
+ * components xy, xz, yz, each the Galerkin entry of test function (p, l) in
+ * the observation voxel at offset D against basis function (q, l') in the
+ * source voxel 0, rows divided by the voxel volume.  Implied entries:
+ * Kt_qp = -Kt_pq (zero diagonal), Kt^(l',l) = sigma Kt^(l,l') with the sigma
+ * of N, and component xy / xz / yz (derivative axis s = z / y / x) is odd
+ * along axis a when [s = a] + [l = a + 1] + [l' = a + 1] is odd.  The
+ * operator applies, in the mass-normalised basis, S K S with
+ *   (K u)^{pl}(m) = sum_{q, l', m'} Kt^{(l,l')}_pq(m - m') u^{ql'}(m')
+ * through vie_matvec_pwl with kind VIE_OP_N and adjoint 0 only (other calls
+ * and vie_solve_pwl return VIE_E_UNSUPPORTED).
+ *   n            HOST int[3] as vie_compress_pwl.
+ *   green_pwl_k  HOST complex128 [10][3][n3][n2][n1].
+ *   opts         HOST, may be NULL (tol 1e-6), per component.
+ *   info         HOST vie_compress_info[10] out, may be NULL: per pair as
+ *                vie_compress_k (slots 0..2 the zero diagonal).
+ * Errors as vie_compress_k.
+ */
+vie_status vie_compress_pwl_k(const int n[3], const double* green_pwl_k, const vie_compress_opts* opts,
+                              vie_pwl_op** out, vie_compress_info* info);
+
+/* grid and the Tucker ranks [pair][component][mode]; either may be NULL (a K
+ * operator: components 3..5 = xy, xz, yz, 0..2 the zero diagonal (1, 1, 1)) */
 vie_status vie_pwl_op_query(const vie_pwl_op* op, int n[3], int ranks[10][6][3]);
 
-/* DEVICE workspace of vie_matvec_pwl in bytes: the 12 padded components of
- * the five passes and the core products W_c(k2) = G_c x2 U2_c(k2, :) of the
- * sixty components for k2 in [0, n2] */
-size_t vie_pwl_workspace_bytes(const vie_pwl_op* op, int dtype);
+/* DEVICE workspace of vie_matvec_pwl in bytes for nrhs vectors: their 12
+ * padded components through the five passes and the core products
+ * W_c(k2) = G_c x2 U2_c(k2, :) of the sixty (K: thirty) components for k2 in
+ * [0, n2] (shared by the vectors) */
+size_t vie_pwl_workspace_bytes(const vie_pwl_op* op, int dtype, int nrhs);
 
 /*
  * vie_matvec_pwl -- y = S A S x (kind VIE_OP_A, needs eps_c) or the bare
@@ -305,15 +331,19 @@ size_t vie_pwl_workspace_bytes(const vie_pwl_op* op, int dtype);
  * mass-normalised basis: the five passes of vie_matvec with the twelve
  * components as four groups of three and a z pass that adds the sixteen
  * (l, l') blocks per Fourier-domain position, each block's six N^ tables
- * rebuilt from its Tucker form per pencil group (Sec. V-A/B).
+ * rebuilt from its Tucker form per pencil group (Sec. V-A/B).  For an
+ * operator of vie_compress_pwl_k: y = S K S x (VIE_OP_N, adjoint 0), the
+ * same passes with each block's three K^ tables and the antisymmetric
+ * product.
  *   dtype  VIE_C64 (FP32 compute) or VIE_C128 (FP64) for x, y, eps_c.
- *   eps_c  DEVICE [n3][n2][n1]; x, y DEVICE [12][n3][n2][n1], not overlapping.
- *   ws     DEVICE, vie_pwl_workspace_bytes(op, dtype).
+ *   eps_c  DEVICE [n3][n2][n1]; x, y DEVICE [nrhs][12][n3][n2][n1], not
+ *          overlapping; nrhs in [1, 4096] vectors with the same contrast.
+ *   ws     DEVICE, vie_pwl_workspace_bytes(op, dtype, nrhs).
  * Asynchronous on `stream`.  VIE_E_UNSUPPORTED when the z pass does not fit
  * in LDS (2 n3 and the ranks too large).
  */
 vie_status vie_matvec_pwl(const vie_pwl_op* op, int kind, int adjoint, int dtype, const void* eps_c, const void* x,
-                          void* y, void* ws, size_t ws_bytes, void* stream);
+                          void* y, int nrhs, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * vie_tucker_cross_pwl -- vie_tucker_cross for one piecewise-linear
@@ -493,6 +523,38 @@ vie_status vie_solve(const vie_op* op, int dtype, const void* eps_c, const void*
 size_t vie_solve_pwl_workspace_bytes(const vie_pwl_op* op, int dtype, const vie_solve_opts* opts);
 vie_status vie_solve_pwl(const vie_pwl_op* op, int dtype, const void* eps_c, const void* b, void* x,
                          const vie_solve_opts* opts, vie_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * vie_matvec_jm_pwl -- the full JMVIE operator of eq. 4 in the
+ * piecewise-linear basis, as vie_matvec_jm with twelve coefficients per
+ * current and voxel (mass-normalised basis, whose mass term is the identity):
+ *     y_J = eps_c J - chi_e (S N S) J + c_e h chi_e (S K S) M,
+ *     y_M = mu_c M  - chi_h (S N S) M - c_m h chi_h (S K S) J,
+ *   the contrasts constant per voxel multiplying whole Galerkin rows;
+ *   op_n from vie_compress_pwl, op_k from vie_compress_pwl_k, same grid
+ *   (VIE_E_ARG otherwise).  J and M go through each operator as two
+ *   right-hand sides of vie_matvec_pwl, then one kernel combines.
+ *   x, y DEVICE complex [2][12][n3][n2][n1] (J then M, not overlapping);
+ *   eps_c, mu_c DEVICE complex [n3][n2][n1]; ws DEVICE scratch of
+ *   vie_jm_pwl_workspace_bytes(op_n, op_k, dtype) bytes.  Asynchronous.
+ */
+size_t vie_jm_pwl_workspace_bytes(const vie_pwl_op* op_n, const vie_pwl_op* op_k, int dtype);
+vie_status vie_matvec_jm_pwl(const vie_pwl_op* op_n, const vie_pwl_op* op_k, int dtype, double h, double omega,
+                             const void* eps_c, const void* mu_c, const void* x, void* y, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/*
+ * vie_solve_jm_pwl -- GMRES(m) on vie_matvec_jm_pwl's operator, one system,
+ * as vie_solve_jm (forward only, x starting at zero, opts refine with FP32
+ * products on VIE_C128 vectors and FP64 restart residuals).  b, x DEVICE
+ * [2][12][n3][n2][n1] in the mass-normalised basis (not overlapping);
+ * ws DEVICE, vie_solve_jm_pwl_workspace_bytes.  Synchronous on `stream`.
+ */
+size_t vie_solve_jm_pwl_workspace_bytes(const vie_pwl_op* op_n, const vie_pwl_op* op_k, int dtype,
+                                        const vie_solve_opts* opts);
+vie_status vie_solve_jm_pwl(const vie_pwl_op* op_n, const vie_pwl_op* op_k, int dtype, double h, double omega,
+                            const void* eps_c, const void* mu_c, const void* b, void* x, const vie_solve_opts* opts,
+                            vie_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
 
 /*

@@ -240,7 +240,7 @@ vie_status run_jm(const vie_op* op_n, const vie_op* op_k, int dtype, double h, d
 KLayout pwl_layout(const vie_pwl_op* op, int dtype, int m)
 {
     const OpView& v = op->blk[0]->d.view;
-    return k_layout(12L * v.n[0] * v.n[1] * v.n[2], vie_pwl_workspace_bytes(op, dtype), dtype, m);
+    return k_layout(12L * v.n[0] * v.n[1] * v.n[2], vie_pwl_workspace_bytes(op, dtype, 1), dtype, m);
 }
 
 template <typename TK>
@@ -251,17 +251,45 @@ vie_status run_pwl(const vie_pwl_op* op, int dtype, const void* eps_c, const c2<
     const long n = 12L * v.n[0] * v.n[1] * v.n[2];
     const KLayout L = pwl_layout(op, dtype, o.restart);
     void* pw = ws + L.op;
-    const size_t pwb = vie_pwl_workspace_bytes(op, dtype);
+    const size_t pwb = vie_pwl_workspace_bytes(op, dtype, 1);
     const int mode = o.adjoint ? MODE_AH : MODE_A;
     const bool refine = o.refine && sizeof(TK) == 8;
     auto apply = [&](const c2<TK>* in, c2<TK>* out) {
-        return vie_matvec_pwl(op, VIE_OP_A, o.adjoint, dtype, eps_c, in, out, pw, pwb, (void*)st);
+        return vie_matvec_pwl(op, VIE_OP_A, o.adjoint, dtype, eps_c, in, out, 1, pw, pwb, (void*)st);
     };
     auto apply_inner = [&](const c2<TK>* in, c2<TK>* out) {
         if (refine) return pwl_apply_mixed(op, mode, eps_c, in, out, pw, st);
-        return vie_matvec_pwl(op, VIE_OP_A, o.adjoint, dtype, eps_c, in, out, pw, pwb, (void*)st);
+        return vie_matvec_pwl(op, VIE_OP_A, o.adjoint, dtype, eps_c, in, out, 1, pw, pwb, (void*)st);
     };
     return gmres_run<TK>(n, L, apply, apply_inner, refine, b, x, o, info, ws, st, "vie_solve_pwl");
+}
+
+KLayout jm_pwl_layout(const vie_pwl_op* op_n, const vie_pwl_op* op_k, int dtype, int m)
+{
+    const OpView& v = op_n->blk[0]->d.view;
+    return k_layout(24L * v.n[0] * v.n[1] * v.n[2], vie_jm_pwl_workspace_bytes(op_n, op_k, dtype), dtype, m);
+}
+
+template <typename TK>
+vie_status run_jm_pwl(const vie_pwl_op* op_n, const vie_pwl_op* op_k, int dtype, double h, double omega,
+                      const void* eps_c, const void* mu_c, const c2<TK>* b, c2<TK>* x, const vie_solve_opts& o,
+                      vie_solve_info* info, char* ws, hipStream_t st)
+{
+    const OpView& v = op_n->blk[0]->d.view;
+    const long n = 24L * v.n[0] * v.n[1] * v.n[2];
+    const KLayout L = jm_pwl_layout(op_n, op_k, dtype, o.restart);
+    void* jw = ws + L.op;
+    const size_t jwb = vie_jm_pwl_workspace_bytes(op_n, op_k, dtype);
+    const bool refine = o.refine && sizeof(TK) == 8;
+    auto apply_prec = [&](const c2<TK>* in, c2<TK>* out, bool mixed) {
+        jm_mixed_products = mixed;
+        vie_status r = vie_matvec_jm_pwl(op_n, op_k, dtype, h, omega, eps_c, mu_c, in, out, jw, jwb, st);
+        jm_mixed_products = false;
+        return r;
+    };
+    auto apply = [&](const c2<TK>* in, c2<TK>* out) { return apply_prec(in, out, false); };
+    auto apply_inner = [&](const c2<TK>* in, c2<TK>* out) { return apply_prec(in, out, refine); };
+    return gmres_run<TK>(n, L, apply, apply_inner, refine, b, x, o, info, ws, st, "vie_solve_jm_pwl");
 }
 
 }  // namespace
@@ -325,6 +353,7 @@ vie_status vie_solve_pwl(const vie_pwl_op* op, int dtype, const void* eps_c, con
                          const vie_solve_opts* opts, vie_solve_info* info, void* ws, size_t ws_bytes, void* stream)
 {
     if (!op || !op->blk[0] || !eps_c || !b || !x || !ws) return fail(VIE_E_ARG, "vie_solve_pwl: null argument");
+    if (op->fam != 0) return fail(VIE_E_UNSUPPORTED, "vie_solve_pwl: the operator is a K operator");
     vie_solve_opts o;
     o.tol = 1e-6;
     o.restart = 50;
@@ -354,6 +383,57 @@ vie_status vie_solve_pwl(const vie_pwl_op* op, int dtype, const void* eps_c, con
     if (dtype == VIE_C128)
         return run_pwl<double>(op, dtype, eps_c, (const c2<double>*)b, (c2<double>*)x, o, info, (char*)ws, st);
     return run_pwl<float>(op, dtype, eps_c, (const c2<float>*)b, (c2<float>*)x, o, info, (char*)ws, st);
+}
+
+size_t vie_solve_jm_pwl_workspace_bytes(const vie_pwl_op* op_n, const vie_pwl_op* op_k, int dtype,
+                                        const vie_solve_opts* opts)
+{
+    if (!op_n || !op_k || !op_n->blk[0] || !op_k->blk[0] || (dtype != VIE_C64 && dtype != VIE_C128)) return 0;
+    const int m = opts ? opts->restart : 50;
+    if (m < 1 || m > 200) return 0;
+    return jm_pwl_layout(op_n, op_k, dtype, m).total;
+}
+
+vie_status vie_solve_jm_pwl(const vie_pwl_op* op_n, const vie_pwl_op* op_k, int dtype, double h, double omega,
+                            const void* eps_c, const void* mu_c, const void* b, void* x, const vie_solve_opts* opts,
+                            vie_solve_info* info, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!op_n || !op_k || !op_n->blk[0] || !op_k->blk[0] || !eps_c || !mu_c || !b || !x || !ws || !(h > 0) ||
+        !(omega > 0))
+        return fail(VIE_E_ARG, "vie_solve_jm_pwl: bad argument");
+    if (op_n->fam != 0 || op_k->fam != 1)
+        return fail(VIE_E_ARG, "vie_solve_jm_pwl: needs an N operator and a K operator");
+    vie_solve_opts o;
+    o.tol = 1e-6;
+    o.restart = 50;
+    o.max_outer = 200;
+    o.adjoint = 0;
+    o.refine = 0;
+    o.inner_recon = VIE_RECON_FP32;
+    o.inner_tol = 1e-4;
+    if (opts) o = *opts;
+    if (!(o.tol > 0) || o.restart < 1 || o.restart > 200 || o.max_outer < 0)
+        return fail(VIE_E_ARG, "vie_solve_jm_pwl: bad options");
+    if (o.adjoint) return fail(VIE_E_UNSUPPORTED, "vie_solve_jm_pwl: forward solves only");
+    if (dtype != VIE_C64 && dtype != VIE_C128) return fail(VIE_E_ARG, "vie_solve_jm_pwl: bad dtype");
+    if (o.refine && (dtype != VIE_C128 || !(o.inner_tol > 0 && o.inner_tol < 1)))
+        return fail(VIE_E_ARG, "vie_solve_jm_pwl: refinement needs VIE_C128 vectors and inner_tol in (0, 1)");
+    if (o.refine && o.inner_recon != VIE_RECON_FP32)
+        return fail(VIE_E_UNSUPPORTED, "vie_solve_jm_pwl: refinement takes FP32 inner products only");
+    if (ws_bytes < vie_solve_jm_pwl_workspace_bytes(op_n, op_k, dtype, &o))
+        return fail(VIE_E_ARG, "vie_solve_jm_pwl: workspace too small");
+    if (info && info->history && info->hist_cap < 0) return fail(VIE_E_ARG, "vie_solve_jm_pwl: bad history capacity");
+    const OpView& v = op_n->blk[0]->d.view;
+    const size_t vbytes = (size_t)24 * v.n[0] * v.n[1] * v.n[2] * (dtype == VIE_C128 ? 16 : 8);
+    const char* xb = (const char*)x;
+    const char* bb = (const char*)b;
+    if (!(xb + vbytes <= bb || bb + vbytes <= xb)) return fail(VIE_E_ARG, "vie_solve_jm_pwl: x and b overlap");
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == VIE_C128)
+        return run_jm_pwl<double>(op_n, op_k, dtype, h, omega, eps_c, mu_c, (const c2<double>*)b, (c2<double>*)x, o,
+                                  info, (char*)ws, st);
+    return run_jm_pwl<float>(op_n, op_k, dtype, h, omega, eps_c, mu_c, (const c2<float>*)b, (c2<float>*)x, o, info,
+                             (char*)ws, st);
 }
 
 }  // extern "C"

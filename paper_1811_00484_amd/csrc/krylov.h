@@ -48,7 +48,7 @@ hipError_t kr_magnetic_field(const c2<T>* h_inc, const c2<T>* KJ, double h, doub
                              hipStream_t st);
 template <typename T>
 hipError_t kr_jm_combine(const c2<T>* eps, const c2<T>* mu, const c2<T>* x, const c2<T>* NX, const c2<T>* KX,
-                         double ce_h, double cm_h, c2<T>* y, long nv, hipStream_t st);
+                         double ce_h, double cm_h, c2<T>* y, long nv, int nq, hipStream_t st);
 template <typename T>
 hipError_t kr_adjoint_source(const c2<T>* g, const c2<T>* NHg, c2<T>* t, long n, hipStream_t st);
 

@@ -236,21 +236,22 @@ __global__ void __launch_bounds__(KB) k_magnetic_field(const c2<T>* __restrict__
 //   y_J = eps J - chi_e N J + i ce_h chi_e K M
 //   y_M = mu M  - chi_h N M - i cm_h chi_h K J
 // (ce_h = omega eps0 h, cm_h = omega mu0 h; chi = contrast - 1); x, NX, KX,
-// y are [2][3][nv], eps and mu [nv]
+// y are [2][nq][nv] (nq = 3 pulse components, or 12 piecewise-linear
+// coefficients in the mass-normalised basis, whose mass term is the
+// identity), eps and mu [nv]
 template <typename T>
 __global__ void __launch_bounds__(KB) k_jm_combine(const c2<T>* __restrict__ eps, const c2<T>* __restrict__ mu,
                                                    const c2<T>* __restrict__ x, const c2<T>* __restrict__ NX,
                                                    const c2<T>* __restrict__ KX, double ce_h, double cm_h,
-                                                   c2<T>* __restrict__ y, long nv)
+                                                   c2<T>* __restrict__ y, long nv, int nq)
 {
     long i = (long)blockIdx.x * KB + threadIdx.x;
     if (i >= nv) return;
     const c2<T> e = eps[i], m = mu[i];
     const c2<T> ce = mk<T>(e.x - (T)1, e.y), cmu = mk<T>(m.x - (T)1, m.y);
     const c2<T> ie = mk<T>(0, (T)ce_h) * ce, im = mk<T>(0, (T)cm_h) * cmu;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const long oJ = q * nv + i, oM = (3 + q) * nv + i;
+    for (int q = 0; q < nq; ++q) {
+        const long oJ = q * nv + i, oM = (nq + q) * nv + i;
         y[oJ] = e * x[oJ] - ce * NX[oJ] + ie * KX[oM];
         y[oM] = m * x[oM] - cmu * NX[oM] - im * KX[oJ];
     }
@@ -359,10 +360,10 @@ hipError_t kr_magnetic_field(const c2<T>* h_inc, const c2<T>* KJ, double h, doub
 
 template <typename T>
 hipError_t kr_jm_combine(const c2<T>* eps, const c2<T>* mu, const c2<T>* x, const c2<T>* NX, const c2<T>* KX,
-                         double ce_h, double cm_h, c2<T>* y, long nv, hipStream_t st)
+                         double ce_h, double cm_h, c2<T>* y, long nv, int nq, hipStream_t st)
 {
     hipLaunchKernelGGL(k_jm_combine<T>, dim3((nv + KB - 1) / KB), dim3(KB), 0, st, eps, mu, x, NX, KX, ce_h, cm_h, y,
-                       nv);
+                       nv, nq);
     return hipGetLastError();
 }
 
@@ -392,7 +393,7 @@ hipError_t kr_adjoint_source(const c2<T>* g, const c2<T>* NHg, c2<T>* t, long n,
     template hipError_t kr_magnetic_field<TK>(const c2<TK>*, const c2<TK>*, double, double, c2<TK>*, TK*, long,   \
                                               hipStream_t);                                                      \
     template hipError_t kr_jm_combine<TK>(const c2<TK>*, const c2<TK>*, const c2<TK>*, const c2<TK>*,             \
-                                          const c2<TK>*, double, double, c2<TK>*, long, hipStream_t);
+                                          const c2<TK>*, double, double, c2<TK>*, long, int, hipStream_t);
 
 VIE_KR_INST(float)
 VIE_KR_INST(double)

@@ -267,6 +267,7 @@ const char* vie_version(void) { return "vie-gfx950 0.1"; }
 static vie_status compress_common(const int n[3], const double* green, const vie_compress_opts* opts, int cp_rank,
                                   int cp_iters, vie_op** out, vie_compress_info* info, double* cp_err,
                                   int lmask = 0, double scale = 1.0);
+static vie_status pwl_upload(vie_pwl_op* P, const char* who);
 
 vie_status vie_compress(const int n[3], const double* green, const vie_compress_opts* opts, vie_op** out,
                         vie_compress_info* info)
@@ -281,8 +282,18 @@ vie_status vie_compress_cp(const int n[3], const double* green, const vie_compre
     return compress_common(n, green, opts, cp_rank, cp_iters == 0 ? 1000 : cp_iters, out, info, cp_rel_err);
 }
 
+static vie_status compress_k_common(const int n[3], const double* green_k, const vie_compress_opts* opts,
+                                    vie_op** out, vie_compress_info* info, int lmask, double scale);
+
 vie_status vie_compress_k(const int n[3], const double* green_k, const vie_compress_opts* opts, vie_op** out,
                           vie_compress_info* info)
+{
+    return compress_k_common(n, green_k, opts, out, info, 0, 1.0);
+}
+
+// lmask, scale: as compress_common (piecewise-linear blocks)
+static vie_status compress_k_common(const int n[3], const double* green_k, const vie_compress_opts* opts,
+                                    vie_op** out, vie_compress_info* info, int lmask, double scale)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!n || !green_k || !out) return fail(VIE_E_ARG, "vie_compress_k: null argument");
@@ -316,16 +327,17 @@ vie_status vie_compress_k(const int n[3], const double* green_k, const vie_compr
     for (int c = 3; c < 6; ++c) {
         const double* g = green_k + 2 * (size_t)(c - 3) * V;
         for (long t = 0; t < V; ++t) A[t] = cd(g[2 * t], g[2 * t + 1]);
-        // the component is odd along one axis: zero at zero offset there
+        // zero at zero offset along the axes the component is odd along
         for (int k = 0; k < n[2]; ++k)
             for (int j = 0; j < n[1]; ++j)
                 for (int i = 0; i < n[0]; ++i)
-                    if ((comp_odd(1, c, 0) && i == 0) || (comp_odd(1, c, 1) && j == 0) || (comp_odd(1, c, 2) && k == 0))
+                    if ((view_odd(1, lmask, c, 0) && i == 0) || (view_odd(1, lmask, c, 1) && j == 0) ||
+                        (view_odd(1, lmask, c, 2) && k == 0))
                         A[((long)k * n[1] + j) * n[0] + i] = 0.0;
         int rc = hosvd_component(A.data(), n, o.tol, o.trunc_rule, o.max_rank, tc[c]);
         if (rc != 0) return fail(VIE_E_UNSUPPORTED, "vie_compress_k: max_rank too small for tol");
     }
-    return build_operator(n, plans, tc, out, info, t0, 1);
+    return build_operator(n, plans, tc, out, info, t0, 1, lmask, scale);
 }
 
 static vie_status compress_common(const int n[3], const double* green, const vie_compress_opts* opts, int cp_rank,
@@ -633,6 +645,47 @@ vie_status vie_compress_pwl(const int n[3], const double* green_pwl, const vie_c
         }
         P->rmax = std::max(P->rmax, P->blk[b]->d.view.rmax);
     }
+    vie_status st = pwl_upload(P, "vie_compress_pwl");
+    if (st == VIE_OK) *out = P;
+    return st;
+}
+
+vie_status vie_compress_pwl_k(const int n[3], const double* green_pwl_k, const vie_compress_opts* opts,
+                              vie_pwl_op** out, vie_compress_info* info)
+{
+    if (!n || !green_pwl_k || !out) return fail(VIE_E_ARG, "vie_compress_pwl_k: null argument");
+    *out = nullptr;
+    for (int a = 0; a < 3; ++a)
+        if (n[a] < 1 || n[a] > 256) return fail(VIE_E_UNSUPPORTED, "vie_compress_pwl_k: n_i must be in [1, 256]");
+    const size_t V = (size_t)n[0] * n[1] * n[2];
+    const double s12 = std::sqrt(12.0);
+    vie_pwl_op* P = new vie_pwl_op();
+    P->fam = 1;
+    for (int b = 0; b < 10; ++b) P->blk[b] = nullptr;
+    for (int b = 0; b < 10; ++b) {
+        const int la = kPwlPairs[b][0], lb = kPwlPairs[b][1];
+        int lmask = 0;
+        for (int a = 0; a < 3; ++a) lmask |= (((la == a + 1) + (lb == a + 1)) & 1) << a;
+        const double scale = (la ? s12 : 1.0) * (lb ? s12 : 1.0);
+        vie_status st = compress_k_common(n, green_pwl_k + (size_t)b * 6 * V, opts, &P->blk[b],
+                                          info ? &info[b] : nullptr, lmask, scale);
+        if (st != VIE_OK) {
+            std::string msg = vie_last_error();
+            vie_pwl_op_destroy(P);
+            return fail(st, "vie_compress_pwl_k: block " + std::to_string(b) + ": " + msg);
+        }
+        P->rmax = std::max(P->rmax, P->blk[b]->d.view.rmax);
+    }
+    vie_status st = pwl_upload(P, "vie_compress_pwl_k");
+    if (st == VIE_OK) *out = P;
+    return st;
+}
+
+}  // extern "C"
+
+// device copies of the ten block views (the z pass reads them by pair)
+static vie_status pwl_upload(vie_pwl_op* P, const char* who)
+{
     PwlBlock<float> h32[10];
     PwlBlock<double> h64[10];
     for (int b = 0; b < 10; ++b) {
@@ -650,11 +703,12 @@ vie_status vie_compress_pwl(const int n[3], const double* green_pwl, const vie_c
     if (e == hipSuccess) e = hipMemcpy(P->dev64, h64, sizeof(h64), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         vie_pwl_op_destroy(P);
-        return hip_fail(e, "vie_compress_pwl upload");
+        return hip_fail(e, (std::string(who) + " upload").c_str());
     }
-    *out = P;
     return VIE_OK;
 }
+
+extern "C" {
 
 vie_status vie_op_query(const vie_op* op, int n[3], int ranks[6][3])
 {
@@ -814,11 +868,11 @@ vie_status vie_matvec_jm(const vie_op* op_n, const vie_op* op_k, int dtype, doub
     if (dtype == VIE_C128)
         e = kr_jm_combine<double>((const c2<double>*)eps_c, (const c2<double>*)mu_c, (const c2<double>*)x,
                                   (const c2<double>*)NX, (const c2<double>*)KX, omega * EPS0 * h, omega * MU0 * h,
-                                  (c2<double>*)y, nv, (hipStream_t)stream);
+                                  (c2<double>*)y, nv, 3, (hipStream_t)stream);
     else
         e = kr_jm_combine<float>((const c2<float>*)eps_c, (const c2<float>*)mu_c, (const c2<float>*)x,
                                  (const c2<float>*)NX, (const c2<float>*)KX, omega * EPS0 * h, omega * MU0 * h,
-                                 (c2<float>*)y, nv, (hipStream_t)stream);
+                                 (c2<float>*)y, nv, 3, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "vie_matvec_jm");
     return VIE_OK;
 }

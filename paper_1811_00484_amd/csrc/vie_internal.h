@@ -275,10 +275,12 @@ constexpr int kPwlPairs[10][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 1}, {1, 2}
 }  // namespace vie
 
 // opaque handle of a piecewise-linear operator: ten six-component blocks
+// (fam 0, N) or ten antisymmetric blocks with slots 3..5 = xy, xz, yz (fam 1, K)
 struct vie_pwl_op {
     vie_op* blk[10];
     vie::PwlBlock<float>* dev32 = nullptr;    // device copies of the ten block views
     vie::PwlBlock<double>* dev64 = nullptr;
     int rmax = 1;
+    int fam = 0;
 };
 

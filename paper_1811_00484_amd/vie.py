@@ -99,6 +99,13 @@ _SIGS = {
     "vie_solve_jm_workspace_bytes": (ctypes.c_size_t, [_P, _P, ctypes.c_int, ctypes.POINTER(SolveOpts)]),
     "vie_solve_jm": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P,
                                     ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P, ctypes.c_size_t, _P]),
+    "vie_jm_pwl_workspace_bytes": (ctypes.c_size_t, [_P, _P, ctypes.c_int]),
+    "vie_matvec_jm_pwl": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P,
+                                         ctypes.c_size_t, _P]),
+    "vie_solve_jm_pwl_workspace_bytes": (ctypes.c_size_t, [_P, _P, ctypes.c_int, ctypes.POINTER(SolveOpts)]),
+    "vie_solve_jm_pwl": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P,
+                                        ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P, ctypes.c_size_t,
+                                        _P]),
     "vie_magnetic_field": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
     "vie_compress_cross": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, _P, ctypes.POINTER(CrossOpts),
                                           ctypes.POINTER(_P), ctypes.POINTER(CompressInfo), ctypes.POINTER(CrossInfo)]),
@@ -116,11 +123,13 @@ _SIGS = {
                                           ctypes.POINTER(_P), ctypes.POINTER(CompressInfo)]),
     "vie_compress_pwl": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.POINTER(CompressOpts), ctypes.c_int,
                                         ctypes.c_int, ctypes.POINTER(_P), _P]),
+    "vie_compress_pwl_k": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _P, ctypes.POINTER(CompressOpts),
+                                          ctypes.POINTER(_P), _P]),
     "vie_pwl_op_destroy": (ctypes.c_int, [_P]),
     "vie_pwl_op_query": (ctypes.c_int, [_P, _P, _P]),
-    "vie_pwl_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int]),
-    "vie_matvec_pwl": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, ctypes.c_size_t,
-                                      _P]),
+    "vie_pwl_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int, ctypes.c_int]),
+    "vie_matvec_pwl": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, ctypes.c_int, _P,
+                                      ctypes.c_size_t, _P]),
     "vie_solve_pwl_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int, ctypes.POINTER(SolveOpts)]),
     "vie_solve_pwl": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.POINTER(SolveOpts),
                                      ctypes.POINTER(SolveInfo), _P, ctypes.c_size_t, _P]),
@@ -321,11 +330,14 @@ def compress_cp(green, tol=1e-6, cp_rank=0, cp_iters=0, trunc_rule=0, max_rank=0
 
 class PwlOperator:
     """Device-resident piecewise-linear operator (owns a vie_pwl_op): ten
-    six-component Tucker (or Tucker+CP) blocks, one per basis pair."""
+    six-component Tucker (or Tucker+CP) blocks, one per basis pair (family
+    'N'), or ten antisymmetric blocks of the magnetic operator (family 'K',
+    ranks[:, 3:] the xy, xz, yz components)."""
 
-    def __init__(self, handle, n, infos):
+    def __init__(self, handle, n, infos, family="N"):
         self._h = handle
         self.n = tuple(n)
+        self.family = family
         self.ranks = np.array([[[info.ranks[c][a] for a in range(3)] for c in range(6)] for info in infos])
         self.tucker_bytes_c64 = int(sum(info.tucker_bytes_c64 for info in infos))
         self.device_bytes = int(sum(info.device_bytes for info in infos))
@@ -370,27 +382,54 @@ def compress_pwl(green_pwl, tol=1e-6, cp_rank=-1, cp_iters=0, trunc_rule=0, max_
     return PwlOperator(h, (g.shape[4], g.shape[3], g.shape[2]), list(infos))
 
 
+def compress_pwl_k(green_pwl_k, tol=1e-6, trunc_rule=0, max_rank=0):
+    """Compress the thirty piecewise-linear K tensors (numpy complex128, shape
+    (10, 3, n3, n2, n1): pairs as compress_pwl, components xy, xz, yz) by
+    HOSVD and upload them (vie_compress_pwl_k); apply with
+    ``matvec_pwl(op, x, kind="N")``."""
+    lib = load()
+    g = np.ascontiguousarray(green_pwl_k, dtype=np.complex128)
+    if g.ndim != 5 or g.shape[:2] != (10, 3):
+        raise ValueError("green_pwl_k must have shape (10, 3, n3, n2, n1)")
+    n = (ctypes.c_int * 3)(g.shape[4], g.shape[3], g.shape[2])
+    opts = CompressOpts(float(tol), int(trunc_rule), int(max_rank))
+    infos = (CompressInfo * 10)()
+    h = ctypes.c_void_p()
+    _check(lib.vie_compress_pwl_k(n, g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts), ctypes.byref(h),
+                                  ctypes.cast(infos, ctypes.c_void_p)), "vie_compress_pwl_k")
+    return PwlOperator(h, (g.shape[4], g.shape[3], g.shape[2]), list(infos), family="K")
+
+
 def matvec_pwl(op, x, eps_c=None, kind="A", adjoint=False, out=None):
     """y = S A S x (kind 'A'), the bare sum S N S x (kind 'N'), or their
-    adjoints, in the mass-normalised piecewise-linear basis; x is
-    (12, n3, n2, n1) = [l][q] complex64 or complex128 on the device."""
+    adjoints, in the mass-normalised piecewise-linear basis (a K operator:
+    S K S x, kind 'N' without adjoint only); x is
+    (12, n3, n2, n1) = [l][q], or (nrhs, 12, n3, n2, n1) for several vectors
+    with the same contrast, complex64 or complex128 on the device."""
     n1, n2, n3 = op.n
     dt = _dt(x)
-    if tuple(x.shape) != (12, n3, n2, n1) or not x.is_contiguous():
-        raise ValueError("x must be a contiguous (12, %d, %d, %d) tensor" % (n3, n2, n1))
-    _require_device(x, "x")
+    single = x.dim() == 4
+    xb = x.unsqueeze(0) if single else x
+    if xb.dim() != 5 or tuple(xb.shape[1:]) != (12, n3, n2, n1) or not xb.is_contiguous():
+        raise ValueError("x must be a contiguous (12, %d, %d, %d) or (nrhs, 12, %d, %d, %d) tensor"
+                         % (n3, n2, n1, n3, n2, n1))
+    _require_device(xb, "x")
     k = VIE_OP_A if kind == "A" else VIE_OP_N
     if k == VIE_OP_A:
         if eps_c is None:
             raise ValueError("eps_c required for kind 'A'")
-        _require_like(eps_c, x, x.shape[1:], "eps_c")
-    y = torch.empty_like(x) if out is None else _require_like(out, x, x.shape, "out")
+        _require_like(eps_c, xb, xb.shape[2:], "eps_c")
+    y = torch.empty_like(xb) if out is None else _require_like(out, x, x.shape, "out")
+    yb = y if out is None else (y.unsqueeze(0) if single else y)
     lib = load()
-    nbytes = lib.vie_pwl_workspace_bytes(op.handle, dt)
-    ws = op.workspace(nbytes, x.device)
+    nrhs = xb.shape[0]
+    nbytes = lib.vie_pwl_workspace_bytes(op.handle, dt, nrhs)
+    ws = op.workspace(nbytes, xb.device)
     _check(lib.vie_matvec_pwl(op.handle, k, 1 if adjoint else 0, dt, _ptr(eps_c) if k == VIE_OP_A else None,
-                              _ptr(x), _ptr(y), _ptr(ws), nbytes, _stream()), "vie_matvec_pwl")
-    return y
+                              _ptr(xb), _ptr(yb), nrhs, _ptr(ws), nbytes, _stream()), "vie_matvec_pwl")
+    if out is not None:
+        return out
+    return y[0] if single else y
 
 
 def solve_pwl(op, b, eps_c, tol=1e-6, restart=50, max_outer=200, adjoint=False, refine=False, inner_tol=1e-4,
@@ -513,6 +552,61 @@ def solve_jm(op_n, op_k, b, eps_c, mu_c, h, freq_hz, tol=1e-6, restart=50, max_o
                           _ptr(mu_c), _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(info), _ptr(ws), nbytes,
                           _stream())
     _check(st, "vie_solve_jm")
+    d = {"matvecs": info.matvecs, "matvecs_fp64": info.matvecs_fp64, "restarts": info.restarts,
+         "refine_steps": info.refine_steps, "converged": bool(info.converged),
+         "rel_residual": info.rel_residual, "history": hist[:info.hist_len].tolist()}
+    return x, d, st
+
+
+def matvec_jm_pwl(op_n, op_k, x, eps_c, mu_c, h, freq_hz):
+    """The JMVIE operator of eq. 4 in the mass-normalised piecewise-linear
+    basis (vie_matvec_jm_pwl) on x = [J; M] of shape (2, 12, n3, n2, n1);
+    op_n from compress_pwl, op_k from compress_pwl_k."""
+    n1, n2, n3 = op_n.n
+    if tuple(x.shape) != (2, 12, n3, n2, n1) or not x.is_contiguous():
+        raise ValueError("x must be contiguous (2, 12, n3, n2, n1)")
+    dt = _dt(x)
+    _require_like(eps_c, x, (n3, n2, n1), "eps_c")
+    _require_like(mu_c, x, (n3, n2, n1), "mu_c")
+    _require_device(x, "x")
+    lib = load()
+    nbytes = lib.vie_jm_pwl_workspace_bytes(op_n.handle, op_k.handle, dt)
+    ws = _scratch(nbytes, x.device)
+    y = torch.empty_like(x)
+    _check(lib.vie_matvec_jm_pwl(op_n.handle, op_k.handle, dt, float(h), 2.0 * np.pi * float(freq_hz),
+                                 _ptr(eps_c), _ptr(mu_c), _ptr(x), _ptr(y), _ptr(ws), nbytes, _stream()),
+           "vie_matvec_jm_pwl")
+    return y
+
+
+def solve_jm_pwl(op_n, op_k, b, eps_c, mu_c, h, freq_hz, tol=1e-6, restart=50, max_outer=200, history=64,
+                 refine=False, inner_tol=1e-5):
+    """GMRES for the JMVIE system in the piecewise-linear basis
+    (vie_solve_jm_pwl): b and the solution (2, 12, n3, n2, n1), mass-normalised
+    basis.  Returns (x, info dict, status)."""
+    n1, n2, n3 = op_n.n
+    if tuple(b.shape) != (2, 12, n3, n2, n1) or not b.is_contiguous():
+        raise ValueError("b must be contiguous (2, 12, n3, n2, n1)")
+    dt = _dt(b)
+    _require_like(eps_c, b, (n3, n2, n1), "eps_c")
+    _require_like(mu_c, b, (n3, n2, n1), "mu_c")
+    _require_device(b, "b")
+    lib = load()
+    opts = SolveOpts(float(tol), int(restart), int(max_outer), 0, int(bool(refine)), VIE_RECON_FP32,
+                     float(inner_tol))
+    nbytes = lib.vie_solve_jm_pwl_workspace_bytes(op_n.handle, op_k.handle, dt, ctypes.byref(opts))
+    if nbytes == 0:
+        raise VieError(VIE_E_ARG, "vie_solve_jm_pwl_workspace_bytes rejected the options")
+    ws = _scratch(nbytes, b.device)
+    x = torch.empty_like(b)
+    hist = np.zeros(max(1, int(history)))
+    info = SolveInfo()
+    info.history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    info.hist_cap = int(history)
+    st = lib.vie_solve_jm_pwl(op_n.handle, op_k.handle, dt, float(h), 2.0 * np.pi * float(freq_hz), _ptr(eps_c),
+                              _ptr(mu_c), _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(info), _ptr(ws), nbytes,
+                              _stream())
+    _check(st, "vie_solve_jm_pwl")
     d = {"matvecs": info.matvecs, "matvecs_fp64": info.matvecs_fp64, "restarts": info.restarts,
          "refine_steps": info.refine_steps, "converged": bool(info.converged),
          "rel_residual": info.rel_residual, "history": hist[:info.hist_len].tolist()}

@@ -172,3 +172,22 @@ def test_pwl_fullsize_sampled_outputs(N):
     err = np.abs(got - ref).max() / np.abs(ref).max()
     say("   max sampled error / max |y|", err)
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("n", [(12, 10, 9), (16, 16, 16)])
+def test_pwl_multi_rhs_equals_single_calls(n):
+    # several vectors in one call: the passes see 4 nrhs groups of three
+    # components and the z pass one grid row per vector
+    say("pwl multi rhs", n)
+    G, epsc, kh, _ = pwl_problem(n)
+    op = vie.compress_pwl(G, tol=1e-6)
+    rng = np.random.default_rng(205)
+    u = rng.standard_normal((3, 12, n[2], n[1], n[0])) + 1j * rng.standard_normal((3, 12, n[2], n[1], n[0]))
+    x = to_dev(u, torch.complex64)
+    e = to_dev(epsc, torch.complex64)
+    yb = vie.matvec_pwl(op, x, e).cpu().numpy()
+    for r in range(3):
+        ys = vie.matvec_pwl(op, x[r].contiguous(), e).cpu().numpy()
+        assert np.array_equal(yb[r], ys), r
+    ref = _reference(kh, epsc, u[1].reshape(4, 3, n[2], n[1], n[0]), "A")
+    assert rel(yb[1].astype(np.complex128).reshape(ref.shape), ref) <= 1e-5
