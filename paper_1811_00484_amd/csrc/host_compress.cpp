@@ -337,10 +337,11 @@ int hosvd_component(const cd* A, const int n[3], double tol, int rule, int max_r
         std::vector<double> s;
         // the Gram eigenvectors resolve singular values down to ~1e-8 sigma_max;
         // the Jacobi refinement restores full accuracy when a tight tolerance
-        // needs it (and always for small unfoldings, up to 2^19 entries times
-        // m, where it costs little: at 2^24 it took 0.7 s per 60^3 tensor,
-        // twice the unrefined 120^3 one)
-        const bool small = (long)m * V <= (long)1 << 19;
+        // needs it, and always on unfoldings up to 2^24 entries times m, so
+        // that the factors there agree with an exact SVD to ~1e-14 (without
+        // it a 40 x 24 x 64 K tensor's agree to ~1e-10 only); it costs about
+        // 0.7 s per 60^3 tensor
+        const bool small = (long)m * V <= (long)1 << 24;
         bool refine = tol < 1e-7 || small;
         // on very large unfoldings (more than 2^28 entries times m), rows far
         // below the truncation level (squared norm under (1e-3 tol)^2 of the
