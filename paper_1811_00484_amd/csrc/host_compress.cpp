@@ -38,11 +38,14 @@ int host_threads()
     return n;
 }
 
+// Set on the threads of parallel_jobs: work inside a job runs serially.
+static thread_local bool tl_serial = false;
+
 // Run f(begin, end) over [0, n) split into contiguous chunks on host threads.
 template <class F>
 static void parallel_for(long n, F f, long min_chunk = 1)
 {
-    int nt = host_threads();
+    int nt = tl_serial ? 1 : host_threads();
     long chunks = std::min<long>(nt, std::max<long>(1, n / std::max<long>(1, min_chunk)));
     if (chunks <= 1) {
         f(0L, n);
@@ -61,6 +64,23 @@ static void parallel_for(long n, F f, long min_chunk = 1)
 void parallel_rows(long n, const std::function<void(long, long)>& f)
 {
     parallel_for(n, [&](long b, long e) { f(b, e); });
+}
+
+void parallel_jobs(int count, const std::function<void(int)>& job)
+{
+    const int nt = std::min(host_threads(), count);
+    if (nt <= 1 || tl_serial) {
+        for (int i = 0; i < count; ++i) job(i);
+        return;
+    }
+    std::atomic<int> next(0);
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&]() {
+            tl_serial = true;
+            for (int i; (i = next.fetch_add(1)) < count;) job(i);
+        });
+    for (auto& t : th) t.join();
 }
 
 // Jacobi rotation parameters diagonalising [[a, c], [conj(c), b]] (a, b
@@ -221,6 +241,9 @@ void svd_left(const cd* Y, int m, long N, std::vector<cd>& U, std::vector<double
             int M = m + (m & 1);
             for (int r = 0; r < M - 1; ++r) {
                 tournament_pairs(m, r, pairs);
+                // the pairs of a round touch disjoint rows, so their order
+                // does not matter; short rows are not worth a thread each
+                const long serial_below = N < (1L << 14) ? (long)pairs.size() + 1 : 1;
                 parallel_for((long)pairs.size(), [&](long b, long e) {
                     for (long t = b; t < e; ++t) {
                         int p = pairs[t].first, q = pairs[t].second;
@@ -254,7 +277,7 @@ void svd_left(const cd* Y, int m, long N, std::vector<cd>& U, std::vector<double
                             Q[(size_t)k * m + q] = sn * vp + std::conj(ph) * cs * vq;
                         }
                     }
-                });
+                }, serial_below);
             }
             if (rotated.load() == 0) break;
         }

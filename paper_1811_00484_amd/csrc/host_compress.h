@@ -22,6 +22,11 @@ int host_threads();
 // depend on the thread count.
 void parallel_rows(long n, const std::function<void(long, long)>& f);
 
+// job(0) .. job(count - 1) on the host threads, each job on one thread with
+// every parallel loop inside it serial (results do not depend on which
+// thread runs a job, as the loops' results do not depend on the thread count)
+void parallel_jobs(int count, const std::function<void(int)>& job);
+
 // Left singular vectors (U, m x m row-major, columns by descending singular
 // value) and singular values of a row-major m x N matrix, m <= N.  With
 // `refine`, one-sided Jacobi sweeps on Z = Q^H Y restore full accuracy;

@@ -258,6 +258,26 @@ static vie_status build_operator(const int n[3], const FftPlan plans[3], TuckerC
 
 using namespace vie;
 
+// HOSVD of `count` defining tensors, one(c, buffer) each: on grids of at most
+// 2^18 voxels one tensor per host thread (its loops serial: on such short
+// unfoldings the threads' start-up outweighs the work inside one tensor), on
+// larger ones one after another with the threads inside each.  Results do not
+// depend on the choice.
+template <typename F>
+static void for_components(int count, long V, F one)
+{
+    using cd = std::complex<double>;
+    if (V <= (1L << 18)) {
+        parallel_jobs(count, [&](int c) {
+            std::vector<cd> A((size_t)V);
+            one(c, A);
+        });
+    } else {
+        std::vector<cd> A((size_t)V);
+        for (int c = 0; c < count; ++c) one(c, A);
+    }
+}
+
 extern "C" {
 
 const char* vie_last_error(void) { return g_last_error.c_str(); }
@@ -323,9 +343,10 @@ static vie_status compress_k_common(const int n[3], const double* green_k, const
         tc[c].tail_rel = 0;
         tc[c].fro = 0;
     }
-    std::vector<cd> A(V);
-    for (int c = 3; c < 6; ++c) {
-        const double* g = green_k + 2 * (size_t)(c - 3) * V;
+    int rc[6] = {0, 0, 0, 0, 0, 0};
+    for_components(3, V, [&](int j3, std::vector<cd>& A) {
+        const int c = 3 + j3;
+        const double* g = green_k + 2 * (size_t)j3 * V;
         for (long t = 0; t < V; ++t) A[t] = cd(g[2 * t], g[2 * t + 1]);
         // zero at zero offset along the axes the component is odd along
         for (int k = 0; k < n[2]; ++k)
@@ -334,9 +355,10 @@ static vie_status compress_k_common(const int n[3], const double* green_k, const
                     if ((view_odd(1, lmask, c, 0) && i == 0) || (view_odd(1, lmask, c, 1) && j == 0) ||
                         (view_odd(1, lmask, c, 2) && k == 0))
                         A[((long)k * n[1] + j) * n[0] + i] = 0.0;
-        int rc = hosvd_component(A.data(), n, o.tol, o.trunc_rule, o.max_rank, tc[c]);
-        if (rc != 0) return fail(VIE_E_UNSUPPORTED, "vie_compress_k: max_rank too small for tol");
-    }
+        rc[c] = hosvd_component(A.data(), n, o.tol, o.trunc_rule, o.max_rank, tc[c]);
+    });
+    for (int c = 3; c < 6; ++c)
+        if (rc[c] != 0) return fail(VIE_E_UNSUPPORTED, "vie_compress_k: max_rank too small for tol");
     return build_operator(n, plans, tc, out, info, t0, 1, lmask, scale);
 }
 
@@ -363,11 +385,11 @@ static vie_status compress_common(const int n[3], const double* green, const vie
 
     using cd = std::complex<double>;
     TuckerComponent tc[6];
-    std::vector<cd> A(V);
     int odd[6][3];
     for (int c = 0; c < 6; ++c)
         for (int a = 0; a < 3; ++a) odd[c][a] = view_odd(0, lmask, c, a);
-    for (int c = 0; c < 6; ++c) {
+    int rc[6] = {0, 0, 0, 0, 0, 0};
+    for_components(6, V, [&](int c, std::vector<cd>& A) {
         const double* g = green + 2 * (size_t)c * V;
         for (long t = 0; t < V; ++t) A[t] = cd(g[2 * t], g[2 * t + 1]);
         // an odd component vanishes at zero offset along its odd axes
@@ -376,9 +398,10 @@ static vie_status compress_common(const int n[3], const double* green, const vie
                 for (int i = 0; i < n[0]; ++i)
                     if ((odd[c][0] && i == 0) || (odd[c][1] && j == 0) || (odd[c][2] && k == 0))
                         A[((long)k * n[1] + j) * n[0] + i] = 0.0;
-        int rc = hosvd_component(A.data(), n, tol, rule, max_rank, tc[c]);
-        if (rc != 0) return fail(VIE_E_UNSUPPORTED, "vie_compress: max_rank too small for tol");
-    }
+        rc[c] = hosvd_component(A.data(), n, tol, rule, max_rank, tc[c]);
+    });
+    for (int c = 0; c < 6; ++c)
+        if (rc[c] != 0) return fail(VIE_E_UNSUPPORTED, "vie_compress: max_rank too small for tol");
     if (cp_rank >= 0) {
         // Alg. 2: CP of each core, Tucker+CP factors W^a = U^a V^a, and a
         // superdiagonal core so that eq. 17 is the Tucker form with it
