@@ -92,15 +92,16 @@ struct PwlZArgs {
     int conj;    // adjoint
     int rmax;    // largest Tucker rank over the ten blocks
     int pb;      // pairs whose tables are built and applied together (1..10)
-    // parity mask of component c of pair b, om[b * nc + c] (bit a: odd along axis a)
-    unsigned char om[60];
+    // for each mirror-flag combination f = f1 | f2 << 1 | f3 << 2, the tables
+    // that change sign there: bit b * nc + c of neg[f] is set when component c
+    // of pair b is odd along an odd number of the flagged axes
+    unsigned long long neg[8];
 };
 
-// the sign of a table entry at a mirrored position: f = f1 | f2 << 1 | f3 << 2
-// (mirror flags), odd along each flagged axis of the mask
-__device__ __forceinline__ bool pwl_neg(unsigned om, unsigned f)
+// the sign bit of table t under the flags' mask nm
+__device__ __forceinline__ bool pwl_neg(unsigned long long nm, int t)
 {
-    return __popc(om & f) & 1;
+    return (nm >> t) & 1ull;
 }
 
 // the (a, b) and (b, a) blocks of stored pair B on one Fourier position,
@@ -109,7 +110,7 @@ __device__ __forceinline__ bool pwl_neg(unsigned om, unsigned f)
 // K (FAM 1): K^_ab = T, K^_ba = sigma T (the sum runs over m - m'); no adjoint
 template <int B, int FAM, typename T>
 __device__ __forceinline__ void pwl_pair(c2<T> (&acc)[12], const c2<T> (&x)[12], const c2<T>* NTT, int n3p1, int kk,
-                                         unsigned f, const unsigned char* om, bool conj)
+                                         unsigned long long nm, bool conj)
 {
     constexpr int la = kPwlPairs[B][0], lb = kPwlPairs[B][1];
     constexpr bool sig = (la == 0) != (lb == 0);
@@ -118,7 +119,7 @@ __device__ __forceinline__ void pwl_pair(c2<T> (&acc)[12], const c2<T> (&x)[12],
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         c2<T> t = NTT[(B * NC + c) * n3p1 + kk];
-        if (pwl_neg(om[B * NC + c], f)) t = mk<T>(-t.x, -t.y);
+        if (pwl_neg(nm, B * NC + c)) t = mk<T>(-t.x, -t.y);
         N[c] = conj ? vie::conj(t) : t;
     }
     T sab, sba;
@@ -146,10 +147,10 @@ __device__ __forceinline__ void pwl_pair(c2<T> (&acc)[12], const c2<T> (&x)[12],
 
 template <int FAM, typename T, int... B>
 __device__ __forceinline__ void pwl_all_pairs(c2<T> (&acc)[12], const c2<T> (&x)[12], const c2<T>* NTT, int n3p1,
-                                              int kk, unsigned f, const unsigned char* om, bool conj,
+                                              int kk, unsigned long long nm, bool conj,
                                               std::integer_sequence<int, B...>)
 {
-    (pwl_pair<B, FAM, T>(acc, x, NTT, n3p1, kk, f, om, conj), ...);
+    (pwl_pair<B, FAM, T>(acc, x, NTT, n3p1, kk, nm, conj), ...);
 }
 
 // mixed-radix LDS transform of the 12 P pencils (sequence-major); LC > 0:
@@ -245,7 +246,12 @@ __global__ void __launch_bounds__(kNTZ) k_pwl_z(c2<T>* __restrict__ S2, FftPlan 
     c2<T>* NTT = X + (size_t)12 * a.G * L3;         // [pb][NC][n3 + 1]
     c2<T>* Vc = NTT + (size_t)a.pb * NC * (n3 + 1); // [pb][NC][rmax]
     c2<T>* tws = Vc + (size_t)a.pb * NC * rmax;     // [L3]
+    unsigned long long* negs = reinterpret_cast<unsigned long long*>(tws + L3);   // [8]
     for (int m = tid; m < L3; m += kNTZ) tws[m] = tw[m];
+    if (tid == 0) {
+#pragma unroll
+        for (int f = 0; f < 8; ++f) negs[f] = a.neg[f];
+    }
 
     for (int e = tid; e < 12 * P * L3; e += kNTZ) {
         const int s = e / L3, m = e - s * L3;
@@ -327,11 +333,12 @@ __global__ void __launch_bounds__(kNTZ) k_pwl_z(c2<T>* __restrict__ S2, FftPlan 
 #pragma unroll
                 for (int c = 0; c < 12; ++c) x[c] = X[(c * P + pe) * L3 + m];
                 const unsigned fb = (unsigned)pf1[pe] | ((unsigned)pf2[pe] << 1) | ((unsigned)f3 << 2);
+                const unsigned long long nm = negs[fb];
                 if (nb == 10) {
                     c2<T> ac[12];
 #pragma unroll
                     for (int c = 0; c < 12; ++c) ac[c] = acc[c][j];
-                    pwl_all_pairs<FAM, T>(ac, x, NTT, n3 + 1, kk, fb, a.om, a.conj != 0,
+                    pwl_all_pairs<FAM, T>(ac, x, NTT, n3 + 1, kk, nm, a.conj != 0,
                                           std::make_integer_sequence<int, 10>{});
 #pragma unroll
                     for (int c = 0; c < 12; ++c) acc[c][j] = ac[c];
@@ -349,7 +356,7 @@ __global__ void __launch_bounds__(kNTZ) k_pwl_z(c2<T>* __restrict__ S2, FftPlan 
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
                         c2<T> t = NTT[(bi * NC + c) * (n3 + 1) + kk];
-                        if (pwl_neg(a.om[b * NC + c], fb)) t = mk<T>(-t.x, -t.y);
+                        if (pwl_neg(nm, b * NC + c)) t = mk<T>(-t.x, -t.y);
                         Nc[c] = a.conj ? vie::conj(t) : t;
                     }
                     // register arrays need compile-time indices: select the rows
@@ -420,7 +427,8 @@ constexpr int pwl_ept()
 template <typename T>
 size_t pwl_z_lds(const OpView& v, int rmax, int nc, int G, int pb)
 {
-    return sizeof(c2<T>) * ((size_t)12 * G * v.L[2] + (size_t)pb * nc * ((v.n[2] + 1) + rmax) + v.L[2]);
+    return sizeof(c2<T>) * ((size_t)12 * G * v.L[2] + (size_t)pb * nc * ((v.n[2] + 1) + rmax) + v.L[2]) +
+           8 * sizeof(unsigned long long);
 }
 
 // pencils per workgroup for the z pass (the largest mirror group whose
@@ -494,11 +502,14 @@ hipError_t launch_pwl_z(const vie_pwl_op& P, int conj, c2<T>* S2, c2<T>* Wg, int
     za.conj = conj;
     za.rmax = P.rmax;
     za.pb = pb;
+    for (int f = 0; f < 8; ++f) za.neg[f] = 0;
     for (int b = 0; b < 10; ++b)
         for (int c = 0; c < nc; ++c) {
             const int lm = P.blk[b]->d.view.lmask;
-            za.om[b * nc + c] = (unsigned char)(view_odd(P.fam, lm, c0 + c, 0) | (view_odd(P.fam, lm, c0 + c, 1) << 1) |
-                                                (view_odd(P.fam, lm, c0 + c, 2) << 2));
+            const int om = view_odd(P.fam, lm, c0 + c, 0) | (view_odd(P.fam, lm, c0 + c, 1) << 1) |
+                           (view_odd(P.fam, lm, c0 + c, 2) << 2);
+            for (int f = 0; f < 8; ++f)
+                if (__builtin_popcount(om & f) & 1) za.neg[f] |= 1ull << (b * nc + c);
         }
     const int n1 = v.n[0], n2 = v.n[1];
     const int nblk = G == 4 ? (n1 + 1) * (n2 + 1) : (G == 2 ? (n1 + 1) * v.L[1] : v.L[0] * v.L[1]);
