@@ -90,3 +90,23 @@ def test_numpy_inputs_are_refused():
     x = _v()
     with pytest.raises(ValueError):
         vie.matvec(op, x, np.zeros(GRID, complex))
+
+
+def test_piecewise_linear_calls_reject_mismatches():
+    op = _FakeOp(N)
+    x = _v(shape=(12,) + GRID)
+    # the product checks the vectors' shape, then their device, then eps_c
+    assert "contiguous" in _raises(vie.matvec_pwl, op, _v(shape=(11,) + GRID))
+    assert "device tensor" in _raises(vie.matvec_pwl, op, x, _v(torch.complex64, GRID))
+    assert "device tensor" in _raises(vie.matvec_pwl, op, x, kind="N")
+    # several vectors: (nrhs, 12, n3, n2, n1)
+    assert "device tensor" in _raises(vie.matvec_pwl, op, _v(shape=(2, 12) + GRID), kind="N")
+    assert "b must be" in _raises(vie.solve_pwl, op, _v(shape=(3,) + GRID), _v(shape=GRID))
+    assert "dtype" in _raises(vie.solve_pwl, op, x, _v(torch.complex64, GRID))
+    xj = _v(shape=(2, 12) + GRID)
+    assert "x must be" in _raises(vie.matvec_jm_pwl, op, op, _v(shape=(2, 3) + GRID), _v(shape=GRID),
+                                  _v(shape=GRID), 0.001, 298e6)
+    assert "dtype" in _raises(vie.matvec_jm_pwl, op, op, xj, _v(shape=GRID), _v(torch.complex64, GRID), 0.001, 298e6)
+    assert "device tensor" in _raises(vie.matvec_jm_pwl, op, op, xj, _v(shape=GRID), _v(shape=GRID), 0.001, 298e6)
+    assert "dtype" in _raises(vie.solve_jm_pwl, op, op, xj, _v(torch.complex64, GRID), _v(shape=GRID), 0.001, 298e6)
+    assert "(10, 3" in _raises(vie.compress_pwl_k, np.zeros((10, 6) + GRID, complex))
