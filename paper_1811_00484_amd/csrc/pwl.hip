@@ -25,6 +25,15 @@
 // the (b, a) block.  T is symmetric over the dyadic pair (p, q), so each
 // block is the 3 x 3 product of the pulse basis.
 //
+// The magnetic operator K (eq. 5) in the same basis runs through the same
+// kernels with the operator family as a template argument: thirty stored
+// tensors (ten pairs x xy, xz, yz, the block views' slots 3..5), the
+// antisymmetric 3 x 3 product Kt_qp = -Kt_pq, and, since K's sum is a
+// convolution over m - m' (test function at the observation voxel),
+//   K^_ab = T,   K^_ba = sigma T.
+// The coupled JM operator of eq. 4 takes [J; M] as two right-hand sides of
+// the N and of the K product and combines them per voxel.
+//
 // Kernel layout: one 512-thread workgroup per mirror group of pencils (as
 // the generic z pass), the twelve pencils of each in LDS; every thread owns
 // up to EPT Fourier-domain positions and keeps their twelve output
