@@ -307,3 +307,30 @@ def test_single_magnetic_voxel_clausius_mossotti():
     assert np.abs(x[0]).max() <= 1e-12 * np.abs(expect).max()
     np.testing.assert_allclose(x[1][:, 0, 0, 0], expect, rtol=1e-9, atol=1e-12 * np.abs(expect).max())
     assert np.abs(expect).max() > 0
+
+
+def _grad_g_fd(D, kappa, d=1e-3):
+    """grad g(|x|) at the point D by central differences of
+    g = exp(-i kappa r) / (4 pi r): no parity rule, no generator code."""
+    def g(x):
+        r = np.sqrt(np.sum(np.square(x)))
+        return np.exp(-1j * kappa * r) / (4 * np.pi * r)
+    D = np.asarray(D, float)
+    return np.array([(g(D + np.eye(3)[s] * d) - g(D - np.eye(3)[s] * d)) / (2 * d) for s in range(3)])
+
+
+def test_k_entries_at_negative_offsets_follow_the_point_curl_kernel():
+    # far from the source Kt_pq = eps_psq d_s g times one scalar, so the ratio
+    # of each stored component (xy ~ d_z, xz ~ d_y, yz ~ d_x) to the matching
+    # derivative of g must be the same at every sign combination of the
+    # offset: pins k_entry's parity rule independently of the embedding
+    kappa = 0.05
+    kt = green_k_tensor((10, 8, 6), 1.0, kappa)
+    base = (9, 7, 5)
+    for c, (p, q) in enumerate(mg.K_COMPONENTS):
+        s = mg.K_ODD_AXIS[c]
+        ref = mg.k_entry(kt, p, q, base) / _grad_g_fd(base, kappa)[s]
+        for flips in range(1, 8):
+            D = tuple(-x if (flips >> a) & 1 else x for a, x in enumerate(base))
+            ratio = mg.k_entry(kt, p, q, D) / _grad_g_fd(D, kappa)[s]
+            assert abs(ratio - ref) < 2e-3 * abs(ref), (c, D, ratio, ref)

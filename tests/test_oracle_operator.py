@@ -114,3 +114,39 @@ def test_tucker_operator_error_tracks_tolerance():
         assert err < prev
         assert err < 50 * tol
         prev = err
+
+
+def _dyadic_fd(D, kappa, d=1e-3):
+    """(d_p d_q + kappa^2 delta_pq) g(|x|) at the point D by central
+    differences of g = exp(-i kappa r) / (4 pi r): the point dyadic written
+    from g alone, with no parity rule and no generator code."""
+    def g(x):
+        r = np.sqrt(np.sum(np.square(x)))
+        return np.exp(-1j * kappa * r) / (4 * np.pi * r)
+    D = np.asarray(D, float)
+    out = np.empty((3, 3), complex)
+    for p in range(3):
+        for q in range(3):
+            ep, eq = np.eye(3)[p] * d, np.eye(3)[q] * d
+            out[p, q] = (g(D + ep + eq) - g(D + ep - eq) - g(D - ep + eq) + g(D - ep - eq)) / (4 * d * d)
+            if p == q:
+                out[p, q] += kappa ** 2 * g(D)
+    return out
+
+
+def test_signed_entries_at_negative_offsets_follow_the_point_dyadic():
+    # far from the source the tensor is the point dyadic times one scalar
+    # (the tent average, 1 - kappa^2/12, and the generator's sign and
+    # normalisation convention), so the ratio of each component to the
+    # dyadic must be the same at every sign combination of the offset: this
+    # pins the parity rule of signed_entry (and of the embedding, which
+    # shares it) against an evaluation that uses no parity at all
+    kappa = 0.05
+    G = vi.green_tensor((10, 8, 6), 1.0, kappa)
+    base = (9, 7, 5)
+    for c, (p, q) in enumerate(circulant.COMPONENTS):
+        ref = opm.signed_entry(G, c, base) / _dyadic_fd(base, kappa)[p, q]
+        for flips in range(1, 8):
+            D = tuple(-x if (flips >> a) & 1 else x for a, x in enumerate(base))
+            ratio = opm.signed_entry(G, c, D) / _dyadic_fd(D, kappa)[p, q]
+            assert abs(ratio - ref) < 2e-3 * abs(ref), (c, D, ratio, ref)
