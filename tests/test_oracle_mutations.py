@@ -121,3 +121,62 @@ def test_truncation_one_column_short_is_caught(monkeypatch):
     orig = tucker.truncation_rank
     monkeypatch.setattr(tucker, "truncation_rank", lambda s, tol, rule, fro: max(1, orig(s, tol, rule, fro) - 1))
     assert not _hosvd_tails_within_share()
+
+
+def _cp_recovers_exact_rank3():
+    from oracle import cp
+    rng = np.random.default_rng(7)
+    Vs = [rng.standard_normal((m, 3)) + 1j * rng.standard_normal((m, 3)) for m in (5, 6, 7)]
+    G = cp.cp_reconstruct(Vs)
+    W, errs = cp.cp_als(G, 3, iters=300)
+    return np.linalg.norm(cp.cp_reconstruct(W) - G) <= 1e-8 * np.linalg.norm(G)
+
+
+def _gmres_solves_dense():
+    from oracle import gmres as gm
+    rng = np.random.default_rng(8)
+    A = np.eye(40) * 20 + rng.standard_normal((40, 40)) + 1j * rng.standard_normal((40, 40))
+    b = rng.standard_normal(40) + 1j * rng.standard_normal(40)
+    # one cycle as long as the dimension: exact in exact arithmetic, so the
+    # restarts on the true residual cannot mend a wrong least-squares step
+    x, info = gm.gmres(lambda v: A @ v, b, tol=1e-12, restart=40, max_outer=1)
+    return np.linalg.norm(x - np.linalg.solve(A, b)) <= 1e-9 * np.linalg.norm(np.linalg.solve(A, b))
+
+
+def _passes_equal_fft_convolution():
+    from oracle import passes
+    n = (4, 3, 5)
+    G = vi.green_tensor(n, 0.01, vi.wavenumber(298e6))
+    op = opm.dense_operator(G)
+    u = vi.random_field(n, 9)
+    y = passes.matvec_by_passes(op, None, u, "N")[0]
+    y0 = opm.apply_N(op, u)
+    return np.linalg.norm(y - y0) <= 1e-12 * np.linalg.norm(y0)
+
+
+def test_more_pins_hold_on_the_unmodified_oracles():
+    assert _cp_recovers_exact_rank3() and _gmres_solves_dense() and _passes_equal_fft_convolution()
+
+
+def test_khatri_rao_with_swapped_operands_is_caught(monkeypatch):
+    from oracle import cp
+    orig = cp.khatri_rao
+    monkeypatch.setattr(cp, "khatri_rao", lambda X, Y: orig(Y, X))
+    assert not _cp_recovers_exact_rank3()
+
+
+def test_givens_with_a_wrong_sign_is_caught(monkeypatch):
+    from oracle import gmres as gm
+    orig = gm._givens
+    monkeypatch.setattr(gm, "_givens", lambda a, b: (lambda c, s: (c, -s))(*orig(a, b)))
+    assert not _gmres_solves_dense()
+
+
+def test_z_pass_with_the_adjoint_tables_is_caught(monkeypatch):
+    # (flipping every DFT direction would not be a mistake here: N is even
+    # under reflection of all three axes, so the correlation equals the
+    # convolution; using conj(N^) in the forward product is one)
+    from oracle import passes
+    orig = passes.pass_z
+    monkeypatch.setattr(passes, "pass_z", lambda S2, nhat, conj=False: orig(S2, nhat, not conj))
+    assert not _passes_equal_fft_convolution()
