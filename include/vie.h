@@ -536,7 +536,10 @@ vie_status vie_solve_pwl(const vie_pwl_op* op, int dtype, const void* eps_c, con
  *   right-hand sides of vie_matvec_pwl, then one kernel combines.
  *   x, y DEVICE complex [2][12][n3][n2][n1] (J then M, not overlapping);
  *   eps_c, mu_c DEVICE complex [n3][n2][n1]; ws DEVICE scratch of
- *   vie_jm_pwl_workspace_bytes(op_n, op_k, dtype) bytes.  Asynchronous.
+ *   vie_jm_pwl_workspace_bytes(op_n, op_k, dtype) bytes (0 for a null
+ *   operator or a bad dtype), owned by the caller.  Asynchronous on
+ *   `stream`; VIE_E_ARG for a null pointer, h or omega not positive, a bad
+ *   dtype, too small a workspace or overlapping x and y.
  */
 size_t vie_jm_pwl_workspace_bytes(const vie_pwl_op* op_n, const vie_pwl_op* op_k, int dtype);
 vie_status vie_matvec_jm_pwl(const vie_pwl_op* op_n, const vie_pwl_op* op_k, int dtype, double h, double omega,
@@ -548,7 +551,10 @@ vie_status vie_matvec_jm_pwl(const vie_pwl_op* op_n, const vie_pwl_op* op_k, int
  * as vie_solve_jm (forward only, x starting at zero, opts refine with FP32
  * products on VIE_C128 vectors and FP64 restart residuals).  b, x DEVICE
  * [2][12][n3][n2][n1] in the mass-normalised basis (not overlapping);
- * ws DEVICE, vie_solve_jm_pwl_workspace_bytes.  Synchronous on `stream`.
+ * ws DEVICE, vie_solve_jm_pwl_workspace_bytes (0 when the options or the
+ * operators are rejected).  Returns VIE_OK, VIE_NOT_CONVERGED with x the
+ * last iterate, VIE_E_UNSUPPORTED for opts->adjoint, VIE_E_ARG for bad
+ * arguments.  Synchronous on `stream`.
  */
 size_t vie_solve_jm_pwl_workspace_bytes(const vie_pwl_op* op_n, const vie_pwl_op* op_k, int dtype,
                                         const vie_solve_opts* opts);
